@@ -1,0 +1,309 @@
+"""Pins for the CPU oracle: facts fixed by the paper and by arithmetic, not by the oracle itself.
+
+Each test names what fixes the expected value.  Mutation tests at the end plant plausible
+mistakes in the oracle (on the CPU) and check that a pin catches each one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import brute, lwe, paillier, params, server
+from tests.instances import make_instance, oracle_client_hint
+
+Q = 1 << 32
+
+
+# ----------------------------------------------------------------------------- LWE (Alg. 1)
+
+def test_delta_closed_form():
+    # Delta = round(q/p) (Sec. 2.1): q = 2^32, p = 256 gives exactly 2^24.
+    assert lwe.delta(Q, 256) == 1 << 24
+    assert lwe.delta(100, 8) == 13          # 12.5 rounds up
+    assert lwe.delta(97, 8) == 12           # 12.125 rounds down
+
+
+def test_lwe_round_trip():
+    # Alg. 1: decrypting a fresh ciphertext with small error returns the message.
+    g = np.random.default_rng(1)
+    n, p = 32, 256
+    sk = g.integers(0, Q, n)
+    for _ in range(50):
+        a = g.integers(0, Q, n)
+        mu = int(g.integers(0, p))
+        e = int(g.integers(-1000, 1000))
+        b = lwe.lwe_encrypt(sk, a, mu, e, Q, p)
+        assert lwe.lwe_decrypt(sk, a, b, Q, p) == mu
+        # the phase is exactly Delta*mu + e mod q
+        assert lwe.lwe_phase(sk, a, b, Q) == (lwe.delta(Q, p) * mu + e) % Q
+
+
+def test_extract_rounding():
+    # Alg. 5 Extract: f = round((mu mod q) p / q) mod p.
+    D24 = 1 << 24
+    for v in (0, 1, 77, 255):
+        for e in (-(D24 // 2) + 1, -5, 0, 5, D24 // 2 - 1):
+            mu = (v * D24 + e) % Q + 7 * Q         # the integer may exceed q; only mu mod q matters
+            assert lwe.pir_extract_value(mu) == v
+
+
+# ----------------------------------------------------------------------------- Paillier (Sec. 2.1)
+
+def test_paillier_hand_example():
+    # Textbook scheme by hand: P=3, Q=5 -> N=15, N^2=225, lambda=lcm(2,4)=4,
+    # g^lambda = 16^4 = 65536 = 291*225 + 61, L(61) = 4, mu = 4^-1 mod 15 = 4.
+    # Enc(7; 2) = 16^7 * 2^15 mod 225 = 106 * 143 mod 225 = 83.
+    sk = paillier.keygen(3, 5)
+    assert (sk.pk.N, sk.lam, sk.mu) == (15, 4, 4)
+    c = paillier.encrypt(sk.pk, 7, 2)
+    assert c == 83
+    # Dec(83): 83^4 mod 225 = 196, L(196) = 13, 13*4 mod 15 = 7.
+    assert paillier.decrypt(sk, 83) == 7
+
+
+@pytest.fixture(scope="module")
+def key512():
+    pr = wl.paillier_primes(99, 0, 512)
+    return paillier.keygen(pr.P, pr.Q)
+
+
+def test_paillier_homomorphisms(key512):
+    # Dec(Enc(m)) = m; Dec(c1 c2) = m1 + m2; Dec(c^k) = k m; Dec(c (N+1)^b) = m + b (mod N).
+    sk = key512
+    pk = sk.pk
+    g = wl.rng(99, "paillier_r", 5)
+    for _ in range(6):
+        m1, m2 = wl.uniform_below(g, pk.N), wl.uniform_below(g, pk.N)
+        r1, r2 = wl.uniform_unit(g, pk.N), wl.uniform_unit(g, pk.N)
+        k = wl.uniform_below(g, 1 << 32)
+        b = wl.uniform_below(g, 1 << 32)
+        c1, c2 = paillier.encrypt(pk, m1, r1), paillier.encrypt(pk, m2, r2)
+        assert paillier.decrypt(sk, c1) == m1
+        assert paillier.decrypt(sk, paillier.add(pk, c1, c2)) == (m1 + m2) % pk.N
+        assert paillier.decrypt(sk, paillier.scalar_mul(pk, k, c1)) == k * m1 % pk.N
+        assert paillier.decrypt(sk, paillier.add_plain(pk, c1, b)) == (m1 + b) % pk.N
+
+
+def test_generator_power_closed_form(key512):
+    # Binomial theorem: (N+1)^b = 1 + bN mod N^2.
+    pk = key512.pk
+    for b in (0, 1, 2, 12345, (1 << 32) - 1):
+        assert pow(pk.g, b, pk.N2) == (1 + b * pk.N) % pk.N2
+
+
+def test_paillier_randomness_does_not_matter(key512):
+    sk = key512
+    pk = sk.pk
+    g = wl.rng(99, "paillier_r", 6)
+    m = wl.uniform_below(g, pk.N)
+    cs = {paillier.encrypt(pk, m, wl.uniform_unit(g, pk.N)) for _ in range(3)}
+    assert len(cs) == 3 and all(paillier.decrypt(sk, c) == m for c in cs)
+
+
+# ----------------------------------------------------------------------------- answer b = D.qu
+
+def test_answer_closed_forms():
+    g = np.random.default_rng(3)
+    rows, cols = 37, 53
+    D = g.integers(0, 256, (rows, cols), dtype=np.uint8)
+    # unit vector e_i selects column i
+    for i in (0, 17, cols - 1):
+        u = np.zeros(cols, np.uint32)
+        u[i] = 1
+        assert np.array_equal(server.answer(D, u), D[:, i].astype(np.uint32))
+    # all-ones query gives the row sums
+    assert np.array_equal(server.answer(D, np.ones(cols, np.uint32)), D.sum(axis=1).astype(np.uint32))
+    # linearity mod 2^32
+    x = g.integers(0, Q, cols, dtype=np.uint32)
+    y = g.integers(0, Q, cols, dtype=np.uint32)
+    lhs = server.answer(D, (x.astype(np.uint64) + y) .astype(np.uint32))
+    rhs = (server.answer(D, x).astype(np.uint64) + server.answer(D, y)) % Q
+    assert np.array_equal(lhs, rhs.astype(np.uint32))
+    # D = 255, qu = 2^32 - 1 everywhere: b = -255 cols mod 2^32
+    b = server.answer(np.full((3, cols), 255, np.uint8), np.full(cols, Q - 1, np.uint32))
+    assert np.all(b == (-255 * cols) % Q)
+    # qu = 2^31 everywhere: b = (rowsum mod 2) 2^31
+    b = server.answer(D, np.full(cols, 1 << 31, np.uint32))
+    assert np.array_equal(b, ((D.sum(axis=1) % 2) << 31).astype(np.uint32))
+
+
+def test_answer_batch_is_columnwise():
+    g = np.random.default_rng(4)
+    D = g.integers(0, 256, (9, 11), dtype=np.uint8)
+    Qm = g.integers(0, Q, (5, 11), dtype=np.uint32)
+    B = server.answer_batch(D, Qm)
+    for c in range(5):
+        assert B[c].tolist() == brute.matvec(D.tolist(), Qm[c].tolist())
+
+
+# ----------------------------------------------------------------------------- H and E
+
+def test_global_hint_vs_brute_rectangular():
+    g = np.random.default_rng(5)
+    D = g.integers(0, 256, (7, 13), dtype=np.uint8)
+    A = g.integers(0, Q, (13, 5), dtype=np.uint32)
+    H = server.global_hint(D, A)
+    assert H.shape == (7, 5)
+    assert H.tolist() == brute.matmul(D.tolist(), A.tolist())
+    assert np.array_equal(server.global_hint(D, A, rows=[6, 0, 3]), H[[6, 0, 3]])
+
+
+def test_global_hint_identity():
+    # A = identity (cols = n) gives H = D.
+    g = np.random.default_rng(6)
+    D = g.integers(0, 256, (10, 10), dtype=np.uint8)
+    assert np.array_equal(server.global_hint(D, np.eye(10, dtype=np.uint32)), D.astype(np.uint32))
+
+
+def test_exponents():
+    H = np.array([[0, 1, 2, Q - 1, 1 << 31]], dtype=np.uint32)
+    E = server.exponents(H)
+    assert E.tolist() == [[0, Q - 1, Q - 2, 1, 1 << 31]]
+    assert np.all((E.astype(np.uint64) + H) % Q == 0)
+
+
+# ----------------------------------------------------------------------------- K and c
+
+@pytest.fixture(scope="module")
+def tiny():
+    # rows=cols=8, n=4, N of 96 bits: N > q + n q^2 = 2^32 + 2^66 holds.
+    return make_instance(cfg=900, rows=8, cols=8, n=4, n_bits=96, zero_row=5)
+
+
+def test_tiny_bound(tiny):
+    N = tiny.clients[0].N
+    assert N.bit_length() == 96
+    assert params.compression_ok(N, tiny.n)
+
+
+def test_hint_matches_brute_force(tiny):
+    cl = tiny.clients[0]
+    H = server.global_hint(tiny.D, tiny.A)
+    E = server.exponents(H)
+    K = server.client_hint(cl.ck, E, cl.N)
+    Hb = brute.matmul(tiny.D.tolist(), tiny.A.tolist())
+    Eb = [[brute.negate(x) for x in row] for row in Hb]
+    for j in range(tiny.rows):
+        assert K[j] == brute.hint_row(cl.ck, Eb[j], cl.N)
+    assert K[5] == 1                          # all-zero row: every exponent is 0
+
+
+def test_hint_plaintext_is_the_integer_sum(tiny):
+    # Proof of Theorem 1: the plaintext sum of E_jk s_k is below N, so Dec returns it exactly.
+    cl = tiny.clients[0]
+    E = server.exponents(server.global_hint(tiny.D, tiny.A))
+    K = server.client_hint(cl.ck, E, cl.N)
+    for j in range(tiny.rows):
+        assert paillier.decrypt(cl.sk, K[j]) == server.hint_plaintext_row(E[j], cl.s)
+
+
+def test_compress_closed_form_and_decrypt(tiny):
+    cl = tiny.clients[0]
+    E = server.exponents(server.global_hint(tiny.D, tiny.A))
+    K = server.client_hint(cl.ck, E, cl.N)
+    b = server.answer(tiny.D, cl.qu)
+    c = server.compress(K, b, cl.N)
+    N2 = cl.N * cl.N
+    for j in range(tiny.rows):
+        assert c[j] == K[j] * (1 + int(b[j]) * cl.N) % N2
+        assert c[j] == brute.combine(K[j], int(b[j]), cl.N)
+        assert paillier.decrypt(cl.sk, c[j]) == int(b[j]) + server.hint_plaintext_row(E[j], cl.s)
+
+
+def _round_trip(inst, cl):
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    K = server.client_hint(cl.ck, E, cl.N)
+    b = server.answer(inst.D, cl.qu)
+    c = server.compress(K, b, cl.N)
+    return [lwe.pir_extract_value(paillier.decrypt(cl.sk, x)) for x in c]
+
+
+def test_pir_round_trip_tiny(tiny):
+    # ZipPIR correctness (Sec. 4.2): the client recovers the selected column.
+    cl = tiny.clients[0]
+    assert _round_trip(tiny, cl) == tiny.D[:, cl.col].tolist()
+
+
+def test_pir_round_trip_small():
+    inst = make_instance(cfg=901, rows=24, cols=40, n=8, n_bits=160)
+    cl = inst.clients[0]
+    # the noise term D.e stays below Delta/2 = 2^23
+    assert np.max(np.abs(inst.D.astype(np.int64) @ cl.e)) < 1 << 23
+    assert _round_trip(inst, cl) == inst.D[:, cl.col].tolist()
+
+
+def test_compression_bound_is_needed():
+    # Theorem 1's bound: with N far below q + n q^2 the plaintext sum wraps mod N and the
+    # client's value mod q is wrong for most rows.
+    inst = make_instance(cfg=902, rows=16, cols=16, n=16, n_bits=64)
+    cl = inst.clients[0]
+    assert not params.compression_ok(cl.N, inst.n)
+    got = _round_trip(inst, cl)
+    assert sum(int(a != b) for a, b in zip(got, inst.D[:, cl.col].tolist())) >= 8
+
+
+def test_noise_condition():
+    # q/p > 2 p sigma sqrt(2 d0 ln(2/delta)): holds for every database side used here.
+    for cols in (256, 16384, 32768, 65536, 131072):
+        assert params.zippir_noise_ok(cols)
+    assert not params.zippir_noise_ok(1 << 24)
+
+
+def test_hint_pool_helper(tiny):
+    cl = tiny.clients[0]
+    E = server.exponents(server.global_hint(tiny.D, tiny.A))
+    d = oracle_client_hint(cl.ck, E, cl.N, rows=[3, 1])
+    assert d == {3: server.client_hint_row(cl.ck, E[3], cl.N), 1: server.client_hint_row(cl.ck, E[1], cl.N)}
+
+
+# ----------------------------------------------------------------------------- mutations
+
+def test_mutation_wrong_exponent_sign_is_caught(tiny, monkeypatch):
+    # Planted mistake: E = H instead of -H.  The round trip (and Dec(K) identity) must fail.
+    cl = tiny.clients[0]
+    monkeypatch.setattr(server, "exponents", lambda H: H.copy())
+    assert _round_trip(tiny, cl) != tiny.D[:, cl.col].tolist()
+
+
+def test_mutation_transposed_database_is_caught(monkeypatch):
+    g = np.random.default_rng(8)
+    D = g.integers(0, 256, (6, 6), dtype=np.uint8)
+    orig = server.answer
+    monkeypatch.setattr(server, "answer", lambda D, qu, chunk_rows=1024: orig(np.ascontiguousarray(D.T), qu))
+    u = np.zeros(6, np.uint32)
+    u[2] = 1
+    assert not np.array_equal(server.answer(D, u), D[:, 2].astype(np.uint32))
+
+
+def test_mutation_dropped_plaintext_term_is_caught(tiny, monkeypatch):
+    # Planted mistake: the combine forgets the (N+1)^b factor.
+    cl = tiny.clients[0]
+    monkeypatch.setattr(server, "compress", lambda K, b, N: [int(k) for k in K])
+    assert _round_trip(tiny, cl) != tiny.D[:, cl.col].tolist()
+
+
+def test_mutation_wrong_delta_is_caught(monkeypatch):
+    monkeypatch.setattr(lwe, "delta", lambda q, p: q // p + 1)
+    # the phase identity of Alg. 1 fails with the wrong scale
+    sk = [3, 5]
+    b = lwe.lwe_encrypt(sk, [7, 11], 200, 0, Q, 256)
+    assert lwe.lwe_phase(sk, [7, 11], b, Q) != (200 << 24) % Q
+
+
+# ----------------------------------------------------------------------------- workload draws
+
+def test_workload_reproducible_and_primes():
+    a = wl.database(7, 5, 9)
+    b = wl.database(7, 5, 9)
+    assert np.array_equal(a, b) and a.dtype == np.uint8
+    pr = wl.paillier_primes(7, 0, 256)
+    for p in (pr.P, pr.Q):
+        # Fermat test with fixed bases (independent of the generator's Miller-Rabin)
+        assert all(pow(base, p - 1, p) == 1 for base in (2, 3, 5, 7, 11, 13))
+    assert (pr.P * pr.Q).bit_length() == 256
+    idx, new = wl.update_rows(7, 32768, 4)
+    assert len(idx) == 328 and len(set(idx.tolist())) == 328 and new.shape == (328, 4)
+    cts = wl.uniform_ciphertexts(7, 0, 4, pr.P * pr.Q)
+    N2 = (pr.P * pr.Q) ** 2
+    assert all(0 < c < N2 and math.gcd(c, pr.P * pr.Q) == 1 for c in cts)
