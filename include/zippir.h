@@ -1,0 +1,179 @@
+/*
+ * zippir.h -- C ABI of the ZipPIR server hot path for AMD Instinct MI355X (gfx950).
+ *
+ * ZipPIR (Akhavan Mahdavi, Diaa, Kerschbaum) is SimplePIR-style LWE PIR whose per-row LWE
+ * answer is compressed into a Paillier ciphertext.  The server side computes
+ *
+ *   global hint      H = D.A mod 2^32                       (Alg. 5 preamble; Sec. 4.3 "Reusability")
+ *   exponents        E = (-H) mod 2^32                      (Alg. 2 multiplies by q - a; Alg. 4)
+ *   client hint      K_j = prod_k ck_k^{E_jk} mod N^2       (Alg. 5 Hint = PaillierMatMul(H, ck))
+ *   answer           b = D.qu mod 2^32                      (Alg. 5 Response, first line)
+ *   compressed row   c_j = K_j * (1 + b_j N) mod N^2        (Sec. 4.3 "Smaller responses w/
+ *                                                             Paillier addition": K (+) Enc(b; 1))
+ *
+ * Orientation: D is rows x cols uint8 (plaintext modulus p = 256), row-major.  A is
+ * cols x n uint32, row-major.  A query has cols entries, an answer has rows entries.  The
+ * paper writes the same protocol on the transpose of D (Alg. 5); a client here retrieves a
+ * column of D.
+ *
+ * Big integers are little-endian arrays of uint32 limbs.  A client with an N_bits-bit
+ * Paillier modulus N uses L = 2*ceil(N_bits/32) limbs per ciphertext (values in [0, N^2)).
+ *
+ * Conventions for every call:
+ *   - Buffers named in a call are borrowed for that call only.  Data the server keeps
+ *     (D, A, H, each client's ck and K) is copied into, or computed in, device memory the
+ *     server owns and frees in pir_destroy / pir_remove_client.
+ *   - ptr_flags says where the call's array arguments live: PIR_PTR_HOST (pageable or pinned
+ *     host memory) or PIR_PTR_DEVICE (device memory on the server's device, e.g. a torch
+ *     tensor's data pointer).  Row-index lists are always host arrays.
+ *   - All device work is enqueued on the HIP stream given to pir_setup.  A call whose
+ *     outputs are host buffers synchronizes that stream before returning; a call with
+ *     device outputs returns once its work is enqueued (use pir_sync or the stream).
+ *   - One pir_server must not be used from two threads at once.
+ *   - No C++ exception crosses this interface.  On error the call returns a negative
+ *     status, leaves the server usable, and pir_last_error() describes the failure.
+ */
+#ifndef ZIPPIR_H
+#define ZIPPIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pir_server pir_server;
+typedef int32_t pir_status;
+
+#define PIR_OK        0
+#define PIR_EINVAL   (-1)  /* bad argument: shape, size, parameter or unknown id            */
+#define PIR_ENOMEM   (-2)  /* device or host allocation failed                               */
+#define PIR_EDEVICE  (-3)  /* a HIP call failed; pir_last_error() has the HIP message        */
+#define PIR_ESTALE   (-4)  /* a client hint is missing or out of date (call pir_hint)        */
+#define PIR_EBUSY    (-5)  /* resource temporarily exhausted (serving admission)             */
+
+#define PIR_PTR_HOST   0u
+#define PIR_PTR_DEVICE 1u
+
+/* Answer paths for pir_answer_path. */
+#define PIR_PATH_AUTO   0  /* batch 1 -> PIR_PATH_MATVEC, batch > 1 -> PIR_PATH_MFMA               */
+#define PIR_PATH_MATVEC 1  /* HBM-streaming u8 x u32 matvec, once per query                        */
+#define PIR_PATH_MFMA   2  /* one fused int8-MFMA contraction over four byte planes of the batch   */
+
+/*
+ * Server side of Setup (Alg. 5): register the database and the public LWE matrix.
+ *   out      receives the new server handle (NULL on failure).
+ *   device   HIP device ordinal; hip_stream is a hipStream_t on that device (NULL = default).
+ *   D        rows x cols uint8, row-major.   A  cols x n uint32, row-major.
+ * rows, cols, n >= 1.  The global hint H is computed lazily by the first pir_hint.
+ * Errors: PIR_EINVAL (zero size, NULL pointer), PIR_ENOMEM, PIR_EDEVICE.
+ */
+pir_status pir_setup(pir_server **out, int device, void *hip_stream,
+                     const uint8_t *D, uint32_t rows, uint32_t cols,
+                     const uint32_t *A, uint32_t n, uint32_t ptr_flags);
+
+/* Frees every device buffer the server owns.  NULL is ignored. */
+void pir_destroy(pir_server *srv);
+
+/*
+ * Register a client's public material (Alg. 5 Setup output sent to the server).
+ *   N        ceil(N_bits/32) limbs of the Paillier modulus; odd, top bit at N_bits-1.
+ *   ck       n ciphertexts of L = 2*ceil(N_bits/32) limbs each (ck[k] = Enc(s_k)), each < N^2.
+ *   client_id receives the new id.
+ * N_bits is in [64, 4096].  Theorem 1 (Sec. 3.1) requires N > q + n q^2 with q = 2^32 for the
+ * compressed answer to decrypt correctly; smaller N is rejected with PIR_EINVAL.
+ */
+pir_status pir_add_client(pir_server *srv, const uint32_t *N, uint32_t N_bits,
+                          const uint32_t *ck, uint32_t ptr_flags, uint32_t *client_id);
+
+/* Drop a client and free its hint.  PIR_EINVAL for an unknown id. */
+pir_status pir_remove_client(pir_server *srv, uint32_t client_id);
+
+/*
+ * Hint (Alg. 5): bring H up to date for every stale row, then compute
+ * K_j = prod_k ck_k^{(-H_jk) mod 2^32} mod N^2 for the listed rows of this client
+ * (rows == NULL or nrows == 0: all rows).  The result stays in device memory.  The
+ * exponentiation uses a fixed-base table of ck powers (Alg. 4 with 8-bit windows), built
+ * for the call and freed after it.  Row indices must be < rows (PIR_EINVAL otherwise).
+ * Synchronizes the stream.
+ */
+pir_status pir_hint(pir_server *srv, uint32_t client_id, const uint32_t *rows, uint32_t nrows);
+
+/*
+ * Replace rows of D (the paper's silent database update, Sec. 6).  new_rows is nrows x cols
+ * uint8.  Marks those rows of H and of every client's K stale; pir_compress then returns
+ * PIR_ESTALE for a client until pir_hint has refreshed them.  Rows must be distinct and < rows.
+ */
+pir_status pir_update_rows(pir_server *srv, const uint32_t *rows, uint32_t nrows,
+                           const uint8_t *new_rows, uint32_t ptr_flags);
+
+/*
+ * Response, first line (Alg. 5): B[c] = D.Q[c] mod 2^32 for c < batch.
+ *   Q  batch x cols uint32 (each query contiguous).   B  batch x rows uint32 (each answer contiguous).
+ * batch in [1, 1024].  PIR_PATH_AUTO picks the matvec for one query and the int8-MFMA
+ * byte-plane contraction otherwise; both give identical bits.
+ */
+pir_status pir_answer(pir_server *srv, const uint32_t *Q, uint32_t batch, uint32_t *B,
+                      uint32_t ptr_flags);
+pir_status pir_answer_path(pir_server *srv, const uint32_t *Q, uint32_t batch, uint32_t *B,
+                           uint32_t ptr_flags, int32_t path);
+
+/*
+ * Combined response (Sec. 4.3): C[c][j] = K_{c}[j] * (1 + B[c][j] * N_c) mod N_c^2, canonical in
+ * [0, N_c^2), for c < batch and j < rows.  client_ids is a host array of batch ids; every
+ * client in one call must use the same limb count L.  B is batch x rows uint32 (as written by
+ * pir_answer); C is batch x rows x L uint32.  PIR_ESTALE if any row of a client's hint is
+ * missing or stale.
+ */
+pir_status pir_compress(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
+                        const uint32_t *B, uint32_t *C, uint32_t ptr_flags);
+
+/* Copy rows [row0, row0+nrows) of H (nrows x n uint32).  PIR_ESTALE if any is stale. */
+pir_status pir_get_global_hint(pir_server *srv, uint32_t row0, uint32_t nrows, uint32_t *H,
+                               uint32_t ptr_flags);
+
+/* Copy rows [row0, row0+nrows) of a client's hint K (nrows x L uint32) -- what a client
+ * downloads in the client-storage variant (Sec. 4.3).  PIR_ESTALE if any is stale. */
+pir_status pir_get_client_hint(pir_server *srv, uint32_t client_id, uint32_t row0,
+                               uint32_t nrows, uint32_t *K, uint32_t ptr_flags);
+
+/* Limb count L of a client's ciphertexts (0 for an unknown id). */
+uint32_t pir_client_limbs(pir_server *srv, uint32_t client_id);
+
+/* Number of stale rows in H (client_id == UINT32_MAX) or in a client's hint. */
+int64_t pir_stale_rows(pir_server *srv, uint32_t client_id);
+
+/* Shapes of a server: rows, cols, n, and device bytes it currently owns. */
+pir_status pir_shape(pir_server *srv, uint32_t *rows, uint32_t *cols, uint32_t *n,
+                     uint64_t *device_bytes);
+
+/*
+ * Per-kernel timing with HIP events recorded on the server's stream around each launch of
+ * the named kernels.  pir_profile(srv, 1) starts (and clears) the record, pir_profile(srv, 0)
+ * stops it.  pir_profile_read synchronizes the stream and returns the summed duration in
+ * milliseconds and the launch count of one kernel since profiling started.
+ */
+#define PIR_KERNEL_MATVEC   0  /* one-query answer (u8 x u32 dot4 stream)               */
+#define PIR_KERNEL_GEMM     1  /* byte-plane int8-MFMA contraction (batched answer, H)  */
+#define PIR_KERNEL_COMPRESS 2  /* per-row Paillier combine                              */
+#define PIR_KERNEL_HINT     3  /* per-row fixed-base multi-exponentiation               */
+#define PIR_KERNEL_TABLE    4  /* fixed-base table build                                */
+#define PIR_KERNEL_KAPPA    5  /* K mod N precompute for the combine                    */
+#define PIR_KERNEL_COUNT    6
+pir_status pir_profile(pir_server *srv, int32_t enable);
+pir_status pir_profile_read(pir_server *srv, int32_t kernel, double *total_ms, uint64_t *launches);
+
+/* Wait for all work the server enqueued. */
+pir_status pir_sync(pir_server *srv);
+
+/* Static description of a status code. */
+const char *pir_strerror(pir_status st);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *pir_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZIPPIR_H */

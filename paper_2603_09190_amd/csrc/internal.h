@@ -1,0 +1,84 @@
+// Internal declarations shared by the runtime and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace zp {
+
+// Native 16-byte vector (usable with the nontemporal load builtin).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Per-client constants, all device pointers into one allocation.
+//   N2  S limbs   N^2 (zero padded)          R1  S limbs   R mod N^2, R = 2^(32 S)
+//   RR  S limbs   R^2 mod N^2                NP  S limbs   N (zero padded, S-limb layout)
+//   Nn  SN limbs  N                          C1  SN limbs  R_N * 2^32 mod N, R_N = 2^(32 SN)
+//   C2  SN limbs  R_N^2 * 2^32 mod N
+struct ClientDev {
+  const uint32_t* N2;
+  const uint32_t* R1;
+  const uint32_t* RR;
+  const uint32_t* NP;
+  const uint32_t* Nn;
+  const uint32_t* C1;
+  const uint32_t* C2;
+  uint32_t m2prime;  // -(N^2)^{-1} mod 2^32
+  uint32_t nprime;   // -N^{-1} mod 2^32
+  int L;             // limbs of a ciphertext (2h)
+  int h;             // limbs of N
+  int P;             // limbs per lane for mod-N^2 numbers (S = 64 P >= L)
+  int PN;            // limbs per lane for mod-N numbers (SN = 64 PN >= h)
+};
+
+// Number of table entries per (base, window) for 8-bit fixed-base windows.
+constexpr int kWindowBits = 8;
+constexpr int kWindows = 32 / kWindowBits;
+constexpr int kDigits = (1 << kWindowBits) - 1;
+
+// ---- matvec.hip
+// planes: 4 consecutive byte arrays of `pitch` bytes, plane b holding byte b of every
+// query entry (zero beyond cols).  One query.
+void launch_pack_planes_u8(const uint32_t* q, int cols, int pitch, uint8_t* planes,
+                           hipStream_t s);
+void launch_matvec(const uint8_t* D, int rows, int pitch, const uint8_t* planes, uint32_t* b,
+                   hipStream_t s);
+
+// ---- gemm_i8.hip
+// Signed byte planes of `ncol` vectors: X element (c, i) is x[c*stride_c + i*stride_i].
+// Xs[(c*4 + b)*pitch + i] = (byte b of X(c,i)) ^ 0x80 for i < cols, 0 beyond.
+// colsum[c*4 + b] = sum_{i<cols} Xs[(c*4+b)*pitch + i].
+void launch_pack_planes_s8(const uint32_t* x, long long stride_c, long long stride_i, int ncol,
+                           int cols, int pitch, int8_t* Xs, int32_t* colsum, hipStream_t s);
+// rowsum[j] = sum_{i<cols} (D[j][i] - 128)
+void launch_rowsum(const uint8_t* D, int rows, int cols, int pitch, int32_t* rowsum,
+                   hipStream_t s);
+// out = D . X mod 2^32 for `rows` rows of D starting at D, all ncol columns.
+// out_rowmajor: out[j*ncol + c]; otherwise out[c*out_ld + j].
+void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, const int8_t* Xs,
+                        const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
+                        bool out_rowmajor, long long out_ld, hipStream_t s);
+
+// ---- rows.hip (row gather/scatter for updates and partial recomputation)
+void launch_gather_rows_u8(const uint8_t* src, int pitch, const uint32_t* rows, int nrows,
+                           uint8_t* dst, hipStream_t s);
+void launch_scatter_rows_u8(const uint8_t* src, int src_pitch, int cols, const uint32_t* rows,
+                            int nrows, uint8_t* dst, int dst_pitch, hipStream_t s);
+void launch_gather_rowsum(const int32_t* src, const uint32_t* rows, int nrows, int32_t* dst,
+                          hipStream_t s);
+void launch_scatter_rows_u32(const uint32_t* src, int width, const uint32_t* rows, int nrows,
+                             uint32_t* dst, hipStream_t s);
+
+// ---- hint.hip
+void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, uint32_t* table,
+                        hipStream_t s);
+// Rows processed: rowlist[i] for i < nrows (rowlist may be null: rows 0..nrows-1).
+void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
+                      int nrows, const uint32_t* table, uint32_t* K, hipStream_t s);
+void launch_kappa(const ClientDev& cd, const uint32_t* K, const uint32_t* rowlist, int nrows,
+                  uint32_t* kappa, hipStream_t s);
+
+// ---- compress.hip
+void launch_compress(const ClientDev& cd, const uint32_t* K, const uint32_t* kappa,
+                     const uint32_t* b, int rows, uint32_t* C, hipStream_t s);
+
+}  // namespace zp

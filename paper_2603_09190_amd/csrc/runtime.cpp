@@ -1,0 +1,785 @@
+// Host runtime behind zippir.h: server state, device residency, per-client constants and
+// the C entry points.  All device work is enqueued on the server's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "zippir.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pir_status fail(pir_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define ZP_HIP(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? PIR_ENOMEM : PIR_EDEVICE,                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+#define ZP_TRY(expr)                 \
+  do {                               \
+    pir_status st_ = (expr);         \
+    if (st_ != PIR_OK) return st_;   \
+  } while (0)
+
+// ----------------------------------------------------------------------------- host bignum
+// Little-endian uint32 limbs, used only for per-client constants at registration time.
+using Big = std::vector<uint32_t>;
+
+Big big_resize(Big a, size_t n) {
+  a.resize(n, 0u);
+  return a;
+}
+
+int big_cmp(const Big& a, const Big& b) {
+  const size_t n = std::max(a.size(), b.size());
+  for (size_t i = n; i-- > 0;) {
+    const uint32_t x = i < a.size() ? a[i] : 0u, y = i < b.size() ? b[i] : 0u;
+    if (x != y) return x < y ? -1 : 1;
+  }
+  return 0;
+}
+
+void big_sub_inplace(Big& a, const Big& b) {  // a -= b, requires a >= b
+  uint64_t br = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const uint64_t y = (i < b.size() ? b[i] : 0u) + br;
+    const uint64_t x = a[i];
+    a[i] = (uint32_t)(x - y);
+    br = x < y ? 1 : 0;
+  }
+}
+
+Big big_mul(const Big& a, const Big& b) {
+  Big r(a.size() + b.size(), 0u);
+  for (size_t i = 0; i < a.size(); ++i) {
+    uint64_t carry = 0;
+    for (size_t j = 0; j < b.size(); ++j) {
+      const uint64_t t = (uint64_t)a[i] * b[j] + r[i + j] + carry;
+      r[i + j] = (uint32_t)t;
+      carry = t >> 32;
+    }
+    size_t k = i + b.size();
+    while (carry) {
+      const uint64_t t = (uint64_t)r[k] + carry;
+      r[k] = (uint32_t)t;
+      carry = t >> 32;
+      ++k;
+    }
+  }
+  return r;
+}
+
+// 2^k mod m by repeated doubling (m odd, m > 1).
+Big big_pow2_mod(uint64_t k, const Big& m) {
+  Big x(m.size() + 1, 0u);
+  x[0] = 1;
+  if (big_cmp(x, m) >= 0) big_sub_inplace(x, m);
+  for (uint64_t t = 0; t < k; ++t) {
+    uint32_t carry = 0;
+    for (size_t i = 0; i < x.size(); ++i) {
+      const uint32_t nc = x[i] >> 31;
+      x[i] = (x[i] << 1) | carry;
+      carry = nc;
+    }
+    if (big_cmp(x, m) >= 0) big_sub_inplace(x, m);
+  }
+  x.resize(m.size());
+  return x;
+}
+
+uint32_t neg_inv32(uint32_t m0) {  // -m0^{-1} mod 2^32 for odd m0 (Newton iteration)
+  uint32_t inv = m0;               // correct to 3 bits
+  for (int i = 0; i < 5; ++i) inv *= 2u - m0 * inv;
+  return 0u - inv;
+}
+
+size_t bit_length(const Big& a) {
+  for (size_t i = a.size(); i-- > 0;)
+    if (a[i]) return 32 * i + (32 - __builtin_clz(a[i]));
+  return 0;
+}
+
+// ----------------------------------------------------------------------------- state
+
+struct DevAlloc {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ClientState {
+  uint32_t id = 0;
+  uint32_t n_bits = 0, h = 0, L = 0, P = 0, PN = 0, S = 0, SN = 0;
+  Big N;
+  uint32_t* ck = nullptr;      // n x L
+  uint32_t* consts = nullptr;  // N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each)
+  uint32_t* K = nullptr;       // rows x L
+  uint32_t* kappa = nullptr;   // rows x h
+  uint32_t m2prime = 0, nprime = 0;
+  std::vector<uint8_t> valid;  // per row: K and kappa up to date
+  int64_t stale = 0;
+
+  zp::ClientDev dev() const {
+    zp::ClientDev d;
+    d.N2 = consts;
+    d.R1 = consts + S;
+    d.RR = consts + 2 * S;
+    d.NP = consts + 3 * S;
+    d.Nn = consts + 4 * S;
+    d.C1 = consts + 4 * S + SN;
+    d.C2 = consts + 4 * S + 2 * SN;
+    d.m2prime = m2prime;
+    d.nprime = nprime;
+    d.L = (int)L;
+    d.h = (int)h;
+    d.P = (int)P;
+    d.PN = (int)PN;
+    return d;
+  }
+};
+
+struct pir_server {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint32_t rows = 0, cols = 0, n = 0, pitch = 0;
+  uint8_t* D = nullptr;         // rows x pitch, zero beyond cols
+  uint32_t* A = nullptr;        // cols x n
+  int8_t* Ap = nullptr;         // n x 4 x pitch signed planes of A's columns
+  int32_t* Acolsum = nullptr;   // n x 4
+  int32_t* rowsum = nullptr;    // rows: sum_i (D[j][i] - 128)
+  uint32_t* H = nullptr;        // rows x n
+  std::vector<uint8_t> H_valid;
+  int64_t H_stale = 0;
+  std::map<uint32_t, std::unique_ptr<ClientState>> clients;
+  uint32_t next_id = 1;
+  std::map<void*, size_t> allocs;
+  uint64_t bytes = 0;
+  // per-kernel event timing (pir_profile)
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[PIR_KERNEL_COUNT];
+  // growable scratch
+  DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c;
+
+  pir_status alloc(void** p, size_t bytes_) {
+    *p = nullptr;
+    if (bytes_ == 0) bytes_ = 256;
+    hipError_t e = hipMalloc(p, bytes_);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      (void)hipGetLastError();
+      return fail(PIR_ENOMEM, std::string("hipMalloc(") + std::to_string(bytes_) +
+                                  " bytes): " + hipGetErrorString(e));
+    }
+    allocs[*p] = bytes_;
+    bytes += bytes_;
+    return PIR_OK;
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = allocs.find(p);
+    if (it != allocs.end()) {
+      bytes -= it->second;
+      allocs.erase(it);
+    }
+    (void)hipFree(p);
+  }
+  pir_status scratch(DevAlloc& a, size_t need) {
+    if (a.bytes >= need) return PIR_OK;
+    if (a.p) {
+      (void)hipStreamSynchronize(stream);
+      release(a.p);
+      a.p = nullptr;
+      a.bytes = 0;
+    }
+    ZP_TRY(alloc(&a.p, need));
+    a.bytes = need;
+    return PIR_OK;
+  }
+};
+
+namespace {
+
+hipMemcpyKind kind_to_dev(uint32_t flags) {
+  return flags == PIR_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+hipMemcpyKind kind_from_dev(uint32_t flags) {
+  return flags == PIR_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+}
+
+pir_status check_flags(uint32_t flags) {
+  if (flags != PIR_PTR_HOST && flags != PIR_PTR_DEVICE)
+    return fail(PIR_EINVAL, "ptr_flags must be PIR_PTR_HOST or PIR_PTR_DEVICE");
+  return PIR_OK;
+}
+
+// Records an event pair around one launch when profiling is on.
+struct ProfScope {
+  pir_server* s;
+  int k;
+  hipEvent_t b = nullptr, e = nullptr;
+  ProfScope(pir_server* s_, int k_) : s(s_), k(k_) {
+    if (!s->prof) return;
+    if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&e) != hipSuccess) {
+      b = e = nullptr;
+      return;
+    }
+    (void)hipEventRecord(b, s->stream);
+  }
+  ~ProfScope() {
+    if (!b) return;
+    (void)hipEventRecord(e, s->stream);
+    s->prof_ev[k].emplace_back(b, e);
+  }
+};
+
+void prof_clear(pir_server* s) {
+  for (auto& v : s->prof_ev) {
+    for (auto& pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    v.clear();
+  }
+}
+
+pir_status use_device(pir_server* s) {
+  ZP_HIP(hipSetDevice(s->device));
+  return PIR_OK;
+}
+
+// Recompute H for the given rows (all rows if the list covers most of them).
+pir_status refresh_H(pir_server* s, const std::vector<uint32_t>& rows_in) {
+  if (rows_in.empty()) return PIR_OK;
+  hipStream_t st = s->stream;
+  if (rows_in.size() * 4 >= s->rows) {
+    ProfScope ps(s, PIR_KERNEL_GEMM);
+    zp::launch_gemm_planes(s->D, (int)s->rows, (int)s->cols, (int)s->pitch, s->Ap, s->Acolsum,
+                           (int)s->n, s->rowsum, s->H, true, 0, st);
+  } else {
+    const size_t m = rows_in.size();
+    ZP_TRY(s->scratch(s->s_rows, m * sizeof(uint32_t)));
+    ZP_TRY(s->scratch(s->s_gath, m * (size_t)s->pitch));
+    ZP_TRY(s->scratch(s->s_gsum, m * sizeof(int32_t)));
+    ZP_TRY(s->scratch(s->s_h, m * (size_t)s->n * sizeof(uint32_t)));
+    auto* drows = (uint32_t*)s->s_rows.p;
+    ZP_HIP(hipMemcpyAsync(drows, rows_in.data(), m * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    zp::launch_gather_rows_u8(s->D, (int)s->pitch, drows, (int)m, (uint8_t*)s->s_gath.p, st);
+    zp::launch_gather_rowsum(s->rowsum, drows, (int)m, (int32_t*)s->s_gsum.p, st);
+    zp::launch_gemm_planes((const uint8_t*)s->s_gath.p, (int)m, (int)s->cols, (int)s->pitch,
+                           s->Ap, s->Acolsum, (int)s->n, (const int32_t*)s->s_gsum.p,
+                           (uint32_t*)s->s_h.p, true, 0, st);
+    zp::launch_scatter_rows_u32((const uint32_t*)s->s_h.p, (int)s->n, drows, (int)m, s->H, st);
+    // the scratch is reused by later calls: finish before returning
+    ZP_HIP(hipStreamSynchronize(st));
+  }
+  ZP_HIP(hipGetLastError());
+  for (uint32_t r : rows_in)
+    if (!s->H_valid[r]) {
+      s->H_valid[r] = 1;
+      --s->H_stale;
+    }
+  return PIR_OK;
+}
+
+pir_status refresh_all_stale_H(pir_server* s) {
+  if (s->H_stale == 0) return PIR_OK;
+  std::vector<uint32_t> rows;
+  rows.reserve((size_t)s->H_stale);
+  for (uint32_t r = 0; r < s->rows; ++r)
+    if (!s->H_valid[r]) rows.push_back(r);
+  return refresh_H(s, rows);
+}
+
+ClientState* find_client(pir_server* s, uint32_t id) {
+  auto it = s->clients.find(id);
+  return it == s->clients.end() ? nullptr : it->second.get();
+}
+
+}  // namespace
+
+// ============================================================================= C ABI
+
+extern "C" {
+
+const char* pir_strerror(pir_status st) {
+  switch (st) {
+    case PIR_OK: return "ok";
+    case PIR_EINVAL: return "invalid argument";
+    case PIR_ENOMEM: return "out of memory";
+    case PIR_EDEVICE: return "device error";
+    case PIR_ESTALE: return "hint missing or stale";
+    case PIR_EBUSY: return "resource busy";
+    default: return "unknown status";
+  }
+}
+
+const char* pir_last_error(void) { return g_last_error.c_str(); }
+
+pir_status pir_setup(pir_server** out, int device, void* hip_stream, const uint8_t* D,
+                     uint32_t rows, uint32_t cols, const uint32_t* A, uint32_t n,
+                     uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!out) return fail(PIR_EINVAL, "out is NULL");
+  *out = nullptr;
+  ZP_TRY(check_flags(ptr_flags));
+  if (!D || !A || rows == 0 || cols == 0 || n == 0)
+    return fail(PIR_EINVAL, "D and A must be non-NULL and rows, cols, n >= 1");
+  if (cols > (1u << 30) || rows > (1u << 30) || n > (1u << 16))
+    return fail(PIR_EINVAL, "shape too large");
+  int ndev = 0;
+  ZP_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(PIR_EINVAL, "no such device");
+  auto s = std::make_unique<pir_server>();
+  s->device = device;
+  s->stream = (hipStream_t)hip_stream;
+  s->rows = rows;
+  s->cols = cols;
+  s->n = n;
+  s->pitch = (cols + 255u) & ~255u;
+  ZP_TRY(use_device(s.get()));
+  hipStream_t st = s->stream;
+  const size_t dbytes = (size_t)rows * s->pitch;
+  ZP_TRY(s->alloc((void**)&s->D, dbytes));
+  if (s->pitch != cols) ZP_HIP(hipMemsetAsync(s->D, 0, dbytes, st));
+  ZP_HIP(hipMemcpy2DAsync(s->D, s->pitch, D, cols, cols, rows, kind_to_dev(ptr_flags), st));
+  ZP_TRY(s->alloc((void**)&s->A, (size_t)cols * n * sizeof(uint32_t)));
+  ZP_HIP(hipMemcpyAsync(s->A, A, (size_t)cols * n * sizeof(uint32_t), kind_to_dev(ptr_flags), st));
+  ZP_TRY(s->alloc((void**)&s->rowsum, (size_t)rows * sizeof(int32_t)));
+  zp::launch_rowsum(s->D, (int)rows, (int)cols, (int)s->pitch, s->rowsum, st);
+  ZP_TRY(s->alloc((void**)&s->Ap, (size_t)n * 4 * s->pitch));
+  ZP_TRY(s->alloc((void**)&s->Acolsum, (size_t)n * 4 * sizeof(int32_t)));
+  // column k of A is the vector (A[i][k])_i: stride 1 between vectors, n between entries
+  zp::launch_pack_planes_s8(s->A, 1, n, (int)n, (int)cols, (int)s->pitch, s->Ap, s->Acolsum, st);
+  ZP_TRY(s->alloc((void**)&s->H, (size_t)rows * n * sizeof(uint32_t)));
+  s->H_valid.assign(rows, 0);
+  s->H_stale = rows;
+  ZP_HIP(hipGetLastError());
+  ZP_HIP(hipStreamSynchronize(st));
+  *out = s.release();
+  return PIR_OK;
+}
+
+void pir_destroy(pir_server* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  prof_clear(s);
+  for (auto& kv : s->allocs) (void)hipFree(kv.first);
+  s->allocs.clear();
+  delete s;
+}
+
+pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, const uint32_t* ck,
+                          uint32_t ptr_flags, uint32_t* client_id) {
+  g_last_error.clear();
+  if (!s || !N || !ck || !client_id) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  if (N_bits < 64 || N_bits > 4096) return fail(PIR_EINVAL, "N_bits must be in [64, 4096]");
+  ZP_TRY(use_device(s));
+  auto c = std::make_unique<ClientState>();
+  c->n_bits = N_bits;
+  c->h = (N_bits + 31) / 32;
+  c->L = 2 * c->h;
+  c->P = (c->L + 63) / 64;
+  c->PN = (c->h + 63) / 64;
+  c->S = 64 * c->P;
+  c->SN = 64 * c->PN;
+  c->N.assign(c->h, 0u);
+  if (ptr_flags == PIR_PTR_DEVICE)
+    ZP_HIP(hipMemcpy(c->N.data(), N, c->h * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(c->N.data(), N, c->h * sizeof(uint32_t));
+  if (bit_length(c->N) != N_bits) return fail(PIR_EINVAL, "N does not have exactly N_bits bits");
+  if ((c->N[0] & 1u) == 0) return fail(PIR_EINVAL, "N must be odd");
+  // Theorem 1: N > q + n q^2 with q = 2^32, i.e. N > 2^32 + n * 2^64
+  {
+    Big bound(4, 0u);
+    bound[1] = 1;
+    bound[2] = s->n;
+    if (big_cmp(c->N, bound) <= 0)
+      return fail(PIR_EINVAL, "N too small: compression needs N > q + n q^2 (q = 2^32)");
+  }
+  const Big N2 = big_resize(big_mul(c->N, c->N), c->S);
+  const Big Nn = big_resize(c->N, c->SN);
+  const Big R1 = big_pow2_mod(32ull * c->S, big_resize(N2, c->L));
+  const Big RR = big_pow2_mod(64ull * c->S, big_resize(N2, c->L));
+  const Big C1 = big_pow2_mod(32ull * c->SN + 32, c->N);
+  const Big C2 = big_pow2_mod(64ull * c->SN + 32, c->N);
+  c->m2prime = neg_inv32(N2[0]);
+  c->nprime = neg_inv32(c->N[0]);
+  std::vector<uint32_t> host(4 * (size_t)c->S + 3 * (size_t)c->SN, 0u);
+  auto put = [&](size_t off, const Big& v, size_t width) {
+    for (size_t i = 0; i < std::min(width, v.size()); ++i) host[off + i] = v[i];
+  };
+  put(0, N2, c->S);
+  put(c->S, R1, c->S);
+  put(2 * (size_t)c->S, RR, c->S);
+  put(3 * (size_t)c->S, c->N, c->S);
+  put(4 * (size_t)c->S, Nn, c->SN);
+  put(4 * (size_t)c->S + c->SN, C1, c->SN);
+  put(4 * (size_t)c->S + 2 * c->SN, C2, c->SN);
+
+  hipStream_t st = s->stream;
+  ZP_TRY(s->alloc((void**)&c->consts, host.size() * sizeof(uint32_t)));
+  ZP_HIP(hipMemcpyAsync(c->consts, host.data(), host.size() * sizeof(uint32_t),
+                        hipMemcpyHostToDevice, st));
+  const size_t ckbytes = (size_t)s->n * c->L * sizeof(uint32_t);
+  ZP_TRY(s->alloc((void**)&c->ck, ckbytes));
+  ZP_HIP(hipMemcpyAsync(c->ck, ck, ckbytes, kind_to_dev(ptr_flags), st));
+  // every ciphertext must be a residue mod N^2
+  {
+    std::vector<uint32_t> hck((size_t)s->n * c->L);
+    ZP_HIP(hipMemcpyAsync(hck.data(), c->ck, ckbytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+    const Big N2L = big_resize(N2, c->L);
+    for (uint32_t k = 0; k < s->n; ++k) {
+      Big v(hck.begin() + (size_t)k * c->L, hck.begin() + (size_t)(k + 1) * c->L);
+      if (big_cmp(v, N2L) >= 0) {
+        s->release(c->ck);
+        s->release(c->consts);
+        return fail(PIR_EINVAL, "ck[" + std::to_string(k) + "] is not below N^2");
+      }
+    }
+  }
+  ZP_TRY(s->alloc((void**)&c->K, (size_t)s->rows * c->L * sizeof(uint32_t)));
+  ZP_TRY(s->alloc((void**)&c->kappa, (size_t)s->rows * c->h * sizeof(uint32_t)));
+  c->valid.assign(s->rows, 0);
+  c->stale = s->rows;
+  c->id = s->next_id++;
+  *client_id = c->id;
+  s->clients[c->id] = std::move(c);
+  return PIR_OK;
+}
+
+pir_status pir_remove_client(pir_server* s, uint32_t id) {
+  g_last_error.clear();
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  ClientState* c = find_client(s, id);
+  if (!c) return fail(PIR_EINVAL, "unknown client id");
+  ZP_TRY(use_device(s));
+  ZP_HIP(hipStreamSynchronize(s->stream));
+  s->release(c->ck);
+  s->release(c->consts);
+  s->release(c->K);
+  s->release(c->kappa);
+  s->clients.erase(id);
+  return PIR_OK;
+}
+
+pir_status pir_hint(pir_server* s, uint32_t id, const uint32_t* rows, uint32_t nrows) {
+  g_last_error.clear();
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  ClientState* c = find_client(s, id);
+  if (!c) return fail(PIR_EINVAL, "unknown client id");
+  ZP_TRY(use_device(s));
+  std::vector<uint32_t> sel;
+  const bool all = (rows == nullptr || nrows == 0);
+  if (!all) {
+    sel.assign(rows, rows + nrows);
+    for (uint32_t r : sel)
+      if (r >= s->rows) return fail(PIR_EINVAL, "row index out of range");
+    std::sort(sel.begin(), sel.end());
+    sel.erase(std::unique(sel.begin(), sel.end()), sel.end());
+  }
+  ZP_TRY(refresh_all_stale_H(s));
+  hipStream_t st = s->stream;
+  const zp::ClientDev cd = c->dev();
+  uint32_t* table = nullptr;
+  const size_t tbytes = (size_t)s->n * zp::kWindows * zp::kDigits * c->S * sizeof(uint32_t);
+  ZP_TRY(s->alloc((void**)&table, tbytes));
+  {
+    ProfScope ps(s, PIR_KERNEL_TABLE);
+    zp::launch_build_table(cd, c->ck, (int)s->n, table, st);
+  }
+  uint32_t* drows = nullptr;
+  const int m = all ? (int)s->rows : (int)sel.size();
+  if (!all) {
+    pir_status a = s->alloc((void**)&drows, sel.size() * sizeof(uint32_t));
+    if (a != PIR_OK) {
+      s->release(table);
+      return a;
+    }
+    (void)hipMemcpyAsync(drows, sel.data(), sel.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+  }
+  {
+    ProfScope ps(s, PIR_KERNEL_HINT);
+    zp::launch_hint_rows(cd, s->H, (int)s->n, drows, m, table, c->K, st);
+  }
+  {
+    ProfScope ps(s, PIR_KERNEL_KAPPA);
+    zp::launch_kappa(cd, c->K, drows, m, c->kappa, st);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  s->release(table);
+  if (drows) s->release(drows);
+  if (e != hipSuccess) return fail(PIR_EDEVICE, std::string("hint kernels: ") + hipGetErrorString(e));
+  if (all) {
+    std::fill(c->valid.begin(), c->valid.end(), 1);
+    c->stale = 0;
+  } else {
+    for (uint32_t r : sel)
+      if (!c->valid[r]) {
+        c->valid[r] = 1;
+        --c->stale;
+      }
+  }
+  return PIR_OK;
+}
+
+pir_status pir_update_rows(pir_server* s, const uint32_t* rows, uint32_t nrows,
+                           const uint8_t* new_rows, uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  ZP_TRY(check_flags(ptr_flags));
+  if (nrows == 0) return PIR_OK;
+  if (!rows || !new_rows) return fail(PIR_EINVAL, "NULL argument");
+  std::vector<uint32_t> sel(rows, rows + nrows);
+  {
+    std::vector<uint32_t> sorted = sel;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(PIR_EINVAL, "row indices must be distinct");
+    if (sorted.back() >= s->rows) return fail(PIR_EINVAL, "row index out of range");
+  }
+  ZP_TRY(use_device(s));
+  hipStream_t st = s->stream;
+  ZP_TRY(s->scratch(s->s_rows, sel.size() * sizeof(uint32_t)));
+  ZP_TRY(s->scratch(s->s_gath, (size_t)nrows * s->cols));
+  auto* drows = (uint32_t*)s->s_rows.p;
+  ZP_HIP(hipMemcpyAsync(drows, sel.data(), sel.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  ZP_HIP(hipMemcpyAsync(s->s_gath.p, new_rows, (size_t)nrows * s->cols, kind_to_dev(ptr_flags), st));
+  zp::launch_scatter_rows_u8((const uint8_t*)s->s_gath.p, (int)s->cols, (int)s->cols, drows,
+                             (int)nrows, s->D, (int)s->pitch, st);
+  // row sums: recompute the changed rows through a gathered copy
+  ZP_TRY(s->scratch(s->s_c, (size_t)nrows * s->pitch));
+  ZP_TRY(s->scratch(s->s_gsum, (size_t)nrows * sizeof(int32_t)));
+  zp::launch_gather_rows_u8(s->D, (int)s->pitch, drows, (int)nrows, (uint8_t*)s->s_c.p, st);
+  zp::launch_rowsum((const uint8_t*)s->s_c.p, (int)nrows, (int)s->cols, (int)s->pitch,
+                    (int32_t*)s->s_gsum.p, st);
+  // scatter the new sums (int32 rows of width 1)
+  zp::launch_scatter_rows_u32((const uint32_t*)s->s_gsum.p, 1, drows, (int)nrows,
+                              (uint32_t*)s->rowsum, st);
+  ZP_HIP(hipGetLastError());
+  ZP_HIP(hipStreamSynchronize(st));
+  for (uint32_t r : sel) {
+    if (s->H_valid[r]) {
+      s->H_valid[r] = 0;
+      ++s->H_stale;
+    }
+    for (auto& kv : s->clients) {
+      ClientState* c = kv.second.get();
+      if (c->valid[r]) {
+        c->valid[r] = 0;
+        ++c->stale;
+      }
+    }
+  }
+  return PIR_OK;
+}
+
+static pir_status answer_impl(pir_server* s, const uint32_t* Q, uint32_t batch, uint32_t* B,
+                              uint32_t ptr_flags, int32_t path) {
+  hipStream_t st = s->stream;
+  const uint32_t* dQ = Q;
+  uint32_t* dB = B;
+  const size_t qbytes = (size_t)batch * s->cols * sizeof(uint32_t);
+  const size_t bbytes = (size_t)batch * s->rows * sizeof(uint32_t);
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_q, qbytes));
+    ZP_TRY(s->scratch(s->s_b, bbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_q.p, Q, qbytes, hipMemcpyHostToDevice, st));
+    dQ = (const uint32_t*)s->s_q.p;
+    dB = (uint32_t*)s->s_b.p;
+  }
+  if (path == PIR_PATH_AUTO) path = batch == 1 ? PIR_PATH_MATVEC : PIR_PATH_MFMA;
+  if (path == PIR_PATH_MATVEC) {
+    ZP_TRY(s->scratch(s->s_planes, 4 * (size_t)s->pitch));
+    for (uint32_t c = 0; c < batch; ++c) {
+      zp::launch_pack_planes_u8(dQ + (size_t)c * s->cols, (int)s->cols, (int)s->pitch,
+                                (uint8_t*)s->s_planes.p, st);
+      ProfScope ps(s, PIR_KERNEL_MATVEC);
+      zp::launch_matvec(s->D, (int)s->rows, (int)s->pitch, (const uint8_t*)s->s_planes.p,
+                        dB + (size_t)c * s->rows, st);
+    }
+  } else if (path == PIR_PATH_MFMA) {
+    ZP_TRY(s->scratch(s->s_planes, (size_t)batch * 4 * s->pitch));
+    ZP_TRY(s->scratch(s->s_colsum, (size_t)batch * 4 * sizeof(int32_t)));
+    zp::launch_pack_planes_s8(dQ, s->cols, 1, (int)batch, (int)s->cols, (int)s->pitch,
+                              (int8_t*)s->s_planes.p, (int32_t*)s->s_colsum.p, st);
+    ProfScope ps(s, PIR_KERNEL_GEMM);
+    zp::launch_gemm_planes(s->D, (int)s->rows, (int)s->cols, (int)s->pitch,
+                           (const int8_t*)s->s_planes.p, (const int32_t*)s->s_colsum.p,
+                           (int)batch, s->rowsum, dB, false, (long long)s->rows, st);
+  } else {
+    return fail(PIR_EINVAL, "unknown answer path");
+  }
+  ZP_HIP(hipGetLastError());
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(B, dB, bbytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_answer_path(pir_server* s, const uint32_t* Q, uint32_t batch, uint32_t* B,
+                           uint32_t ptr_flags, int32_t path) {
+  g_last_error.clear();
+  if (!s || !Q || !B) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  if (batch < 1 || batch > 1024) return fail(PIR_EINVAL, "batch must be in [1, 1024]");
+  ZP_TRY(use_device(s));
+  return answer_impl(s, Q, batch, B, ptr_flags, path);
+}
+
+pir_status pir_answer(pir_server* s, const uint32_t* Q, uint32_t batch, uint32_t* B,
+                      uint32_t ptr_flags) {
+  return pir_answer_path(s, Q, batch, B, ptr_flags, PIR_PATH_AUTO);
+}
+
+pir_status pir_compress(pir_server* s, const uint32_t* ids, uint32_t batch, const uint32_t* B,
+                        uint32_t* C, uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !ids || !B || !C) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  if (batch < 1 || batch > 1024) return fail(PIR_EINVAL, "batch must be in [1, 1024]");
+  std::vector<ClientState*> cs(batch);
+  for (uint32_t i = 0; i < batch; ++i) {
+    cs[i] = find_client(s, ids[i]);
+    if (!cs[i]) return fail(PIR_EINVAL, "unknown client id " + std::to_string(ids[i]));
+    if (cs[i]->L != cs[0]->L) return fail(PIR_EINVAL, "clients in one call must share L");
+    if (cs[i]->stale != 0)
+      return fail(PIR_ESTALE, "client " + std::to_string(ids[i]) + " has " +
+                                  std::to_string(cs[i]->stale) + " stale hint rows");
+  }
+  ZP_TRY(use_device(s));
+  hipStream_t st = s->stream;
+  const uint32_t L = cs[0]->L;
+  const uint32_t* dB = B;
+  uint32_t* dC = C;
+  const size_t bbytes = (size_t)batch * s->rows * sizeof(uint32_t);
+  const size_t cbytes = (size_t)batch * s->rows * L * sizeof(uint32_t);
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_b, bbytes));
+    ZP_TRY(s->scratch(s->s_c, cbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_b.p, B, bbytes, hipMemcpyHostToDevice, st));
+    dB = (const uint32_t*)s->s_b.p;
+    dC = (uint32_t*)s->s_c.p;
+  }
+  for (uint32_t i = 0; i < batch; ++i) {
+    ProfScope ps(s, PIR_KERNEL_COMPRESS);
+    zp::launch_compress(cs[i]->dev(), cs[i]->K, cs[i]->kappa, dB + (size_t)i * s->rows,
+                        (int)s->rows, dC + (size_t)i * s->rows * L, st);
+  }
+  ZP_HIP(hipGetLastError());
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(C, dC, cbytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_get_global_hint(pir_server* s, uint32_t row0, uint32_t nrows, uint32_t* H,
+                               uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !H) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  if ((uint64_t)row0 + nrows > s->rows) return fail(PIR_EINVAL, "row range out of bounds");
+  for (uint32_t r = row0; r < row0 + nrows; ++r)
+    if (!s->H_valid[r]) return fail(PIR_ESTALE, "H row " + std::to_string(r) + " is stale");
+  ZP_TRY(use_device(s));
+  ZP_HIP(hipMemcpyAsync(H, s->H + (size_t)row0 * s->n, (size_t)nrows * s->n * sizeof(uint32_t),
+                        kind_from_dev(ptr_flags), s->stream));
+  if (ptr_flags == PIR_PTR_HOST) ZP_HIP(hipStreamSynchronize(s->stream));
+  return PIR_OK;
+}
+
+pir_status pir_get_client_hint(pir_server* s, uint32_t id, uint32_t row0, uint32_t nrows,
+                               uint32_t* K, uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !K) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  ClientState* c = find_client(s, id);
+  if (!c) return fail(PIR_EINVAL, "unknown client id");
+  if ((uint64_t)row0 + nrows > s->rows) return fail(PIR_EINVAL, "row range out of bounds");
+  for (uint32_t r = row0; r < row0 + nrows; ++r)
+    if (!c->valid[r]) return fail(PIR_ESTALE, "K row " + std::to_string(r) + " is stale");
+  ZP_TRY(use_device(s));
+  ZP_HIP(hipMemcpyAsync(K, c->K + (size_t)row0 * c->L, (size_t)nrows * c->L * sizeof(uint32_t),
+                        kind_from_dev(ptr_flags), s->stream));
+  if (ptr_flags == PIR_PTR_HOST) ZP_HIP(hipStreamSynchronize(s->stream));
+  return PIR_OK;
+}
+
+uint32_t pir_client_limbs(pir_server* s, uint32_t id) {
+  if (!s) return 0;
+  ClientState* c = find_client(s, id);
+  return c ? c->L : 0;
+}
+
+int64_t pir_stale_rows(pir_server* s, uint32_t id) {
+  if (!s) return -1;
+  if (id == UINT32_MAX) return s->H_stale;
+  ClientState* c = find_client(s, id);
+  return c ? c->stale : -1;
+}
+
+pir_status pir_shape(pir_server* s, uint32_t* rows, uint32_t* cols, uint32_t* n,
+                     uint64_t* device_bytes) {
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  if (rows) *rows = s->rows;
+  if (cols) *cols = s->cols;
+  if (n) *n = s->n;
+  if (device_bytes) *device_bytes = s->bytes;
+  return PIR_OK;
+}
+
+pir_status pir_profile(pir_server* s, int32_t enable) {
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  ZP_TRY(use_device(s));
+  ZP_HIP(hipStreamSynchronize(s->stream));
+  if (enable) prof_clear(s);
+  s->prof = enable != 0;
+  return PIR_OK;
+}
+
+pir_status pir_profile_read(pir_server* s, int32_t kernel, double* total_ms, uint64_t* launches) {
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  if (kernel < 0 || kernel >= PIR_KERNEL_COUNT) return fail(PIR_EINVAL, "unknown kernel id");
+  ZP_TRY(use_device(s));
+  ZP_HIP(hipStreamSynchronize(s->stream));
+  double tot = 0;
+  for (auto& pr : s->prof_ev[kernel]) {
+    float ms = 0;
+    ZP_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = s->prof_ev[kernel].size();
+  return PIR_OK;
+}
+
+pir_status pir_sync(pir_server* s) {
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  ZP_TRY(use_device(s));
+  ZP_HIP(hipStreamSynchronize(s->stream));
+  return PIR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+// Wave-distributed multiprecision arithmetic for gfx950 (wave64).
+//
+// One wavefront holds one big integer of S = 64*P little-endian 32-bit limbs: lane l owns
+// limbs [P*l, P*l + P) in registers ("P-layout").  Moduli shorter than S limbs are zero
+// padded, so Montgomery arithmetic uses R = 2^(32*S).
+//
+// Montgomery multiplication is the coarsely integrated operand scanning (CIOS) method of
+// Koc, Acar and Kaliski (1996): for each limb a_i of the first operand, t += a_i*b, then
+// t += q*M with q = t_0 * (-M^{-1}) mod 2^32, then t /= 2^32.  Here the division by 2^32 is
+// a one-limb shift across lanes, and each lane keeps the carry out of its own P-limb chain
+// as a pending 64-bit word (positioned just above its top limb) instead of propagating it
+// through the whole wave every step; pending carries are resolved once at the end.
+//
+// Every routine must be called by all 64 lanes of a wave with wave-uniform arguments.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace zp {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Lane l receives lane l+1's value; lane 63 receives 0.
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t x) {
+  uint32_t y = (uint32_t)__shfl_down((int)x, 1, 64);
+  return lane_id() == 63 ? 0u : y;
+}
+
+// Lane l receives lane l-1's value; lane 0 receives 0.
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t x) {
+  uint32_t y = (uint32_t)__shfl_up((int)x, 1, 64);
+  return lane_id() == 0 ? 0u : y;
+}
+
+__device__ __forceinline__ uint64_t from_prev_lane64(uint64_t x) {
+  uint32_t lo = from_prev_lane((uint32_t)x);
+  uint32_t hi = from_prev_lane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t bcast(uint32_t x, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+template <int P>
+struct WNum {
+  uint32_t v[P];
+};
+
+template <int P>
+__device__ __forceinline__ void wn_zero(WNum<P>& x) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) x.v[j] = 0;
+}
+
+// Load/store S = 64*P limbs from a contiguous little-endian array (fully coalesced).
+template <int P>
+__device__ __forceinline__ void wn_load(WNum<P>& x, const uint32_t* __restrict__ src) {
+  const uint32_t* p = src + P * lane_id();
+#pragma unroll
+  for (int j = 0; j < P; ++j) x.v[j] = p[j];
+}
+
+// Load the first `nl` limbs and zero the rest (nl <= S).
+template <int P>
+__device__ __forceinline__ void wn_load_n(WNum<P>& x, const uint32_t* __restrict__ src, int nl) {
+  const int base = P * lane_id();
+#pragma unroll
+  for (int j = 0; j < P; ++j) x.v[j] = (base + j < nl) ? src[base + j] : 0u;
+}
+
+template <int P>
+__device__ __forceinline__ void wn_store(uint32_t* __restrict__ dst, const WNum<P>& x) {
+  uint32_t* p = dst + P * lane_id();
+#pragma unroll
+  for (int j = 0; j < P; ++j) p[j] = x.v[j];
+}
+
+template <int P>
+__device__ __forceinline__ void wn_store_n(uint32_t* __restrict__ dst, const WNum<P>& x, int nl) {
+  const int base = P * lane_id();
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+    if (base + j < nl) dst[base + j] = x.v[j];
+}
+
+// Limb i of a distributed number, as a wave-uniform value.
+template <int P>
+__device__ __forceinline__ uint32_t wn_limb(const WNum<P>& x, int i) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+    if (i % P == j) r = bcast(x.v[j], i / P);
+  return r;
+}
+
+// Resolve pending per-lane carries: value = sum_l (chunk_l + c_l * 2^(32P)) * 2^(32Pl).
+// Returns the carry out of the top limb (the part at and above 2^(32S)), wave-uniform.
+template <int P>
+__device__ __forceinline__ uint64_t wn_resolve(WNum<P>& t, uint64_t c) {
+  uint64_t ovf = 0;
+  while (true) {
+    ovf += bcast((uint32_t)c, 63) | ((uint64_t)bcast((uint32_t)(c >> 32), 63) << 32);
+    uint64_t cin = from_prev_lane64(c);
+    uint64_t acc = cin;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      acc += t.v[j];
+      t.v[j] = (uint32_t)acc;
+      acc >>= 32;
+    }
+    c = acc;
+    if (!wave_any(c != 0)) break;
+  }
+  return ovf;
+}
+
+// If (x + ovf*2^(32S)) >= m then x -= m.  Requires the value to be < 2m.
+template <int P>
+__device__ __forceinline__ void wn_cond_sub(WNum<P>& x, uint64_t ovf, const WNum<P>& m) {
+  WNum<P> d;
+  uint32_t br = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    uint64_t s = (uint64_t)x.v[j] - m.v[j] - br;
+    d.v[j] = (uint32_t)s;
+    br = (uint32_t)(s >> 63);
+  }
+  // ripple borrows across lanes; borrows leaving lane 63 are counted in final_borrow
+  uint32_t final_borrow = 0;
+  while (true) {
+    final_borrow += bcast(br, 63);
+    uint32_t b = from_prev_lane(br);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      uint64_t u = (uint64_t)d.v[j] - b;
+      d.v[j] = (uint32_t)u;
+      b = (uint32_t)(u >> 63);
+    }
+    br = b;
+    if (!wave_any(br != 0)) break;
+  }
+  // value >= m  <=>  ovf*2^(32S) + x - m >= 0  <=>  not (ovf == 0 and a borrow left the top)
+  const bool ge = (ovf != 0) || (final_borrow == 0);
+  if (ge) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) x.v[j] = d.v[j];
+  }
+}
+
+// One CIOS step: t = (t + a_i*b + q*m) / 2^32 with q chosen so the division is exact.
+// c is the lane's pending carry word (see file comment).
+template <int P>
+__device__ __forceinline__ void mont_step(WNum<P>& t, uint64_t& c, uint32_t ai, const WNum<P>& b,
+                                          const WNum<P>& m, uint32_t mprime) {
+  uint32_t carry = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    uint64_t x = (uint64_t)ai * b.v[j] + t.v[j] + carry;
+    t.v[j] = (uint32_t)x;
+    carry = (uint32_t)(x >> 32);
+  }
+  c += carry;
+  const uint32_t q = bcast(t.v[0], 0) * mprime;
+  carry = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    uint64_t x = (uint64_t)q * m.v[j] + t.v[j] + carry;
+    t.v[j] = (uint32_t)x;
+    carry = (uint32_t)(x >> 32);
+  }
+  c += carry;
+  // lane 0's limb 0 is now zero: shift the whole number down one limb
+  const uint32_t up = from_next_lane(t.v[0]);
+#pragma unroll
+  for (int j = 0; j < P - 1; ++j) t.v[j] = t.v[j + 1];
+  const uint64_t top = (uint64_t)up + c;
+  t.v[P - 1] = (uint32_t)top;
+  c = top >> 32;
+}
+
+// out = a * b * R^{-1} mod m, canonical, for a < R and b < m (m odd, m < R).
+template <int P>
+__device__ __forceinline__ void mont_mul(WNum<P>& out, const WNum<P>& a, const WNum<P>& b,
+                                         const WNum<P>& m, uint32_t mprime) {
+  WNum<P> t;
+  wn_zero(t);
+  uint64_t c = 0;
+  for (int src = 0; src < 64; ++src) {
+#pragma unroll
+    for (int jj = 0; jj < P; ++jj) {
+      const uint32_t ai = bcast(a.v[jj], src);
+      mont_step(t, c, ai, b, m, mprime);
+    }
+  }
+  const uint64_t ovf = wn_resolve(t, c);
+  wn_cond_sub(t, ovf, m);
+  out = t;
+}
+
+// Montgomery multiplication by a number given only through its first `na` limbs
+// (the remaining limbs are zero): skips the zero limbs of a.
+template <int P>
+__device__ __forceinline__ void mont_mul_short(WNum<P>& out, const WNum<P>& a, int na,
+                                               const WNum<P>& b, const WNum<P>& m,
+                                               uint32_t mprime) {
+  WNum<P> t;
+  wn_zero(t);
+  uint64_t c = 0;
+  for (int i = 0; i < na; ++i) mont_step(t, c, wn_limb(a, i), b, m, mprime);
+  // the remaining S - na steps have a_i = 0: only the reduction part remains
+  for (int i = na; i < 64 * P; ++i) {
+    WNum<P> z;
+    wn_zero(z);
+    mont_step(t, c, 0u, z, m, mprime);
+  }
+  const uint64_t ovf = wn_resolve(t, c);
+  wn_cond_sub(t, ovf, m);
+  out = t;
+}
+
+}  // namespace zp

@@ -1,0 +1,54 @@
+"""The C-ABI library loads on the CPU and exports every function include/zippir.h declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "zippir.h")
+LIB = os.path.join(ROOT, "paper_2603_09190_amd", "libzippir.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pir_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libzippir.so is not built (python -m paper_2603_09190_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("pir_setup", "pir_hint", "pir_answer", "pir_compress", "pir_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_binding_covers_the_header():
+    from paper_2603_09190_amd import native
+    assert set(declared_functions()) <= set(native.EXPORTED)
+
+
+def test_strerror_without_gpu(lib):
+    lib.pir_strerror.restype = ctypes.c_char_p
+    assert lib.pir_strerror(0) == b"ok"
+    assert lib.pir_strerror(-4) == b"hint missing or stale"
+
+
+def test_setup_rejects_null_without_touching_the_gpu(lib):
+    lib.pir_setup.restype = ctypes.c_int32
+    lib.pir_last_error.restype = ctypes.c_char_p
+    h = ctypes.c_void_p()
+    st = lib.pir_setup(ctypes.byref(h), 0, None, None, 4, 4, None, 4, 0)
+    assert st == -1 and h.value is None
+    assert b"non-NULL" in lib.pir_last_error()

@@ -1,0 +1,260 @@
+"""GPU parity at small sizes: every server step through the C-ABI against the CPU oracle.
+
+Integer path: every comparison is bit-exact.  Sizes span several tiles and ragged tails
+(rows and cols that are not multiples of the kernels' tile sizes).
+"""
+from multiprocessing import Pool
+
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import lwe, paillier, server
+from tests.gpu_util import client_arrays, limbs_rows_to_ints, log, pool_size
+from tests.instances import make_instance, oracle_client_hint
+
+pytestmark = pytest.mark.gpu
+
+Q32 = 1 << 32
+
+
+@pytest.fixture(scope="module")
+def native():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_09190_amd import native as nat
+    return nat
+
+
+def _rand(seed, shape, hi, dtype):
+    return np.random.default_rng(seed).integers(0, hi, size=shape, dtype=dtype)
+
+
+# ----------------------------------------------------------------------------- answer
+
+@pytest.mark.parametrize("rows,cols", [(200, 1000), (33, 256), (1, 17), (513, 4100)])
+def test_matvec_matches_oracle(native, rows, cols):
+    log(f"matvec rows={rows} cols={cols}")
+    D = _rand(1, (rows, cols), 256, np.uint8)
+    A = _rand(2, (cols, 8), Q32, np.uint32)
+    qu = _rand(3, (1, cols), Q32, np.uint32)
+    with native.Server(D, A) as srv:
+        B = np.zeros((1, rows), np.uint32)
+        srv.answer(qu, B, native.PATH_MATVEC)
+        assert np.array_equal(B[0], server.answer(D, qu[0]))
+        # closed forms: a unit vector selects a column, all-ones gives row sums
+        u = np.zeros((1, cols), np.uint32)
+        u[0, cols // 2] = 1
+        srv.answer(u, B, native.PATH_MATVEC)
+        assert np.array_equal(B[0], D[:, cols // 2].astype(np.uint32))
+
+
+def test_matvec_extremes(native):
+    rows, cols = 64, 768
+    D = np.full((rows, cols), 255, np.uint8)
+    A = np.zeros((cols, 4), np.uint32)
+    with native.Server(D, A) as srv:
+        B = np.zeros((1, rows), np.uint32)
+        srv.answer(np.full((1, cols), Q32 - 1, np.uint32), B, native.PATH_MATVEC)
+        assert np.all(B == (-255 * cols) % Q32)
+
+
+@pytest.mark.parametrize("batch", [2, 5, 16, 32])
+def test_mfma_batch_matches_oracle(native, batch):
+    rows, cols = 300, 700
+    log(f"mfma batch={batch}")
+    D = _rand(4, (rows, cols), 256, np.uint8)
+    A = _rand(5, (cols, 4), Q32, np.uint32)
+    Qm = _rand(6 + batch, (batch, cols), Q32, np.uint32)
+    with native.Server(D, A) as srv:
+        B = np.zeros((batch, rows), np.uint32)
+        srv.answer(Qm, B, native.PATH_MFMA)
+        assert np.array_equal(B, server.answer_batch(D, Qm))
+        B2 = np.zeros_like(B)
+        srv.answer(Qm, B2, native.PATH_MATVEC)
+        assert np.array_equal(B2, B)
+
+
+@pytest.mark.parametrize("dval,qval", [(0, 0), (255, Q32 - 1), (0, Q32 - 1), (255, 0), (128, 0x80808080)])
+def test_mfma_extreme_values(native, dval, qval):
+    # D = 0 and Q = 0 both shift to -128 in every plane: the largest MFMA partial sums.
+    rows, cols = 130, 512
+    D = np.full((rows, cols), dval, np.uint8)
+    A = np.zeros((cols, 4), np.uint32)
+    Qm = np.full((3, cols), qval, np.uint32)
+    with native.Server(D, A) as srv:
+        B = np.zeros((3, rows), np.uint32)
+        srv.answer(Qm, B, native.PATH_MFMA)
+        assert np.all(B == (dval * qval * cols) % Q32)
+
+
+def test_answer_device_tensors(native):
+    import torch
+    rows, cols = 96, 512
+    D = _rand(7, (rows, cols), 256, np.uint8)
+    A = _rand(8, (cols, 4), Q32, np.uint32)
+    Qm = _rand(9, (4, cols), Q32, np.uint32)
+    Dt = torch.from_numpy(D).cuda()
+    At = torch.from_numpy(A.view(np.int32)).cuda()
+    with native.Server(Dt, At) as srv:
+        Qt = torch.from_numpy(Qm.view(np.int32)).cuda()
+        Bt = torch.zeros((4, rows), dtype=torch.int32, device="cuda")
+        srv.answer(Qt, Bt)
+        srv.sync()
+        assert np.array_equal(Bt.cpu().numpy().view(np.uint32), server.answer_batch(D, Qm))
+
+
+# ----------------------------------------------------------------------------- global hint
+
+@pytest.mark.parametrize("rows,cols,n", [(100, 300, 40), (257, 256, 33)])
+def test_global_hint_matches_oracle(native, rows, cols, n):
+    log(f"global hint rows={rows} cols={cols} n={n}")
+    inst = make_instance(cfg=910, rows=rows, cols=cols, n=n, n_bits=256, encrypt_secret=False)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, 256)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, 256, ck)
+        srv.hint(cid, rows=[0])
+        H = np.zeros((rows, n), np.uint32)
+        srv.global_hint(0, rows, H)
+        assert np.array_equal(H, server.global_hint(inst.D, inst.A))
+
+
+# ----------------------------------------------------------------------------- Paillier
+
+def test_small_hint_and_compress_match_oracle(native):
+    # rows 12 (ragged), n 8, 256-bit N: K, c and the client round trip, all rows.
+    inst = make_instance(cfg=911, rows=12, cols=40, n=8, n_bits=256, zero_row=3)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, 256)
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    K_or = server.client_hint(cl.ck, E, cl.N)
+    b_or = server.answer(inst.D, cl.qu)
+    c_or = server.compress(K_or, b_or, cl.N)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, 256, ck)
+        assert srv.limbs(cid) == L
+        srv.hint(cid)
+        K = np.zeros((inst.rows, L), np.uint32)
+        srv.client_hint(cid, 0, inst.rows, K)
+        assert limbs_rows_to_ints(K) == K_or
+        assert K_or[3] == 1
+        B = np.zeros((1, inst.rows), np.uint32)
+        srv.answer(cl.qu[None, :], B)
+        assert np.array_equal(B[0], b_or)
+        C = np.zeros((1, inst.rows, L), np.uint32)
+        srv.compress([cid], B, C)
+        got = limbs_rows_to_ints(C[0])
+        assert got == c_or
+    f = [lwe.pir_extract_value(paillier.decrypt(cl.sk, x)) for x in got]
+    assert f == inst.D[:, cl.col].tolist()
+
+
+@pytest.mark.parametrize("n_bits", [1024, 2048])
+def test_compress_edge_values(native, n_bits):
+    # b in {0, 1, 2^32-1}; K in {1, N^2-1, random}: c must equal K (1 + bN) mod N^2.
+    rows, cols, n = 9, 256, 4
+    inst = make_instance(cfg=912, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False)
+    cl = inst.clients[0]
+    N = cl.N
+    N2 = N * N
+    # choose ck so that K rows take edge values: with all-zero D rows, K_j = 1
+    D = inst.D.copy()
+    D[0] = 0
+    N_limbs, ck, L = client_arrays(cl, n_bits)
+    E = server.exponents(server.global_hint(D, inst.A))
+    K_or = server.client_hint(cl.ck, E, N)
+    with native.Server(D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ck)
+        srv.hint(cid)
+        for bvals in ([0] * rows, [Q32 - 1] * rows, list(range(rows)), [1] * rows):
+            B = np.array([bvals], np.uint32)
+            C = np.zeros((1, rows, L), np.uint32)
+            srv.compress([cid], B, C)
+            got = limbs_rows_to_ints(C[0])
+            assert got == [K_or[j] * (1 + int(bvals[j]) * N) % N2 for j in range(rows)]
+            assert got[0] == (1 + int(bvals[0]) * N) % N2
+
+
+def test_stale_and_update(native):
+    inst = make_instance(cfg=913, rows=40, cols=64, n=6, n_bits=256, encrypt_secret=False)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, 256)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, 256, ck)
+        B = np.zeros((1, inst.rows), np.uint32)
+        srv.answer(cl.qu[None, :], B)
+        C = np.zeros((1, inst.rows, L), np.uint32)
+        with pytest.raises(native.ZipPIRError) as ei:
+            srv.compress([cid], B, C)
+        assert ei.value.status == native.PIR_ESTALE
+        srv.hint(cid)
+        K0 = np.zeros((inst.rows, L), np.uint32)
+        srv.client_hint(cid, 0, inst.rows, K0)
+        # update three rows
+        idx = np.array([2, 17, 39], np.uint32)
+        new = _rand(55, (3, inst.cols), 256, np.uint8)
+        srv.update_rows(idx, new)
+        assert srv.stale_rows(cid) == 3 and srv.stale_rows() == 3
+        with pytest.raises(native.ZipPIRError):
+            srv.compress([cid], B, C)
+        srv.hint(cid, rows=idx)
+        assert srv.stale_rows(cid) == 0 and srv.stale_rows() == 0
+        D2 = inst.D.copy()
+        D2[idx] = new
+        K1 = np.zeros_like(K0)
+        srv.client_hint(cid, 0, inst.rows, K1)
+        E2 = server.exponents(server.global_hint(D2, inst.A))
+        K_or = server.client_hint(cl.ck, E2, cl.N)
+        assert limbs_rows_to_ints(K1) == K_or
+        untouched = np.setdiff1d(np.arange(inst.rows), idx)
+        assert np.array_equal(K1[untouched], K0[untouched])
+        H = np.zeros((inst.rows, inst.n), np.uint32)
+        srv.global_hint(0, inst.rows, H)
+        assert np.array_equal(H, server.global_hint(D2, inst.A))
+        srv.answer(cl.qu[None, :], B)
+        assert np.array_equal(B[0], server.answer(D2, cl.qu))
+
+
+def test_rejects_small_modulus(native):
+    # Theorem 1: N must exceed q + n q^2 = 2^32 + n 2^64.
+    rows, cols, n = 8, 16, 16
+    D = _rand(60, (rows, cols), 256, np.uint8)
+    A = _rand(61, (cols, n), Q32, np.uint32)
+    N = (1 << 67) + 1   # 68 bits < 2^32 + 16 * 2^64 = 2^68 + 2^32
+    with native.Server(D, A) as srv:
+        with pytest.raises(native.ZipPIRError) as ei:
+            srv.add_client(wl.int_to_limbs(N, 3), 68, np.ones((n, 6), np.uint32))
+        assert ei.value.status == native.PIR_EINVAL
+
+
+# ----------------------------------------------------------------------------- toy end to end
+
+def test_toy_config_end_to_end(native):
+    """Toy PIR: D 256x256, n = 256, N 1024-bit, every row of K and c checked, and the
+    client's decryption recovers the selected column."""
+    log("toy: building instance")
+    with Pool(pool_size()) as pool:
+        inst = make_instance(cfg=0, rows=256, cols=256, n=256, n_bits=1024, pool=pool)
+        cl = inst.clients[0]
+        E = server.exponents(server.global_hint(inst.D, inst.A))
+        log("toy: oracle hint")
+        K_or = oracle_client_hint(cl.ck, E, cl.N, pool=pool)
+    N_limbs, ck, L = client_arrays(cl, 1024)
+    log("toy: GPU")
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, 1024, ck)
+        srv.hint(cid)
+        K = np.zeros((256, L), np.uint32)
+        srv.client_hint(cid, 0, 256, K)
+        assert limbs_rows_to_ints(K) == [K_or[j] for j in range(256)]
+        B = np.zeros((1, 256), np.uint32)
+        srv.answer(cl.qu[None, :], B)
+        assert np.array_equal(B[0], server.answer(inst.D, cl.qu))
+        C = np.zeros((1, 256, L), np.uint32)
+        srv.compress([cid], B, C)
+        got = limbs_rows_to_ints(C[0])
+    assert got == server.compress([K_or[j] for j in range(256)], B[0], cl.N)
+    f = [lwe.pir_extract_value(paillier.decrypt(cl.sk, x)) for x in got]
+    assert f == inst.D[:, cl.col].tolist()
