@@ -68,7 +68,9 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--nbits", type=int, default=2048)
     ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--cpu-rows", type=int, default=2048, help="rows in the CPU-oracle sample (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=32768, help="rows in the CPU-oracle sample (0: skip)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -108,7 +110,10 @@ def main() -> int:
     log("offline: pir_hint (H = D.A, then K for every row)")
     srv.profile(True)
     t0 = time.perf_counter()
-    srv.hint(cid)
+    chunk = max(1, rows // 8)
+    for r0 in range(0, rows, chunk):
+        srv.hint(cid, rows=np.arange(r0, min(rows, r0 + chunk), dtype=np.uint32))
+        log(f"  hint rows {r0}..{min(rows, r0 + chunk) - 1} done at {time.perf_counter() - t0:.1f} s")
     hint_s = time.perf_counter() - t0
     gemm_ms, _ = srv.profile_read("gemm")
     table_ms, _ = srv.profile_read("table")
@@ -197,13 +202,22 @@ def main() -> int:
             "kernel": "matvec_kernel<8>", "kernel_avg_us": round(mv_avg_ms * 1e3, 2),
             "bytes_per_launch": mv_bytes}
 
+    if args.copy_calib:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     cpu = None
     if args.cpu_rows > 0:
         log(f"cpu baseline on {args.cpu_rows} rows")
-        Kh = np.zeros((args.cpu_rows, L), np.uint32)
-        srv.client_hint(cid, 0, args.cpu_rows, Kh)
-        K_ints = [wl.limbs_to_int(Kh[j]) for j in range(args.cpu_rows)]
-        cpu = cpu_baseline(D, Qh[0], K_ints, N, args.cpu_rows)
+        cr = min(args.cpu_rows, rows)
+        Kh = np.zeros((cr, L), np.uint32)
+        srv.client_hint(cid, 0, cr, Kh)
+        K_ints = [wl.limbs_to_int(Kh[j]) for j in range(cr)]
+        cpu = cpu_baseline(D, Qh[0], K_ints, N, cr)
     srv.close()
 
     out = {

@@ -49,13 +49,42 @@ def rng(cfg: int, role: str, client: int = 0) -> np.random.Generator:
 
 # ----------------------------------------------------------------------------- matrices
 
-def database(cfg: int, rows: int, cols: int, chunk_rows: int = 4096) -> np.ndarray:
+DB_CHUNK_ROWS = 256
+
+
+def _db_chunk(cfg: int, chunk: int, nrows: int, cols: int) -> np.ndarray:
+    # every block of DB_CHUNK_ROWS rows has its own stream, so any rows can be regenerated alone
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(cfg), ROLE["db"], 1 << 20, chunk])))
+    return g.integers(0, 256, size=(nrows, cols), dtype=np.uint8)
+
+
+def database(cfg: int, rows: int, cols: int, threads: int = 8) -> np.ndarray:
     """Uniform uint8 database of ``rows x cols`` (row-major)."""
-    g = rng(cfg, "db")
+    from concurrent.futures import ThreadPoolExecutor
     out = np.empty((rows, cols), dtype=np.uint8)
-    for r0 in range(0, rows, chunk_rows):
-        r1 = min(rows, r0 + chunk_rows)
-        out[r0:r1] = g.integers(0, 256, size=(r1 - r0, cols), dtype=np.uint8)
+
+    def fill(c):
+        r0 = c * DB_CHUNK_ROWS
+        r1 = min(rows, r0 + DB_CHUNK_ROWS)
+        out[r0:r1] = _db_chunk(cfg, c, r1 - r0, cols)
+
+    nchunks = (rows + DB_CHUNK_ROWS - 1) // DB_CHUNK_ROWS
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        list(ex.map(fill, range(nchunks)))
+    return out
+
+
+def database_rows(cfg: int, rows: int, cols: int, idx) -> np.ndarray:
+    """The listed rows of ``database(cfg, rows, cols)`` without generating the rest."""
+    idx = np.asarray(idx, dtype=np.int64)
+    out = np.empty((len(idx), cols), dtype=np.uint8)
+    cache = {}
+    for k, r in enumerate(idx):
+        c = int(r) // DB_CHUNK_ROWS
+        if c not in cache:
+            r0 = c * DB_CHUNK_ROWS
+            cache[c] = _db_chunk(cfg, c, min(rows, r0 + DB_CHUNK_ROWS) - r0, cols)
+        out[k] = cache[c][int(r) - c * DB_CHUNK_ROWS]
     return out
 
 
