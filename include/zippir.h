@@ -172,6 +172,86 @@ const char *pir_strerror(pir_status st);
 /* Detail of the last failure on the calling thread ("" if none). */
 const char *pir_last_error(void);
 
+/* ============================================================================
+ * Serving engine: continuous batching over several resident databases.
+ *
+ * Clients issue many queries, each answered with its own resident hint (Sec. 4.3,
+ * "Supporting multiple queries"); D, A and H are shared by all clients.  The engine owns a
+ * scheduler thread.  Requests for one database wait in a FIFO queue; whenever that
+ * database has a free slot (at most two batches in flight per database) the scheduler
+ * takes up to max_batch queued requests whose clients share a limb count, runs
+ * pir_answer (batch 1: matvec; larger: one int8-MFMA contraction) and pir_compress on the
+ * database's stream, and copies each compressed response into the caller's buffer.
+ * Batches of different databases run on different streams and overlap on the device.
+ * Device buffers for in-flight batches are admitted against a byte budget: a batch that
+ * does not fit waits until earlier batches complete.  Results do not depend on how
+ * requests were batched.
+ * ==========================================================================*/
+typedef struct pir_engine pir_engine;
+
+typedef struct pir_completion {
+  uint64_t request_id;
+  uint32_t db;          /* engine database index                                   */
+  uint32_t client_id;
+  int32_t status;       /* PIR_OK or the status of the batch the request ran in    */
+  uint32_t batch;       /* number of requests in that batch                        */
+  double arrival_ms;    /* engine clock (ms since pir_engine_create): arrival       */
+  double start_ms;      /* batch enqueued on the device                             */
+  double done_ms;       /* response written to the caller's buffer                  */
+} pir_completion;
+
+typedef struct pir_engine_stats {
+  uint64_t submitted, completed, failed, batches;
+  uint64_t admission_waits;   /* times a formed batch waited for device budget          */
+  uint64_t device_bytes_peak; /* peak bytes of in-flight batch buffers                  */
+  double p50_ms, p99_ms;      /* latency = done - arrival over completed requests       */
+  double mean_batch;
+} pir_engine_stats;
+
+/* max_batch in [1, 1024].  hbm_budget_bytes: device bytes the engine may hold for in-flight
+ * batches (0: the device's free memory at creation minus 1 GiB). */
+pir_status pir_engine_create(pir_engine **out, uint32_t max_batch, uint64_t hbm_budget_bytes);
+
+/* Register a database.  The server must have been set up with its own stream (not NULL); from
+ * now until pir_engine_destroy only the engine may use it. */
+pir_status pir_engine_add_db(pir_engine *eng, pir_server *srv, uint32_t *db_index);
+
+/* Queue one request.  query: host array of the database's cols uint32 (copied before the call
+ * returns).  result: rows x L uint32 in pinned host memory (pir_host_alloc) or device memory;
+ * it must stay valid until the request's completion is returned by pir_engine_poll.
+ * arrival_ms: engine-clock time before which the request is not started (< 0: now).
+ * Errors: PIR_EINVAL (unknown database or client, pageable result buffer). */
+pir_status pir_engine_submit(pir_engine *eng, uint32_t db_index, uint32_t client_id,
+                             const uint32_t *query, uint32_t *result, double arrival_ms,
+                             uint64_t *request_id);
+
+/* Up to max completions, oldest first; waits up to timeout_ms (0: do not wait) for one. */
+pir_status pir_engine_poll(pir_engine *eng, pir_completion *out, uint32_t max, uint32_t *count,
+                           int32_t timeout_ms);
+
+/* Wait until every submitted request has completed (PIR_EBUSY on timeout; < 0: no limit). */
+pir_status pir_engine_drain(pir_engine *eng, int32_t timeout_ms);
+
+pir_status pir_engine_stats_get(pir_engine *eng, pir_engine_stats *st);
+
+/* Engine clock now (ms since creation). */
+double pir_engine_now_ms(pir_engine *eng);
+
+/* Stops the scheduler after in-flight work completes and frees the engine's buffers (the
+ * servers stay alive and usable again). */
+void pir_engine_destroy(pir_engine *eng);
+
+/* Admission policy, exposed for testing.  pir_engine_capacity: how many requests' buffers
+ * (bytes_per_request each) fit in budget_free, at most max_batch.  pir_engine_plan: how many
+ * leading queued requests form the next batch: those sharing the first one's limb count,
+ * at most capacity. */
+uint32_t pir_engine_capacity(uint64_t budget_free, uint64_t bytes_per_request, uint32_t max_batch);
+uint32_t pir_engine_plan(const uint32_t *queued_limbs, uint32_t nqueued, uint32_t capacity);
+
+/* Pinned host memory for engine results (NULL on failure). */
+void *pir_host_alloc(uint64_t bytes);
+void pir_host_free(void *p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,15 +1,14 @@
 // D . X mod 2^32 for a uint8 matrix D and uint32 vectors X, on signed int8 MFMA.
 //
-// Used for the batched online answer B = D.Q (many clients' queries at once; D and the
-// answer are shared, Sec. 4.3) and for the global hint H = D.A (Alg. 5 preamble).
+// Used for the batched online answer B = D.Q (many clients' queries at once; D is shared
+// by all clients, Sec. 4.3) and for the global hint H = D.A (Alg. 5 preamble).
 //
 // Byte planes: with X_b = byte b of X,  D.X = sum_b 2^(8b) (D . X_b) mod 2^32.
 // Shift to signed: D' = D - 128 and X_b' = X_b - 128 lie in [-128, 127] (XOR 0x80), and
 //   D.X_b = D'.X_b' + 128 sum_i X_b'[i] + 128 sum_i D'[i] + 16384 cols      (exact),
 // so each plane is one int8 MFMA contraction plus a per-column term (colsum, per batch)
 // and a per-row term (rowsum, per database).  Everything is accumulated in wrapping
-// 32-bit integers.  One launch covers at most 65536 columns of D, which keeps every MFMA
-// partial sum within +-2^30; longer rows are processed in chunks added into the output.
+// 32-bit integers.
 #include "internal.h"
 
 namespace zp {
@@ -93,34 +92,50 @@ constexpr int kBM = 128;          // rows of D per block (4 waves x 32 rows)
 constexpr int kBC = 32;           // vectors per block (2 blocks of 16)
 constexpr int kKB = 256;          // bytes of K per pipeline step
 constexpr int kLdsStride = kKB + 16;
-constexpr int kChunk = 65536;     // K bytes per launch (keeps MFMA partials within +-2^30)
 
-// LDS holds the X tile of one K step as 128 rows (plane-major: row = b*32 + c) of 256 bytes.
-// Lane (g = lane/16, r = lane%16) feeds MFMA s of the step with bytes [64g + 16s, +16) of its
+// A wave computes 32 rows x 32 vectors x 4 planes with v_mfma_i32_16x16x64_i8: for each
+// 64-byte slice of K, lane (g = lane/16, r = lane%16) supplies bytes [64g + 16s, +16) of its
 // D row (A operand) and of its X row (B operand).  The same k-set feeds both operands, so
-// the MFMA's internal ordering of k inside one instruction does not matter.
-__global__ __launch_bounds__(256) void gemm_planes_kernel(
+// the MFMA's internal ordering of k does not matter.  The four plane results of one output
+// sit in the same lane and register, so the epilogue combines them without data exchange.
+// A block of kW waves covers 32 kW rows and one K range (split-K over grid.z); each wave
+// keeps kDepth 256-byte K steps of D in flight, the X tile (4 planes x 32 vectors x 256
+// bytes) is double-buffered in LDS with one barrier per step, and partial results are
+// added into the zeroed output with 32-bit atomic adds (exact modulo 2^32 in any order).
+// A block spans at most 256 K steps (64 KiB), which keeps every MFMA partial within +-2^30.
+template <int kW, int kDepth>
+__global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     const uint8_t* __restrict__ D, int rows, int cols, int pitch, const int8_t* __restrict__ Xs,
     const int32_t* __restrict__ colsum, int ncol, const int32_t* __restrict__ rowsum,
-    uint32_t* __restrict__ out, int out_rowmajor, long long out_ld, int k0, int k1,
-    int first_chunk) {
-  __shared__ __attribute__((aligned(16))) int8_t xs[4 * kBC][kLdsStride];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t* __restrict__ out, int out_rowmajor, long long out_ld, int ksteps_per_block) {
+  __shared__ __attribute__((aligned(16))) int8_t xs[2][4 * kBC][kLdsStride];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, r = lane & 15;
-  const int rowblk = blockIdx.x * kBM;
+  const int rowblk = blockIdx.x * 32 * kW;
   const int cblk = blockIdx.y * kBC;
+  const int kstep0 = blockIdx.z * ksteps_per_block;
+  const int nsteps = min(ksteps_per_block, pitch / kKB - kstep0);
+  if (nsteps <= 0) return;
 
   const uint8_t* dp[2];
 #pragma unroll
   for (int mr = 0; mr < 2; ++mr) {
     const int row = min(rowblk + 32 * wave + 16 * mr + r, rows - 1);
-    dp[mr] = D + (size_t)row * pitch + 64 * g;
+    dp[mr] = D + (size_t)row * pitch + (size_t)kstep0 * kKB + 64 * g;
   }
-  // X tile loading: thread tid fills LDS row tid/2 (plane b = row/32, vector row%32), half tid%2
-  const int xrow = tid >> 1, xhalf = tid & 1;
-  const int xb = xrow >> 5, xc = cblk + (xrow & 31);
-  const bool xvalid = xc < ncol;
-  const int8_t* xp = Xs + ((size_t)(xvalid ? xc : 0) * 4 + xb) * pitch + 128 * xhalf;
+  constexpr int kPieces = 4 * kBC * (kKB / 16) / (64 * kW);
+  int xoff[kPieces], lrow[kPieces], lcol[kPieces];
+  bool xval[kPieces];
+#pragma unroll
+  for (int t = 0; t < kPieces; ++t) {
+    const int piece = tid + t * 64 * kW;
+    lrow[t] = piece >> 4;
+    lcol[t] = (piece & 15) * 16;
+    const int b = lrow[t] >> 5, c = cblk + (lrow[t] & 31);
+    xval[t] = c < ncol;
+    xoff[t] = xval[t] ? ((c * 4 + b) * pitch + kstep0 * kKB + lcol[t]) : 0;
+  }
 
   v4i acc[2][2][4];
 #pragma unroll
@@ -130,59 +145,77 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[mr][qb][b] = v4i{0, 0, 0, 0};
 
-  u32x4 xr[8];
-  u32x4 da[2][4];
-  auto load_step = [&](int k) {
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-      xr[t] = xvalid ? *reinterpret_cast<const u32x4*>(xp + k + 16 * t) : u32x4{0u, 0u, 0u, 0u};
+  u32x4 ring[kDepth][2][4];
+  u32x4 xn[kPieces];
+  auto load_d = [&](int slot, int st) {
 #pragma unroll
     for (int mr = 0; mr < 2; ++mr)
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        da[mr][s] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(dp[mr] + k) + s);
+        ring[slot][mr][s] = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x4*>(dp[mr] + (size_t)st * kKB) + s);
+  };
+  auto load_x = [&](int st) {
+#pragma unroll
+    for (int t = 0; t < kPieces; ++t)
+      xn[t] = xval[t] ? *reinterpret_cast<const u32x4*>(Xs + (size_t)xoff[t] + (size_t)st * kKB)
+                      : u32x4{0u, 0u, 0u, 0u};
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < kPieces; ++t) *reinterpret_cast<u32x4*>(&xs[buf][lrow[t]][lcol[t]]) = xn[t];
   };
 
-  load_step(k0);
-  for (int k = k0; k < k1; k += kKB) {
-    __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-      *reinterpret_cast<u32x4*>(&xs[xrow][128 * xhalf + 16 * t]) = xr[t];
-    __syncthreads();
-    u32x4 dcur[2][4];
+  for (int d = 0; d < kDepth; ++d)
+    if (d < nsteps) load_d(d, d);
+  load_x(0);
+  stash(0);
+  if (nsteps > 1) load_x(1);
+  __syncthreads();
+  for (int st = 0; st < nsteps; st += kDepth) {
 #pragma unroll
-    for (int mr = 0; mr < 2; ++mr)
+    for (int d = 0; d < kDepth; ++d) {
+      const int cur = st + d;
+      if (cur >= nsteps) break;
+      const int buf = cur & 1;
+      u32x4 dc[2][4];
+#pragma unroll
+      for (int mr = 0; mr < 2; ++mr)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          u32x4 v = ring[d][mr][s];
+          v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
+          dc[mr][s] = v;
+        }
+      if (cur + kDepth < nsteps) load_d(d, cur + kDepth);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        u32x4 v = da[mr][s];
-        v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
-        dcur[mr][s] = v;
-      }
-    if (k + kKB < k1) load_step(k + kKB);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      v4i xf[2][4];
-#pragma unroll
-      for (int qb = 0; qb < 2; ++qb)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          xf[qb][b] = *reinterpret_cast<const v4i*>(&xs[b * 32 + 16 * qb + r][64 * g + 16 * s]);
-#pragma unroll
-      for (int mr = 0; mr < 2; ++mr) {
-        const u32x4 dv = dcur[mr][s];
-        const v4i a = v4i{(int)dv.x, (int)dv.y, (int)dv.z, (int)dv.w};
+        v4i xf[2][4];
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
           for (int b = 0; b < 4; ++b)
-            acc[mr][qb][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, xf[qb][b], acc[mr][qb][b], 0, 0, 0);
+            xf[qb][b] = *reinterpret_cast<const v4i*>(&xs[buf][b * 32 + 16 * qb + r][64 * g + 16 * s]);
+#pragma unroll
+        for (int mr = 0; mr < 2; ++mr) {
+          const v4i a = v4i{(int)dc[mr][s].x, (int)dc[mr][s].y, (int)dc[mr][s].z, (int)dc[mr][s].w};
+#pragma unroll
+          for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              acc[mr][qb][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, xf[qb][b], acc[mr][qb][b], 0, 0, 0);
+        }
       }
+      if (cur + 1 < nsteps) {
+        stash(buf ^ 1);
+        if (cur + 2 < nsteps) load_x(cur + 2);
+      }
+      __syncthreads();
     }
   }
 
-  // epilogue: output element (row, c) sits in lane (g, r) register i with
-  // row = 16 mr + 4 g + i inside the wave's 32 rows and c = 16 qb + r inside the block.
+  const bool first = blockIdx.z == 0;
 #pragma unroll
   for (int mr = 0; mr < 2; ++mr)
 #pragma unroll
@@ -191,31 +224,47 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(
       if (c >= ncol) continue;
       uint32_t cs[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) cs[b] = first_chunk ? 128u * (uint32_t)colsum[c * 4 + b] : 0u;
+      for (int b = 0; b < 4; ++b) cs[b] = first ? 128u * (uint32_t)colsum[c * 4 + b] : 0u;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = rowblk + 32 * wave + 16 * mr + 4 * g + i;
-        if (row >= rows) continue;
-        const uint32_t rterm = first_chunk ? 128u * (uint32_t)rowsum[row] + 16384u * (uint32_t)cols : 0u;
+        const int orow = rowblk + 32 * wave + 16 * mr + 4 * g + i;
+        if (orow >= rows) continue;
+        const uint32_t rterm = first ? 128u * (uint32_t)rowsum[orow] + 16384u * (uint32_t)cols : 0u;
         uint32_t v = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          v += ((uint32_t)acc[mr][qb][b][i] + cs[b] + rterm) << (8 * b);
-        uint32_t* o = out_rowmajor ? out + (size_t)row * ncol + c : out + (size_t)c * out_ld + row;
-        if (first_chunk) *o = v; else *o += v;
+        for (int b = 0; b < 4; ++b) v += ((uint32_t)acc[mr][qb][b][i] + cs[b] + rterm) << (8 * b);
+        uint32_t* o = out_rowmajor ? out + (size_t)orow * ncol + c : out + (size_t)c * out_ld + orow;
+        atomicAdd(o, v);
       }
     }
 }
 
+__global__ void zero_out_kernel(uint32_t* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, const int8_t* Xs,
-                        const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
-                        bool out_rowmajor, long long out_ld, hipStream_t s) {
-  dim3 grid((rows + kBM - 1) / kBM, (ncol + kBC - 1) / kBC);
-  for (int k0 = 0; k0 < pitch; k0 += kChunk) {
-    const int k1 = min(pitch, k0 + kChunk);
-    gemm_planes_kernel<<<grid, 256, 0, s>>>(D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out,
-                                            out_rowmajor ? 1 : 0, out_ld, k0, k1, k0 == 0 ? 1 : 0);
-  }
+                   const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
+                   bool out_rowmajor, long long out_ld, int waves, int depth, int ksplit,
+                   hipStream_t s) {
+  const long long nout = out_rowmajor ? (long long)rows * ncol : (long long)ncol * out_ld;
+  zero_out_kernel<<<1024, 256, 0, s>>>(out, nout);
+  const int nsteps = pitch / kKB;
+  const int per = min(256, (nsteps + ksplit - 1) / ksplit);
+  const int kz = (nsteps + per - 1) / per;
+  dim3 grid((rows + 32 * waves - 1) / (32 * waves), (ncol + kBC - 1) / kBC, kz);
+#define ZP_G16(W, DP) gemm_planes_kernel<W, DP><<<grid, 64 * W, 0, s>>>(D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per)
+  if (waves == 4 && depth == 1) ZP_G16(4, 1);
+  else if (waves == 4 && depth == 2) ZP_G16(4, 2);
+  else if (waves == 4 && depth == 3) ZP_G16(4, 3);
+  else if (waves == 8 && depth == 1) ZP_G16(8, 1);
+  else if (waves == 8 && depth == 2) ZP_G16(8, 2);
+  else if (waves == 8 && depth == 3) ZP_G16(8, 3);
+  else if (waves == 2 && depth == 2) ZP_G16(2, 2);
+  else ZP_G16(4, 2);
+#undef ZP_G16
 }
 
 }  // namespace zp

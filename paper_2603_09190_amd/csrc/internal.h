@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "zippir.h"
+
 namespace zp {
 
 // Native 16-byte vector (usable with the nontemporal load builtin).
@@ -52,11 +54,17 @@ void launch_pack_planes_s8(const uint32_t* x, long long stride_c, long long stri
 // rowsum[j] = sum_{i<cols} (D[j][i] - 128)
 void launch_rowsum(const uint8_t* D, int rows, int cols, int pitch, int32_t* rowsum,
                    hipStream_t s);
-// out = D . X mod 2^32 for `rows` rows of D starting at D, all ncol columns.
-// out_rowmajor: out[j*ncol + c]; otherwise out[c*out_ld + j].
+// out = D . X mod 2^32 for `rows` rows of D starting at D, all ncol columns (out is
+// overwritten).  out_rowmajor: out[j*ncol + c]; otherwise out[c*out_ld + j].
+// Launch shape: `waves` per block (2, 4 or 8), `depth` K steps of D in flight per wave
+// (1..3), `ksplit` K ranges per output tile.  Every shape gives identical bits.
+struct GemmShape {
+  int waves, depth, ksplit;
+};
 void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, const int8_t* Xs,
                         const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
-                        bool out_rowmajor, long long out_ld, hipStream_t s);
+                        bool out_rowmajor, long long out_ld, int waves, int depth, int ksplit,
+                        hipStream_t s);
 
 // ---- rows.hip (row gather/scatter for updates and partial recomputation)
 void launch_gather_rows_u8(const uint8_t* src, int pitch, const uint32_t* rows, int nrows,
@@ -76,6 +84,11 @@ void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint3
                       int nrows, const uint32_t* table, uint32_t* K, hipStream_t s);
 void launch_kappa(const ClientDev& cd, const uint32_t* K, const uint32_t* rowlist, int nrows,
                   uint32_t* kappa, hipStream_t s);
+
+// ---- runtime.cpp accessors used by the serving engine
+hipStream_t server_stream(pir_server* s);
+void set_error(const char* msg);  // sets the calling thread's pir_last_error() text
+int server_device(pir_server* s);
 
 // ---- compress.hip
 void launch_compress(const ClientDev& cd, const uint32_t* K, const uint32_t* kappa,

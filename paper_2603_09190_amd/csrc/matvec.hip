@@ -38,74 +38,80 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-// Each wave owns kRows consecutive rows; lanes stride over 16-byte column chunks, so
-// one iteration reads kRows x 1 KiB of D, fully coalesced, and the query planes once.
-template <int kRows>
-__global__ __launch_bounds__(256) void matvec_kernel(const uint8_t* __restrict__ D, int rows,
-                                                     int pitch,
-                                                     const uint8_t* __restrict__ planes,
-                                                     uint32_t* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int row0 = (blockIdx.x * 4 + wave) * kRows;
-  if (row0 >= rows) return;
-  const int nchunk = pitch >> 4;
-  const u32x4* __restrict__ p0 = reinterpret_cast<const u32x4*>(planes);
-  const u32x4* __restrict__ p1 = reinterpret_cast<const u32x4*>(planes + (size_t)pitch);
-  const u32x4* __restrict__ p2 = reinterpret_cast<const u32x4*>(planes + 2 * (size_t)pitch);
-  const u32x4* __restrict__ p3 = reinterpret_cast<const u32x4*>(planes + 3 * (size_t)pitch);
-  const u32x4* rowp[kRows];
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    const int row = min(row0 + r, rows - 1);
-    rowp[r] = reinterpret_cast<const u32x4*>(D + (size_t)row * pitch);
-  }
-  uint32_t acc[kRows][4];
-#pragma unroll
-  for (int r = 0; r < kRows; ++r)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[r][b] = 0;
+// A wave owns 4096 columns of the query (64 per lane, as four
+// 1 KiB-coalesced 16-byte pieces) held in registers as byte planes, and streams down
+// `rows_per_wave` rows.  Per row the wave reduces its partial dot product and adds it into
+// b with a 32-bit atomic add, which is exact modulo 2^32 and independent of order.
+// b must be zero before the launch.
+constexpr int kSegCols = 4096;
 
-  for (int ch = lane; ch < nchunk; ch += 64) {
-    const u32x4 q0 = p0[ch], q1 = p1[ch], q2 = p2[ch], q3 = p3[ch];
-    u32x4 d[kRows];
+template <int kR>
+__global__ __launch_bounds__(256) void matvec_seg_kernel(const uint8_t* __restrict__ D, int rows,
+                                                         int pitch,
+                                                         const uint8_t* __restrict__ planes,
+                                                         uint32_t* __restrict__ out,
+                                                         int rows_per_wave) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int seg0 = blockIdx.y * kSegCols;
+  const int row_begin = (blockIdx.x * 4 + wave) * rows_per_wave;
+  if (row_begin >= rows) return;
+  const int row_end = min(rows, row_begin + rows_per_wave);
+  bool valid[4];
+  int off[4];
+  u32x4 q[4][4];
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) d[r] = __builtin_nontemporal_load(rowp[r] + ch);
+  for (int k = 0; k < 4; ++k) {
+    off[k] = seg0 + 1024 * k + 16 * lane;
+    valid[k] = off[k] < pitch;
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-      acc[r][0] = __builtin_amdgcn_udot4(d[r].x, q0.x, acc[r][0], false);
-      acc[r][0] = __builtin_amdgcn_udot4(d[r].y, q0.y, acc[r][0], false);
-      acc[r][0] = __builtin_amdgcn_udot4(d[r].z, q0.z, acc[r][0], false);
-      acc[r][0] = __builtin_amdgcn_udot4(d[r].w, q0.w, acc[r][0], false);
-      acc[r][1] = __builtin_amdgcn_udot4(d[r].x, q1.x, acc[r][1], false);
-      acc[r][1] = __builtin_amdgcn_udot4(d[r].y, q1.y, acc[r][1], false);
-      acc[r][1] = __builtin_amdgcn_udot4(d[r].z, q1.z, acc[r][1], false);
-      acc[r][1] = __builtin_amdgcn_udot4(d[r].w, q1.w, acc[r][1], false);
-      acc[r][2] = __builtin_amdgcn_udot4(d[r].x, q2.x, acc[r][2], false);
-      acc[r][2] = __builtin_amdgcn_udot4(d[r].y, q2.y, acc[r][2], false);
-      acc[r][2] = __builtin_amdgcn_udot4(d[r].z, q2.z, acc[r][2], false);
-      acc[r][2] = __builtin_amdgcn_udot4(d[r].w, q2.w, acc[r][2], false);
-      acc[r][3] = __builtin_amdgcn_udot4(d[r].x, q3.x, acc[r][3], false);
-      acc[r][3] = __builtin_amdgcn_udot4(d[r].y, q3.y, acc[r][3], false);
-      acc[r][3] = __builtin_amdgcn_udot4(d[r].z, q3.z, acc[r][3], false);
-      acc[r][3] = __builtin_amdgcn_udot4(d[r].w, q3.w, acc[r][3], false);
-    }
+    for (int b = 0; b < 4; ++b)
+      q[k][b] = valid[k] ? *reinterpret_cast<const u32x4*>(planes + (size_t)b * pitch + off[k])
+                         : u32x4{0u, 0u, 0u, 0u};
   }
+  for (int row = row_begin; row < row_end; row += kR) {
+    u32x4 d[kR][4];
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    uint32_t v = acc[r][0] + (acc[r][1] << 8) + (acc[r][2] << 16) + (acc[r][3] << 24);
-    v = wave_sum(v);
-    if (lane == 0 && row0 + r < rows) out[row0 + r] = v;
+    for (int r = 0; r < kR; ++r) {
+      const int rr = min(row + r, row_end - 1);
+      const uint8_t* rp = D + (size_t)rr * pitch;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        d[r][k] = valid[k] ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rp + off[k]))
+                           : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      uint32_t a[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          a[b] = __builtin_amdgcn_udot4(d[r][k].x, q[k][b].x, a[b], false);
+          a[b] = __builtin_amdgcn_udot4(d[r][k].y, q[k][b].y, a[b], false);
+          a[b] = __builtin_amdgcn_udot4(d[r][k].z, q[k][b].z, a[b], false);
+          a[b] = __builtin_amdgcn_udot4(d[r][k].w, q[k][b].w, a[b], false);
+        }
+      uint32_t v = a[0] + (a[1] << 8) + (a[2] << 16) + (a[3] << 24);
+      v = wave_sum(v);
+      if (lane == 0 && row + r < row_end) atomicAdd(out + row + r, v);
+    }
   }
 }
 
-constexpr int kMatvecRows = 8;
+__global__ void zero_u32_kernel(uint32_t* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+constexpr int kSegRowsPerWave = 32;
 
 void launch_matvec(const uint8_t* D, int rows, int pitch, const uint8_t* planes, uint32_t* b,
                    hipStream_t s) {
-  const int per_block = 4 * kMatvecRows;
-  const int blocks = (rows + per_block - 1) / per_block;
-  matvec_kernel<kMatvecRows><<<blocks, 256, 0, s>>>(D, rows, pitch, planes, b);
+  // b accumulates one atomic partial per column segment: clear it first
+  zero_u32_kernel<<<(rows + 255) / 256, 256, 0, s>>>(b, rows);
+  dim3 grid((rows + 4 * kSegRowsPerWave - 1) / (4 * kSegRowsPerWave), (pitch + kSegCols - 1) / kSegCols);
+  matvec_seg_kernel<2><<<grid, 256, 0, s>>>(D, rows, pitch, planes, b, kSegRowsPerWave);
 }
 
 }  // namespace zp

@@ -4,10 +4,15 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -258,6 +263,98 @@ void prof_clear(pir_server* s) {
   }
 }
 
+// ----------------------------------------------------------------------------- autotuner
+// Launch shape of the byte-plane contraction per problem shape.  The first contraction of a
+// shape times every candidate once (after a warm-up) with events on the server's stream and
+// keeps the fastest; every candidate computes identical bits, so tuning never changes a
+// result.  ZIPPIR_AUTOTUNE=0 disables tuning (default shape); ZIPPIR_TUNE_CACHE=<file>
+// persists choices as lines "rows pitch ncol rowmajor waves depth ksplit".
+using TuneKey = std::tuple<int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, zp::GemmShape> g_tune;
+bool g_tune_loaded = false;
+
+constexpr zp::GemmShape kDefaultShape{8, 2, 2};
+const zp::GemmShape kCandidates[] = {{8, 2, 2}, {8, 1, 2}, {8, 2, 4}, {4, 1, 1}, {4, 3, 1},
+                                     {4, 2, 2}, {2, 2, 1}};
+
+const char* tune_cache_path() {
+  const char* p = std::getenv("ZIPPIR_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  std::ifstream f(path);
+  int r, p, n, m, w, d, k;
+  while (f >> r >> p >> n >> m >> w >> d >> k) g_tune[TuneKey(r, p, n, m)] = zp::GemmShape{w, d, k};
+}
+
+void tune_store_locked() {
+  const char* path = tune_cache_path();
+  if (!path) return;
+  std::ofstream f(path, std::ios::trunc);
+  for (auto& kv : g_tune)
+    f << std::get<0>(kv.first) << " " << std::get<1>(kv.first) << " " << std::get<2>(kv.first) << " "
+      << std::get<3>(kv.first) << " " << kv.second.waves << " " << kv.second.depth << " "
+      << kv.second.ksplit << "\n";
+}
+
+bool autotune_enabled() {
+  const char* e = std::getenv("ZIPPIR_AUTOTUNE");
+  return !(e && std::strcmp(e, "0") == 0);
+}
+
+// out = D . X mod 2^32 with the tuned launch shape.
+pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
+                    const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
+                    bool rowmajor, long long ld) {
+  hipStream_t st = s->stream;
+  const TuneKey key((int)rows, (int)s->pitch, ncol, rowmajor ? 1 : 0);
+  zp::GemmShape shape = kDefaultShape;
+  bool need_tune = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) shape = it->second;
+    else need_tune = autotune_enabled();
+  }
+  if (need_tune) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ZP_HIP(hipEventCreate(&e0));
+    ZP_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    for (const zp::GemmShape& c : kCandidates) {
+      zp::launch_gemm_planes(D, rows, (int)s->cols, (int)s->pitch, Xs, colsum, ncol, rowsum, out,
+                             rowmajor, ld, c.waves, c.depth, c.ksplit, st);
+      ZP_HIP(hipEventRecord(e0, st));
+      zp::launch_gemm_planes(D, rows, (int)s->cols, (int)s->pitch, Xs, colsum, ncol, rowsum, out,
+                             rowmajor, ld, c.waves, c.depth, c.ksplit, st);
+      ZP_HIP(hipEventRecord(e1, st));
+      ZP_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      ZP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        shape = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = shape;
+    tune_store_locked();
+  }
+  ProfScope ps(s, PIR_KERNEL_GEMM);
+  zp::launch_gemm_planes(D, rows, (int)s->cols, (int)s->pitch, Xs, colsum, ncol, rowsum, out,
+                         rowmajor, ld, shape.waves, shape.depth, shape.ksplit, st);
+  return PIR_OK;
+}
+
 pir_status use_device(pir_server* s) {
   ZP_HIP(hipSetDevice(s->device));
   return PIR_OK;
@@ -268,9 +365,7 @@ pir_status refresh_H(pir_server* s, const std::vector<uint32_t>& rows_in) {
   if (rows_in.empty()) return PIR_OK;
   hipStream_t st = s->stream;
   if (rows_in.size() * 4 >= s->rows) {
-    ProfScope ps(s, PIR_KERNEL_GEMM);
-    zp::launch_gemm_planes(s->D, (int)s->rows, (int)s->cols, (int)s->pitch, s->Ap, s->Acolsum,
-                           (int)s->n, s->rowsum, s->H, true, 0, st);
+    ZP_TRY(run_gemm(s, s->D, (int)s->rows, s->Ap, s->Acolsum, (int)s->n, s->rowsum, s->H, true, 0));
   } else {
     const size_t m = rows_in.size();
     ZP_TRY(s->scratch(s->s_rows, m * sizeof(uint32_t)));
@@ -281,9 +376,8 @@ pir_status refresh_H(pir_server* s, const std::vector<uint32_t>& rows_in) {
     ZP_HIP(hipMemcpyAsync(drows, rows_in.data(), m * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     zp::launch_gather_rows_u8(s->D, (int)s->pitch, drows, (int)m, (uint8_t*)s->s_gath.p, st);
     zp::launch_gather_rowsum(s->rowsum, drows, (int)m, (int32_t*)s->s_gsum.p, st);
-    zp::launch_gemm_planes((const uint8_t*)s->s_gath.p, (int)m, (int)s->cols, (int)s->pitch,
-                           s->Ap, s->Acolsum, (int)s->n, (const int32_t*)s->s_gsum.p,
-                           (uint32_t*)s->s_h.p, true, 0, st);
+    ZP_TRY(run_gemm(s, (const uint8_t*)s->s_gath.p, (int)m, s->Ap, s->Acolsum, (int)s->n,
+                    (const int32_t*)s->s_gsum.p, (uint32_t*)s->s_h.p, true, 0));
     zp::launch_scatter_rows_u32((const uint32_t*)s->s_h.p, (int)s->n, drows, (int)m, s->H, st);
     // the scratch is reused by later calls: finish before returning
     ZP_HIP(hipStreamSynchronize(st));
@@ -312,6 +406,10 @@ ClientState* find_client(pir_server* s, uint32_t id) {
 }
 
 }  // namespace
+
+hipStream_t zp::server_stream(pir_server* s) { return s->stream; }
+int zp::server_device(pir_server* s) { return s->device; }
+void zp::set_error(const char* msg) { g_last_error = msg; }
 
 // ============================================================================= C ABI
 
@@ -623,10 +721,9 @@ static pir_status answer_impl(pir_server* s, const uint32_t* Q, uint32_t batch, 
     ZP_TRY(s->scratch(s->s_colsum, (size_t)batch * 4 * sizeof(int32_t)));
     zp::launch_pack_planes_s8(dQ, s->cols, 1, (int)batch, (int)s->cols, (int)s->pitch,
                               (int8_t*)s->s_planes.p, (int32_t*)s->s_colsum.p, st);
-    ProfScope ps(s, PIR_KERNEL_GEMM);
-    zp::launch_gemm_planes(s->D, (int)s->rows, (int)s->cols, (int)s->pitch,
-                           (const int8_t*)s->s_planes.p, (const int32_t*)s->s_colsum.p,
-                           (int)batch, s->rowsum, dB, false, (long long)s->rows, st);
+    ZP_TRY(run_gemm(s, s->D, (int)s->rows, (const int8_t*)s->s_planes.p,
+                    (const int32_t*)s->s_colsum.p, (int)batch, s->rowsum, dB, false,
+                    (long long)s->rows));
   } else {
     return fail(PIR_EINVAL, "unknown answer path");
   }

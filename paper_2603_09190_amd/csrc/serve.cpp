@@ -1,0 +1,475 @@
+// Serving engine behind the pir_engine_* calls of zippir.h: continuous batching of PIR
+// requests over several resident databases, admitted against a device-memory budget.
+//
+// A request is (database, client, query, result buffer, arrival time).  The scheduler thread
+// keeps one FIFO queue per database.  Each database has two batch slots (device buffers for
+// the queries, the answers and the compressed responses of one batch); whenever a slot is
+// free and arrived requests are waiting, it takes up to max_batch of them whose clients
+// share a limb count and enqueues on the database's stream: query uploads, pir_answer
+// (matvec for one request, one int8-MFMA contraction otherwise), pir_compress, and one
+// download per response.  An event marks the batch's end; the scheduler polls events and
+// hands completions to pir_engine_poll.  Databases use different streams, so their batches
+// overlap on the device, and a database with a batch in flight forms its next one meanwhile.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "zippir.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t id = 0;
+  uint32_t db = 0, client = 0, L = 0;
+  double arrival_ms = 0;
+  uint32_t* host_q = nullptr;  // pinned copy of the query
+  uint32_t* result = nullptr;
+};
+
+struct Slot {
+  uint32_t* dev = nullptr;  // queries | answers | responses, capacity `cap` requests of `L_cap`
+  uint64_t bytes = 0;
+  bool busy = false;
+  hipEvent_t ev = nullptr;
+  std::vector<Request> reqs;
+  double start_ms = 0;
+  int32_t status = PIR_OK;
+};
+
+struct Db {
+  pir_server* srv = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  uint32_t rows = 0, cols = 0;
+  std::deque<Request> queue;
+  Slot slots[2];
+  std::vector<uint32_t*> qpool;  // free pinned query buffers (cols words each)
+};
+
+uint64_t bytes_per_request(const Db& d, uint32_t L) {
+  return 4ull * d.cols + 4ull * d.rows + 4ull * d.rows * L;
+}
+
+}  // namespace
+
+struct pir_engine {
+  Clock::time_point t0 = Clock::now();
+  uint32_t max_batch = 32;
+  uint64_t budget = 0, in_use = 0, peak = 0;
+  std::vector<std::unique_ptr<Db>> dbs;
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done;
+  std::deque<Request> incoming;
+  std::deque<pir_completion> done;
+  std::vector<double> lat;
+  uint64_t next_id = 1, submitted = 0, completed = 0, failed = 0, batches = 0, waits = 0;
+  uint64_t batched_reqs = 0;
+  bool stop = false, started = false;
+  std::thread th;
+
+  double now() const {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+  }
+  void run();
+  bool launch(Db& d, Slot& slot, uint32_t n);
+  void complete(Db& d, Slot& slot);
+  bool reserve(Db& d, Slot& slot, uint64_t need);
+};
+
+namespace {
+pir_status efail(pir_status st, const std::string& m) {
+  zp::set_error(m.c_str());
+  return st;
+}
+}  // namespace
+
+extern "C" uint32_t pir_engine_capacity(uint64_t budget_free, uint64_t bytes_per_request,
+                                        uint32_t max_batch) {
+  if (bytes_per_request == 0) return max_batch;
+  const uint64_t fit = budget_free / bytes_per_request;
+  return (uint32_t)std::min<uint64_t>(fit, max_batch);
+}
+
+extern "C" uint32_t pir_engine_plan(const uint32_t* queued_limbs, uint32_t nqueued,
+                                    uint32_t capacity) {
+  if (nqueued == 0 || capacity == 0 || !queued_limbs) return 0;
+  uint32_t n = 1;
+  while (n < nqueued && n < capacity && queued_limbs[n] == queued_limbs[0]) ++n;
+  return n;
+}
+
+// Make sure `slot` holds at least `need` bytes of device memory within the budget.  Idle
+// slots of every database are released if the budget is short.  Called with mu held.
+bool pir_engine::reserve(Db& d, Slot& slot, uint64_t need) {
+  if (slot.bytes >= need) return true;
+  auto release = [&](Slot& s) {
+    if (s.dev) {
+      (void)hipFree(s.dev);
+      in_use -= s.bytes;
+      s.dev = nullptr;
+      s.bytes = 0;
+    }
+  };
+  release(slot);
+  if (in_use + need > budget) {
+    for (auto& other : dbs)
+      for (Slot& s : other->slots)
+        if (!s.busy && &s != &slot) release(s);
+  }
+  if (in_use + need > budget) return false;
+  (void)hipSetDevice(d.device);
+  if (hipMalloc((void**)&slot.dev, need) != hipSuccess) {
+    (void)hipGetLastError();
+    slot.dev = nullptr;
+    return false;
+  }
+  slot.bytes = need;
+  in_use += need;
+  peak = std::max(peak, in_use);
+  return true;
+}
+
+bool pir_engine::launch(Db& d, Slot& slot, uint32_t n) {
+  const uint32_t L = d.queue.front().L;
+  const uint64_t need = bytes_per_request(d, L) * n;
+  if (!reserve(d, slot, need)) return false;
+  slot.reqs.assign(d.queue.begin(), d.queue.begin() + n);
+  d.queue.erase(d.queue.begin(), d.queue.begin() + n);
+  uint32_t* dQ = slot.dev;
+  uint32_t* dB = dQ + (size_t)n * d.cols;
+  uint32_t* dC = dB + (size_t)n * d.rows;
+  (void)hipSetDevice(d.device);
+  int32_t st = PIR_OK;
+  for (uint32_t i = 0; i < n && st == PIR_OK; ++i)
+    if (hipMemcpyAsync(dQ + (size_t)i * d.cols, slot.reqs[i].host_q, 4ull * d.cols,
+                       hipMemcpyHostToDevice, d.stream) != hipSuccess)
+      st = PIR_EDEVICE;
+  std::vector<uint32_t> ids(n);
+  for (uint32_t i = 0; i < n; ++i) ids[i] = slot.reqs[i].client;
+  if (st == PIR_OK) st = pir_answer(d.srv, dQ, n, dB, PIR_PTR_DEVICE);
+  if (st == PIR_OK) st = pir_compress(d.srv, ids.data(), n, dB, dC, PIR_PTR_DEVICE);
+  for (uint32_t i = 0; i < n && st == PIR_OK; ++i)
+    if (hipMemcpyAsync(slot.reqs[i].result, dC + (size_t)i * d.rows * L, 4ull * d.rows * L,
+                       hipMemcpyDefault, d.stream) != hipSuccess)
+      st = PIR_EDEVICE;
+  if (!slot.ev) (void)hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming);
+  (void)hipEventRecord(slot.ev, d.stream);
+  slot.status = st;
+  slot.start_ms = now();
+  slot.busy = true;
+  ++batches;
+  batched_reqs += n;
+  return true;
+}
+
+void pir_engine::complete(Db& d, Slot& slot) {
+  const double t = now();
+  for (Request& r : slot.reqs) {
+    pir_completion c;
+    c.request_id = r.id;
+    c.db = r.db;
+    c.client_id = r.client;
+    c.status = slot.status;
+    c.batch = (uint32_t)slot.reqs.size();
+    c.arrival_ms = r.arrival_ms;
+    c.start_ms = slot.start_ms;
+    c.done_ms = t;
+    done.push_back(c);
+    if (slot.status == PIR_OK) {
+      ++completed;
+      lat.push_back(t - r.arrival_ms);
+    } else {
+      ++failed;
+    }
+    d.qpool.push_back(r.host_q);
+  }
+  slot.reqs.clear();
+  slot.busy = false;
+}
+
+void pir_engine::run() {
+  std::unique_lock<std::mutex> lk(mu);
+  std::vector<uint32_t> limbs;
+  bool waited_for_budget = false;
+  while (true) {
+    while (!incoming.empty()) {
+      Request r = incoming.front();
+      incoming.pop_front();
+      dbs[r.db]->queue.push_back(r);
+    }
+    bool progress = false, inflight = false, queued = false;
+    double next_arrival = 1e300;
+    const double t = now();
+    for (auto& dp : dbs) {
+      Db& d = *dp;
+      for (Slot& s : d.slots)
+        if (s.busy) {
+          if (hipEventQuery(s.ev) == hipSuccess) {
+            complete(d, s);
+            progress = true;
+          } else {
+            inflight = true;
+          }
+        }
+      for (Slot& s : d.slots) {
+        if (s.busy || d.queue.empty()) continue;
+        // requests that have arrived, in FIFO order
+        limbs.clear();
+        for (const Request& r : d.queue) {
+          if (r.arrival_ms > t) {
+            next_arrival = std::min(next_arrival, r.arrival_ms);
+            break;
+          }
+          limbs.push_back(r.L);
+        }
+        if (limbs.empty()) continue;
+        const uint64_t per = bytes_per_request(d, limbs[0]);
+        uint64_t avail = budget - std::min(budget, in_use) + s.bytes;
+        uint32_t cap = pir_engine_capacity(avail, per, max_batch);
+        if (cap == 0) {
+          // idle slots elsewhere can be released to make room
+          uint64_t idle = 0;
+          for (auto& other : dbs)
+            for (Slot& o : other->slots)
+              if (!o.busy && &o != &s) idle += o.bytes;
+          cap = pir_engine_capacity(avail + idle, per, max_batch);
+        }
+        const uint32_t n = pir_engine_plan(limbs.data(), (uint32_t)limbs.size(), cap);
+        if (n > 0 && launch(d, s, n)) {
+          progress = true;
+          inflight = true;
+          waited_for_budget = false;
+        } else {
+          queued = true;
+          if (!waited_for_budget) {
+            ++waits;
+            waited_for_budget = true;
+          }
+          if (!inflight) {
+            // nothing in flight anywhere can free memory: this request can never run
+            bool any_busy = false;
+            for (auto& other : dbs)
+              for (Slot& o : other->slots) any_busy |= o.busy;
+            if (!any_busy) {
+              Request r = d.queue.front();
+              d.queue.pop_front();
+              pir_completion c{r.id, r.db, r.client, PIR_ENOMEM, 0, r.arrival_ms, t, t};
+              done.push_back(c);
+              ++failed;
+              d.qpool.push_back(r.host_q);
+              progress = true;
+            }
+          }
+        }
+      }
+      if (!d.queue.empty()) queued = true;
+    }
+    if (progress) cv_done.notify_all();
+    if (stop && !inflight && !queued && incoming.empty()) break;
+    if (!progress) {
+      if (inflight) {
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        lk.lock();
+      } else if (next_arrival < 1e299) {
+        const double wait = std::max(0.0, next_arrival - now());
+        cv_sched.wait_for(lk, std::chrono::duration<double, std::milli>(wait));
+      } else {
+        cv_sched.wait_for(lk, std::chrono::milliseconds(50));
+      }
+    }
+  }
+}
+
+extern "C" {
+
+pir_status pir_engine_create(pir_engine** out, uint32_t max_batch, uint64_t hbm_budget_bytes) {
+  if (!out) return efail(PIR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_batch < 1 || max_batch > 1024) return efail(PIR_EINVAL, "max_batch must be in [1, 1024]");
+  auto e = std::make_unique<pir_engine>();
+  e->max_batch = max_batch;
+  if (hbm_budget_bytes == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return efail(PIR_EDEVICE, "hipMemGetInfo failed");
+    hbm_budget_bytes = fr > (1ull << 30) ? fr - (1ull << 30) : fr / 2;
+  }
+  e->budget = hbm_budget_bytes;
+  *out = e.release();
+  return PIR_OK;
+}
+
+pir_status pir_engine_add_db(pir_engine* e, pir_server* srv, uint32_t* db_index) {
+  if (!e || !srv || !db_index) return efail(PIR_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(e->mu);
+  if (e->started) return efail(PIR_EINVAL, "databases must be added before the first request");
+  auto d = std::make_unique<Db>();
+  d->srv = srv;
+  d->stream = zp::server_stream(srv);
+  d->device = zp::server_device(srv);
+  if (!d->stream) return efail(PIR_EINVAL, "the server needs its own (non-NULL) stream");
+  uint32_t rows = 0, cols = 0, n = 0;
+  uint64_t b = 0;
+  if (pir_shape(srv, &rows, &cols, &n, &b) != PIR_OK) return efail(PIR_EINVAL, "bad server");
+  d->rows = rows;
+  d->cols = cols;
+  *db_index = (uint32_t)e->dbs.size();
+  e->dbs.push_back(std::move(d));
+  return PIR_OK;
+}
+
+pir_status pir_engine_submit(pir_engine* e, uint32_t db, uint32_t client, const uint32_t* query,
+                             uint32_t* result, double arrival_ms, uint64_t* request_id) {
+  if (!e || !query || !result) return efail(PIR_EINVAL, "NULL argument");
+  uint32_t* qbuf = nullptr;
+  Request r;
+  {
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (db >= e->dbs.size()) return efail(PIR_EINVAL, "unknown database index");
+    Db& d = *e->dbs[db];
+    r.L = pir_client_limbs(d.srv, client);
+    if (r.L == 0) return efail(PIR_EINVAL, "unknown client id");
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof(attr));
+    const hipError_t pe = hipPointerGetAttributes(&attr, result);
+    if (pe != hipSuccess || attr.type == hipMemoryTypeUnregistered) {
+      (void)hipGetLastError();
+      return efail(PIR_EINVAL, "result must be pinned host memory (pir_host_alloc) or device memory");
+    }
+    if (!d.qpool.empty()) {
+      qbuf = d.qpool.back();
+      d.qpool.pop_back();
+    }
+  }
+  const uint32_t cols = e->dbs[db]->cols;
+  if (!qbuf && hipHostMalloc((void**)&qbuf, 4ull * cols, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return efail(PIR_ENOMEM, "pinned query buffer");
+  }
+  std::memcpy(qbuf, query, 4ull * cols);
+  std::lock_guard<std::mutex> lk(e->mu);
+  r.id = e->next_id++;
+  r.db = db;
+  r.client = client;
+  r.host_q = qbuf;
+  r.result = result;
+  const double t = e->now();
+  r.arrival_ms = arrival_ms < 0 ? t : arrival_ms;
+  e->incoming.push_back(r);
+  ++e->submitted;
+  if (request_id) *request_id = r.id;
+  if (!e->started) {
+    e->started = true;
+    e->th = std::thread([e] { e->run(); });
+  }
+  e->cv_sched.notify_one();
+  return PIR_OK;
+}
+
+pir_status pir_engine_poll(pir_engine* e, pir_completion* out, uint32_t max, uint32_t* count,
+                           int32_t timeout_ms) {
+  if (!e || !count || (max > 0 && !out)) return efail(PIR_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(e->mu);
+  if (e->done.empty() && timeout_ms != 0) {
+    if (timeout_ms < 0)
+      e->cv_done.wait(lk, [&] { return !e->done.empty(); });
+    else
+      e->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), [&] { return !e->done.empty(); });
+  }
+  uint32_t n = 0;
+  while (n < max && !e->done.empty()) {
+    out[n++] = e->done.front();
+    e->done.pop_front();
+  }
+  *count = n;
+  return PIR_OK;
+}
+
+pir_status pir_engine_drain(pir_engine* e, int32_t timeout_ms) {
+  if (!e) return efail(PIR_EINVAL, "NULL engine");
+  std::unique_lock<std::mutex> lk(e->mu);
+  auto finished = [&] { return e->completed + e->failed == e->submitted; };
+  if (timeout_ms < 0) {
+    e->cv_done.wait(lk, finished);
+    return PIR_OK;
+  }
+  return e->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), finished)
+             ? PIR_OK
+             : efail(PIR_EBUSY, "requests still pending");
+}
+
+pir_status pir_engine_stats_get(pir_engine* e, pir_engine_stats* st) {
+  if (!e || !st) return efail(PIR_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(e->mu);
+  st->submitted = e->submitted;
+  st->completed = e->completed;
+  st->failed = e->failed;
+  st->batches = e->batches;
+  st->admission_waits = e->waits;
+  st->device_bytes_peak = e->peak;
+  st->mean_batch = e->batches ? (double)e->batched_reqs / e->batches : 0.0;
+  std::vector<double> v = e->lat;
+  std::sort(v.begin(), v.end());
+  auto rank = [&](double q) {
+    if (v.empty()) return 0.0;
+    size_t k = (size_t)std::ceil(q * v.size());
+    k = std::min(v.size(), std::max<size_t>(k, 1));
+    return v[k - 1];
+  };
+  st->p50_ms = rank(0.50);
+  st->p99_ms = rank(0.99);
+  return PIR_OK;
+}
+
+double pir_engine_now_ms(pir_engine* e) { return e ? e->now() : 0.0; }
+
+void pir_engine_destroy(pir_engine* e) {
+  if (!e) return;
+  {
+    std::lock_guard<std::mutex> lk(e->mu);
+    e->stop = true;
+  }
+  e->cv_sched.notify_all();
+  if (e->th.joinable()) e->th.join();
+  for (auto& d : e->dbs) {
+    (void)hipSetDevice(d->device);
+    (void)hipStreamSynchronize(d->stream);
+    for (Slot& s : d->slots) {
+      if (s.dev) (void)hipFree(s.dev);
+      if (s.ev) (void)hipEventDestroy(s.ev);
+    }
+    for (uint32_t* q : d->qpool) (void)hipHostFree(q);
+    for (Request& r : d->queue) (void)hipHostFree(r.host_q);
+  }
+  for (Request& r : e->incoming) (void)hipHostFree(r.host_q);
+  delete e;
+}
+
+void* pir_host_alloc(uint64_t bytes) {
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes ? bytes : 1, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void pir_host_free(void* p) {
+  if (p) (void)hipHostFree(p);
+}
+
+}  // extern "C"

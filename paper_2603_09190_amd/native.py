@@ -63,6 +63,20 @@ _sig = {
     "pir_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_uint64)]),
     "pir_sync": (ctypes.c_int32, [ctypes.c_void_p]),
+    "pir_engine_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.c_uint64]),
+    "pir_engine_add_db": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
+    "pir_engine_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
+    "pir_engine_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_uint32), ctypes.c_int32]),
+    "pir_engine_drain": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "pir_engine_stats_get": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pir_engine_now_ms": (ctypes.c_double, [ctypes.c_void_p]),
+    "pir_engine_destroy": (None, [ctypes.c_void_p]),
+    "pir_engine_capacity": (ctypes.c_uint32, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]),
+    "pir_engine_plan": (ctypes.c_uint32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
+    "pir_host_alloc": (ctypes.c_void_p, [ctypes.c_uint64]),
+    "pir_host_free": (None, [ctypes.c_void_p]),
     "pir_strerror": (ctypes.c_char_p, [ctypes.c_int32]),
     "pir_last_error": (ctypes.c_char_p, []),
 }
@@ -215,3 +229,102 @@ class Server:
 
     def sync(self) -> None:
         _check(_lib.pir_sync(self._h), "pir_sync")
+
+
+# ----------------------------------------------------------------------------- serving engine
+
+class Completion(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("db", ctypes.c_uint32), ("client_id", ctypes.c_uint32),
+                ("status", ctypes.c_int32), ("batch", ctypes.c_uint32), ("arrival_ms", ctypes.c_double),
+                ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
+
+
+class EngineStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("admission_waits", ctypes.c_uint64),
+                ("device_bytes_peak", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_batch", ctypes.c_double)]
+
+
+class PinnedArray:
+    """A numpy view of pinned host memory from pir_host_alloc."""
+
+    def __init__(self, shape, dtype=np.uint32):
+        self.nbytes = int(np.prod(shape)) * np.dtype(dtype).itemsize
+        self._p = _lib.pir_host_alloc(self.nbytes)
+        if not self._p:
+            raise MemoryError("pir_host_alloc failed")
+        buf = (ctypes.c_char * self.nbytes).from_address(self._p)
+        self.array = np.frombuffer(buf, dtype=dtype).reshape(shape)
+
+    def close(self):
+        if getattr(self, "_p", None):
+            self.array = None
+            _lib.pir_host_free(self._p)
+            self._p = None
+
+    def __del__(self):
+        self.close()
+
+
+def engine_capacity(budget_free: int, bytes_per_request: int, max_batch: int) -> int:
+    return _lib.pir_engine_capacity(budget_free, bytes_per_request, max_batch)
+
+
+def engine_plan(queued_limbs, capacity: int) -> int:
+    a = np.ascontiguousarray(np.asarray(queued_limbs, dtype=np.uint32))
+    return _lib.pir_engine_plan(ctypes.c_void_p(a.ctypes.data), len(a), capacity)
+
+
+class Engine:
+    """Continuous-batching serving engine over several Servers (each with its own stream)."""
+
+    def __init__(self, max_batch: int = 32, hbm_budget: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib.pir_engine_create(ctypes.byref(h), max_batch, hbm_budget), "pir_engine_create")
+        self._h = h
+        self._servers = []
+
+    def add_db(self, server: Server) -> int:
+        idx = ctypes.c_uint32()
+        _check(_lib.pir_engine_add_db(self._h, server._h, ctypes.byref(idx)), "pir_engine_add_db")
+        self._servers.append(server)
+        return idx.value
+
+    def submit(self, db: int, client: int, query, result, arrival_ms: float = -1.0) -> int:
+        q = np.ascontiguousarray(np.asarray(query, dtype=np.uint32))
+        rid = ctypes.c_uint64()
+        _check(_lib.pir_engine_submit(self._h, db, client, ctypes.c_void_p(q.ctypes.data), _ptr(result)[0],
+                                      float(arrival_ms), ctypes.byref(rid)), "pir_engine_submit")
+        return rid.value
+
+    def poll(self, max_items: int = 256, timeout_ms: int = 0):
+        arr = (Completion * max_items)()
+        cnt = ctypes.c_uint32()
+        _check(_lib.pir_engine_poll(self._h, arr, max_items, ctypes.byref(cnt), timeout_ms), "pir_engine_poll")
+        return [{f: getattr(arr[i], f) for f, _ in Completion._fields_} for i in range(cnt.value)]
+
+    def drain(self, timeout_ms: int = -1) -> None:
+        _check(_lib.pir_engine_drain(self._h, timeout_ms), "pir_engine_drain")
+
+    def stats(self) -> dict:
+        st = EngineStats()
+        _check(_lib.pir_engine_stats_get(self._h, ctypes.byref(st)), "pir_engine_stats_get")
+        return {f: getattr(st, f) for f, _ in EngineStats._fields_}
+
+    def now_ms(self) -> float:
+        return _lib.pir_engine_now_ms(self._h)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.pir_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

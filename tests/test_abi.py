@@ -52,3 +52,20 @@ def test_setup_rejects_null_without_touching_the_gpu(lib):
     st = lib.pir_setup(ctypes.byref(h), 0, None, None, 4, 4, None, 4, 0)
     assert st == -1 and h.value is None
     assert b"non-NULL" in lib.pir_last_error()
+
+
+def test_engine_policy_capacity():
+    from paper_2603_09190_amd import native
+    assert native.engine_capacity(1000, 100, 32) == 10
+    assert native.engine_capacity(10**12, 100, 32) == 32
+    assert native.engine_capacity(99, 100, 32) == 0
+    assert native.engine_capacity(0, 1, 8) == 0
+
+
+def test_engine_policy_plan():
+    from paper_2603_09190_amd import native
+    assert native.engine_plan([64, 64, 64, 128, 64], 32) == 3   # stops at the first other limb count
+    assert native.engine_plan([64, 64, 64], 2) == 2             # capacity bound
+    assert native.engine_plan([128], 32) == 1
+    assert native.engine_plan([], 32) == 0
+    assert native.engine_plan([64, 64], 0) == 0

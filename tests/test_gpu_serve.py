@@ -1,0 +1,189 @@
+"""Serving engine on the GPU: every response is the same alone and in a concurrent mix
+(bit-exact, tolerance 0 on an integer path), under memory pressure too, and equals the
+oracle's compressed row."""
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import server
+from tests.gpu_util import client_arrays, limbs_rows_to_ints, log
+from tests.instances import make_instance
+
+pytestmark = pytest.mark.gpu
+
+# (rows, cols, client modulus sizes)
+DBS = [(300, 1000, (512, 512)), (512, 512, (512, 1024)), (1100, 768, (1024,))]
+N_LWE = 8
+
+
+@pytest.fixture(scope="module")
+def native():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_09190_amd import native as nat
+    return nat
+
+
+@pytest.fixture(scope="module")
+def setup(native):
+    import torch
+    streams, servers, infos = [], [], []
+    for i, (rows, cols, sizes) in enumerate(DBS):
+        inst = make_instance(cfg=920 + i, rows=rows, cols=cols, n=N_LWE, n_bits=sizes[0], encrypt_secret=False)
+        st = torch.cuda.Stream()
+        streams.append(st)
+        srv = native.Server(inst.D, inst.A, stream=st.cuda_stream)
+        clients = []
+        for k, nb in enumerate(sizes):
+            from tests.instances import make_client
+            cl = make_client(920 + i, k, inst.A, nb, encrypt_secret=False)
+            N_limbs, ck, L = client_arrays(cl, nb)
+            cid = srv.add_client(N_limbs, nb, ck)
+            srv.hint(cid)
+            clients.append((cid, cl, L))
+        servers.append(srv)
+        infos.append((inst, clients))
+    yield servers, infos, streams
+    for s in servers:
+        s.close()
+
+
+def _requests(infos, count, seed):
+    g = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(count):
+        db = int(g.integers(0, len(infos)))
+        inst, clients = infos[db]
+        ci = int(g.integers(0, len(clients)))
+        q = g.integers(0, 1 << 32, size=inst.cols, dtype=np.uint32)
+        reqs.append((db, ci, q))
+    return reqs
+
+
+def _run(native, servers, infos, reqs, max_batch=32, budget=0, together=True):
+    outs = []
+    with native.Engine(max_batch=max_batch, hbm_budget=budget) as eng:
+        for s in servers:
+            eng.add_db(s)
+        bufs = []
+        for db, ci, q in reqs:
+            inst, clients = infos[db]
+            cid, cl, L = clients[ci]
+            buf = native.PinnedArray((inst.rows, L))
+            bufs.append(buf)
+        comps = []
+        for (db, ci, q), buf in zip(reqs, bufs):
+            cid = infos[db][1][ci][0]
+            eng.submit(db, cid, q, buf.array)
+            if not together:
+                eng.drain()
+        eng.drain()
+        comps = eng.poll(max_items=len(reqs) + 8)
+        stats = eng.stats()
+        outs = [b.array.copy() for b in bufs]
+        for b in bufs:
+            b.close()
+    return outs, comps, stats
+
+
+def test_alone_equals_mix(native, setup):
+    servers, infos, _ = setup
+    reqs = _requests(infos, 48, seed=1)
+    log("serve: alone")
+    alone, comps_a, _ = _run(native, servers, infos, reqs, together=False)
+    log("serve: mix")
+    mix, comps_m, stats = _run(native, servers, infos, reqs, together=True)
+    assert len(comps_m) == len(reqs) and all(c["status"] == 0 for c in comps_m)
+    assert all(c["batch"] == 1 for c in comps_a)
+    assert stats["mean_batch"] > 1.0, "the mix never formed a batch"
+    for a, m in zip(alone, mix):
+        assert np.array_equal(a, m)
+    # the oracle on three requests, every row
+    for idx in (0, 1, 2):
+        db, ci, q = reqs[idx]
+        inst, clients = infos[db]
+        cid, cl, L = clients[ci]
+        E = server.exponents(server.global_hint(inst.D, inst.A))
+        K = server.client_hint(cl.ck, E, cl.N)
+        b = server.answer(inst.D, q)
+        assert limbs_rows_to_ints(mix[idx]) == server.compress(K, b, cl.N)
+    assert stats["p99_ms"] >= stats["p50_ms"] > 0
+
+
+def test_memory_pressure_still_exact(native, setup):
+    servers, infos, _ = setup
+    reqs = _requests(infos, 24, seed=2)
+    free, _, _ = _run(native, servers, infos, reqs)
+    # budget for one request of the largest database: every batch has one request
+    rows, cols, sizes = DBS[2]
+    one = 4 * cols + 4 * rows + 4 * rows * 2 * ((max(sizes) + 31) // 32)
+    tight, comps, stats = _run(native, servers, infos, reqs, budget=one + 1024)
+    assert all(c["status"] == 0 for c in comps)
+    assert all(c["batch"] == 1 for c in comps)
+    for a, b in zip(free, tight):
+        assert np.array_equal(a, b)
+
+
+def test_arrival_times_are_respected(native, setup):
+    servers, infos, _ = setup
+    inst, clients = infos[0]
+    cid, cl, L = clients[0]
+    with native.Engine() as eng:
+        for s in servers:
+            eng.add_db(s)
+        bufs = [native.PinnedArray((inst.rows, L)) for _ in range(5)]
+        t0 = eng.now_ms()
+        for k, b in enumerate(bufs):
+            eng.submit(0, cid, np.full(inst.cols, k, np.uint32), b.array, arrival_ms=t0 + 20.0 + 10.0 * k)
+        eng.drain()
+        comps = sorted(eng.poll(16), key=lambda c: c["request_id"])
+        for k, c in enumerate(comps):
+            assert c["start_ms"] >= t0 + 20.0 + 10.0 * k - 1e-6
+            assert c["done_ms"] >= c["start_ms"]
+        for b in bufs:
+            b.close()
+
+
+def test_engine_errors(native, setup):
+    servers, infos, _ = setup
+    inst, clients = infos[0]
+    cid, cl, L = clients[0]
+    with native.Engine() as eng:
+        eng.add_db(servers[0])
+        buf = native.PinnedArray((inst.rows, L))
+        with pytest.raises(native.ZipPIRError):
+            eng.submit(5, cid, np.zeros(inst.cols, np.uint32), buf.array)           # unknown database
+        with pytest.raises(native.ZipPIRError):
+            eng.submit(0, 999, np.zeros(inst.cols, np.uint32), buf.array)           # unknown client
+        with pytest.raises(native.ZipPIRError):
+            eng.submit(0, cid, np.zeros(inst.cols, np.uint32), np.zeros((inst.rows, L), np.uint32))  # pageable
+        buf.close()
+    # a client whose hint is stale completes with PIR_ESTALE and the engine keeps serving
+    srv = servers[1]
+    inst1, clients1 = infos[1]
+    cid1, cl1, L1 = clients1[0]
+    row = np.array([3], np.uint32)
+    srv_new = np.random.default_rng(3).integers(0, 256, (1, inst1.cols), dtype=np.uint8)
+    srv.update_rows(row, srv_new)   # no engine holds the server during the update
+    with native.Engine() as eng:
+        eng.add_db(srv)
+        b1 = native.PinnedArray((inst1.rows, L1))
+        eng.submit(0, cid1, np.zeros(inst1.cols, np.uint32), b1.array)
+        eng.drain()
+        c = eng.poll(4)
+        assert c[0]["status"] == native.PIR_ESTALE
+        b1.close()
+    srv.hint(cid1, rows=row)
+    inst1.D[3] = srv_new[0]
+    with native.Engine() as eng:
+        eng.add_db(srv)
+        b1 = native.PinnedArray((inst1.rows, L1))
+        q = np.arange(inst1.cols, dtype=np.uint32)
+        eng.submit(0, cid1, q, b1.array)
+        eng.drain()
+        assert eng.poll(4)[0]["status"] == 0
+        E = server.exponents(server.global_hint(inst1.D, inst1.A))
+        K = server.client_hint(cl1.ck, E, cl1.N)
+        assert limbs_rows_to_ints(b1.array) == server.compress(K, server.answer(inst1.D, q), cl1.N)
+        b1.close()
