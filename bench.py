@@ -33,6 +33,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA
 
+# HBM bytes per launch of the matvec on the 1 GiB database, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (calibrated on a plain 1 GiB device copy), keyed by the SHA-256 of the matvec
+# source they were taken on: a changed kernel reports null until the counters are re-taken.
+MATVEC_TRAFFIC = {}
+
+
+def matvec_source_hash() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2603_09190_amd", "csrc", "matvec.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -69,6 +80,15 @@ def main() -> int:
     ap.add_argument("--nbits", type=int, default=2048)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--cpu-rows", type=int, default=32768, help="rows in the CPU-oracle sample (0: skip)")
+    ap.add_argument("--workload", choices=["answer", "serve"], default="answer",
+                    help="answer: 1 GiB database, one query per step (default); "
+                         "serve: four resident databases under Poisson arrivals")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals")
+    ap.add_argument("--sides", type=str, default="16384,32768,65536,131072",
+                    help="serve: database sides (square uint8 matrices)")
+    ap.add_argument("--mix", type=str, default="40,30,20,10", help="serve: request share per database")
+    ap.add_argument("--clients", type=int, default=2, help="serve: clients (resident hints) per database")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -84,6 +104,8 @@ def main() -> int:
     from paper_2603_09190_amd import native
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "serve":
+        return serve(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -190,17 +212,28 @@ def main() -> int:
     mv32_ms = (time.perf_counter() - t0) * 1e3 / max(2, reps // 4)
     same = bool(torch.equal(Bb, Bm))
 
+    # dominant kernel's own duration: 8 queries' matvecs back to back between two events
+    Q8 = Qt[:8].contiguous()
+    B8 = torch.zeros((8, rows), dtype=torch.int32, device=dev)
+    srv.answer(Q8, B8, native.PATH_MATVEC)
+    srv.profile(True)
+    for _ in range(max(2, args.steps // 8)):
+        srv.answer(Q8, B8, native.PATH_MATVEC)
+    mvk_ms, mvk_n = srv.profile_read("matvec")
+    srv.profile(False)
+
     # roofline of the dominant kernel of the step (the matvec): algorithmic bytes per launch
-    mv_avg_ms = mv_ms / max(1, mv_n)
+    mv_avg_ms = mvk_ms / max(1, mvk_n)
     cp_avg_ms = cp_ms / max(1, cp_n)
     mv_bytes = db_bytes + 4 * cols + 4 * rows
     achieved = mv_bytes / (mv_avg_ms * 1e-3) / 1e9
     gm_avg_ms = gm_ms / max(1, gm_n)
     mfma_ops = 2.0 * 4 * rows * cols * bsz
+    traffic = MATVEC_TRAFFIC.get(matvec_source_hash()) if (rows, cols) == (32768, 32768) else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "matvec_kernel<8>", "kernel_avg_us": round(mv_avg_ms * 1e3, 2),
-            "bytes_per_launch": mv_bytes}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "matvec_seg_kernel<2>", "kernel_avg_us": round(mv_avg_ms * 1e3, 2),
+            "bytes_per_launch": mv_bytes, "step_matvec_event_us": round(mv_ms / max(1, mv_n) * 1e3, 2)}
 
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -251,6 +284,139 @@ def main() -> int:
         "hint_kernel_ms": round(hintk_ms, 1),
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def serve(args) -> int:
+    """Serving mix: resident databases, Poisson arrivals, continuous batching, p50/p99."""
+    import torch
+    import workload as wl
+    from paper_2603_09190_amd import native
+
+    dev = torch.device("cuda:0")
+    sides = [int(x) for x in args.sides.split(",")]
+    mix = [float(x) for x in args.mix.split(",")]
+    assert len(mix) == len(sides)
+    n, nbits = args.n, args.nbits
+    h = (nbits + 31) // 32
+    L = 2 * h
+    servers, streams, clients = [], [], []
+    for i, side in enumerate(sides):
+        log(f"serve: database {i}: {side}x{side} ({side * side / 2**30:.2f} GiB)")
+        D = wl.database(30 + i, side, side, threads=16)
+        A = wl.lwe_matrix(30 + i, side, n)
+        st = torch.cuda.Stream(device=dev)
+        Dt = torch.from_numpy(D)
+        del D
+        srv = native.Server(Dt.to(dev), torch.from_numpy(A.view(np.int32)).to(dev), stream=st.cuda_stream)
+        del Dt, A
+        torch.cuda.empty_cache()
+        ids = []
+        for c in range(args.clients):
+            pr = wl.paillier_primes(30 + i, c, nbits)
+            N = pr.P * pr.Q
+            ck = wl.ints_to_limbs(wl.uniform_ciphertexts(30 + i, c, n, N), L)
+            cid = srv.add_client(wl.int_to_limbs(N, h), nbits, ck)
+            t0 = time.perf_counter()
+            srv.hint(cid)
+            log(f"  client {c}: hint for {side} rows in {time.perf_counter() - t0:.2f} s")
+            ids.append(cid)
+        servers.append(srv)
+        streams.append(st)
+        clients.append(ids)
+
+    arr = wl.arrivals(40, args.rate, args.duration)
+    which = wl.db_choices(40, len(arr), mix)
+    g = wl.rng(40, "query")
+    nreq = len(arr)
+    log(f"serve: {nreq} requests over {args.duration:.0f} s at {args.rate:.0f}/s, mix {args.mix}")
+    ring = 16
+    rings = [[native.PinnedArray((side, L)) for _ in range(ring)] for side in sides]
+    slot_owner = [[None] * ring for _ in sides]
+    queries = [g.integers(0, 1 << 32, size=(8, side), dtype=np.uint32) for side in sides]
+    comps = {}
+    eng = native.Engine(max_batch=args.batch)
+    for srv in servers:
+        eng.add_db(srv)
+    # warm the paths (autotuned contraction shapes, first launches) before the clock starts
+    for i, side in enumerate(sides):
+        for b in (1, 2):
+            for k in range(b):
+                eng.submit(i, clients[i][0], queries[i][k], rings[i][k].array)
+            eng.drain()
+    eng.poll(64)
+    t_start = eng.now_ms() + 200.0
+    counters = [0] * len(sides)
+
+    def collect(timeout_ms=0):
+        for c in eng.poll(1024, timeout_ms):
+            comps[c["request_id"]] = c
+
+    rid_of = []
+    for k in range(nreq):
+        i = int(which[k])
+        slot = counters[i] % ring
+        counters[i] += 1
+        prev = slot_owner[i][slot]
+        while prev is not None and prev not in comps:
+            collect(50)
+        cid = clients[i][k % len(clients[i])]
+        rid = eng.submit(i, cid, queries[i][k % 8], rings[i][slot].array, arrival_ms=t_start + 1000.0 * arr[k])
+        slot_owner[i][slot] = rid
+        rid_of.append((rid, i))
+        if k % 500 == 0:
+            log(f"  submitted {k}/{nreq}")
+    eng.drain()
+    collect(0)
+    st = eng.stats()
+    eng.close()
+    lat = np.array([comps[r]["done_ms"] - comps[r]["arrival_ms"] for r, _ in rid_of])
+    dbi = np.array([i for _, i in rid_of])
+    ok = all(comps[r]["status"] == 0 for r, _ in rid_of)
+    first = min(comps[r]["arrival_ms"] for r, _ in rid_of)
+    last = max(comps[r]["done_ms"] for r, _ in rid_of)
+    wall_s = (last - first) / 1e3
+    db_bytes = float(sum(sides[i] ** 2 for i in dbi))
+    per_db = {}
+    for i, side in enumerate(sides):
+        li = lat[dbi == i]
+        if len(li):
+            per_db[f"{side}x{side}"] = {"requests": int(len(li)), "p50_ms": round(percentile(li, 50), 3),
+                                        "p99_ms": round(percentile(li, 99), 3)}
+    for r in rings:
+        for b in r:
+            b.close()
+    for srv in servers:
+        srv.close()
+    out = {
+        "metric": "online answer DB GB/s (1 GB DB, batch 1 vs 32) + p50/p99 latency",
+        "value": round(db_bytes / wall_s / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": nreq,
+        "warmup": 3 * len(sides),
+        "ms_per_step": round(wall_s * 1e3 / nreq, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"serving mix: {len(sides)} resident databases "
+                               f"({', '.join(f'{s}x{s}' for s in sides)} uint8), Poisson arrivals "
+                               f"{args.rate:.0f}/s split {args.mix}, {args.clients} clients per database "
+                               f"with resident hints, N {nbits}-bit, answer + Paillier combine per request",
+                   "rate_qps": args.rate, "duration_s": args.duration, "max_batch": args.batch},
+        "p50_ms": round(percentile(lat, 50), 3),
+        "p99_ms": round(percentile(lat, 99), 3),
+        "all_ok": ok,
+        "per_db": per_db,
+        "requests_per_s": round(nreq / wall_s, 2),
+        "mean_batch": round(st["mean_batch"], 3),
+        "batches": st["batches"],
+        "admission_waits": st["admission_waits"],
+        "engine_device_bytes_peak": st["device_bytes_peak"],
     }
     print(json.dumps(out), flush=True)
     return 0

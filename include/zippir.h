@@ -158,7 +158,7 @@ pir_status pir_shape(pir_server *srv, uint32_t *rows, uint32_t *cols, uint32_t *
 #define PIR_KERNEL_COMPRESS 2  /* per-row Paillier combine                              */
 #define PIR_KERNEL_HINT     3  /* per-row fixed-base multi-exponentiation               */
 #define PIR_KERNEL_TABLE    4  /* fixed-base table build                                */
-#define PIR_KERNEL_KAPPA    5  /* K mod N precompute for the combine                    */
+#define PIR_KERNEL_KEY      5  /* per-row combine key N (K mod N), computed with the hint */
 #define PIR_KERNEL_COUNT    6
 pir_status pir_profile(pir_server *srv, int32_t enable);
 pir_status pir_profile_read(pir_server *srv, int32_t kernel, double *total_ms, uint64_t *launches);

@@ -10,7 +10,8 @@
 // the multiplications gives the same residue.
 //
 // One wavefront computes one row; every value stays in Montgomery form (x R mod N^2) until
-// the final conversion.
+// the final conversion, which stores K'_j = K_j 2^32 mod N^2 (the form the online combine
+// consumes; pir_get_client_hint converts back to K_j).
 #include "internal.h"
 #include "wavenum.h"
 
@@ -68,19 +69,22 @@ __global__ __launch_bounds__(256) void hint_rows_kernel(ClientDev cd, const uint
       }
     }
   }
-  WNum<P> one;
-  wn_zero(one);
-  if (lane_id() == 0) one.v[0] = 1;
-  mont_mul(acc, acc, one, M, cd.m2prime);  // leave Montgomery form
+  // leave Montgomery form scaled by 2^32: acc * 2^32 * R^{-1} = K_j * 2^32 mod N^2
+  WNum<P> two32;
+  wn_zero(two32);
+  if (lane_id() == 1 / P) two32.v[1 % P] = 1;
+  mont_mul(acc, acc, two32, M, cd.m2prime);
   wn_store_n(K + (size_t)row * cd.L, acc, cd.L);
 }
 
-// kappa_j = K_j * 2^32 mod N, the per-row constant the online combine needs
-// (K_j mod N, pre-scaled so that a single Montgomery step yields K_j * b mod N).
-template <int PN>
-__global__ __launch_bounds__(256) void kappa_kernel(ClientDev cd, const uint32_t* __restrict__ K,
-                                                    const uint32_t* __restrict__ rowlist,
-                                                    int nrows, uint32_t* __restrict__ kappa) {
+// The per-row key of the online combine: M'_j = N * (K'_j mod N), with K'_j = K_j 2^32 mod N^2.
+// It is a plain product below N^2 and satisfies M'_j = N K_j 2^32 (mod N^2), so that
+// K_j (1 + b N) 2^32 = K'_j + b M'_j (mod N^2).
+template <int P, int PN>
+__global__ __launch_bounds__(256) void combine_key_kernel(ClientDev cd,
+                                                          const uint32_t* __restrict__ Kp,
+                                                          const uint32_t* __restrict__ rowlist,
+                                                          int nrows, uint32_t* __restrict__ Mp) {
   constexpr int SN = 64 * PN;
   const int widx = wave_index();
   if (widx >= nrows) return;
@@ -89,12 +93,12 @@ __global__ __launch_bounds__(256) void kappa_kernel(ClientDev cd, const uint32_t
   wn_load(Nn, cd.Nn);
   wn_load(C1, cd.C1);
   wn_load(C2, cd.C2);
-  const uint32_t* kr = K + (size_t)row * cd.L;
-  // K = lo + hi * R_N with lo < R_N and hi < N (since K < N^2 and N < R_N)
+  const uint32_t* kr = Kp + (size_t)row * cd.L;
+  // K' = lo + hi R_N with lo < R_N and hi < N (K' < N^2 and N < R_N)
   wn_load_n(lo, kr, cd.L < SN ? cd.L : SN);
   if (cd.L > SN) wn_load_n(hi, kr + SN, cd.L - SN); else wn_zero(hi);
-  mont_mul(x, lo, C1, Nn, cd.nprime);  // lo * 2^32 mod N
-  mont_mul(y, hi, C2, Nn, cd.nprime);  // hi * R_N * 2^32 mod N
+  mont_mul(x, lo, C1, Nn, cd.nprime);  // lo mod N          (C1 = R_N mod N)
+  mont_mul(y, hi, C2, Nn, cd.nprime);  // hi R_N mod N      (C2 = R_N^2 mod N)
   uint32_t carry = 0;
 #pragma unroll
   for (int j = 0; j < PN; ++j) {
@@ -103,8 +107,46 @@ __global__ __launch_bounds__(256) void kappa_kernel(ClientDev cd, const uint32_t
     carry = (uint32_t)(s >> 32);
   }
   const uint64_t ovf = wn_resolve(x, (uint64_t)carry);
-  wn_cond_sub(x, ovf, Nn);
-  wn_store_n(kappa + (size_t)row * cd.h, x, cd.h);
+  wn_cond_sub(x, ovf, Nn);  // x = K' mod N
+  // M' = N * x: h broadcast limbs of x times N shifted up one limb per step
+  WNum<P> acc, Nsh;
+  wn_zero(acc);
+  wn_load(Nsh, cd.NP);
+  uint64_t pend = 0;
+  for (int i = 0; i < cd.h; ++i) {
+    const uint32_t xi = wn_limb(x, i);
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const uint64_t t = (uint64_t)xi * Nsh.v[j] + acc.v[j] + c;
+      acc.v[j] = (uint32_t)t;
+      c = (uint32_t)(t >> 32);
+    }
+    pend += c;
+    const uint32_t in = from_prev_lane(Nsh.v[P - 1]);
+#pragma unroll
+    for (int j = P - 1; j > 0; --j) Nsh.v[j] = Nsh.v[j - 1];
+    Nsh.v[0] = in;
+  }
+  (void)wn_resolve(acc, pend);  // N x < N^2 fits in L limbs
+  wn_store_n(Mp + (size_t)row * cd.L, acc, cd.L);
+}
+
+// K_j = K'_j 2^{-32} mod N^2 (one Montgomery reduction step), for hint export.
+template <int P>
+__global__ __launch_bounds__(256) void unscale_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
+                                                      int row0, int nrows, uint32_t* __restrict__ K) {
+  const int widx = wave_index();
+  if (widx >= nrows) return;
+  WNum<P> M, t, z;
+  wn_load(M, cd.N2);
+  wn_load_n(t, Kp + (size_t)(row0 + widx) * cd.L, cd.L);
+  wn_zero(z);
+  uint64_t c = 0;
+  mont_step(t, c, 0u, z, M, cd.m2prime);
+  const uint64_t ovf = wn_resolve(t, c);
+  wn_cond_sub(t, ovf, M);
+  wn_store_n(K + (size_t)widx * cd.L, t, cd.L);
 }
 
 void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, uint32_t* table,
@@ -131,13 +173,27 @@ void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint3
   }
 }
 
-void launch_kappa(const ClientDev& cd, const uint32_t* K, const uint32_t* rowlist, int nrows,
-                  uint32_t* kappa, hipStream_t s) {
+void launch_combine_key(const ClientDev& cd, const uint32_t* Kp, const uint32_t* rowlist,
+                        int nrows, uint32_t* Mp, hipStream_t s) {
   if (nrows <= 0) return;
   const int blocks = (nrows + 3) / 4;
-  switch (cd.PN) {
-    case 1: kappa_kernel<1><<<blocks, 256, 0, s>>>(cd, K, rowlist, nrows, kappa); break;
-    case 2: kappa_kernel<2><<<blocks, 256, 0, s>>>(cd, K, rowlist, nrows, kappa); break;
+  switch (cd.P) {
+    case 1: combine_key_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp); break;
+    case 2: combine_key_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp); break;
+    case 3: combine_key_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp); break;
+    case 4: combine_key_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp); break;
+  }
+}
+
+void launch_unscale(const ClientDev& cd, const uint32_t* Kp, int row0, int nrows, uint32_t* K,
+                    hipStream_t s) {
+  if (nrows <= 0) return;
+  const int blocks = (nrows + 3) / 4;
+  switch (cd.P) {
+    case 1: unscale_kernel<1><<<blocks, 256, 0, s>>>(cd, Kp, row0, nrows, K); break;
+    case 2: unscale_kernel<2><<<blocks, 256, 0, s>>>(cd, Kp, row0, nrows, K); break;
+    case 3: unscale_kernel<3><<<blocks, 256, 0, s>>>(cd, Kp, row0, nrows, K); break;
+    case 4: unscale_kernel<4><<<blocks, 256, 0, s>>>(cd, Kp, row0, nrows, K); break;
   }
 }
 

@@ -14,8 +14,8 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Per-client constants, all device pointers into one allocation.
 //   N2  S limbs   N^2 (zero padded)          R1  S limbs   R mod N^2, R = 2^(32 S)
 //   RR  S limbs   R^2 mod N^2                NP  S limbs   N (zero padded, S-limb layout)
-//   Nn  SN limbs  N                          C1  SN limbs  R_N * 2^32 mod N, R_N = 2^(32 SN)
-//   C2  SN limbs  R_N^2 * 2^32 mod N
+//   Nn  SN limbs  N                          C1  SN limbs  R_N mod N, R_N = 2^(32 SN)
+//   C2  SN limbs  R_N^2 mod N
 struct ClientDev {
   const uint32_t* N2;
   const uint32_t* R1;
@@ -39,9 +39,10 @@ constexpr int kDigits = (1 << kWindowBits) - 1;
 
 // ---- matvec.hip
 // planes: 4 consecutive byte arrays of `pitch` bytes, plane b holding byte b of every
-// query entry (zero beyond cols).  One query.
-void launch_pack_planes_u8(const uint32_t* q, int cols, int pitch, uint8_t* planes,
-                           hipStream_t s);
+// query entry (zero beyond cols).  One query.  Also clears b (rows entries), which
+// launch_matvec accumulates into.
+void launch_pack_planes_u8(const uint32_t* q, int cols, int pitch, uint8_t* planes, uint32_t* b,
+                           int rows, hipStream_t s);
 void launch_matvec(const uint8_t* D, int rows, int pitch, const uint8_t* planes, uint32_t* b,
                    hipStream_t s);
 
@@ -80,10 +81,15 @@ void launch_scatter_rows_u32(const uint32_t* src, int width, const uint32_t* row
 void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, uint32_t* table,
                         hipStream_t s);
 // Rows processed: rowlist[i] for i < nrows (rowlist may be null: rows 0..nrows-1).
+// Writes K'_j = K_j 2^32 mod N^2 (rows x L limbs).
 void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
-                      int nrows, const uint32_t* table, uint32_t* K, hipStream_t s);
-void launch_kappa(const ClientDev& cd, const uint32_t* K, const uint32_t* rowlist, int nrows,
-                  uint32_t* kappa, hipStream_t s);
+                      int nrows, const uint32_t* table, uint32_t* Kp, hipStream_t s);
+// M'_j = N (K'_j mod N) (rows x L limbs), the combine key.
+void launch_combine_key(const ClientDev& cd, const uint32_t* Kp, const uint32_t* rowlist,
+                        int nrows, uint32_t* Mp, hipStream_t s);
+// K_j = K'_j 2^{-32} mod N^2 for rows [row0, row0+nrows) into K (nrows x L).
+void launch_unscale(const ClientDev& cd, const uint32_t* Kp, int row0, int nrows, uint32_t* K,
+                    hipStream_t s);
 
 // ---- runtime.cpp accessors used by the serving engine
 hipStream_t server_stream(pir_server* s);
@@ -91,7 +97,7 @@ void set_error(const char* msg);  // sets the calling thread's pir_last_error() 
 int server_device(pir_server* s);
 
 // ---- compress.hip
-void launch_compress(const ClientDev& cd, const uint32_t* K, const uint32_t* kappa,
+void launch_compress(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Mp,
                      const uint32_t* b, int rows, uint32_t* C, hipStream_t s);
 
 }  // namespace zp

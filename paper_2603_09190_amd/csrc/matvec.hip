@@ -9,10 +9,13 @@
 
 namespace zp {
 
+// Packs the query's byte planes and clears the answer vector (the matvec adds into it).
 __global__ __launch_bounds__(256) void pack_planes_u8_kernel(const uint32_t* __restrict__ q,
                                                              int cols, int pitch,
-                                                             uint8_t* __restrict__ planes) {
+                                                             uint8_t* __restrict__ planes,
+                                                             uint32_t* __restrict__ b, int rows) {
   const int i4 = blockIdx.x * blockDim.x + threadIdx.x;  // one thread per 4 columns
+  for (int r = i4; r < rows; r += gridDim.x * blockDim.x) b[r] = 0u;
   if (4 * i4 >= pitch) return;
   uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -26,10 +29,10 @@ __global__ __launch_bounds__(256) void pack_planes_u8_kernel(const uint32_t* __r
   for (int b = 0; b < 4; ++b) reinterpret_cast<uint32_t*>(planes + (size_t)b * pitch)[i4] = w[b];
 }
 
-void launch_pack_planes_u8(const uint32_t* q, int cols, int pitch, uint8_t* planes,
-                           hipStream_t s) {
+void launch_pack_planes_u8(const uint32_t* q, int cols, int pitch, uint8_t* planes, uint32_t* b,
+                           int rows, hipStream_t s) {
   const int n4 = pitch / 4;
-  pack_planes_u8_kernel<<<(n4 + 255) / 256, 256, 0, s>>>(q, cols, pitch, planes);
+  pack_planes_u8_kernel<<<(n4 + 255) / 256, 256, 0, s>>>(q, cols, pitch, planes, b, rows);
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -99,17 +102,11 @@ __global__ __launch_bounds__(256) void matvec_seg_kernel(const uint8_t* __restri
   }
 }
 
-__global__ void zero_u32_kernel(uint32_t* __restrict__ p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
 constexpr int kSegRowsPerWave = 32;
 
 void launch_matvec(const uint8_t* D, int rows, int pitch, const uint8_t* planes, uint32_t* b,
                    hipStream_t s) {
-  // b accumulates one atomic partial per column segment: clear it first
-  zero_u32_kernel<<<(rows + 255) / 256, 256, 0, s>>>(b, rows);
+  // b accumulates one atomic partial per column segment; launch_pack_planes_u8 cleared it
   dim3 grid((rows + 4 * kSegRowsPerWave - 1) / (4 * kSegRowsPerWave), (pitch + kSegCols - 1) / kSegCols);
   matvec_seg_kernel<2><<<grid, 256, 0, s>>>(D, rows, pitch, planes, b, kSegRowsPerWave);
 }

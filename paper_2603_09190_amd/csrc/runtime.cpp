@@ -134,10 +134,10 @@ struct ClientState {
   Big N;
   uint32_t* ck = nullptr;      // n x L
   uint32_t* consts = nullptr;  // N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each)
-  uint32_t* K = nullptr;       // rows x L
-  uint32_t* kappa = nullptr;   // rows x h
+  uint32_t* Kp = nullptr;      // rows x L: K_j 2^32 mod N^2
+  uint32_t* Mp = nullptr;      // rows x L: N (K'_j mod N), the combine key
   uint32_t m2prime = 0, nprime = 0;
-  std::vector<uint8_t> valid;  // per row: K and kappa up to date
+  std::vector<uint8_t> valid;  // per row: K' and M' up to date
   int64_t stale = 0;
 
   zp::ClientDev dev() const {
@@ -177,7 +177,11 @@ struct pir_server {
   uint64_t bytes = 0;
   // per-kernel event timing (pir_profile)
   bool prof = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[PIR_KERNEL_COUNT];
+  struct ProfRecord {
+    hipEvent_t begin, end;
+    int launches;
+  };
+  std::vector<ProfRecord> prof_ev[PIR_KERNEL_COUNT];
   // growable scratch
   DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c;
 
@@ -237,8 +241,9 @@ pir_status check_flags(uint32_t flags) {
 struct ProfScope {
   pir_server* s;
   int k;
+  int launches;
   hipEvent_t b = nullptr, e = nullptr;
-  ProfScope(pir_server* s_, int k_) : s(s_), k(k_) {
+  ProfScope(pir_server* s_, int k_, int launches_ = 1) : s(s_), k(k_), launches(launches_) {
     if (!s->prof) return;
     if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&e) != hipSuccess) {
       b = e = nullptr;
@@ -249,15 +254,15 @@ struct ProfScope {
   ~ProfScope() {
     if (!b) return;
     (void)hipEventRecord(e, s->stream);
-    s->prof_ev[k].emplace_back(b, e);
+    s->prof_ev[k].push_back(pir_server::ProfRecord{b, e, launches});
   }
 };
 
 void prof_clear(pir_server* s) {
   for (auto& v : s->prof_ev) {
     for (auto& pr : v) {
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
+      (void)hipEventDestroy(pr.begin);
+      (void)hipEventDestroy(pr.end);
     }
     v.clear();
   }
@@ -517,8 +522,8 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
   const Big Nn = big_resize(c->N, c->SN);
   const Big R1 = big_pow2_mod(32ull * c->S, big_resize(N2, c->L));
   const Big RR = big_pow2_mod(64ull * c->S, big_resize(N2, c->L));
-  const Big C1 = big_pow2_mod(32ull * c->SN + 32, c->N);
-  const Big C2 = big_pow2_mod(64ull * c->SN + 32, c->N);
+  const Big C1 = big_pow2_mod(32ull * c->SN, c->N);
+  const Big C2 = big_pow2_mod(64ull * c->SN, c->N);
   c->m2prime = neg_inv32(N2[0]);
   c->nprime = neg_inv32(c->N[0]);
   std::vector<uint32_t> host(4 * (size_t)c->S + 3 * (size_t)c->SN, 0u);
@@ -555,8 +560,8 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
       }
     }
   }
-  ZP_TRY(s->alloc((void**)&c->K, (size_t)s->rows * c->L * sizeof(uint32_t)));
-  ZP_TRY(s->alloc((void**)&c->kappa, (size_t)s->rows * c->h * sizeof(uint32_t)));
+  ZP_TRY(s->alloc((void**)&c->Kp, (size_t)s->rows * c->L * sizeof(uint32_t)));
+  ZP_TRY(s->alloc((void**)&c->Mp, (size_t)s->rows * c->L * sizeof(uint32_t)));
   c->valid.assign(s->rows, 0);
   c->stale = s->rows;
   c->id = s->next_id++;
@@ -574,8 +579,8 @@ pir_status pir_remove_client(pir_server* s, uint32_t id) {
   ZP_HIP(hipStreamSynchronize(s->stream));
   s->release(c->ck);
   s->release(c->consts);
-  s->release(c->K);
-  s->release(c->kappa);
+  s->release(c->Kp);
+  s->release(c->Mp);
   s->clients.erase(id);
   return PIR_OK;
 }
@@ -617,11 +622,11 @@ pir_status pir_hint(pir_server* s, uint32_t id, const uint32_t* rows, uint32_t n
   }
   {
     ProfScope ps(s, PIR_KERNEL_HINT);
-    zp::launch_hint_rows(cd, s->H, (int)s->n, drows, m, table, c->K, st);
+    zp::launch_hint_rows(cd, s->H, (int)s->n, drows, m, table, c->Kp, st);
   }
   {
-    ProfScope ps(s, PIR_KERNEL_KAPPA);
-    zp::launch_kappa(cd, c->K, drows, m, c->kappa, st);
+    ProfScope ps(s, PIR_KERNEL_KEY);
+    zp::launch_combine_key(cd, c->Kp, drows, m, c->Mp, st);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -708,14 +713,17 @@ static pir_status answer_impl(pir_server* s, const uint32_t* Q, uint32_t batch, 
   }
   if (path == PIR_PATH_AUTO) path = batch == 1 ? PIR_PATH_MATVEC : PIR_PATH_MFMA;
   if (path == PIR_PATH_MATVEC) {
-    ZP_TRY(s->scratch(s->s_planes, 4 * (size_t)s->pitch));
-    for (uint32_t c = 0; c < batch; ++c) {
+    // pack every query first so the matvecs run back to back
+    ZP_TRY(s->scratch(s->s_planes, (size_t)batch * 4 * s->pitch));
+    uint8_t* planes = (uint8_t*)s->s_planes.p;
+    for (uint32_t c = 0; c < batch; ++c)
       zp::launch_pack_planes_u8(dQ + (size_t)c * s->cols, (int)s->cols, (int)s->pitch,
-                                (uint8_t*)s->s_planes.p, st);
-      ProfScope ps(s, PIR_KERNEL_MATVEC);
-      zp::launch_matvec(s->D, (int)s->rows, (int)s->pitch, (const uint8_t*)s->s_planes.p,
+                                planes + (size_t)c * 4 * s->pitch, dB + (size_t)c * s->rows,
+                                (int)s->rows, st);
+    ProfScope ps(s, PIR_KERNEL_MATVEC, (int)batch);
+    for (uint32_t c = 0; c < batch; ++c)
+      zp::launch_matvec(s->D, (int)s->rows, (int)s->pitch, planes + (size_t)c * 4 * s->pitch,
                         dB + (size_t)c * s->rows, st);
-    }
   } else if (path == PIR_PATH_MFMA) {
     ZP_TRY(s->scratch(s->s_planes, (size_t)batch * 4 * s->pitch));
     ZP_TRY(s->scratch(s->s_colsum, (size_t)batch * 4 * sizeof(int32_t)));
@@ -781,7 +789,7 @@ pir_status pir_compress(pir_server* s, const uint32_t* ids, uint32_t batch, cons
   }
   for (uint32_t i = 0; i < batch; ++i) {
     ProfScope ps(s, PIR_KERNEL_COMPRESS);
-    zp::launch_compress(cs[i]->dev(), cs[i]->K, cs[i]->kappa, dB + (size_t)i * s->rows,
+    zp::launch_compress(cs[i]->dev(), cs[i]->Kp, cs[i]->Mp, dB + (size_t)i * s->rows,
                         (int)s->rows, dC + (size_t)i * s->rows * L, st);
   }
   ZP_HIP(hipGetLastError());
@@ -818,9 +826,19 @@ pir_status pir_get_client_hint(pir_server* s, uint32_t id, uint32_t row0, uint32
   for (uint32_t r = row0; r < row0 + nrows; ++r)
     if (!c->valid[r]) return fail(PIR_ESTALE, "K row " + std::to_string(r) + " is stale");
   ZP_TRY(use_device(s));
-  ZP_HIP(hipMemcpyAsync(K, c->K + (size_t)row0 * c->L, (size_t)nrows * c->L * sizeof(uint32_t),
-                        kind_from_dev(ptr_flags), s->stream));
-  if (ptr_flags == PIR_PTR_HOST) ZP_HIP(hipStreamSynchronize(s->stream));
+  hipStream_t st = s->stream;
+  const size_t bytes = (size_t)nrows * c->L * sizeof(uint32_t);
+  uint32_t* dK = K;
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_c, bytes));
+    dK = (uint32_t*)s->s_c.p;
+  }
+  zp::launch_unscale(c->dev(), c->Kp, (int)row0, (int)nrows, dK, st);
+  ZP_HIP(hipGetLastError());
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(K, dK, bytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+  }
   return PIR_OK;
 }
 
@@ -862,13 +880,15 @@ pir_status pir_profile_read(pir_server* s, int32_t kernel, double* total_ms, uin
   ZP_TRY(use_device(s));
   ZP_HIP(hipStreamSynchronize(s->stream));
   double tot = 0;
+  uint64_t cnt = 0;
   for (auto& pr : s->prof_ev[kernel]) {
     float ms = 0;
-    ZP_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    ZP_HIP(hipEventElapsedTime(&ms, pr.begin, pr.end));
     tot += ms;
+    cnt += (uint64_t)pr.launches;
   }
   if (total_ms) *total_ms = tot;
-  if (launches) *launches = s->prof_ev[kernel].size();
+  if (launches) *launches = cnt;
   return PIR_OK;
 }
 

@@ -218,11 +218,16 @@ void pir_engine::run() {
       Db& d = *dp;
       for (Slot& s : d.slots)
         if (s.busy) {
-          if (hipEventQuery(s.ev) == hipSuccess) {
+          const hipError_t q = hipEventQuery(s.ev);
+          if (q == hipErrorNotReady) {
+            inflight = true;
+          } else {
+            if (q != hipSuccess) {
+              (void)hipGetLastError();
+              s.status = PIR_EDEVICE;
+            }
             complete(d, s);
             progress = true;
-          } else {
-            inflight = true;
           }
         }
       for (Slot& s : d.slots) {

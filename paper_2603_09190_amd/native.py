@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libzippir.so")
 PIR_OK, PIR_EINVAL, PIR_ENOMEM, PIR_EDEVICE, PIR_ESTALE, PIR_EBUSY = 0, -1, -2, -3, -4, -5
 PIR_PTR_HOST, PIR_PTR_DEVICE = 0, 1
 PATH_AUTO, PATH_MATVEC, PATH_MFMA = 0, 1, 2
-KERNELS = {"matvec": 0, "gemm": 1, "compress": 2, "hint": 3, "table": 4, "kappa": 5}
+KERNELS = {"matvec": 0, "gemm": 1, "compress": 2, "hint": 3, "table": 4, "key": 5}
 
 
 class ZipPIRError(RuntimeError):

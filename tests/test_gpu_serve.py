@@ -115,12 +115,21 @@ def test_memory_pressure_still_exact(native, setup):
     servers, infos, _ = setup
     reqs = _requests(infos, 24, seed=2)
     free, _, _ = _run(native, servers, infos, reqs)
-    # budget for one request of the largest database: every batch has one request
+    # budget for one request of the largest database: its batches hold one request, and no
+    # batch's buffers exceed the budget
+    def per_request(db, L):
+        rows, cols, _ = DBS[db]
+        return 4 * cols + 4 * rows + 4 * rows * L
+
     rows, cols, sizes = DBS[2]
-    one = 4 * cols + 4 * rows + 4 * rows * 2 * ((max(sizes) + 31) // 32)
-    tight, comps, stats = _run(native, servers, infos, reqs, budget=one + 1024)
+    budget = per_request(2, 2 * ((max(sizes) + 31) // 32)) + 1024
+    tight, comps, stats = _run(native, servers, infos, reqs, budget=budget)
     assert all(c["status"] == 0 for c in comps)
-    assert all(c["batch"] == 1 for c in comps)
+    assert all(c["batch"] == 1 for c in comps if c["db"] == 2)
+    limbs = {r: infos[db][1][ci][2] for r, (db, ci, q) in enumerate(reqs, start=1)}
+    for c in comps:
+        assert c["batch"] * per_request(c["db"], limbs[c["request_id"]]) <= budget
+    assert stats["device_bytes_peak"] <= budget
     for a, b in zip(free, tight):
         assert np.array_equal(a, b)
 
