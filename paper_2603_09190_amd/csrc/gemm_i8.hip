@@ -15,6 +15,14 @@ namespace zp {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also waits for every
+// outstanding global load, which would drain the D prefetch ring at each K step.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ----------------------------------------------------------------------------- packing
 
 __global__ __launch_bounds__(256) void pack_planes_s8_kernel(const uint32_t* __restrict__ x,
@@ -134,7 +142,8 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     lcol[t] = (piece & 15) * 16;
     const int b = lrow[t] >> 5, c = cblk + (lrow[t] & 31);
     xval[t] = c < ncol;
-    xoff[t] = xval[t] ? ((c * 4 + b) * pitch + kstep0 * kKB + lcol[t]) : 0;
+    // vectors beyond ncol read vector ncol-1 (a valid address) and are zeroed after the load
+    xoff[t] = (min(c, ncol - 1) * 4 + b) * pitch + kstep0 * kKB + lcol[t];
   }
 
   v4i acc[2][2][4];
@@ -157,9 +166,10 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
   };
   auto load_x = [&](int st) {
 #pragma unroll
-    for (int t = 0; t < kPieces; ++t)
-      xn[t] = xval[t] ? *reinterpret_cast<const u32x4*>(Xs + (size_t)xoff[t] + (size_t)st * kKB)
-                      : u32x4{0u, 0u, 0u, 0u};
+    for (int t = 0; t < kPieces; ++t) {
+      const u32x4 v = *reinterpret_cast<const u32x4*>(Xs + (size_t)xoff[t] + (size_t)st * kKB);
+      xn[t] = xval[t] ? v : u32x4{0u, 0u, 0u, 0u};
+    }
   };
   auto stash = [&](int buf) {
 #pragma unroll
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
   load_x(0);
   stash(0);
   if (nsteps > 1) load_x(1);
-  __syncthreads();
+  lds_barrier();
   for (int st = 0; st < nsteps; st += kDepth) {
 #pragma unroll
     for (int d = 0; d < kDepth; ++d) {
@@ -211,7 +221,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
         stash(buf ^ 1);
         if (cur + 2 < nsteps) load_x(cur + 2);
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
 
