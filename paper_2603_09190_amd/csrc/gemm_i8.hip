@@ -101,9 +101,10 @@ constexpr int kBC = 32;           // vectors per block (2 blocks of 16)
 constexpr int kKB = 256;          // bytes of K per pipeline step
 constexpr int kLdsStride = kKB + 16;
 
-// A wave computes 32 rows x 32 vectors x 4 planes with v_mfma_i32_16x16x64_i8: for each
-// 64-byte slice of K, lane (g = lane/16, r = lane%16) supplies bytes [64g + 16s, +16) of its
-// D row (A operand) and of its X row (B operand).  The same k-set feeds both operands, so
+// A wave computes 32 rows x 32 vectors x 4 planes with v_mfma_i32_16x16x64_i8: in slice s of
+// a 256-byte K step, lane (g = lane/16, r = lane%16) supplies bytes [64s + 16g, +16) of its
+// D row (A operand) and of its X row (B operand), so each load instruction reads 64
+// contiguous bytes of each of 16 rows.  The same k-set feeds both operands, so
 // the MFMA's internal ordering of k does not matter.  The four plane results of one output
 // sit in the same lane and register, so the epilogue combines them without data exchange.
 // A block of kW waves covers 32 kW rows and one K range (split-K over grid.z); each wave
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
 #pragma unroll
   for (int mr = 0; mr < 2; ++mr) {
     const int row = min(rowblk + 32 * wave + 16 * mr + r, rows - 1);
-    dp[mr] = D + (size_t)row * pitch + (size_t)kstep0 * kKB + 64 * g;
+    dp[mr] = D + (size_t)row * pitch + (size_t)kstep0 * kKB + 16 * g;
   }
   constexpr int kPieces = 4 * kBC * (kKB / 16) / (64 * kW);
   int xoff[kPieces], lrow[kPieces], lcol[kPieces];
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
 #pragma unroll
       for (int s = 0; s < 4; ++s)
         ring[slot][mr][s] = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x4*>(dp[mr] + (size_t)st * kKB) + s);
+            reinterpret_cast<const u32x4*>(dp[mr] + (size_t)st * kKB + 64 * s));
   };
   auto load_x = [&](int st) {
 #pragma unroll
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
         for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
           for (int b = 0; b < 4; ++b)
-            xf[qb][b] = *reinterpret_cast<const v4i*>(&xs[buf][b * 32 + 16 * qb + r][64 * g + 16 * s]);
+            xf[qb][b] = *reinterpret_cast<const v4i*>(&xs[buf][b * 32 + 16 * qb + r][16 * g + 64 * s]);
 #pragma unroll
         for (int mr = 0; mr < 2; ++mr) {
           const v4i a = v4i{(int)dc[mr][s].x, (int)dc[mr][s].y, (int)dc[mr][s].z, (int)dc[mr][s].w};
@@ -249,18 +250,26 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     }
 }
 
-__global__ void zero_out_kernel(uint32_t* __restrict__ p, long long n) {
+// Clears the rows x ncol output block: out[j*ncol + c] (row-major) or out[c*ld + j].
+__global__ void zero_out_kernel(uint32_t* __restrict__ p, int rows, int ncol, int rowmajor,
+                                long long ld) {
+  const long long n = (long long)rows * ncol;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    p[i] = 0u;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (rowmajor) {
+      p[i] = 0u;
+    } else {
+      const long long c = i / rows, j = i - c * rows;
+      p[c * ld + j] = 0u;
+    }
+  }
 }
 
 void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, const int8_t* Xs,
                    const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
                    bool out_rowmajor, long long out_ld, int waves, int depth, int ksplit,
                    hipStream_t s) {
-  const long long nout = out_rowmajor ? (long long)rows * ncol : (long long)ncol * out_ld;
-  zero_out_kernel<<<1024, 256, 0, s>>>(out, nout);
+  zero_out_kernel<<<1024, 256, 0, s>>>(out, rows, ncol, out_rowmajor ? 1 : 0, out_ld);
   const int nsteps = pitch / kKB;
   const int per = min(256, (nsteps + ksplit - 1) / ksplit);
   const int kz = (nsteps + per - 1) / per;

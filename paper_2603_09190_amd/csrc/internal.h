@@ -32,6 +32,10 @@ struct ClientDev {
   int PN;            // limbs per lane for mod-N numbers (SN = 64 PN >= h)
 };
 
+// Online kernels stream at most this many bytes of D per launch (larger databases are cut
+// into row chunks), bounding how long one database's launch holds the device.
+constexpr long long kLaunchBytes = 2LL << 30;
+
 // Number of table entries per (base, window) for 8-bit fixed-base windows.
 constexpr int kWindowBits = 8;
 constexpr int kWindows = 32 / kWindowBits;

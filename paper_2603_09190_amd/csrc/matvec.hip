@@ -5,6 +5,8 @@
 // into a wrapping u32), so one full-rate instruction covers one byte of D:
 //   D.qu = sum_b 2^(8b) * (D . qu_b)  mod 2^32,  qu_b = byte b of qu.
 // Each plane sum may wrap mod 2^32; the shifted recombination is still exact mod 2^32.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace zp {
@@ -106,9 +108,18 @@ constexpr int kSegRowsPerWave = 32;
 
 void launch_matvec(const uint8_t* D, int rows, int pitch, const uint8_t* planes, uint32_t* b,
                    hipStream_t s) {
-  // b accumulates one atomic partial per column segment; launch_pack_planes_u8 cleared it
-  dim3 grid((rows + 4 * kSegRowsPerWave - 1) / (4 * kSegRowsPerWave), (pitch + kSegCols - 1) / kSegCols);
-  matvec_seg_kernel<2><<<grid, 256, 0, s>>>(D, rows, pitch, planes, b, kSegRowsPerWave);
+  // b accumulates one atomic partial per column segment; launch_pack_planes_u8 cleared it.
+  // Databases above kLaunchBytes are streamed in row chunks of at most that many bytes, so
+  // work queued on other streams is dispatched between chunks instead of waiting for the
+  // whole database.
+  const int chunk_rows = (int)std::max<long long>(4 * kSegRowsPerWave,
+                                                  (kLaunchBytes / pitch) / (4 * kSegRowsPerWave) * (4 * kSegRowsPerWave));
+  for (int r0 = 0; r0 < rows; r0 += chunk_rows) {
+    const int nr = std::min(chunk_rows, rows - r0);
+    dim3 grid((nr + 4 * kSegRowsPerWave - 1) / (4 * kSegRowsPerWave), (pitch + kSegCols - 1) / kSegCols);
+    matvec_seg_kernel<2><<<grid, 256, 0, s>>>(D + (size_t)r0 * pitch, nr, pitch, planes, b + r0,
+                                              kSegRowsPerWave);
+  }
 }
 
 }  // namespace zp

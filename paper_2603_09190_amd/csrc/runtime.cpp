@@ -360,6 +360,18 @@ pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
   return PIR_OK;
 }
 
+// Batched answers stream D in row chunks of at most kLaunchBytes (see launch_matvec).
+pir_status run_gemm_chunked(pir_server* s, const int8_t* Xs, const int32_t* colsum, int ncol,
+                            uint32_t* out, long long ld) {
+  const long long per = std::max<long long>(256, zp::kLaunchBytes / s->pitch / 256 * 256);
+  for (long long r0 = 0; r0 < s->rows; r0 += per) {
+    const int nr = (int)std::min<long long>(per, s->rows - r0);
+    ZP_TRY(run_gemm(s, s->D + (size_t)r0 * s->pitch, nr, Xs, colsum, ncol, s->rowsum + r0,
+                    out + r0, false, ld));
+  }
+  return PIR_OK;
+}
+
 pir_status use_device(pir_server* s) {
   ZP_HIP(hipSetDevice(s->device));
   return PIR_OK;
@@ -729,9 +741,8 @@ static pir_status answer_impl(pir_server* s, const uint32_t* Q, uint32_t batch, 
     ZP_TRY(s->scratch(s->s_colsum, (size_t)batch * 4 * sizeof(int32_t)));
     zp::launch_pack_planes_s8(dQ, s->cols, 1, (int)batch, (int)s->cols, (int)s->pitch,
                               (int8_t*)s->s_planes.p, (int32_t*)s->s_colsum.p, st);
-    ZP_TRY(run_gemm(s, s->D, (int)s->rows, (const int8_t*)s->s_planes.p,
-                    (const int32_t*)s->s_colsum.p, (int)batch, s->rowsum, dB, false,
-                    (long long)s->rows));
+    ZP_TRY(run_gemm_chunked(s, (const int8_t*)s->s_planes.p, (const int32_t*)s->s_colsum.p,
+                            (int)batch, dB, (long long)s->rows));
   } else {
     return fail(PIR_EINVAL, "unknown answer path");
   }

@@ -21,16 +21,20 @@ namespace zp {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// One-lane moves use DPP wavefront shifts, a VALU operand modifier (no LDS round trip):
+// wave_shl:1 gives lane l the value of lane l+1, wave_shr:1 the value of lane l-1; a lane
+// without a source keeps the `old` operand, here 0.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+
 // Lane l receives lane l+1's value; lane 63 receives 0.
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t x) {
-  uint32_t y = (uint32_t)__shfl_down((int)x, 1, 64);
-  return lane_id() == 63 ? 0u : y;
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppWaveShl1, 0xF, 0xF, false);
 }
 
 // Lane l receives lane l-1's value; lane 0 receives 0.
 __device__ __forceinline__ uint32_t from_prev_lane(uint32_t x) {
-  uint32_t y = (uint32_t)__shfl_up((int)x, 1, 64);
-  return lane_id() == 0 ? 0u : y;
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppWaveShr1, 0xF, 0xF, false);
 }
 
 __device__ __forceinline__ uint64_t from_prev_lane64(uint64_t x) {

@@ -203,3 +203,30 @@ def test_c5_hint_and_update(native, big):
         K_or = oracle_client_hint(cl.ck, E, cl.N, pool=pool)
     for i, j in enumerate(urows[:16]):
         assert wl.limbs_to_int(K1[j]) == K_or[i], f"updated K row {j}"
+
+
+def test_database_above_one_launch(native):
+    """A 40000 x 65536 database (2.4 GiB) is streamed in two row chunks per query; every row of
+    the matvec and of the batched contraction agrees, and sampled rows on both sides of the
+    chunk boundary (row 32768) match the oracle."""
+    import torch
+    rows, cols = 40000, 65536
+    log("chunked: generating 2.4 GiB database")
+    D = wl.database(6, rows, cols)
+    A = wl.lwe_matrix(6, cols, 4)
+    Q = wl.uniform_queries(6, 3, cols)
+    dev = torch.device("cuda:0")
+    with native.Server(torch.from_numpy(D).to(dev), torch.from_numpy(A.view(np.int32)).to(dev),
+                       stream=torch.cuda.current_stream().cuda_stream) as srv:
+        Qt = torch.from_numpy(Q.view(np.int32)).to(dev)
+        Bm = torch.zeros((3, rows), dtype=torch.int32, device=dev)
+        Bv = torch.zeros_like(Bm)
+        srv.answer(Qt, Bv, native.PATH_MATVEC)
+        srv.answer(Qt, Bm, native.PATH_MFMA)
+        srv.sync()
+        assert torch.equal(Bm, Bv)
+        B = Bv.cpu().numpy().view(np.uint32)
+    sample = [0, 1, 32766, 32767, 32768, 32769, 39998, 39999] + list(range(1000, 40000, 4111))
+    Dr = D[sample].astype(np.uint64)
+    ref = ((Dr @ Q.astype(np.uint64).T) & np.uint64(0xFFFFFFFF)).astype(np.uint32).T
+    assert np.array_equal(B[:, sample], ref)

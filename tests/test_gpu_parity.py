@@ -151,7 +151,7 @@ def test_small_hint_and_compress_match_oracle(native):
     assert f == inst.D[:, cl.col].tolist()
 
 
-@pytest.mark.parametrize("n_bits", [1024, 2048])
+@pytest.mark.parametrize("n_bits", [1024, 2048, 3072, 4096])
 def test_compress_edge_values(native, n_bits):
     # b in {0, 1, 2^32-1}; K in {1, N^2-1, random}: c must equal K (1 + bN) mod N^2.
     rows, cols, n = 9, 256, 4
@@ -256,5 +256,34 @@ def test_toy_config_end_to_end(native):
         srv.compress([cid], B, C)
         got = limbs_rows_to_ints(C[0])
     assert got == server.compress([K_or[j] for j in range(256)], B[0], cl.N)
+    f = [lwe.pir_extract_value(paillier.decrypt(cl.sk, x)) for x in got]
+    assert f == inst.D[:, cl.col].tolist()
+
+
+@pytest.mark.parametrize("n_bits", [1536, 3072, 4096])
+def test_hint_and_combine_other_moduli(native, n_bits):
+    """Every limbs-per-lane instantiation of the Montgomery kernels (N of 1536, 3072 -- the
+    paper's Paillier size -- and 4096 bits): K on every row, the combine, and the client's
+    decryption of every compressed row."""
+    rows, cols, n = 20, 96, 6
+    log(f"modulus {n_bits}: instance")
+    inst = make_instance(cfg=930 + n_bits, rows=rows, cols=cols, n=n, n_bits=n_bits, zero_row=7)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, n_bits)
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    K_or = server.client_hint(cl.ck, E, cl.N)
+    b_or = server.answer(inst.D, cl.qu)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ck)
+        srv.hint(cid)
+        K = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K)
+        assert limbs_rows_to_ints(K) == K_or
+        B = np.zeros((1, rows), np.uint32)
+        srv.answer(cl.qu[None, :], B)
+        C = np.zeros((1, rows, L), np.uint32)
+        srv.compress([cid], B, C)
+    got = limbs_rows_to_ints(C[0])
+    assert got == server.compress(K_or, b_or, cl.N)
     f = [lwe.pir_extract_value(paillier.decrypt(cl.sk, x)) for x in got]
     assert f == inst.D[:, cl.col].tolist()
