@@ -8,35 +8,52 @@
 //   t = K' + b M'            (< N^2 2^32)
 //   c = (t + q N^2) / 2^32   with q = -t N^{-2} mod 2^32, so c = K (1 + bN) mod N^2, c < 2 N^2,
 // followed by one conditional subtraction of N^2.  About 2 L word products per row; the
-// kernel is bound by reading K' and M' and writing c.  One wavefront handles one row.
+// kernel is bound by reading K' and M' and writing c.
 #include "internal.h"
 #include "wavenum.h"
 
 namespace zp {
+
+// Each wave combines kRowsPerWave consecutive rows, loading the modulus once and the next
+// row's K', M' and b while it reduces the current one.
+constexpr int kRowsPerWave = 8;
 
 template <int P>
 __global__ __launch_bounds__(256) void compress_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
                                                        const uint32_t* __restrict__ Mp,
                                                        const uint32_t* __restrict__ b, int rows,
                                                        uint32_t* __restrict__ C) {
-  const int row = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (row >= rows) return;
-  const uint32_t bj = b[row];
-  WNum<P> t, m, M2;
-  wn_load_n(t, Kp + (size_t)row * cd.L, cd.L);
-  wn_load_n(m, Mp + (size_t)row * cd.L, cd.L);
+  const int wave = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row0 = wave * kRowsPerWave;
+  if (row0 >= rows) return;
+  const int row1 = min(rows, row0 + kRowsPerWave);
+  WNum<P> M2, t, m, tn, mn;
   wn_load(M2, cd.N2);
-  uint64_t c = 0;
-  mont_step(t, c, bj, m, M2, cd.m2prime);
-  const uint64_t ovf = wn_resolve(t, c);
-  wn_cond_sub(t, ovf, M2);
-  wn_store_n(C + (size_t)row * cd.L, t, cd.L);
+  wn_load_n(t, Kp + (size_t)row0 * cd.L, cd.L);
+  wn_load_n(m, Mp + (size_t)row0 * cd.L, cd.L);
+  uint32_t bj = b[row0], bn = 0;
+  for (int row = row0; row < row1; ++row) {
+    if (row + 1 < row1) {
+      wn_load_n(tn, Kp + (size_t)(row + 1) * cd.L, cd.L);
+      wn_load_n(mn, Mp + (size_t)(row + 1) * cd.L, cd.L);
+      bn = b[row + 1];
+    }
+    uint64_t c = 0;
+    mont_step(t, c, bj, m, M2, cd.m2prime);
+    const uint64_t ovf = wn_resolve(t, c);
+    wn_cond_sub(t, ovf, M2);
+    wn_store_n(C + (size_t)row * cd.L, t, cd.L);
+    t = tn;
+    m = mn;
+    bj = bn;
+  }
 }
 
 void launch_compress(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Mp,
                      const uint32_t* b, int rows, uint32_t* C, hipStream_t s) {
   if (rows <= 0) return;
-  const int blocks = (rows + 3) / 4;
+  const int waves = (rows + kRowsPerWave - 1) / kRowsPerWave;
+  const int blocks = (waves + 3) / 4;
   switch (cd.P) {
     case 1: compress_kernel<1><<<blocks, 256, 0, s>>>(cd, Kp, Mp, b, rows, C); break;
     case 2: compress_kernel<2><<<blocks, 256, 0, s>>>(cd, Kp, Mp, b, rows, C); break;

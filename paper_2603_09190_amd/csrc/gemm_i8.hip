@@ -9,6 +9,8 @@
 // so each plane is one int8 MFMA contraction plus a per-column term (colsum, per batch)
 // and a per-row term (rowsum, per database).  Everything is accumulated in wrapping
 // 32-bit integers.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace zp {
@@ -98,39 +100,40 @@ void launch_rowsum(const uint8_t* D, int rows, int cols, int pitch, int32_t* row
 
 constexpr int kBM = 128;          // rows of D per block (4 waves x 32 rows)
 constexpr int kBC = 32;           // vectors per block (2 blocks of 16)
-constexpr int kKB = 256;          // bytes of K per pipeline step
-constexpr int kLdsStride = kKB + 16;
+constexpr int kMaxBlockK = 65536; // K bytes per block (keeps MFMA partials within +-2^30)
 
-// A wave computes 32 rows x 32 vectors x 4 planes with v_mfma_i32_16x16x64_i8: in slice s of
-// a 256-byte K step, lane (g = lane/16, r = lane%16) supplies bytes [64s + 16g, +16) of its
+// A wave computes 16 kMR rows x 32 vectors x 4 planes with v_mfma_i32_16x16x64_i8: in slice s
+// of a kKB-byte K step, lane (g = lane/16, r = lane%16) supplies bytes [64s + 16g, +16) of its
 // D row (A operand) and of its X row (B operand), so each load instruction reads 64
-// contiguous bytes of each of 16 rows.  The same k-set feeds both operands, so
-// the MFMA's internal ordering of k does not matter.  The four plane results of one output
-// sit in the same lane and register, so the epilogue combines them without data exchange.
-// A block of kW waves covers 32 kW rows and one K range (split-K over grid.z); each wave
-// keeps kDepth 256-byte K steps of D in flight, the X tile (4 planes x 32 vectors x 256
-// bytes) is double-buffered in LDS with one barrier per step, and partial results are
-// added into the zeroed output with 32-bit atomic adds (exact modulo 2^32 in any order).
-// A block spans at most 256 K steps (64 KiB), which keeps every MFMA partial within +-2^30.
-template <int kW, int kDepth>
+// contiguous bytes of each of 16 rows.  The same k-set feeds both operands, so the MFMA's
+// internal ordering of k does not matter.  The four plane results of one output sit in the
+// same lane and register, so the epilogue combines them without data exchange.
+// A block of kW waves covers 16 kMR kW rows and one K range of at most 64 KiB (split-K over
+// grid.z, which keeps every MFMA partial within +-2^30); each wave keeps kDepth K steps of D
+// in flight, the X tile (4 planes x 32 vectors x kKB bytes) is double-buffered in LDS with one
+// barrier per step, and partial results are added into the zeroed output with 32-bit atomic
+// adds (exact modulo 2^32 in any order).
+template <int kW, int kDepth, int kMR, int kKB>
 __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     const uint8_t* __restrict__ D, int rows, int cols, int pitch, const int8_t* __restrict__ Xs,
     const int32_t* __restrict__ colsum, int ncol, const int32_t* __restrict__ rowsum,
     uint32_t* __restrict__ out, int out_rowmajor, long long out_ld, int ksteps_per_block) {
-  __shared__ __attribute__((aligned(16))) int8_t xs[2][4 * kBC][kLdsStride];
+  constexpr int kSl = kKB / 64;            // MFMA K slices per step
+  constexpr int kStride = kKB + 16;        // LDS row stride; the skew spreads banks
+  __shared__ __attribute__((aligned(16))) int8_t xs[2][4 * kBC][kStride];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, r = lane & 15;
-  const int rowblk = blockIdx.x * 32 * kW;
+  const int rowblk = blockIdx.x * 16 * kMR * kW;
   const int cblk = blockIdx.y * kBC;
   const int kstep0 = blockIdx.z * ksteps_per_block;
   const int nsteps = min(ksteps_per_block, pitch / kKB - kstep0);
   if (nsteps <= 0) return;
 
-  const uint8_t* dp[2];
+  const uint8_t* dp[kMR];
 #pragma unroll
-  for (int mr = 0; mr < 2; ++mr) {
-    const int row = min(rowblk + 32 * wave + 16 * mr + r, rows - 1);
+  for (int mr = 0; mr < kMR; ++mr) {
+    const int row = min(rowblk + 16 * kMR * wave + 16 * mr + r, rows - 1);
     dp[mr] = D + (size_t)row * pitch + (size_t)kstep0 * kKB + 16 * g;
   }
   constexpr int kPieces = 4 * kBC * (kKB / 16) / (64 * kW);
@@ -139,29 +142,29 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
 #pragma unroll
   for (int t = 0; t < kPieces; ++t) {
     const int piece = tid + t * 64 * kW;
-    lrow[t] = piece >> 4;
-    lcol[t] = (piece & 15) * 16;
+    lrow[t] = piece / (kKB / 16);
+    lcol[t] = (piece % (kKB / 16)) * 16;
     const int b = lrow[t] >> 5, c = cblk + (lrow[t] & 31);
     xval[t] = c < ncol;
     // vectors beyond ncol read vector ncol-1 (a valid address) and are zeroed after the load
     xoff[t] = (min(c, ncol - 1) * 4 + b) * pitch + kstep0 * kKB + lcol[t];
   }
 
-  v4i acc[2][2][4];
+  v4i acc[kMR][2][4];
 #pragma unroll
-  for (int mr = 0; mr < 2; ++mr)
+  for (int mr = 0; mr < kMR; ++mr)
 #pragma unroll
     for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[mr][qb][b] = v4i{0, 0, 0, 0};
 
-  u32x4 ring[kDepth][2][4];
+  u32x4 ring[kDepth][kMR][kSl];
   u32x4 xn[kPieces];
   auto load_d = [&](int slot, int st) {
 #pragma unroll
-    for (int mr = 0; mr < 2; ++mr)
+    for (int mr = 0; mr < kMR; ++mr)
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < kSl; ++s)
         ring[slot][mr][s] = __builtin_nontemporal_load(
             reinterpret_cast<const u32x4*>(dp[mr] + (size_t)st * kKB + 64 * s));
   };
@@ -190,18 +193,18 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
       const int cur = st + d;
       if (cur >= nsteps) break;
       const int buf = cur & 1;
-      u32x4 dc[2][4];
+      u32x4 dc[kMR][kSl];
 #pragma unroll
-      for (int mr = 0; mr < 2; ++mr)
+      for (int mr = 0; mr < kMR; ++mr)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < kSl; ++s) {
           u32x4 v = ring[d][mr][s];
           v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
           dc[mr][s] = v;
         }
       if (cur + kDepth < nsteps) load_d(d, cur + kDepth);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < kSl; ++s) {
         v4i xf[2][4];
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb)
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
           for (int b = 0; b < 4; ++b)
             xf[qb][b] = *reinterpret_cast<const v4i*>(&xs[buf][b * 32 + 16 * qb + r][16 * g + 64 * s]);
 #pragma unroll
-        for (int mr = 0; mr < 2; ++mr) {
+        for (int mr = 0; mr < kMR; ++mr) {
           const v4i a = v4i{(int)dc[mr][s].x, (int)dc[mr][s].y, (int)dc[mr][s].z, (int)dc[mr][s].w};
 #pragma unroll
           for (int qb = 0; qb < 2; ++qb)
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
 
   const bool first = blockIdx.z == 0;
 #pragma unroll
-  for (int mr = 0; mr < 2; ++mr)
+  for (int mr = 0; mr < kMR; ++mr)
 #pragma unroll
     for (int qb = 0; qb < 2; ++qb) {
       const int c = cblk + 16 * qb + r;
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
       for (int b = 0; b < 4; ++b) cs[b] = first ? 128u * (uint32_t)colsum[c * 4 + b] : 0u;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int orow = rowblk + 32 * wave + 16 * mr + 4 * g + i;
+        const int orow = rowblk + 16 * kMR * wave + 16 * mr + 4 * g + i;
         if (orow >= rows) continue;
         const uint32_t rterm = first ? 128u * (uint32_t)rowsum[orow] + 16384u * (uint32_t)cols : 0u;
         uint32_t v = 0;
@@ -265,25 +268,39 @@ __global__ void zero_out_kernel(uint32_t* __restrict__ p, int rows, int ncol, in
   }
 }
 
+bool gemm_shape_valid(const GemmShape& sh, int pitch) {
+  const bool known = (sh.waves == 8 && sh.depth == 1 && sh.mr == 2 && sh.kb == 256) ||
+                     (sh.waves == 8 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) ||
+                     (sh.waves == 8 && sh.depth == 1 && sh.mr == 1 && sh.kb == 256) ||
+                     (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 256) ||
+                     (sh.waves == 2 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) ||
+                     (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 512);
+  if (!known || sh.ksplit < 1) return false;
+  return pitch % sh.kb == 0;
+}
+
 void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, const int8_t* Xs,
-                   const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
-                   bool out_rowmajor, long long out_ld, int waves, int depth, int ksplit,
-                   hipStream_t s) {
+                        const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
+                        bool out_rowmajor, long long out_ld, const GemmShape& sh, hipStream_t s) {
   zero_out_kernel<<<1024, 256, 0, s>>>(out, rows, ncol, out_rowmajor ? 1 : 0, out_ld);
-  const int nsteps = pitch / kKB;
-  const int per = min(256, (nsteps + ksplit - 1) / ksplit);
+  const int nsteps = pitch / sh.kb;
+  const int per = std::min(kMaxBlockK / sh.kb, (nsteps + sh.ksplit - 1) / sh.ksplit);
   const int kz = (nsteps + per - 1) / per;
-  dim3 grid((rows + 32 * waves - 1) / (32 * waves), (ncol + kBC - 1) / kBC, kz);
-#define ZP_G16(W, DP) gemm_planes_kernel<W, DP><<<grid, 64 * W, 0, s>>>(D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per)
-  if (waves == 4 && depth == 1) ZP_G16(4, 1);
-  else if (waves == 4 && depth == 2) ZP_G16(4, 2);
-  else if (waves == 4 && depth == 3) ZP_G16(4, 3);
-  else if (waves == 8 && depth == 1) ZP_G16(8, 1);
-  else if (waves == 8 && depth == 2) ZP_G16(8, 2);
-  else if (waves == 8 && depth == 3) ZP_G16(8, 3);
-  else if (waves == 2 && depth == 2) ZP_G16(2, 2);
-  else ZP_G16(4, 2);
-#undef ZP_G16
+  const int rows_per_block = 16 * sh.mr * sh.waves;
+  dim3 grid((rows + rows_per_block - 1) / rows_per_block, (ncol + kBC - 1) / kBC, kz);
+#define ZP_G(W, DP, MR, KB)                                                                        \
+  if (sh.waves == W && sh.depth == DP && sh.mr == MR && sh.kb == KB) {                             \
+    gemm_planes_kernel<W, DP, MR, KB><<<grid, 64 * W, 0, s>>>(D, rows, cols, pitch, Xs, colsum,    \
+                                                              ncol, rowsum, out, out_rowmajor,     \
+                                                              out_ld, per);                        \
+    return;                                                                                        \
+  }
+  ZP_G(8, 1, 2, 256) ZP_G(8, 2, 2, 256) ZP_G(8, 1, 1, 256) ZP_G(4, 1, 2, 256)
+  ZP_G(2, 2, 2, 256) ZP_G(4, 1, 2, 512)
+#undef ZP_G
+  // any other shape falls back to the default
+  gemm_planes_kernel<8, 1, 2, 256><<<grid, 512, 0, s>>>(D, rows, cols, pitch, Xs, colsum, ncol,
+                                                        rowsum, out, out_rowmajor, out_ld, per);
 }
 
 }  // namespace zp

@@ -61,15 +61,16 @@ void launch_rowsum(const uint8_t* D, int rows, int cols, int pitch, int32_t* row
                    hipStream_t s);
 // out = D . X mod 2^32 for `rows` rows of D starting at D, all ncol columns (out is
 // overwritten).  out_rowmajor: out[j*ncol + c]; otherwise out[c*out_ld + j].
-// Launch shape: `waves` per block (2, 4 or 8), `depth` K steps of D in flight per wave
-// (1..3), `ksplit` K ranges per output tile.  Every shape gives identical bits.
+// Launch shape: `waves` per block, `depth` K steps of D in flight per wave, `mr` x 16 rows per
+// wave, `kb` bytes of K per step, `ksplit` K ranges per output tile.  Every shape gives
+// identical bits; gemm_shape_valid tells whether a shape is built and fits the pitch.
 struct GemmShape {
-  int waves, depth, ksplit;
+  int waves, depth, mr, kb, ksplit;
 };
+bool gemm_shape_valid(const GemmShape& sh, int pitch);
 void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, const int8_t* Xs,
                         const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
-                        bool out_rowmajor, long long out_ld, int waves, int depth, int ksplit,
-                        hipStream_t s);
+                        bool out_rowmajor, long long out_ld, const GemmShape& sh, hipStream_t s);
 
 // ---- rows.hip (row gather/scatter for updates and partial recomputation)
 void launch_gather_rows_u8(const uint8_t* src, int pitch, const uint32_t* rows, int nrows,

@@ -273,15 +273,16 @@ void prof_clear(pir_server* s) {
 // shape times every candidate once (after a warm-up) with events on the server's stream and
 // keeps the fastest; every candidate computes identical bits, so tuning never changes a
 // result.  ZIPPIR_AUTOTUNE=0 disables tuning (default shape); ZIPPIR_TUNE_CACHE=<file>
-// persists choices as lines "rows pitch ncol rowmajor waves depth ksplit".
+// persists choices as lines "rows pitch ncol rowmajor waves depth mr kb ksplit".
 using TuneKey = std::tuple<int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, zp::GemmShape> g_tune;
 bool g_tune_loaded = false;
 
-constexpr zp::GemmShape kDefaultShape{8, 2, 2};
-const zp::GemmShape kCandidates[] = {{8, 2, 2}, {8, 1, 2}, {8, 2, 4}, {4, 1, 1}, {4, 3, 1},
-                                     {4, 2, 2}, {2, 2, 1}};
+constexpr zp::GemmShape kDefaultShape{8, 1, 2, 256, 2};
+const zp::GemmShape kCandidates[] = {{8, 1, 2, 256, 2}, {8, 2, 2, 256, 2}, {8, 1, 2, 256, 4},
+                                     {8, 1, 1, 256, 2}, {4, 1, 2, 512, 1}, {2, 2, 2, 256, 1},
+                                     {4, 1, 2, 256, 1}};
 
 const char* tune_cache_path() {
   const char* p = std::getenv("ZIPPIR_TUNE_CACHE");
@@ -294,8 +295,11 @@ void tune_load_locked() {
   const char* path = tune_cache_path();
   if (!path) return;
   std::ifstream f(path);
-  int r, p, n, m, w, d, k;
-  while (f >> r >> p >> n >> m >> w >> d >> k) g_tune[TuneKey(r, p, n, m)] = zp::GemmShape{w, d, k};
+  int r, p, n, m, w, d, mr, kb, k;
+  while (f >> r >> p >> n >> m >> w >> d >> mr >> kb >> k) {
+    const zp::GemmShape sh{w, d, mr, kb, k};
+    if (zp::gemm_shape_valid(sh, p)) g_tune[TuneKey(r, p, n, m)] = sh;
+  }
 }
 
 void tune_store_locked() {
@@ -305,7 +309,7 @@ void tune_store_locked() {
   for (auto& kv : g_tune)
     f << std::get<0>(kv.first) << " " << std::get<1>(kv.first) << " " << std::get<2>(kv.first) << " "
       << std::get<3>(kv.first) << " " << kv.second.waves << " " << kv.second.depth << " "
-      << kv.second.ksplit << "\n";
+      << kv.second.mr << " " << kv.second.kb << " " << kv.second.ksplit << "\n";
 }
 
 bool autotune_enabled() {
@@ -334,11 +338,12 @@ pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
     ZP_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     for (const zp::GemmShape& c : kCandidates) {
+      if (!zp::gemm_shape_valid(c, (int)s->pitch)) continue;
       zp::launch_gemm_planes(D, rows, (int)s->cols, (int)s->pitch, Xs, colsum, ncol, rowsum, out,
-                             rowmajor, ld, c.waves, c.depth, c.ksplit, st);
+                             rowmajor, ld, c, st);
       ZP_HIP(hipEventRecord(e0, st));
       zp::launch_gemm_planes(D, rows, (int)s->cols, (int)s->pitch, Xs, colsum, ncol, rowsum, out,
-                             rowmajor, ld, c.waves, c.depth, c.ksplit, st);
+                             rowmajor, ld, c, st);
       ZP_HIP(hipEventRecord(e1, st));
       ZP_HIP(hipEventSynchronize(e1));
       float ms = 0;
@@ -356,7 +361,7 @@ pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
   }
   ProfScope ps(s, PIR_KERNEL_GEMM);
   zp::launch_gemm_planes(D, rows, (int)s->cols, (int)s->pitch, Xs, colsum, ncol, rowsum, out,
-                         rowmajor, ld, shape.waves, shape.depth, shape.ksplit, st);
+                         rowmajor, ld, shape, st);
   return PIR_OK;
 }
 

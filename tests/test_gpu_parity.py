@@ -287,3 +287,21 @@ def test_hint_and_combine_other_moduli(native, n_bits):
     assert got == server.compress(K_or, b_or, cl.N)
     f = [lwe.pir_extract_value(paillier.decrypt(cl.sk, x)) for x in got]
     assert f == inst.D[:, cl.col].tolist()
+
+
+def test_autotuned_shape_is_persisted(native, tmp_path, monkeypatch):
+    # The first batched contraction of a new shape times the candidate launch shapes and
+    # records the winner; every candidate computes the same bits.
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("ZIPPIR_TUNE_CACHE", str(cache))
+    rows, cols, batch = 77, 1280, 3
+    D = _rand(70, (rows, cols), 256, np.uint8)
+    A = _rand(71, (cols, 4), Q32, np.uint32)
+    Qm = _rand(72, (batch, cols), Q32, np.uint32)
+    with native.Server(D, A) as srv:
+        B = np.zeros((batch, rows), np.uint32)
+        srv.answer(Qm, B, native.PATH_MFMA)
+        assert np.array_equal(B, server.answer_batch(D, Qm))
+    lines = [l.split() for l in cache.read_text().splitlines()]
+    mine = [l for l in lines if l[:4] == [str(rows), str(cols + (-cols) % 256), str(batch), "0"]]
+    assert len(mine) == 1 and len(mine[0]) == 9
