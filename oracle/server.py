@@ -87,3 +87,32 @@ def compress(K, b, N: int) -> list[int]:
 def hint_plaintext_row(e_row, s) -> int:
     """The integer sum_k E_jk * s_k that Dec(K_j) must equal when it stays below N."""
     return sum(int(e) * int(x) for e, x in zip(e_row, s))
+
+
+# ----------------------------------------------------------------------------- batched compression
+# Alg. 3 (BatchedLWECompress, Sec. 3.3) in the combined form of ZipPIR (Sec. 4.3, "Batched
+# compression for smaller responses"): the compressed rows x_j of a group of ell rows are
+# folded into one ciphertext x = (+)_j gamma^j (x) x_j.  Correct when N > gamma^ell and
+# gamma >= q + n q^2 (Theorem 2, Sec. 3.3).
+
+def packing_scale_min(n: int, q: int = 1 << 32) -> int:
+    """q + n q^2, the smallest admissible gamma (Theorem 2)."""
+    return q + n * q * q
+
+
+def compress_packed(K, b, N: int, ell: int, gamma: int) -> list[int]:
+    """c_g = prod_{j<ell} c_{g ell + j}^{gamma^j} mod N^2, c_r the combined row r (last group may be short)."""
+    N2 = N * N
+    rows = len(K)
+    out = []
+    for g0 in range(0, rows, ell):
+        acc = 1
+        for j in range(min(ell, rows - g0)):
+            acc = acc * pow(compress_row(K[g0 + j], int(b[g0 + j]), N), gamma ** j, N2) % N2
+        out.append(acc)
+    return out
+
+
+def packed_digits(mu: int, ell: int, gamma: int) -> list[int]:
+    """mu_j = floor(mu / gamma^j) mod gamma for j < ell (ModifiedBatchedLWEDecrypt, Alg. 3)."""
+    return [(mu // gamma ** j) % gamma for j in range(ell)]

@@ -307,3 +307,63 @@ def test_workload_reproducible_and_primes():
     cts = wl.uniform_ciphertexts(7, 0, 4, pr.P * pr.Q)
     N2 = (pr.P * pr.Q) ** 2
     assert all(0 < c < N2 and math.gcd(c, pr.P * pr.Q) == 1 for c in cts)
+
+
+# ----------------------------------------------------------------------------- batched compression (Alg. 3)
+
+@pytest.mark.parametrize("gamma_kind", ["paper", "pow2"])
+def test_packed_round_trip(gamma_kind):
+    # Theorem 2: with gamma >= q + n q^2 and N > gamma^ell the digits of Dec(c_g) are the
+    # per-row plaintexts, and the client recovers the column from each digit.
+    inst = make_instance(cfg=903, rows=11, cols=24, n=4, n_bits=384)
+    cl = inst.clients[0]
+    gmin = server.packing_scale_min(inst.n)
+    gamma = gmin if gamma_kind == "paper" else 1 << (gmin - 1).bit_length()
+    assert gamma >= gmin
+    ell = 1
+    while gamma ** (ell + 1) < cl.N:
+        ell += 1
+    assert ell >= 4 and gamma ** ell < cl.N
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    K = server.client_hint(cl.ck, E, cl.N)
+    b = server.answer(inst.D, cl.qu)
+    cg = server.compress_packed(K, b, cl.N, ell, gamma)
+    assert len(cg) == -(-inst.rows // ell)
+    rec = []
+    for g, c in enumerate(cg):
+        digits = server.packed_digits(paillier.decrypt(cl.sk, c), ell, gamma)
+        for j in range(min(ell, inst.rows - g * ell)):
+            r = g * ell + j
+            assert digits[j] == int(b[r]) + server.hint_plaintext_row(E[r], cl.s)
+            rec.append(lwe.pir_extract_value(digits[j]))
+    assert rec == inst.D[:, cl.col].tolist()
+
+
+def test_packed_needs_theorem2_bound():
+    # gamma^ell >= N: the packed plaintext wraps modulo N and the digits are wrong.
+    inst = make_instance(cfg=904, rows=6, cols=16, n=4, n_bits=256)
+    cl = inst.clients[0]
+    gamma = 1 << 70
+    ell = 6                      # 2^420 > N
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    K = server.client_hint(cl.ck, E, cl.N)
+    b = server.answer(inst.D, cl.qu)
+    c = server.compress_packed(K, b, cl.N, ell, gamma)[0]
+    digits = server.packed_digits(paillier.decrypt(cl.sk, c), ell, gamma)
+    truth = [int(b[r]) + server.hint_plaintext_row(E[r], cl.s) for r in range(6)]
+    assert digits != truth
+
+
+def test_packed_is_power_product_closed_form():
+    # With gamma = 2^t the group ciphertext is the Horner fold c = (...((c_last^{2^t}) c_.)^{2^t} ...) c_0.
+    N = 1000003 * 1000033
+    N2 = N * N
+    g = np.random.default_rng(12)
+    K = [int(g.integers(1, 1 << 62)) % N2 for _ in range(5)]
+    b = [int(x) for x in g.integers(0, 1 << 32, 5)]
+    t = 7
+    got = server.compress_packed(K, b, N, 5, 1 << t)[0]
+    acc = 1
+    for j in reversed(range(5)):
+        acc = pow(acc, 1 << t, N2) * server.compress_row(K[j], b[j], N) % N2
+    assert got == acc
