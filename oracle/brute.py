@@ -47,3 +47,11 @@ def combine(K_j: int, b_j: int, N: int) -> int:
     """K_j times the unit-randomness encryption of b_j, i.e. (N+1)^{b_j}."""
     N2 = N * N
     return int(K_j) * modexp(N + 1, int(b_j), N2) % N2
+
+
+def offset_row(b_j: int, e_row, cko, N: int) -> int:
+    """b_j + sum_k E_jk ck_o,k reduced mod N once, by an explicit loop."""
+    acc = int(b_j)
+    for k in range(len(e_row)):
+        acc = acc + int(e_row[k]) * int(cko[k])
+    return acc - (acc // N) * N

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workload as wl
-from oracle import brute, lwe, paillier, params, server
+from oracle import brute, lwe, paillier, params, protocol, server
 from tests.instances import make_instance, oracle_client_hint
 
 Q = 1 << 32
@@ -367,3 +367,94 @@ def test_packed_is_power_product_closed_form():
     for j in reversed(range(5)):
         acc = pow(acc, 1 << t, N2) * server.compress_row(K[j], b[j], N) % N2
     assert got == acc
+
+
+# ----------------------------------------------------------------------------- full protocol (Alg. 5)
+
+def _full_protocol(inst, cl):
+    """(E, b, k, pt_r, ck_o, t) for a client whose ck holds random ciphertexts (ck_r)."""
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    b = server.answer(inst.D, cl.qu)
+    k = server.client_hint(cl.ck, E, cl.N)
+    pt_r = protocol.random_key_plaintexts(cl.sk, cl.ck)
+    cko = protocol.query_offset(cl.s, pt_r, cl.N)
+    t = protocol.offset_answer(b, E, cko, cl.N)
+    return E, b, k, pt_r, cko, t
+
+
+@pytest.fixture(scope="module")
+def full_small():
+    # ck_r: uniform elements of Z*_{N^2} (Alg. 5 Setup samples the random key uniformly)
+    return make_instance(cfg=905, rows=20, cols=32, n=6, n_bits=192, encrypt_secret=False)
+
+
+def test_full_protocol_round_trip(full_small):
+    # ZipPIR correctness theorem: from (k_j, t_j), and from the Sec. 4.3 combined ciphertext,
+    # the client recovers the selected column on every row.
+    inst = full_small
+    cl = inst.clients[0]
+    E, b, k, pt_r, cko, t = _full_protocol(inst, cl)
+    want = inst.D[:, cl.col].tolist()
+    assert [protocol.extract(cl.sk, k[j], t[j]) for j in range(inst.rows)] == want
+    c = [protocol.combine_offset(k[j], t[j], cl.N) for j in range(inst.rows)]
+    assert [protocol.extract_combined(cl.sk, x) for x in c] == want
+
+
+def test_full_protocol_identity(full_small):
+    # Appendix proof of correctness: t_j + Dec(k_j) = b_j + sum_k E_jk s_k mod N, and the
+    # right side is an integer below N (Theorem 1's bound), so equality holds over Z.
+    inst = full_small
+    cl = inst.clients[0]
+    E, b, k, pt_r, cko, t = _full_protocol(inst, cl)
+    assert all(0 <= x < cl.N for x in cko)
+    for j in range(inst.rows):
+        lhs = (t[j] + paillier.decrypt(cl.sk, k[j])) % cl.N
+        assert lhs == int(b[j]) + server.hint_plaintext_row(E[j], cl.s)
+        # the combined form decrypts to the same value (Paillier addition, randomness 1)
+        assert paillier.decrypt(cl.sk, protocol.combine_offset(k[j], t[j], cl.N)) == lhs
+        assert protocol.combine_offset(k[j], t[j], cl.N) == brute.combine(k[j], t[j], cl.N)
+
+
+def test_offset_answer_brute_and_closed_forms(full_small):
+    inst = full_small
+    cl = inst.clients[0]
+    N = cl.N
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    b = server.answer(inst.D, cl.qu)
+    g = np.random.default_rng(21)
+    cko = [wl.uniform_below(g, N) for _ in range(inst.n)]
+    t = protocol.offset_answer(b, E, cko, N)
+    for j in range(inst.rows):
+        assert t[j] == brute.offset_row(int(b[j]), E[j].tolist(), cko, N)
+    # ck_o = 0: t = b; ck_o = unit vector at k: t_j = b_j + E_jk; ck_o = N - 1 everywhere:
+    # t_j = b_j - sum_k E_jk mod N
+    assert protocol.offset_answer(b, E, [0] * inst.n, N) == [int(x) for x in b]
+    for kk in (0, inst.n - 1):
+        u = [0] * inst.n
+        u[kk] = 1
+        assert protocol.offset_answer(b, E, u, N) == [int(b[j]) + int(E[j, kk]) for j in range(inst.rows)]
+    assert protocol.offset_answer(b, E, [N - 1] * inst.n, N) == \
+        [(int(b[j]) - int(E[j].astype(np.int64).sum())) % N for j in range(inst.rows)]
+    # listed rows come back in the given order
+    assert protocol.offset_answer(b, E, cko, N, rows=[7, 2]) == [t[7], t[2]]
+
+
+def test_mutation_offset_sign_is_caught(full_small, monkeypatch):
+    # Planted mistake: ck_o = s + pt_r instead of s - pt_r.
+    inst = full_small
+    cl = inst.clients[0]
+    monkeypatch.setattr(protocol, "query_offset", lambda s, pt, N: [(int(x) + int(p)) % N for x, p in zip(s, pt)])
+    E, b, k, pt_r, cko, t = _full_protocol(inst, cl)
+    got = [protocol.extract(cl.sk, k[j], t[j]) for j in range(inst.rows)]
+    assert got != inst.D[:, cl.col].tolist()
+
+
+def test_mutation_offset_without_answer_is_caught(full_small, monkeypatch):
+    # Planted mistake: the response drops the LWE answer b.
+    inst = full_small
+    cl = inst.clients[0]
+    orig = protocol.offset_answer_row
+    monkeypatch.setattr(protocol, "offset_answer_row", lambda b_j, e, c, N: orig(0, e, c, N))
+    E, b, k, pt_r, cko, t = _full_protocol(inst, cl)
+    got = [protocol.extract(cl.sk, k[j], t[j]) for j in range(inst.rows)]
+    assert got != inst.D[:, cl.col].tolist()
