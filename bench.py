@@ -36,7 +36,7 @@ INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA
 # HBM bytes per launch of the matvec on the 1 GiB database, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (calibrated on a plain 1 GiB device copy), keyed by the SHA-256 of the matvec
 # source they were taken on: a changed kernel reports null until the counters are re-taken.
-MATVEC_TRAFFIC = {"516af2384f6f7619": 1083210692}
+MATVEC_TRAFFIC = {"3942b980745b36ab": 1083180014}
 
 
 def matvec_source_hash() -> str:
@@ -212,6 +212,36 @@ def main() -> int:
     mv32_ms = (time.perf_counter() - t0) * 1e3 / max(2, reps // 4)
     same = bool(torch.equal(Bb, Bm))
 
+    # packed responses (batched compression): ell answers per ciphertext, gamma = 2^t
+    pinfo = srv.packing_info(cid)
+    ell = pinfo["ell_max"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    srv.set_packing(cid, ell)   # builds the group keys from the resident hint
+    torch.cuda.synchronize()
+    gk_s = time.perf_counter() - t0
+    G = srv.packing_info(cid)["groups"]
+    Cp = torch.zeros((1, G, L), dtype=torch.int32, device=dev)
+    for _ in range(3):
+        srv.compress_packed([cid], B1, Cp)
+    srv.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        srv.answer(q1, B1, native.PATH_MATVEC)
+        srv.compress_packed([cid], B1, Cp)
+    torch.cuda.synchronize()
+    pk_step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    pk_ms, pk_n = srv.profile_read("compress")
+    srv.profile(False)
+    srv.set_packing(cid, 1)
+    packed = {"ell": ell, "log2_gamma": pinfo["log2_gamma"], "groups": G,
+              "response_bytes": G * L * 4, "unpacked_response_bytes": rows * L * 4,
+              "ms_per_step": round(pk_step_ms, 4),
+              "db_gbs": round(db_bytes / (pk_step_ms * 1e-3) / 1e9, 3),
+              "compress_kernel_avg_us": round(pk_ms / max(1, pk_n) * 1e3, 2),
+              "group_key_build_s": round(gk_s, 3)}
+
     # dominant kernel's own duration: 8 queries' matvecs back to back between two events
     Q8 = Qt[:8].contiguous()
     B8 = torch.zeros((8, rows), dtype=torch.int32, device=dev)
@@ -280,6 +310,7 @@ def main() -> int:
                     "mfma_frac_of_peak": round(mfma_ops / (gm_avg_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
                     "db_gbs": round(db_bytes / (gm_avg_ms * 1e-3) / 1e9, 1),
                     "bit_identical_to_matvec": same},
+        "packed": packed,
         "offline_hint_s": round(hint_s, 3),
         "hint_kernel_ms": round(hintk_ms, 1),
         "roofline": roof,

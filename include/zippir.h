@@ -128,6 +128,30 @@ pir_status pir_answer_path(pir_server *srv, const uint32_t *Q, uint32_t batch, u
 pir_status pir_compress(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
                         const uint32_t *B, uint32_t *C, uint32_t ptr_flags);
 
+/*
+ * Packed responses: batched compression (Alg. 3, Sec. 3.3; in ZipPIR, Sec. 4.3 "Batched
+ * compression for smaller responses").  With packing factor ell, rows g*ell .. g*ell+ell-1
+ * share one ciphertext
+ *     C_g = prod_j c_{g ell + j}^(gamma^j) mod N^2,   c_r = K_r (1 + B[r] N) mod N^2,
+ * whose plaintext holds the rows' plaintexts as base-gamma digits.  gamma = 2^t with
+ * t = 64 + bitlen(n), the smallest power of two >= q + n q^2 (q = 2^32); Theorem 2 of the paper
+ * holds for any gamma >= q + n q^2 and needs N > gamma^ell, so ell <= (N_bits - 1) / t.
+ *
+ * pir_set_packing: ell in [1, ell_max] (1 = one ciphertext per row, the default).  The group
+ *   keys are derived from the client's hint: immediately if it is complete, else by the next
+ *   pir_hint.  pir_update_rows marks the affected groups stale.
+ * pir_packing_info: current ell, its maximum, t = log2(gamma), and the group count
+ *   ceil(rows / ell) (any pointer may be NULL).
+ * pir_compress_packed: C is batch x groups x L uint32 (the last group may hold fewer rows);
+ *   every client in the call must have the same ell > 1 and L.  PIR_ESTALE if a row or group
+ *   is stale.
+ */
+pir_status pir_set_packing(pir_server *srv, uint32_t client_id, uint32_t ell);
+pir_status pir_packing_info(pir_server *srv, uint32_t client_id, uint32_t *ell, uint32_t *ell_max,
+                            uint32_t *log2_gamma, uint32_t *groups);
+pir_status pir_compress_packed(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
+                               const uint32_t *B, uint32_t *C, uint32_t ptr_flags);
+
 /* Copy rows [row0, row0+nrows) of H (nrows x n uint32).  PIR_ESTALE if any is stale. */
 pir_status pir_get_global_hint(pir_server *srv, uint32_t row0, uint32_t nrows, uint32_t *H,
                                uint32_t ptr_flags);
@@ -159,7 +183,9 @@ pir_status pir_shape(pir_server *srv, uint32_t *rows, uint32_t *cols, uint32_t *
 #define PIR_KERNEL_HINT     3  /* per-row fixed-base multi-exponentiation               */
 #define PIR_KERNEL_TABLE    4  /* fixed-base table build                                */
 #define PIR_KERNEL_KEY      5  /* per-row combine key N (K mod N), computed with the hint */
-#define PIR_KERNEL_COUNT    6
+#define PIR_KERNEL_OFFSET_GEMM 6  /* offset answer: E bytes x offset bytes on int8 MFMA   */
+#define PIR_KERNEL_OFFSET   7  /* offset answer: byte positions -> limbs, + b, mod N     */
+#define PIR_KERNEL_COUNT    8
 pir_status pir_profile(pir_server *srv, int32_t enable);
 pir_status pir_profile_read(pir_server *srv, int32_t kernel, double *total_ms, uint64_t *launches);
 

@@ -62,4 +62,62 @@ void launch_compress(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Mp
   }
 }
 
+// Packed response (Alg. 3, online part, gamma = 2^t): for group g of ell rows,
+//   c_g = K_g (1 + beta_g N) mod N^2 = K_g + beta_g M_g mod N^2,  beta_g = sum_j b_{g ell + j} 2^(t j),
+// with M_g = N (K_g mod N) < N^2 kept in Montgomery form (Mr = M_g R mod N^2), so one
+// Montgomery product by the h-limb beta_g gives beta_g M_g mod N^2.  Since t >= 32 the answers
+// occupy disjoint bit ranges of beta_g: each limb takes at most two of them.  One wavefront
+// per group.
+template <int P>
+__global__ __launch_bounds__(256) void compress_packed_kernel(
+    ClientDev cd, const uint32_t* __restrict__ Kg, const uint32_t* __restrict__ Mr,
+    const uint32_t* __restrict__ b, int rows, int ell, int t, uint32_t* __restrict__ C) {
+  const int g = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = g * ell;
+  if (r0 >= rows) return;
+  const int nj = min(ell, rows - r0);
+  WNum<P> beta, mr, M2, acc;
+#pragma unroll
+  for (int jj = 0; jj < P; ++jj) {
+    const int w = P * lane_id() + jj;  // limb index: bits [32w, 32w + 32)
+    uint32_t v = 0;
+    const int jlo = max(0, (32 * w - 31 + t - 1) / t);
+    const int jhi = min(nj - 1, (32 * w + 31) / t);
+    for (int j = jlo; j <= jhi; ++j) {
+      const int sh = t * j - 32 * w;
+      const uint32_t bj = b[r0 + j];
+      v |= sh >= 0 ? (bj << sh) : (bj >> (-sh));
+    }
+    beta.v[jj] = v;
+  }
+  wn_load_n(mr, Mr + (size_t)g * cd.L, cd.L);
+  wn_load(M2, cd.N2);
+  mont_mul_short(acc, beta, cd.h, mr, M2, cd.m2prime);  // beta_g M_g mod N^2
+  WNum<P> k;
+  wn_load_n(k, Kg + (size_t)g * cd.L, cd.L);
+  uint32_t carry = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const uint64_t s = (uint64_t)acc.v[j] + k.v[j] + carry;
+    acc.v[j] = (uint32_t)s;
+    carry = (uint32_t)(s >> 32);
+  }
+  const uint64_t ovf = wn_resolve(acc, (uint64_t)carry);
+  wn_cond_sub(acc, ovf, M2);
+  wn_store_n(C + (size_t)g * cd.L, acc, cd.L);
+}
+
+void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint32_t* Mr,
+                            const uint32_t* b, int rows, int ell, int t, uint32_t* C, hipStream_t s) {
+  if (rows <= 0) return;
+  const int groups = (rows + ell - 1) / ell;
+  const int blocks = (groups + 3) / 4;
+  switch (cd.P) {
+    case 1: compress_packed_kernel<1><<<blocks, 256, 0, s>>>(cd, Kg, Mr, b, rows, ell, t, C); break;
+    case 2: compress_packed_kernel<2><<<blocks, 256, 0, s>>>(cd, Kg, Mr, b, rows, ell, t, C); break;
+    case 3: compress_packed_kernel<3><<<blocks, 256, 0, s>>>(cd, Kg, Mr, b, rows, ell, t, C); break;
+    case 4: compress_packed_kernel<4><<<blocks, 256, 0, s>>>(cd, Kg, Mr, b, rows, ell, t, C); break;
+  }
+}
+
 }  // namespace zp

@@ -1,4 +1,5 @@
-// D . X mod 2^32 for a uint8 matrix D and uint32 vectors X, on signed int8 MFMA.
+// D . X mod 2^32 for a uint8 matrix D and uint32 vectors X, on signed int8 MFMA; with one
+// plane, D . X for uint8 vectors X (exact 32-bit sums, used by the offset answer).
 //
 // Used for the batched online answer B = D.Q (many clients' queries at once; D is shared
 // by all clients, Sec. 4.3) and for the global hint H = D.A (Alg. 5 preamble).
@@ -98,29 +99,29 @@ void launch_rowsum(const uint8_t* D, int rows, int cols, int pitch, int32_t* row
 
 // ----------------------------------------------------------------------------- contraction
 
-constexpr int kBM = 128;          // rows of D per block (4 waves x 32 rows)
 constexpr int kBC = 32;           // vectors per block (2 blocks of 16)
 constexpr int kMaxBlockK = 65536; // K bytes per block (keeps MFMA partials within +-2^30)
 
-// A wave computes 16 kMR rows x 32 vectors x 4 planes with v_mfma_i32_16x16x64_i8: in slice s
-// of a kKB-byte K step, lane (g = lane/16, r = lane%16) supplies bytes [64s + 16g, +16) of its
-// D row (A operand) and of its X row (B operand), so each load instruction reads 64
-// contiguous bytes of each of 16 rows.  The same k-set feeds both operands, so the MFMA's
-// internal ordering of k does not matter.  The four plane results of one output sit in the
-// same lane and register, so the epilogue combines them without data exchange.
+// A wave computes 16 kMR rows x 32 vectors x kPl planes (4 for uint32 vectors, 1 for uint8
+// vectors) with v_mfma_i32_16x16x64_i8: in slice s of a kKB-byte K step, lane (g = lane/16,
+// r = lane%16) supplies bytes [64s + 16g, +16) of its D row (A operand) and of its X row
+// (B operand), so each load instruction reads 64 contiguous bytes of each of 16 rows.  The
+// same k-set feeds both operands, so the MFMA's internal ordering of k does not matter.  The
+// plane results of one output sit in the same lane and register, so the epilogue combines
+// them without data exchange.
 // A block of kW waves covers 16 kMR kW rows and one K range of at most 64 KiB (split-K over
 // grid.z, which keeps every MFMA partial within +-2^30); each wave keeps kDepth K steps of D
-// in flight, the X tile (4 planes x 32 vectors x kKB bytes) is double-buffered in LDS with one
-// barrier per step, and partial results are added into the zeroed output with 32-bit atomic
-// adds (exact modulo 2^32 in any order).
-template <int kW, int kDepth, int kMR, int kKB>
+// in flight, the X tile (kPl planes x 32 vectors x kKB bytes) is double-buffered in LDS with
+// one barrier per step, and partial results are added into the zeroed output with 32-bit
+// atomic adds (exact modulo 2^32 in any order).
+template <int kW, int kDepth, int kMR, int kKB, int kPl>
 __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     const uint8_t* __restrict__ D, int rows, int cols, int pitch, const int8_t* __restrict__ Xs,
     const int32_t* __restrict__ colsum, int ncol, const int32_t* __restrict__ rowsum,
     uint32_t* __restrict__ out, int out_rowmajor, long long out_ld, int ksteps_per_block) {
   constexpr int kSl = kKB / 64;            // MFMA K slices per step
   constexpr int kStride = kKB + 16;        // LDS row stride; the skew spreads banks
-  __shared__ __attribute__((aligned(16))) int8_t xs[2][4 * kBC][kStride];
+  __shared__ __attribute__((aligned(16))) int8_t xs[2][kPl * kBC][kStride];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, r = lane & 15;
@@ -136,7 +137,8 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     const int row = min(rowblk + 16 * kMR * wave + 16 * mr + r, rows - 1);
     dp[mr] = D + (size_t)row * pitch + (size_t)kstep0 * kKB + 16 * g;
   }
-  constexpr int kPieces = 4 * kBC * (kKB / 16) / (64 * kW);
+  constexpr int kPieces = kPl * kBC * (kKB / 16) / (64 * kW);
+  static_assert(kPieces >= 1 && kPieces * 64 * kW == kPl * kBC * (kKB / 16), "X tile split");
   int xoff[kPieces], lrow[kPieces], lcol[kPieces];
   bool xval[kPieces];
 #pragma unroll
@@ -147,16 +149,16 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     const int b = lrow[t] >> 5, c = cblk + (lrow[t] & 31);
     xval[t] = c < ncol;
     // vectors beyond ncol read vector ncol-1 (a valid address) and are zeroed after the load
-    xoff[t] = (min(c, ncol - 1) * 4 + b) * pitch + kstep0 * kKB + lcol[t];
+    xoff[t] = (min(c, ncol - 1) * kPl + b) * pitch + kstep0 * kKB + lcol[t];
   }
 
-  v4i acc[kMR][2][4];
+  v4i acc[kMR][2][kPl];
 #pragma unroll
   for (int mr = 0; mr < kMR; ++mr)
 #pragma unroll
     for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[mr][qb][b] = v4i{0, 0, 0, 0};
+      for (int b = 0; b < kPl; ++b) acc[mr][qb][b] = v4i{0, 0, 0, 0};
 
   u32x4 ring[kDepth][kMR][kSl];
   u32x4 xn[kPieces];
@@ -205,11 +207,11 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
       if (cur + kDepth < nsteps) load_d(d, cur + kDepth);
 #pragma unroll
       for (int s = 0; s < kSl; ++s) {
-        v4i xf[2][4];
+        v4i xf[2][kPl];
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
+          for (int b = 0; b < kPl; ++b)
             xf[qb][b] = *reinterpret_cast<const v4i*>(&xs[buf][b * 32 + 16 * qb + r][16 * g + 64 * s]);
 #pragma unroll
         for (int mr = 0; mr < kMR; ++mr) {
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
 #pragma unroll
           for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int b = 0; b < kPl; ++b)
               acc[mr][qb][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, xf[qb][b], acc[mr][qb][b], 0, 0, 0);
         }
       }
@@ -236,9 +238,9 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     for (int qb = 0; qb < 2; ++qb) {
       const int c = cblk + 16 * qb + r;
       if (c >= ncol) continue;
-      uint32_t cs[4];
+      uint32_t cs[kPl];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) cs[b] = first ? 128u * (uint32_t)colsum[c * 4 + b] : 0u;
+      for (int b = 0; b < kPl; ++b) cs[b] = first ? 128u * (uint32_t)colsum[c * kPl + b] : 0u;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int orow = rowblk + 16 * kMR * wave + 16 * mr + 4 * g + i;
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
         const uint32_t rterm = first ? 128u * (uint32_t)rowsum[orow] + 16384u * (uint32_t)cols : 0u;
         uint32_t v = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) v += ((uint32_t)acc[mr][qb][b][i] + cs[b] + rterm) << (8 * b);
+        for (int b = 0; b < kPl; ++b) v += ((uint32_t)acc[mr][qb][b][i] + cs[b] + rterm) << (8 * b);
         uint32_t* o = out_rowmajor ? out + (size_t)orow * ncol + c : out + (size_t)c * out_ld + orow;
         atomicAdd(o, v);
       }
@@ -279,9 +281,10 @@ bool gemm_shape_valid(const GemmShape& sh, int pitch) {
   return pitch % sh.kb == 0;
 }
 
-void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, const int8_t* Xs,
-                        const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
-                        bool out_rowmajor, long long out_ld, const GemmShape& sh, hipStream_t s) {
+void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int planes,
+                        const int8_t* Xs, const int32_t* colsum, int ncol, const int32_t* rowsum,
+                        uint32_t* out, bool out_rowmajor, long long out_ld, const GemmShape& sh,
+                        hipStream_t s) {
   zero_out_kernel<<<1024, 256, 0, s>>>(out, rows, ncol, out_rowmajor ? 1 : 0, out_ld);
   const int nsteps = pitch / sh.kb;
   const int per = std::min(kMaxBlockK / sh.kb, (nsteps + sh.ksplit - 1) / sh.ksplit);
@@ -290,17 +293,24 @@ void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, const i
   dim3 grid((rows + rows_per_block - 1) / rows_per_block, (ncol + kBC - 1) / kBC, kz);
 #define ZP_G(W, DP, MR, KB)                                                                        \
   if (sh.waves == W && sh.depth == DP && sh.mr == MR && sh.kb == KB) {                             \
-    gemm_planes_kernel<W, DP, MR, KB><<<grid, 64 * W, 0, s>>>(D, rows, cols, pitch, Xs, colsum,    \
-                                                              ncol, rowsum, out, out_rowmajor,     \
-                                                              out_ld, per);                        \
+    if (planes == 4)                                                                               \
+      gemm_planes_kernel<W, DP, MR, KB, 4><<<grid, 64 * W, 0, s>>>(                                \
+          D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per);         \
+    else                                                                                           \
+      gemm_planes_kernel<W, DP, MR, KB, 1><<<grid, 64 * W, 0, s>>>(                                \
+          D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per);         \
     return;                                                                                        \
   }
   ZP_G(8, 1, 2, 256) ZP_G(8, 2, 2, 256) ZP_G(8, 1, 1, 256) ZP_G(4, 1, 2, 256)
   ZP_G(2, 2, 2, 256) ZP_G(4, 1, 2, 512)
 #undef ZP_G
   // any other shape falls back to the default
-  gemm_planes_kernel<8, 1, 2, 256><<<grid, 512, 0, s>>>(D, rows, cols, pitch, Xs, colsum, ncol,
-                                                        rowsum, out, out_rowmajor, out_ld, per);
+  if (planes == 4)
+    gemm_planes_kernel<8, 1, 2, 256, 4><<<grid, 512, 0, s>>>(D, rows, cols, pitch, Xs, colsum, ncol,
+                                                             rowsum, out, out_rowmajor, out_ld, per);
+  else
+    gemm_planes_kernel<8, 1, 2, 256, 1><<<grid, 512, 0, s>>>(D, rows, cols, pitch, Xs, colsum, ncol,
+                                                             rowsum, out, out_rowmajor, out_ld, per);
 }
 
 }  // namespace zp

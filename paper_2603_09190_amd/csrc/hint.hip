@@ -149,6 +149,75 @@ __global__ __launch_bounds__(256) void unscale_kernel(ClientDev cd, const uint32
   wn_store_n(K + (size_t)widx * cd.L, t, cd.L);
 }
 
+// Group key of the packed response (Alg. 3 with gamma = 2^t, offline part):
+//   K_g = prod_{j < ell} K_{g ell + j}^{2^(t j)} mod N^2,
+// by Horner from the last row of the group: acc <- acc^(2^t) * K_row (t squarings per row).
+template <int P>
+__global__ __launch_bounds__(256) void group_keys_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
+                                                         int rows, int ell, int t,
+                                                         const uint32_t* __restrict__ glist,
+                                                         int ngroups, uint32_t* __restrict__ Kg) {
+  const int widx = wave_index();
+  if (widx >= ngroups) return;
+  const int g = glist ? (int)glist[widx] : widx;
+  const int r0 = g * ell;
+  const int r1 = min(rows, r0 + ell);
+  WNum<P> M, CP, acc, x;
+  wn_load(M, cd.N2);
+  wn_load(CP, cd.CP);
+  wn_load_n(acc, Kp + (size_t)(r1 - 1) * cd.L, cd.L);
+  mont_mul(acc, acc, CP, M, cd.m2prime);  // K' 2^(64S-32) R^{-1} = K R
+  for (int r = r1 - 2; r >= r0; --r) {
+    for (int i = 0; i < t; ++i) mont_mul(acc, acc, acc, M, cd.m2prime);
+    wn_load_n(x, Kp + (size_t)r * cd.L, cd.L);
+    mont_mul(x, x, CP, M, cd.m2prime);
+    mont_mul(acc, acc, x, M, cd.m2prime);
+  }
+  WNum<P> one;
+  wn_zero(one);
+  if (lane_id() == 0) one.v[0] = 1;
+  mont_mul(acc, acc, one, M, cd.m2prime);
+  wn_store_n(Kg + (size_t)g * cd.L, acc, cd.L);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void to_mont_kernel(ClientDev cd, uint32_t* __restrict__ x,
+                                                      const uint32_t* __restrict__ rowlist, int nrows) {
+  const int widx = wave_index();
+  if (widx >= nrows) return;
+  const int row = rowlist ? (int)rowlist[widx] : widx;
+  WNum<P> M, RR, v;
+  wn_load(M, cd.N2);
+  wn_load(RR, cd.RR);
+  wn_load_n(v, x + (size_t)row * cd.L, cd.L);
+  mont_mul(v, v, RR, M, cd.m2prime);
+  wn_store_n(x + (size_t)row * cd.L, v, cd.L);
+}
+
+void launch_group_keys(const ClientDev& cd, const uint32_t* Kp, int rows, int ell, int t,
+                       const uint32_t* glist, int ngroups, uint32_t* Kg, hipStream_t s) {
+  if (ngroups <= 0) return;
+  const int blocks = (ngroups + 3) / 4;
+  switch (cd.P) {
+    case 1: group_keys_kernel<1><<<blocks, 256, 0, s>>>(cd, Kp, rows, ell, t, glist, ngroups, Kg); break;
+    case 2: group_keys_kernel<2><<<blocks, 256, 0, s>>>(cd, Kp, rows, ell, t, glist, ngroups, Kg); break;
+    case 3: group_keys_kernel<3><<<blocks, 256, 0, s>>>(cd, Kp, rows, ell, t, glist, ngroups, Kg); break;
+    case 4: group_keys_kernel<4><<<blocks, 256, 0, s>>>(cd, Kp, rows, ell, t, glist, ngroups, Kg); break;
+  }
+}
+
+void launch_to_mont(const ClientDev& cd, uint32_t* x, const uint32_t* rowlist, int nrows,
+                    hipStream_t s) {
+  if (nrows <= 0) return;
+  const int blocks = (nrows + 3) / 4;
+  switch (cd.P) {
+    case 1: to_mont_kernel<1><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows); break;
+    case 2: to_mont_kernel<2><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows); break;
+    case 3: to_mont_kernel<3><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows); break;
+    case 4: to_mont_kernel<4><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows); break;
+  }
+}
+
 void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, uint32_t* table,
                         hipStream_t s) {
   const int waves = n * kWindows;

@@ -15,7 +15,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 //   N2  S limbs   N^2 (zero padded)          R1  S limbs   R mod N^2, R = 2^(32 S)
 //   RR  S limbs   R^2 mod N^2                NP  S limbs   N (zero padded, S-limb layout)
 //   Nn  SN limbs  N                          C1  SN limbs  R_N mod N, R_N = 2^(32 SN)
-//   C2  SN limbs  R_N^2 mod N
+//   C2  SN limbs  R_N^2 mod N              CP  S limbs   2^(64 S - 32) mod N^2 (K' -> K R)
 struct ClientDev {
   const uint32_t* N2;
   const uint32_t* R1;
@@ -24,6 +24,7 @@ struct ClientDev {
   const uint32_t* Nn;
   const uint32_t* C1;
   const uint32_t* C2;
+  const uint32_t* CP;
   uint32_t m2prime;  // -(N^2)^{-1} mod 2^32
   uint32_t nprime;   // -N^{-1} mod 2^32
   int L;             // limbs of a ciphertext (2h)
@@ -68,9 +69,14 @@ struct GemmShape {
   int waves, depth, mr, kb, ksplit;
 };
 bool gemm_shape_valid(const GemmShape& sh, int pitch);
-void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, const int8_t* Xs,
-                        const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
-                        bool out_rowmajor, long long out_ld, const GemmShape& sh, hipStream_t s);
+// planes = 4: X holds uint32 vectors as four byte planes (launch_pack_planes_s8) and
+// out = D . X mod 2^32.  planes = 1: X holds uint8 vectors as one plane,
+// Xs[c*pitch + i] = X(c,i) ^ 0x80 (0 beyond cols), colsum[c] = sum_{i<cols} Xs[c*pitch + i],
+// and out = D . X, exact while cols * 255^2 < 2^32.
+void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int planes,
+                        const int8_t* Xs, const int32_t* colsum, int ncol, const int32_t* rowsum,
+                        uint32_t* out, bool out_rowmajor, long long out_ld, const GemmShape& sh,
+                        hipStream_t s);
 
 // ---- rows.hip (row gather/scatter for updates and partial recomputation)
 void launch_gather_rows_u8(const uint8_t* src, int pitch, const uint32_t* rows, int nrows,
@@ -95,6 +101,17 @@ void launch_combine_key(const ClientDev& cd, const uint32_t* Kp, const uint32_t*
 // K_j = K'_j 2^{-32} mod N^2 for rows [row0, row0+nrows) into K (nrows x L).
 void launch_unscale(const ClientDev& cd, const uint32_t* Kp, int row0, int nrows, uint32_t* K,
                     hipStream_t s);
+
+// ---- packed responses (batched compression, gamma = 2^t)
+// Kg[g] = prod_{j} K_{g ell + j}^{2^(t j)} mod N^2 (canonical) for the listed groups, from K'.
+void launch_group_keys(const ClientDev& cd, const uint32_t* Kp, int rows, int ell, int t,
+                       const uint32_t* glist, int ngroups, uint32_t* Kg, hipStream_t s);
+// x[i] <- x[i] R mod N^2 for the listed rows of an L-limb array (Montgomery form).
+void launch_to_mont(const ClientDev& cd, uint32_t* x, const uint32_t* rowlist, int nrows,
+                    hipStream_t s);
+// C[g] = K_g + beta_g M_g mod N^2 with beta_g = sum_j b[g ell + j] 2^(t j); Mr holds M_g R.
+void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint32_t* Mr,
+                            const uint32_t* b, int rows, int ell, int t, uint32_t* C, hipStream_t s);
 
 // ---- runtime.cpp accessors used by the serving engine
 hipStream_t server_stream(pir_server* s);

@@ -133,12 +133,18 @@ struct ClientState {
   uint32_t n_bits = 0, h = 0, L = 0, P = 0, PN = 0, S = 0, SN = 0;
   Big N;
   uint32_t* ck = nullptr;      // n x L
-  uint32_t* consts = nullptr;  // N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each)
+  uint32_t* consts = nullptr;  // N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each) | CP (S)
   uint32_t* Kp = nullptr;      // rows x L: K_j 2^32 mod N^2
   uint32_t* Mp = nullptr;      // rows x L: N (K'_j mod N), the combine key
   uint32_t m2prime = 0, nprime = 0;
   std::vector<uint8_t> valid;  // per row: K' and M' up to date
   int64_t stale = 0;
+  // packed responses (batched compression): ell rows per ciphertext, gamma = 2^t
+  uint32_t ell = 1, t = 0, ell_max = 1;
+  uint32_t* Kg = nullptr;      // groups x L: group keys K_g
+  uint32_t* Mr = nullptr;      // groups x L: N (K_g mod N) R mod N^2
+  std::vector<uint8_t> gvalid; // per group
+  int64_t gstale = 0;
 
   zp::ClientDev dev() const {
     zp::ClientDev d;
@@ -149,6 +155,7 @@ struct ClientState {
     d.Nn = consts + 4 * S;
     d.C1 = consts + 4 * S + SN;
     d.C2 = consts + 4 * S + 2 * SN;
+    d.CP = consts + 4 * S + 3 * SN;
     d.m2prime = m2prime;
     d.nprime = nprime;
     d.L = (int)L;
@@ -273,8 +280,8 @@ void prof_clear(pir_server* s) {
 // shape times every candidate once (after a warm-up) with events on the server's stream and
 // keeps the fastest; every candidate computes identical bits, so tuning never changes a
 // result.  ZIPPIR_AUTOTUNE=0 disables tuning (default shape); ZIPPIR_TUNE_CACHE=<file>
-// persists choices as lines "rows pitch ncol rowmajor waves depth mr kb ksplit".
-using TuneKey = std::tuple<int, int, int, int>;
+// persists choices as lines "rows pitch ncol rowmajor planes waves depth mr kb ksplit".
+using TuneKey = std::tuple<int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, zp::GemmShape> g_tune;
 bool g_tune_loaded = false;
@@ -295,10 +302,10 @@ void tune_load_locked() {
   const char* path = tune_cache_path();
   if (!path) return;
   std::ifstream f(path);
-  int r, p, n, m, w, d, mr, kb, k;
-  while (f >> r >> p >> n >> m >> w >> d >> mr >> kb >> k) {
+  int r, p, n, m, pl, w, d, mr, kb, k;
+  while (f >> r >> p >> n >> m >> pl >> w >> d >> mr >> kb >> k) {
     const zp::GemmShape sh{w, d, mr, kb, k};
-    if (zp::gemm_shape_valid(sh, p)) g_tune[TuneKey(r, p, n, m)] = sh;
+    if (zp::gemm_shape_valid(sh, p) && (pl == 1 || pl == 4)) g_tune[TuneKey(r, p, n, m, pl)] = sh;
   }
 }
 
@@ -308,7 +315,8 @@ void tune_store_locked() {
   std::ofstream f(path, std::ios::trunc);
   for (auto& kv : g_tune)
     f << std::get<0>(kv.first) << " " << std::get<1>(kv.first) << " " << std::get<2>(kv.first) << " "
-      << std::get<3>(kv.first) << " " << kv.second.waves << " " << kv.second.depth << " "
+      << std::get<3>(kv.first) << " " << std::get<4>(kv.first) << " " << kv.second.waves << " "
+      << kv.second.depth << " "
       << kv.second.mr << " " << kv.second.kb << " " << kv.second.ksplit << "\n";
 }
 
@@ -317,12 +325,12 @@ bool autotune_enabled() {
   return !(e && std::strcmp(e, "0") == 0);
 }
 
-// out = D . X mod 2^32 with the tuned launch shape.
-pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
-                    const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
-                    bool rowmajor, long long ld) {
+// out = D . X (mod 2^32 for four planes) with the tuned launch shape.
+pir_status run_gemm_x(pir_server* s, const uint8_t* D, int rows, int cols, int pitch, int planes,
+                      const int8_t* Xs, const int32_t* colsum, int ncol, const int32_t* rowsum,
+                      uint32_t* out, bool rowmajor, long long ld) {
   hipStream_t st = s->stream;
-  const TuneKey key((int)rows, (int)s->pitch, ncol, rowmajor ? 1 : 0);
+  const TuneKey key((int)rows, pitch, ncol, rowmajor ? 1 : 0, planes);
   zp::GemmShape shape = kDefaultShape;
   bool need_tune = false;
   {
@@ -338,12 +346,12 @@ pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
     ZP_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     for (const zp::GemmShape& c : kCandidates) {
-      if (!zp::gemm_shape_valid(c, (int)s->pitch)) continue;
-      zp::launch_gemm_planes(D, rows, (int)s->cols, (int)s->pitch, Xs, colsum, ncol, rowsum, out,
-                             rowmajor, ld, c, st);
+      if (!zp::gemm_shape_valid(c, pitch)) continue;
+      zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor,
+                             ld, c, st);
       ZP_HIP(hipEventRecord(e0, st));
-      zp::launch_gemm_planes(D, rows, (int)s->cols, (int)s->pitch, Xs, colsum, ncol, rowsum, out,
-                             rowmajor, ld, c, st);
+      zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor,
+                             ld, c, st);
       ZP_HIP(hipEventRecord(e1, st));
       ZP_HIP(hipEventSynchronize(e1));
       float ms = 0;
@@ -359,10 +367,18 @@ pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
     g_tune[key] = shape;
     tune_store_locked();
   }
-  ProfScope ps(s, PIR_KERNEL_GEMM);
-  zp::launch_gemm_planes(D, rows, (int)s->cols, (int)s->pitch, Xs, colsum, ncol, rowsum, out,
-                         rowmajor, ld, shape, st);
+  ProfScope ps(s, planes == 4 ? PIR_KERNEL_GEMM : PIR_KERNEL_OFFSET_GEMM);
+  zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor, ld,
+                         shape, st);
   return PIR_OK;
+}
+
+// The database contraction: out = D . X mod 2^32 over the rows of D starting at D.
+pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
+                    const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
+                    bool rowmajor, long long ld) {
+  return run_gemm_x(s, D, rows, (int)s->cols, (int)s->pitch, 4, Xs, colsum, ncol, rowsum, out,
+                    rowmajor, ld);
 }
 
 // Batched answers stream D in row chunks of at most kLaunchBytes (see launch_matvec).
@@ -432,6 +448,40 @@ ClientState* find_client(pir_server* s, uint32_t id) {
 hipStream_t zp::server_stream(pir_server* s) { return s->stream; }
 int zp::server_device(pir_server* s) { return s->device; }
 void zp::set_error(const char* msg) { g_last_error = msg; }
+
+// Recompute the packed group keys of `groups` (all groups when empty) for a client whose rows
+// in those groups are valid.  Synchronizes the stream.
+pir_status refresh_groups(pir_server* s, ClientState* c, std::vector<uint32_t> groups) {
+  if (c->ell <= 1) return PIR_OK;
+  const uint32_t G = (s->rows + c->ell - 1) / c->ell;
+  const bool all = groups.empty();
+  hipStream_t st = s->stream;
+  const zp::ClientDev cd = c->dev();
+  uint32_t* dg = nullptr;
+  const int ng = all ? (int)G : (int)groups.size();
+  if (!all) {
+    ZP_TRY(s->alloc((void**)&dg, groups.size() * sizeof(uint32_t)));
+    (void)hipMemcpyAsync(dg, groups.data(), groups.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+  }
+  zp::launch_group_keys(cd, c->Kp, (int)s->rows, (int)c->ell, (int)c->t, dg, ng, c->Kg, st);
+  zp::launch_combine_key(cd, c->Kg, dg, ng, c->Mr, st);
+  zp::launch_to_mont(cd, c->Mr, dg, ng, st);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (dg) s->release(dg);
+  if (e != hipSuccess) return fail(PIR_EDEVICE, std::string("group keys: ") + hipGetErrorString(e));
+  if (all) {
+    std::fill(c->gvalid.begin(), c->gvalid.end(), 1);
+    c->gstale = 0;
+  } else {
+    for (uint32_t g : groups)
+      if (!c->gvalid[g]) {
+        c->gvalid[g] = 1;
+        --c->gstale;
+      }
+  }
+  return PIR_OK;
+}
 
 // ============================================================================= C ABI
 
@@ -543,7 +593,8 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
   const Big C2 = big_pow2_mod(64ull * c->SN, c->N);
   c->m2prime = neg_inv32(N2[0]);
   c->nprime = neg_inv32(c->N[0]);
-  std::vector<uint32_t> host(4 * (size_t)c->S + 3 * (size_t)c->SN, 0u);
+  const Big CP = big_pow2_mod(64ull * c->S - 32, big_resize(N2, c->L));
+  std::vector<uint32_t> host(5 * (size_t)c->S + 3 * (size_t)c->SN, 0u);
   auto put = [&](size_t off, const Big& v, size_t width) {
     for (size_t i = 0; i < std::min(width, v.size()); ++i) host[off + i] = v[i];
   };
@@ -554,6 +605,14 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
   put(4 * (size_t)c->S, Nn, c->SN);
   put(4 * (size_t)c->S + c->SN, C1, c->SN);
   put(4 * (size_t)c->S + 2 * c->SN, C2, c->SN);
+  put(4 * (size_t)c->S + 3 * c->SN, CP, c->S);
+  // packing scale gamma = 2^t >= q + n q^2 (q = 2^32): t = 64 + bitlen(n); ell t <= N_bits - 1
+  {
+    uint32_t bl = 0;
+    for (uint32_t v = s->n; v; v >>= 1) ++bl;
+    c->t = 64 + bl;
+    c->ell_max = std::max<uint32_t>(1, (N_bits - 1) / c->t);
+  }
 
   hipStream_t st = s->stream;
   ZP_TRY(s->alloc((void**)&c->consts, host.size() * sizeof(uint32_t)));
@@ -598,6 +657,8 @@ pir_status pir_remove_client(pir_server* s, uint32_t id) {
   s->release(c->consts);
   s->release(c->Kp);
   s->release(c->Mp);
+  s->release(c->Kg);
+  s->release(c->Mr);
   s->clients.erase(id);
   return PIR_OK;
 }
@@ -660,6 +721,21 @@ pir_status pir_hint(pir_server* s, uint32_t id, const uint32_t* rows, uint32_t n
         --c->stale;
       }
   }
+  if (c->ell > 1) {
+    // refresh the groups whose rows are now all valid
+    std::vector<uint32_t> groups;
+    const uint32_t G = (s->rows + c->ell - 1) / c->ell;
+    for (uint32_t g = 0; g < G; ++g) {
+      if (c->gvalid[g]) continue;
+      bool ok = true;
+      for (uint32_t r = g * c->ell; r < std::min(s->rows, (g + 1) * c->ell) && ok; ++r) ok = c->valid[r] != 0;
+      if (ok) groups.push_back(g);
+    }
+    if (!groups.empty()) {
+      if (groups.size() == G) groups.clear();
+      ZP_TRY(refresh_groups(s, c, groups));
+    }
+  }
   return PIR_OK;
 }
 
@@ -708,6 +784,10 @@ pir_status pir_update_rows(pir_server* s, const uint32_t* rows, uint32_t nrows,
       if (c->valid[r]) {
         c->valid[r] = 0;
         ++c->stale;
+      }
+      if (c->ell > 1 && c->gvalid[r / c->ell]) {
+        c->gvalid[r / c->ell] = 0;
+        ++c->gstale;
       }
     }
   }
@@ -807,6 +887,87 @@ pir_status pir_compress(pir_server* s, const uint32_t* ids, uint32_t batch, cons
     ProfScope ps(s, PIR_KERNEL_COMPRESS);
     zp::launch_compress(cs[i]->dev(), cs[i]->Kp, cs[i]->Mp, dB + (size_t)i * s->rows,
                         (int)s->rows, dC + (size_t)i * s->rows * L, st);
+  }
+  ZP_HIP(hipGetLastError());
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(C, dC, cbytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_set_packing(pir_server* s, uint32_t id, uint32_t ell) {
+  g_last_error.clear();
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  ClientState* c = find_client(s, id);
+  if (!c) return fail(PIR_EINVAL, "unknown client id");
+  if (ell < 1 || ell > c->ell_max)
+    return fail(PIR_EINVAL, "ell must be in [1, " + std::to_string(c->ell_max) + "] (gamma^ell < N)");
+  ZP_TRY(use_device(s));
+  ZP_HIP(hipStreamSynchronize(s->stream));
+  s->release(c->Kg);
+  s->release(c->Mr);
+  c->Kg = c->Mr = nullptr;
+  c->ell = ell;
+  c->gvalid.clear();
+  c->gstale = 0;
+  if (ell == 1) return PIR_OK;
+  const uint32_t G = (s->rows + ell - 1) / ell;
+  ZP_TRY(s->alloc((void**)&c->Kg, (size_t)G * c->L * sizeof(uint32_t)));
+  ZP_TRY(s->alloc((void**)&c->Mr, (size_t)G * c->L * sizeof(uint32_t)));
+  c->gvalid.assign(G, 0);
+  c->gstale = G;
+  if (c->stale == 0) ZP_TRY(refresh_groups(s, c, {}));
+  return PIR_OK;
+}
+
+pir_status pir_packing_info(pir_server* s, uint32_t id, uint32_t* ell, uint32_t* ell_max,
+                            uint32_t* log2_gamma, uint32_t* groups) {
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  ClientState* c = find_client(s, id);
+  if (!c) return fail(PIR_EINVAL, "unknown client id");
+  if (ell) *ell = c->ell;
+  if (ell_max) *ell_max = c->ell_max;
+  if (log2_gamma) *log2_gamma = c->t;
+  if (groups) *groups = (s->rows + c->ell - 1) / c->ell;
+  return PIR_OK;
+}
+
+pir_status pir_compress_packed(pir_server* s, const uint32_t* ids, uint32_t batch,
+                               const uint32_t* B, uint32_t* C, uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !ids || !B || !C) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  if (batch < 1 || batch > 1024) return fail(PIR_EINVAL, "batch must be in [1, 1024]");
+  std::vector<ClientState*> cs(batch);
+  for (uint32_t i = 0; i < batch; ++i) {
+    cs[i] = find_client(s, ids[i]);
+    if (!cs[i]) return fail(PIR_EINVAL, "unknown client id " + std::to_string(ids[i]));
+    if (cs[i]->ell <= 1) return fail(PIR_EINVAL, "client " + std::to_string(ids[i]) + " has no packing set");
+    if (cs[i]->L != cs[0]->L || cs[i]->ell != cs[0]->ell)
+      return fail(PIR_EINVAL, "clients in one call must share L and ell");
+    if (cs[i]->stale != 0 || cs[i]->gstale != 0)
+      return fail(PIR_ESTALE, "client " + std::to_string(ids[i]) + " has stale hint rows or groups");
+  }
+  ZP_TRY(use_device(s));
+  hipStream_t st = s->stream;
+  const uint32_t L = cs[0]->L, ell = cs[0]->ell;
+  const uint32_t G = (s->rows + ell - 1) / ell;
+  const uint32_t* dB = B;
+  uint32_t* dC = C;
+  const size_t bbytes = (size_t)batch * s->rows * sizeof(uint32_t);
+  const size_t cbytes = (size_t)batch * G * L * sizeof(uint32_t);
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_b, bbytes));
+    ZP_TRY(s->scratch(s->s_c, cbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_b.p, B, bbytes, hipMemcpyHostToDevice, st));
+    dB = (const uint32_t*)s->s_b.p;
+    dC = (uint32_t*)s->s_c.p;
+  }
+  for (uint32_t i = 0; i < batch; ++i) {
+    ProfScope ps(s, PIR_KERNEL_COMPRESS);
+    zp::launch_compress_packed(cs[i]->dev(), cs[i]->Kg, cs[i]->Mr, dB + (size_t)i * s->rows,
+                               (int)s->rows, (int)ell, (int)cs[i]->t, dC + (size_t)i * G * L, st);
   }
   ZP_HIP(hipGetLastError());
   if (ptr_flags == PIR_PTR_HOST) {

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libzippir.so")
 PIR_OK, PIR_EINVAL, PIR_ENOMEM, PIR_EDEVICE, PIR_ESTALE, PIR_EBUSY = 0, -1, -2, -3, -4, -5
 PIR_PTR_HOST, PIR_PTR_DEVICE = 0, 1
 PATH_AUTO, PATH_MATVEC, PATH_MFMA = 0, 1, 2
-KERNELS = {"matvec": 0, "gemm": 1, "compress": 2, "hint": 3, "table": 4, "key": 5}
+KERNELS = {"matvec": 0, "gemm": 1, "compress": 2, "hint": 3, "table": 4, "key": 5, "offset_gemm": 6,
+           "offset": 7}
 
 
 class ZipPIRError(RuntimeError):
@@ -50,6 +51,12 @@ _sig = {
                                          ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32]),
     "pir_compress": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_set_packing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
+    "pir_packing_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                          ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                          ctypes.POINTER(ctypes.c_uint32)]),
+    "pir_compress_packed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_get_global_hint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                              ctypes.c_void_p, ctypes.c_uint32]),
     "pir_get_client_hint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
@@ -201,6 +208,20 @@ class Server:
         ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
         _check(_lib.pir_compress(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(B)[0],
                                  _ptr(C)[0], _flags(B, C)), "pir_compress")
+
+    # -- packed responses
+    def set_packing(self, cid: int, ell: int) -> None:
+        _check(_lib.pir_set_packing(self._h, cid, ell), "pir_set_packing")
+
+    def packing_info(self, cid: int) -> dict:
+        v = [ctypes.c_uint32() for _ in range(4)]
+        _check(_lib.pir_packing_info(self._h, cid, *[ctypes.byref(x) for x in v]), "pir_packing_info")
+        return dict(zip(("ell", "ell_max", "log2_gamma", "groups"), (x.value for x in v)))
+
+    def compress_packed(self, ids, B, C) -> None:
+        ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        _check(_lib.pir_compress_packed(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(B)[0],
+                                        _ptr(C)[0], _flags(B, C)), "pir_compress_packed")
 
     # -- introspection
     def global_hint(self, row0: int, nrows: int, out) -> None:

@@ -3,6 +3,8 @@
 * 1 GiB database, one query (32768 x 32768 uint8, n = 1024, N 2048-bit): full answer vs the
   oracle on every row; K and c on sampled rows (first, last, a planted zero row and seeded
   random rows) vs the oracle; the client's decryption recovers the column on those rows.
+  Packed response at ell = 27 (gamma = 2^75): three groups (first, the zero row's, the short
+  last one) vs the oracle, and their decryption recovers the column on every row.
 * 1 GiB database, 32 clients: the int8-MFMA batch vs 32 matvecs on every row, vs the oracle
   on sampled rows; the batch-32 combine vs the oracle on sampled rows per client.
 * Offline hint and 1% update: H on sampled rows vs the oracle; after replacing 328 rows,
@@ -75,6 +77,16 @@ def test_c2_one_query_full(native, big):
             K_gpu = np.zeros((SIDE, L), np.uint32)
             srv.client_hint(cid, 0, SIDE, K_gpu)
             C_gpu = C.cpu().numpy().view(np.uint32)[0]
+            log("fullsize c2: packed response (ell = ell_max)")
+            info = srv.packing_info(cid)
+            ell, t = info["ell_max"], info["log2_gamma"]
+            assert (t, ell) == (75, 27)
+            srv.set_packing(cid, ell)
+            G = srv.packing_info(cid)["groups"]
+            Cp = torch.zeros((1, G, L), dtype=torch.int32, device=dev)
+            srv.compress_packed([cid], B, Cp)
+            srv.sync()
+            Cp_gpu = Cp.cpu().numpy().view(np.uint32)[0]
             B2 = torch.zeros_like(B)
             srv.answer(q, B2, native.PATH_MFMA)
             srv.sync()
@@ -93,6 +105,16 @@ def test_c2_one_query_full(native, big):
         mu = paillier.decrypt(cl.sk, c_or)
         assert lwe.pir_extract_value(mu) == int(D[j, cl.col]), f"round trip row {j}"
     assert wl.limbs_to_int(K_gpu[ZERO_ROW]) == 1
+    # packed groups: first, the zero row's, last (17 rows); every row's digit decrypts to D
+    log("fullsize c2: packed groups vs oracle")
+    gamma = 1 << t
+    for g in (0, ZERO_ROW // ell, G - 1):
+        r0, r1 = g * ell, min(SIDE, g * ell + ell)
+        Kg = [wl.limbs_to_int(K_gpu[j]) for j in range(r0, r1)]
+        want = server.compress_packed(Kg, b_or[r0:r1], cl.N, ell, gamma)[0]
+        assert wl.limbs_to_int(Cp_gpu[g]) == want, f"packed group {g}"
+        digits = server.packed_digits(paillier.decrypt(cl.sk, want), r1 - r0, gamma)
+        assert [lwe.pir_extract_value(m) for m in digits] == D[r0:r1, cl.col].tolist()
 
 
 def test_c3_batch32_full(native, big):

@@ -303,5 +303,5 @@ def test_autotuned_shape_is_persisted(native, tmp_path, monkeypatch):
         srv.answer(Qm, B, native.PATH_MFMA)
         assert np.array_equal(B, server.answer_batch(D, Qm))
     lines = [l.split() for l in cache.read_text().splitlines()]
-    mine = [l for l in lines if l[:4] == [str(rows), str(cols + (-cols) % 256), str(batch), "0"]]
-    assert len(mine) == 1 and len(mine[0]) == 9
+    mine = [l for l in lines if l[:5] == [str(rows), str(cols + (-cols) % 256), str(batch), "0", "4"]]
+    assert len(mine) == 1 and len(mine[0]) == 10
