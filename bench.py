@@ -242,6 +242,48 @@ def main() -> int:
               "compress_kernel_avg_us": round(pk_ms / max(1, pk_n) * 1e3, 2),
               "group_key_build_s": round(gk_s, 3)}
 
+    # full protocol (Alg. 5): online offset answer t = (b + E.ck_o) mod N after the matvec,
+    # then optionally the Paillier-added response k (1 + t N) mod N^2
+    og = wl.rng(1, "query", 1 << 16)
+    cko = [wl.uniform_below(og, N) for _ in range(n)]
+    CKOt = torch.from_numpy(wl.ints_to_limbs(cko, h).view(np.int32)[None].copy()).to(dev)
+    T1 = torch.zeros((1, rows, h), dtype=torch.int32, device=dev)
+    for _ in range(3):
+        srv.answer(q1, B1, native.PATH_MATVEC)
+        srv.offset_answer([cid], CKOt, B1, T1)
+    srv.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        srv.answer(q1, B1, native.PATH_MATVEC)
+        srv.offset_answer([cid], CKOt, B1, T1)
+    torch.cuda.synchronize()
+    fp_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    og_ms, og_n = srv.profile_read("offset_gemm")
+    or_ms, or_n = srv.profile_read("offset")
+    srv.profile(False)
+    srv.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        srv.answer(q1, B1, native.PATH_MATVEC)
+        srv.offset_answer([cid], CKOt, B1, T1)
+        srv.compress_offset([cid], T1, C1)
+    torch.cuda.synchronize()
+    fpc_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    oc_ms, oc_n = srv.profile_read("compress")
+    srv.profile(False)
+    og_avg = og_ms / max(1, og_n)
+    off_ops = 2.0 * rows * 4 * n * (4 * h + 3)
+    full = {"ms_per_step": round(fp_ms, 4), "db_gbs": round(db_bytes / (fp_ms * 1e-3) / 1e9, 3),
+            "with_combine_ms_per_step": round(fpc_ms, 4),
+            "offset_gemm_kernel_avg_us": round(og_avg * 1e3, 2),
+            "offset_gemm_int8_tops": round(off_ops / (og_avg * 1e-3) / 1e12, 1),
+            "offset_gemm_frac_of_peak": round(off_ops / (og_avg * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+            "offset_reduce_kernel_avg_us": round(or_ms / max(1, or_n) * 1e3, 2),
+            "combine_kernel_avg_us": round(oc_ms / max(1, oc_n) * 1e3, 2),
+            "response_bytes": rows * h * 4, "hint_bytes": rows * L * 4}
+
     # dominant kernel's own duration: 8 queries' matvecs back to back between two events
     Q8 = Qt[:8].contiguous()
     B8 = torch.zeros((8, rows), dtype=torch.int32, device=dev)
@@ -311,6 +353,7 @@ def main() -> int:
                     "db_gbs": round(db_bytes / (gm_avg_ms * 1e-3) / 1e9, 1),
                     "bit_identical_to_matvec": same},
         "packed": packed,
+        "full_protocol": full,
         "offline_hint_s": round(hint_s, 3),
         "hint_kernel_ms": round(hintk_ms, 1),
         "roofline": roof,

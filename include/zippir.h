@@ -152,6 +152,32 @@ pir_status pir_packing_info(pir_server *srv, uint32_t client_id, uint32_t *ell, 
 pir_status pir_compress_packed(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
                                const uint32_t *B, uint32_t *C, uint32_t ptr_flags);
 
+/*
+ * The paper's full protocol (Alg. 5; Sec. 4.3 "Faster matrix multiplication using RNS",
+ * "Lowering offline communication costs").  The client registers random ciphertexts ck_r
+ * as its key (pir_add_client), so pir_hint computes k_j = prod_k ck_r,k^{E_jk} mod N^2, and
+ * sends online the offset ck_o = (s - Dec(ck_r)) mod N beside the LWE query.
+ *
+ * pir_offset_answer (Alg. 5 Response, second line):
+ *     T[c][j] = (B[c][j] + sum_k E_jk CKO[c][k]) mod N_c,   E = (-H) mod 2^32,
+ *   CKO is batch x n x h uint32 (entry k of client c's offset as h little-endian limbs; any
+ *   value below 2^(32 h)), B is batch x rows uint32 (pir_answer's output), T is
+ *   batch x rows x h uint32, canonical in [0, N_c).  Computes the global hint first if it is
+ *   missing or stale (as pir_hint does).  Needs n <= 16384; every client in one call must use
+ *   the same limb count h; batch <= 128.  Uses device scratch of about
+ *   rows x batch x (16 h + 16) bytes.
+ *   The client finishes with mu = (T + Dec(k_j)) mod N (Alg. 5 Extract).
+ * pir_compress_offset (Sec. 4.3 "Smaller responses w/ Paillier addition" applied to t):
+ *     C[c][j] = k_{c,j} (1 + T[c][j] N_c) mod N_c^2,
+ *   T as written by pir_offset_answer, C batch x rows x L uint32; then mu = Dec(C).
+ *   PIR_ESTALE if a client's hint has stale rows.
+ */
+pir_status pir_offset_answer(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
+                             const uint32_t *CKO, const uint32_t *B, uint32_t *T,
+                             uint32_t ptr_flags);
+pir_status pir_compress_offset(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
+                               const uint32_t *T, uint32_t *C, uint32_t ptr_flags);
+
 /* Copy rows [row0, row0+nrows) of H (nrows x n uint32).  PIR_ESTALE if any is stale. */
 pir_status pir_get_global_hint(pir_server *srv, uint32_t row0, uint32_t nrows, uint32_t *H,
                                uint32_t ptr_flags);

@@ -16,6 +16,8 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 //   RR  S limbs   R^2 mod N^2                NP  S limbs   N (zero padded, S-limb layout)
 //   Nn  SN limbs  N                          C1  SN limbs  R_N mod N, R_N = 2^(32 SN)
 //   C2  SN limbs  R_N^2 mod N              CP  S limbs   2^(64 S - 32) mod N^2 (K' -> K R)
+//   D1  SN limbs  R_N^2 2^-32 mod N         D2  SN limbs  R_N^3 2^-32 mod N
+//   (D1, D2 map K' = lo + hi R_N to (K mod N) R_N mod N with two Montgomery products)
 struct ClientDev {
   const uint32_t* N2;
   const uint32_t* R1;
@@ -25,6 +27,8 @@ struct ClientDev {
   const uint32_t* C1;
   const uint32_t* C2;
   const uint32_t* CP;
+  const uint32_t* D1;
+  const uint32_t* D2;
   uint32_t m2prime;  // -(N^2)^{-1} mod 2^32
   uint32_t nprime;   // -N^{-1} mod 2^32
   int L;             // limbs of a ciphertext (2h)
@@ -112,6 +116,24 @@ void launch_to_mont(const ClientDev& cd, uint32_t* x, const uint32_t* rowlist, i
 // C[g] = K_g + beta_g M_g mod N^2 with beta_g = sum_j b[g ell + j] 2^(t j); Mr holds M_g R.
 void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint32_t* Mr,
                             const uint32_t* b, int rows, int ell, int t, uint32_t* C, hipStream_t s);
+
+// ---- offset answer of the full protocol (offset.hip)
+// Eb row j (epitch bytes) = the 4n little-endian bytes of E row j = -H row j mod 2^32, zero
+// beyond 4n; epitch is a multiple of 256.
+void launch_e_bytes(const uint32_t* H, int rows, int n, int epitch, uint8_t* Eb, hipStream_t s);
+// One-plane operand for `batch` offset vectors cko (batch x n x h limbs): column
+// i*cpc + pos, K index 4k + a holds byte (pos - a) of cko[i][k] (XOR 0x80, 0 beyond 4n);
+// also zeroes and fills colsum (batch*cpc).  cpc >= 4h + 3.
+void launch_pack_offset(const uint32_t* cko, int batch, int n, int h, int cpc, int epitch,
+                        int8_t* X, int32_t* colsum, hipStream_t s);
+// T[j] (h limbs) = (b[j] + sum_pos W[j*ldw + pos] 2^(8 pos)) mod N, pos < 4h + 3.
+void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,
+                          int rows, uint32_t* T, hipStream_t s);
+
+// C[j] = K_j (1 + T[j] N) mod N^2 for rows [0, rows): T is rows x h (any value below 2^(32h)),
+// K_j from the stored K'; C is rows x L.
+void launch_compress_offset(const ClientDev& cd, const uint32_t* Kp, const uint32_t* T, int rows,
+                            uint32_t* C, hipStream_t s);
 
 // ---- runtime.cpp accessors used by the serving engine
 hipStream_t server_stream(pir_server* s);

@@ -1,0 +1,145 @@
+// Online offset answer of the full protocol (Alg. 5, Response, second line):
+//   t_j = (b_j + sum_k E_jk ck_o,k) mod N,   E = (-H) mod 2^32,  ck_o,k < 2^(32 h),
+// the product of the shared hint matrix with one client's vector of big integers.
+//
+// The paper evaluates it in an RNS basis of small primes so that a CPU can use machine
+// words (Sec. 4.3, "Faster matrix multiplication using RNS").  Here it is one exact integer
+// contraction on int8 MFMA instead: write E_jk = sum_a 2^(8a) e_jk[a] and
+// ck_o,k = sum_c 2^(8c) y_k[c] by bytes; then
+//   sum_k E_jk ck_o,k = sum_pos 2^(8 pos) W[j][pos],
+//   W[j][pos] = sum_{k, a} e_jk[a] y_k[pos - a]          (0 <= pos - a < 4h),
+// which is the uint8 product of E's rows read as 4n bytes (little-endian, so the byte of
+// E_jk with weight 2^(8a) sits at K index 4k + a) with a 4n x (4h + 3) byte matrix whose
+// column pos holds the bytes y_k[pos - a].  Every W entry is below 4n 255^2 < 2^32, so the
+// contraction is exact in 32-bit accumulators.  A reduction kernel then folds the byte
+// positions into limbs, adds b_j and reduces modulo N.
+#include "internal.h"
+#include "wavenum.h"
+
+namespace zp {
+
+// Eb row j = the 4n bytes of E row j (E_jk = -H_jk mod 2^32), zero up to the pitch.
+__global__ __launch_bounds__(256) void e_bytes_kernel(const uint32_t* __restrict__ H, int rows,
+                                                      int n, int epitch_words,
+                                                      uint32_t* __restrict__ Eb) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= (long long)rows * epitch_words) return;
+  const long long j = i / epitch_words;
+  const int k = (int)(i - j * epitch_words);
+  Eb[i] = k < n ? 0u - H[j * n + k] : 0u;
+}
+
+void launch_e_bytes(const uint32_t* H, int rows, int n, int epitch, uint8_t* Eb, hipStream_t s) {
+  const long long words = (long long)rows * (epitch / 4);
+  const int blocks = (int)((words + 255) / 256);
+  e_bytes_kernel<<<blocks, 256, 0, s>>>(H, rows, n, epitch / 4, reinterpret_cast<uint32_t*>(Eb));
+}
+
+// Column col = i*cpc + pos of the shifted-byte operand for client i: X[col][4k + a] is byte
+// (pos - a) of ck_o,k (0 outside [0, 4h)), stored as X ^ 0x80 for K indices below 4n and 0
+// beyond (the one-plane layout of launch_gemm_planes); colsum[col] sums the stored int8s.
+__global__ __launch_bounds__(256) void pack_offset_kernel(const uint32_t* __restrict__ cko, int n,
+                                                          int h, int cpc, int epitch,
+                                                          int8_t* __restrict__ X,
+                                                          int32_t* __restrict__ colsum) {
+  const int col = blockIdx.y;
+  const int client = col / cpc, pos = col - client * cpc;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;  // one K quadruple (4k .. 4k+3)
+  int32_t part = 0;
+  if (4 * k < epitch) {
+    uint32_t w = 0;
+    if (k < n) {
+      const uint32_t* y = cko + ((size_t)client * n + k) * h;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int idx = pos - a;
+        uint32_t v = 0;
+        if (idx >= 0 && idx < 4 * h) v = (y[idx >> 2] >> (8 * (idx & 3))) & 0xFFu;
+        const uint32_t sb = v ^ 0x80u;
+        w |= sb << (8 * a);
+        part += (int32_t)(int8_t)sb;
+      }
+    }
+    reinterpret_cast<uint32_t*>(X + (size_t)col * epitch)[k] = w;
+  }
+  __shared__ int32_t red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
+  if (lane == 0) red[wave] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(colsum + col, red[0] + red[1] + red[2] + red[3]);
+}
+
+void launch_pack_offset(const uint32_t* cko, int batch, int n, int h, int cpc, int epitch,
+                        int8_t* X, int32_t* colsum, hipStream_t s) {
+  (void)hipMemsetAsync(colsum, 0, sizeof(int32_t) * (size_t)batch * cpc, s);
+  dim3 grid((epitch / 4 + 255) / 256, batch * cpc);
+  pack_offset_kernel<<<grid, 256, 0, s>>>(cko, n, h, cpc, epitch, X, colsum);
+}
+
+// t_j from W[j][0 .. 4h+3): one wavefront per row, numbers of SN = 64 PN limbs.
+//   value = b_j + sum_pos W[j][pos] 2^(8 pos) = lo + hi 2^(32 SN),  lo < 2^(32 SN), hi < 2^64,
+//   t_j   = (lo mod N + hi 2^(32 SN) mod N) mod N
+// with lo mod N = lo C1 R_N^{-1} (C1 = R_N mod N) and hi R_N mod N = hi C2 R_N^{-1}
+// (C2 = R_N^2 mod N), two Montgomery products modulo N, as for the combine key.
+template <int PN>
+__global__ __launch_bounds__(256) void offset_reduce_kernel(ClientDev cd, const uint32_t* __restrict__ W,
+                                                            long long ldw,
+                                                            const uint32_t* __restrict__ b, int rows,
+                                                            uint32_t* __restrict__ T) {
+  constexpr int SN = 64 * PN;
+  const int j = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (j >= rows) return;
+  const uint32_t* w = W + (size_t)j * ldw;
+  const int npos = 4 * cd.h + 3;
+  WNum<PN> lo, hiw, Nn, C1, C2, x, y;
+  uint64_t carry = 0;
+#pragma unroll
+  for (int jj = 0; jj < PN; ++jj) {
+    const int limb = PN * lane_id() + jj;
+    uint64_t v = carry;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int pos = 4 * limb + u;
+      if (pos < npos) v += (uint64_t)w[pos] << (8 * u);
+    }
+    if (limb == 0) v += b[j];
+    lo.v[jj] = (uint32_t)v;
+    carry = v >> 32;
+  }
+  uint64_t hi = wn_resolve(lo, carry);
+  for (int pos = 4 * SN; pos < npos; ++pos) hi += (uint64_t)w[pos] << (8 * (pos - 4 * SN));
+#pragma unroll
+  for (int jj = 0; jj < PN; ++jj) {
+    const int limb = PN * lane_id() + jj;
+    hiw.v[jj] = limb == 0 ? (uint32_t)hi : (limb == 1 ? (uint32_t)(hi >> 32) : 0u);
+  }
+  wn_load(Nn, cd.Nn);
+  wn_load(C1, cd.C1);
+  wn_load(C2, cd.C2);
+  mont_mul(x, lo, C1, Nn, cd.nprime);
+  mont_mul(y, hiw, C2, Nn, cd.nprime);
+  uint32_t c = 0;
+#pragma unroll
+  for (int jj = 0; jj < PN; ++jj) {
+    const uint64_t s = (uint64_t)x.v[jj] + y.v[jj] + c;
+    x.v[jj] = (uint32_t)s;
+    c = (uint32_t)(s >> 32);
+  }
+  const uint64_t ovf = wn_resolve(x, (uint64_t)c);
+  wn_cond_sub(x, ovf, Nn);
+  wn_store_n(T + (size_t)j * cd.h, x, cd.h);
+}
+
+void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,
+                          int rows, uint32_t* T, hipStream_t s) {
+  if (rows <= 0) return;
+  const int blocks = (rows + 3) / 4;
+  if (cd.PN == 1)
+    offset_reduce_kernel<1><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T);
+  else
+    offset_reduce_kernel<2><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T);
+}
+
+}  // namespace zp

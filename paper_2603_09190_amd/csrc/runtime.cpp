@@ -133,7 +133,7 @@ struct ClientState {
   uint32_t n_bits = 0, h = 0, L = 0, P = 0, PN = 0, S = 0, SN = 0;
   Big N;
   uint32_t* ck = nullptr;      // n x L
-  uint32_t* consts = nullptr;  // N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each) | CP (S)
+  uint32_t* consts = nullptr;  // N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each) | CP (S) | D1 | D2 (SN each)
   uint32_t* Kp = nullptr;      // rows x L: K_j 2^32 mod N^2
   uint32_t* Mp = nullptr;      // rows x L: N (K'_j mod N), the combine key
   uint32_t m2prime = 0, nprime = 0;
@@ -156,6 +156,8 @@ struct ClientState {
     d.C1 = consts + 4 * S + SN;
     d.C2 = consts + 4 * S + 2 * SN;
     d.CP = consts + 4 * S + 3 * SN;
+    d.D1 = consts + 5 * S + 3 * SN;
+    d.D2 = consts + 5 * S + 4 * SN;
     d.m2prime = m2prime;
     d.nprime = nprime;
     d.L = (int)L;
@@ -178,6 +180,11 @@ struct pir_server {
   uint32_t* H = nullptr;        // rows x n
   std::vector<uint8_t> H_valid;
   int64_t H_stale = 0;
+  // E = -H mod 2^32 as bytes for the offset answer, built on first use after H changes
+  uint8_t* Eb = nullptr;        // rows x epitch
+  int32_t* Erowsum = nullptr;   // rows: sum_{i<4n} (Eb[j][i] - 128)
+  uint32_t epitch = 0;
+  bool E_ready = false;
   std::map<uint32_t, std::unique_ptr<ClientState>> clients;
   uint32_t next_id = 1;
   std::map<void*, size_t> allocs;
@@ -190,7 +197,7 @@ struct pir_server {
   };
   std::vector<ProfRecord> prof_ev[PIR_KERNEL_COUNT];
   // growable scratch
-  DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c;
+  DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c, s_x, s_xcs, s_w, s_t;
 
   pir_status alloc(void** p, size_t bytes_) {
     *p = nullptr;
@@ -426,6 +433,7 @@ pir_status refresh_H(pir_server* s, const std::vector<uint32_t>& rows_in) {
       s->H_valid[r] = 1;
       --s->H_stale;
     }
+  s->E_ready = false;
   return PIR_OK;
 }
 
@@ -448,6 +456,22 @@ ClientState* find_client(pir_server* s, uint32_t id) {
 hipStream_t zp::server_stream(pir_server* s) { return s->stream; }
 int zp::server_device(pir_server* s) { return s->device; }
 void zp::set_error(const char* msg) { g_last_error = msg; }
+
+// E bytes and their row sums for the offset answer (H must be valid).
+pir_status ensure_E(pir_server* s) {
+  if (s->E_ready) return PIR_OK;
+  hipStream_t st = s->stream;
+  if (!s->Eb) {
+    s->epitch = (4 * s->n + 255) / 256 * 256;
+    ZP_TRY(s->alloc((void**)&s->Eb, (size_t)s->rows * s->epitch));
+    ZP_TRY(s->alloc((void**)&s->Erowsum, (size_t)s->rows * sizeof(int32_t)));
+  }
+  zp::launch_e_bytes(s->H, (int)s->rows, (int)s->n, (int)s->epitch, s->Eb, st);
+  zp::launch_rowsum(s->Eb, (int)s->rows, 4 * (int)s->n, (int)s->epitch, s->Erowsum, st);
+  ZP_HIP(hipGetLastError());
+  s->E_ready = true;
+  return PIR_OK;
+}
 
 // Recompute the packed group keys of `groups` (all groups when empty) for a client whose rows
 // in those groups are valid.  Synchronizes the stream.
@@ -594,7 +618,9 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
   c->m2prime = neg_inv32(N2[0]);
   c->nprime = neg_inv32(c->N[0]);
   const Big CP = big_pow2_mod(64ull * c->S - 32, big_resize(N2, c->L));
-  std::vector<uint32_t> host(5 * (size_t)c->S + 3 * (size_t)c->SN, 0u);
+  const Big D1 = big_pow2_mod(64ull * c->SN - 32, c->N);
+  const Big D2 = big_pow2_mod(96ull * c->SN - 32, c->N);
+  std::vector<uint32_t> host(5 * (size_t)c->S + 5 * (size_t)c->SN, 0u);
   auto put = [&](size_t off, const Big& v, size_t width) {
     for (size_t i = 0; i < std::min(width, v.size()); ++i) host[off + i] = v[i];
   };
@@ -606,6 +632,8 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
   put(4 * (size_t)c->S + c->SN, C1, c->SN);
   put(4 * (size_t)c->S + 2 * c->SN, C2, c->SN);
   put(4 * (size_t)c->S + 3 * c->SN, CP, c->S);
+  put(5 * (size_t)c->S + 3 * c->SN, D1, c->SN);
+  put(5 * (size_t)c->S + 4 * c->SN, D2, c->SN);
   // packing scale gamma = 2^t >= q + n q^2 (q = 2^32): t = 64 + bitlen(n); ell t <= N_bits - 1
   {
     uint32_t bl = 0;
@@ -968,6 +996,106 @@ pir_status pir_compress_packed(pir_server* s, const uint32_t* ids, uint32_t batc
     ProfScope ps(s, PIR_KERNEL_COMPRESS);
     zp::launch_compress_packed(cs[i]->dev(), cs[i]->Kg, cs[i]->Mr, dB + (size_t)i * s->rows,
                                (int)s->rows, (int)ell, (int)cs[i]->t, dC + (size_t)i * G * L, st);
+  }
+  ZP_HIP(hipGetLastError());
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(C, dC, cbytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_offset_answer(pir_server* s, const uint32_t* ids, uint32_t batch, const uint32_t* CKO,
+                             const uint32_t* B, uint32_t* T, uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !ids || !CKO || !B || !T) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  if (batch < 1 || batch > 128) return fail(PIR_EINVAL, "batch must be in [1, 128]");
+  if (s->n > 16384) return fail(PIR_EINVAL, "the offset answer needs n <= 16384");
+  std::vector<ClientState*> cs(batch);
+  for (uint32_t i = 0; i < batch; ++i) {
+    cs[i] = find_client(s, ids[i]);
+    if (!cs[i]) return fail(PIR_EINVAL, "unknown client id " + std::to_string(ids[i]));
+    if (cs[i]->h != cs[0]->h) return fail(PIR_EINVAL, "clients in one call must share the limb count");
+  }
+  ZP_TRY(use_device(s));
+  ZP_TRY(refresh_all_stale_H(s));
+  ZP_TRY(ensure_E(s));
+  hipStream_t st = s->stream;
+  const uint32_t h = cs[0]->h;
+  const int cpc = (int)(4 * h + 4);
+  const long long ncol = (long long)batch * cpc;
+  const size_t kbytes = (size_t)batch * s->n * h * sizeof(uint32_t);
+  const size_t bbytes = (size_t)batch * s->rows * sizeof(uint32_t);
+  const size_t tbytes = (size_t)batch * s->rows * h * sizeof(uint32_t);
+  const uint32_t* dK = CKO;
+  const uint32_t* dB = B;
+  uint32_t* dT = T;
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_q, kbytes));
+    ZP_TRY(s->scratch(s->s_b, bbytes));
+    ZP_TRY(s->scratch(s->s_t, tbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_q.p, CKO, kbytes, hipMemcpyHostToDevice, st));
+    ZP_HIP(hipMemcpyAsync(s->s_b.p, B, bbytes, hipMemcpyHostToDevice, st));
+    dK = (const uint32_t*)s->s_q.p;
+    dB = (const uint32_t*)s->s_b.p;
+    dT = (uint32_t*)s->s_t.p;
+  }
+  ZP_TRY(s->scratch(s->s_x, (size_t)ncol * s->epitch));
+  ZP_TRY(s->scratch(s->s_xcs, (size_t)ncol * sizeof(int32_t)));
+  ZP_TRY(s->scratch(s->s_w, (size_t)s->rows * ncol * sizeof(uint32_t)));
+  auto* X = (int8_t*)s->s_x.p;
+  auto* xcs = (int32_t*)s->s_xcs.p;
+  auto* W = (uint32_t*)s->s_w.p;
+  zp::launch_pack_offset(dK, (int)batch, (int)s->n, (int)h, cpc, (int)s->epitch, X, xcs, st);
+  ZP_TRY(run_gemm_x(s, s->Eb, (int)s->rows, 4 * (int)s->n, (int)s->epitch, 1, X, xcs, (int)ncol,
+                    s->Erowsum, W, true, 0));
+  {
+    ProfScope ps(s, PIR_KERNEL_OFFSET, (int)batch);
+    for (uint32_t i = 0; i < batch; ++i)
+      zp::launch_offset_reduce(cs[i]->dev(), W + (size_t)i * cpc, ncol, dB + (size_t)i * s->rows,
+                               (int)s->rows, dT + (size_t)i * s->rows * h, st);
+  }
+  ZP_HIP(hipGetLastError());
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(T, dT, tbytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_compress_offset(pir_server* s, const uint32_t* ids, uint32_t batch, const uint32_t* T,
+                               uint32_t* C, uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !ids || !T || !C) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  if (batch < 1 || batch > 1024) return fail(PIR_EINVAL, "batch must be in [1, 1024]");
+  std::vector<ClientState*> cs(batch);
+  for (uint32_t i = 0; i < batch; ++i) {
+    cs[i] = find_client(s, ids[i]);
+    if (!cs[i]) return fail(PIR_EINVAL, "unknown client id " + std::to_string(ids[i]));
+    if (cs[i]->L != cs[0]->L) return fail(PIR_EINVAL, "clients in one call must share L");
+    if (cs[i]->stale != 0)
+      return fail(PIR_ESTALE, "client " + std::to_string(ids[i]) + " has stale hint rows");
+  }
+  ZP_TRY(use_device(s));
+  hipStream_t st = s->stream;
+  const uint32_t L = cs[0]->L, h = cs[0]->h;
+  const size_t tbytes = (size_t)batch * s->rows * h * sizeof(uint32_t);
+  const size_t cbytes = (size_t)batch * s->rows * L * sizeof(uint32_t);
+  const uint32_t* dT = T;
+  uint32_t* dC = C;
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_t, tbytes));
+    ZP_TRY(s->scratch(s->s_c, cbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_t.p, T, tbytes, hipMemcpyHostToDevice, st));
+    dT = (const uint32_t*)s->s_t.p;
+    dC = (uint32_t*)s->s_c.p;
+  }
+  for (uint32_t i = 0; i < batch; ++i) {
+    ProfScope ps(s, PIR_KERNEL_COMPRESS);
+    zp::launch_compress_offset(cs[i]->dev(), cs[i]->Kp, dT + (size_t)i * s->rows * h, (int)s->rows,
+                               dC + (size_t)i * s->rows * L, st);
   }
   ZP_HIP(hipGetLastError());
   if (ptr_flags == PIR_PTR_HOST) {

@@ -57,6 +57,10 @@ _sig = {
                                           ctypes.POINTER(ctypes.c_uint32)]),
     "pir_compress_packed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_offset_answer": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_compress_offset": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_get_global_hint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                              ctypes.c_void_p, ctypes.c_uint32]),
     "pir_get_client_hint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
@@ -222,6 +226,17 @@ class Server:
         ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
         _check(_lib.pir_compress_packed(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(B)[0],
                                         _ptr(C)[0], _flags(B, C)), "pir_compress_packed")
+
+    # -- full protocol (offset answer)
+    def offset_answer(self, ids, CKO, B, T) -> None:
+        ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        _check(_lib.pir_offset_answer(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(CKO)[0],
+                                      _ptr(B)[0], _ptr(T)[0], _flags(CKO, B, T)), "pir_offset_answer")
+
+    def compress_offset(self, ids, T, C) -> None:
+        ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        _check(_lib.pir_compress_offset(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(T)[0],
+                                        _ptr(C)[0], _flags(T, C)), "pir_compress_offset")
 
     # -- introspection
     def global_hint(self, row0: int, nrows: int, out) -> None:

@@ -1,0 +1,187 @@
+"""GPU parity of the paper's full protocol (Alg. 5 with random hint keys): the online offset
+answer t = (b + E.ck_o) mod N and the Paillier-added response c = k (1 + t N) mod N^2.
+
+Every comparison is bit-exact against ``oracle.protocol`` on the same seeded inputs, and the
+client's extraction recovers the selected column (ZipPIR correctness theorem).
+"""
+from multiprocessing import Pool
+
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import protocol, server
+from tests.gpu_util import client_arrays, limbs_rows_to_ints, log, pool_size
+from tests.instances import make_client, make_instance, oracle_client_hint
+
+pytestmark = pytest.mark.gpu
+
+Q32 = 1 << 32
+
+
+@pytest.fixture(scope="module")
+def native():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_09190_amd import native as nat
+    return nat
+
+
+def _decrypt_one(args):
+    sk, c = args
+    return protocol.random_key_plaintexts(sk, [c])[0]
+
+
+def _offsets(cl, pool=None):
+    """ck_o for a client whose ck holds random ciphertexts (ck_r), and its limb array."""
+    if pool is None:
+        pt_r = protocol.random_key_plaintexts(cl.sk, cl.ck)
+    else:
+        pt_r = pool.map(_decrypt_one, [(cl.sk, int(c)) for c in cl.ck])
+    cko = protocol.query_offset(cl.s, pt_r, cl.N)
+    h = (cl.N.bit_length() + 31) // 32
+    return cko, wl.ints_to_limbs(cko, h)
+
+
+@pytest.mark.parametrize("n_bits,rows,cols,n", [(256, 13, 40, 6), (1024, 70, 96, 70), (2048, 33, 64, 16),
+                                                (3072, 20, 48, 9), (4096, 17, 40, 8)])
+def test_offset_answer_and_combine(native, n_bits, rows, cols, n):
+    log(f"full protocol: N {n_bits} rows {rows} n {n}")
+    inst = make_instance(cfg=970 + n_bits, rows=rows, cols=cols, n=n, n_bits=n_bits,
+                         encrypt_secret=False, zero_row=rows // 3)
+    cl = inst.clients[0]
+    N_limbs, ckr, L = client_arrays(cl, n_bits)
+    h = L // 2
+    cko, CKO = _offsets(cl)
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    b = server.answer(inst.D, cl.qu)
+    k_or = server.client_hint(cl.ck, E, cl.N)
+    t_or = protocol.offset_answer(b, E, cko, cl.N)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ckr)
+        B = np.zeros((1, rows), np.uint32)
+        srv.answer(cl.qu[None, :], B)
+        T = np.zeros((1, rows, h), np.uint32)
+        srv.offset_answer([cid], CKO[None], B, T)   # computes H on first use
+        t_gpu = limbs_rows_to_ints(T[0])
+        srv.hint(cid)
+        C = np.zeros((1, rows, L), np.uint32)
+        srv.compress_offset([cid], T, C)
+        c_gpu = limbs_rows_to_ints(C[0])
+    assert t_gpu == t_or
+    assert c_gpu == [protocol.combine_offset(k_or[j], t_or[j], cl.N) for j in range(rows)]
+    want = inst.D[:, cl.col].tolist()
+    assert [protocol.extract(cl.sk, k_or[j], t_gpu[j]) for j in range(rows)] == want
+    assert [protocol.extract_combined(cl.sk, x) for x in c_gpu] == want
+
+
+def test_offset_answer_extremes(native):
+    # ck_o entries at 0, N - 1 and 2^(32h) - 1 (the largest the layout holds), E rows from an
+    # all-zero and an all-255 database row, b at 0 and 2^32 - 1.
+    n_bits, rows, cols, n = 2048, 8, 64, 12
+    inst = make_instance(cfg=981, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False)
+    cl = inst.clients[0]
+    N_limbs, ckr, L = client_arrays(cl, n_bits)
+    h = L // 2
+    D = inst.D.copy()
+    D[0] = 0
+    D[1] = 255
+    E = server.exponents(server.global_hint(D, inst.A))
+    cases = [[0] * n, [cl.N - 1] * n, [(1 << (32 * h)) - 1] * n,
+             [(1 << (32 * h)) - 1 if k % 2 else cl.N - 1 for k in range(n)]]
+    with native.Server(D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ckr)
+        for cko in cases:
+            for bval in (0, Q32 - 1):
+                B = np.full((1, rows), bval, np.uint32)
+                T = np.zeros((1, rows, h), np.uint32)
+                srv.offset_answer([cid], wl.ints_to_limbs(cko, h)[None], B, T)
+                assert limbs_rows_to_ints(T[0]) == protocol.offset_answer(B[0], E, cko, cl.N)
+
+
+def test_offset_batch_of_clients_and_update(native):
+    # three clients with their own keys in one call; after a row update the next call
+    # rebuilds E from the refreshed H
+    n_bits, rows, cols, n = 1024, 40, 80, 10
+    inst = make_instance(cfg=982, rows=rows, cols=cols, n=n, n_bits=n_bits, nclients=3, encrypt_secret=False)
+    offs = [_offsets(cl) for cl in inst.clients]
+    h = (n_bits + 31) // 32
+    CKO = np.stack([o[1] for o in offs])
+    Q = np.stack([cl.qu for cl in inst.clients])
+    idx = np.array([3, 39], np.uint32)
+    new = np.random.default_rng(9).integers(0, 256, size=(2, cols), dtype=np.uint8)
+    with native.Server(inst.D, inst.A) as srv:
+        ids = []
+        for cl in inst.clients:
+            N_limbs, ckr, _ = client_arrays(cl, n_bits)
+            ids.append(srv.add_client(N_limbs, n_bits, ckr))
+        B = np.zeros((3, rows), np.uint32)
+        srv.answer(Q, B)
+        T = np.zeros((3, rows, h), np.uint32)
+        srv.offset_answer(ids, CKO, B, T)
+        E = server.exponents(server.global_hint(inst.D, inst.A))
+        for i, cl in enumerate(inst.clients):
+            assert limbs_rows_to_ints(T[i]) == protocol.offset_answer(B[i], E, offs[i][0], cl.N)
+        srv.update_rows(idx, new)
+        D2 = inst.D.copy()
+        D2[idx] = new
+        srv.answer(Q, B)
+        srv.offset_answer(ids, CKO, B, T)
+        E2 = server.exponents(server.global_hint(D2, inst.A))
+        for i, cl in enumerate(inst.clients):
+            assert limbs_rows_to_ints(T[i]) == protocol.offset_answer(B[i], E2, offs[i][0], cl.N)
+        # the combined form needs each client's hint
+        C = np.zeros((3, rows, 2 * h), np.uint32)
+        with pytest.raises(native.ZipPIRError) as ei:
+            srv.compress_offset(ids, T, C)
+        assert ei.value.status == native.PIR_ESTALE
+
+
+def test_offset_full_size(native):
+    """1 GiB database, n = 1024, N 2048-bit: t on sampled rows vs the oracle, the combined
+    response on the same rows, and the client's extraction of each."""
+    import torch
+    side, nlwe, nbits = 32768, 1024, 2048
+    log("full protocol 1 GiB: database")
+    D = wl.database(1, side, side)
+    A = wl.lwe_matrix(1, side, nlwe)
+    with Pool(pool_size()) as pool:
+        log("full protocol 1 GiB: client (random key, 1024 decryptions)")
+        cl = make_client(11, 0, A, nbits, encrypt_secret=False)
+        cko, CKO = _offsets(cl, pool)
+        N_limbs, ckr, L = client_arrays(cl, nbits)
+        h = L // 2
+        dev = torch.device("cuda:0")
+        with native.Server(torch.from_numpy(D).to(dev), torch.from_numpy(A.view(np.int32)).to(dev),
+                           stream=torch.cuda.current_stream().cuda_stream) as srv:
+            cid = srv.add_client(N_limbs, nbits, ckr)
+            log("full protocol 1 GiB: hint")
+            srv.hint(cid)
+            q = torch.from_numpy(cl.qu.view(np.int32)[None, :].copy()).to(dev)
+            B = torch.zeros((1, side), dtype=torch.int32, device=dev)
+            Kt = torch.from_numpy(CKO.view(np.int32)[None].copy()).to(dev)
+            T = torch.zeros((1, side, h), dtype=torch.int32, device=dev)
+            C = torch.zeros((1, side, L), dtype=torch.int32, device=dev)
+            log("full protocol 1 GiB: answer, offset answer, combine")
+            srv.answer(q, B, native.PATH_MATVEC)
+            srv.offset_answer([cid], Kt, B, T)
+            srv.compress_offset([cid], T, C)
+            srv.sync()
+            b = B.cpu().numpy().view(np.uint32)[0]
+            Tn = T.cpu().numpy().view(np.uint32)[0]
+            Cn = C.cpu().numpy().view(np.uint32)[0]
+        g = np.random.default_rng(13)
+        rows = sorted(set([0, side - 1, *g.choice(side, 40, replace=False).tolist()]))
+        log(f"full protocol 1 GiB: oracle on {len(rows)} rows")
+        E = server.exponents(server.global_hint(D, A, rows=rows))
+        b_or = server.answer_rows(D, cl.qu, rows)
+        assert np.array_equal(b[rows], b_or)
+        k_or = oracle_client_hint(cl.ck, E, cl.N, pool=pool)
+    for i, j in enumerate(rows):
+        t_or = protocol.offset_answer_row(int(b_or[i]), E[i], cko, cl.N)
+        assert wl.limbs_to_int(Tn[j]) == t_or, f"t row {j}"
+        c_or = protocol.combine_offset(k_or[i], t_or, cl.N)
+        assert wl.limbs_to_int(Cn[j]) == c_or, f"c row {j}"
+        assert protocol.extract(cl.sk, k_or[i], t_or) == int(D[j, cl.col])
+        assert protocol.extract_combined(cl.sk, c_or) == int(D[j, cl.col])
