@@ -458,3 +458,48 @@ def test_mutation_offset_without_answer_is_caught(full_small, monkeypatch):
     E, b, k, pt_r, cko, t = _full_protocol(inst, cl)
     got = [protocol.extract(cl.sk, k[j], t[j]) for j in range(inst.rows)]
     assert got != inst.D[:, cl.col].tolist()
+
+
+# ----------------------------------------------------------------------------- sizes the paper prints
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if line:
+            rows.append(line.split())
+    return rows
+
+
+def test_table2_single_compression_sizes():
+    # Table 2: one 3072-bit Paillier ciphertext (768 B) against (n + 1) log2 q bits.
+    rows = _golden("table2_single_compression.txt")
+    assert len(rows) == 8
+    for n, logq, comp, unc_kb, red in rows:
+        n, logq = int(n), int(logq)
+        assert params.additive_ciphertext_bits(3072) // 8 == int(comp)
+        assert round(params.lwe_ciphertext_bits(n, logq) / 8 / 1000, 2) == float(unc_kb)
+        assert abs(100 * params.size_reduction(n, logq, 3072) - float(red)) <= 0.01
+
+
+def test_table3_packed_key_sizes():
+    # Table 3: ceil(n / floor(3072 / log2 delta)) ciphertexts of 768 B, in KiB, rounded.
+    rows = _golden("table3_packed_keys.txt")
+    assert len(rows) == 4
+    for n, logq, nb_kb, b_kb in rows:
+        n, q = int(n), 1 << int(logq)
+        for binary, want in ((False, int(nb_kb)), (True, int(b_kb))):
+            kib = params.packed_key_ciphertexts(n, q, 3072, binary) * 768 / 1024
+            assert abs(kib - want) <= 0.5, (n, binary, kib, want)
+
+
+def test_packing_count_matches_sec_3_3():
+    # Sec. 3.3: floor(log2 m / log2 (q + n q^2)) ciphertexts per additive plaintext; the power
+    # of two used by the packed response never packs more than that.
+    for n in (256, 1024, 1400):
+        gmin = server.packing_scale_min(n)
+        t = (gmin - 1).bit_length()
+        for N_bits in (1024, 2048, 3072, 4096):
+            assert (N_bits - 1) // t <= params.pack_count(N_bits, gmin)
