@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workload as wl
-from oracle import brute, lwe, paillier, params, protocol, server
+from oracle import brute, compress, lwe, paillier, params, protocol, server
 from tests.instances import make_instance, oracle_client_hint
 
 Q = 1 << 32
@@ -503,3 +503,148 @@ def test_packing_count_matches_sec_3_3():
         t = (gmin - 1).bit_length()
         for N_bits in (1024, 2048, 3072, 4096):
             assert (N_bits - 1) // t <= params.pack_count(N_bits, gmin)
+
+
+# ----------------------------------------------------------------------------- standalone compression (Sec. 3)
+
+def _key(cfg, bits):
+    pr = wl.paillier_primes(cfg, 0, bits)
+    return paillier.keygen(pr.P, pr.Q)
+
+
+def _lwe_cts(g, s, q, p, count):
+    n = len(s)
+    cts = []
+    for _ in range(count):
+        a = [int(x) for x in g.integers(0, q, size=n, dtype=np.uint64)]
+        mu = int(g.integers(0, p))
+        e = int(np.rint(6.4 * g.standard_normal()))
+        b = lwe.lwe_encrypt(s, a, mu, e, q, p)
+        cts.append((a, b, mu))
+    return cts
+
+
+def test_lwe_compress_round_trip_q64():
+    # Theorem 1 at the Table 2 modulus q = 2^64: Dec(x) is the integer b + sum (q - a_i) s_i
+    # and ModifiedLWEDecrypt returns the LWE plaintext.
+    q, p, n = 1 << 64, 16, 12
+    sk = _key(950, 512)
+    g = np.random.default_rng(50)
+    s = [int(x) for x in g.integers(0, q, size=n, dtype=np.uint64)]
+    rs = wl.paillier_randomness(950, 0, n, sk.pk.N)
+    ck = [paillier.encrypt(sk.pk, s[i], rs[i]) for i in range(n)]
+    assert sk.pk.N > params.compression_bound(n, q)
+    for a, b, mu in _lwe_cts(g, s, q, p, 8):
+        x = compress.lwe_compress(ck, a, b, q, sk.pk.N)
+        assert paillier.decrypt(sk, x) == compress.lwe_phase_plaintext(a, b, s, q)
+        assert compress.modified_lwe_decrypt(sk, x, q, p) == mu == lwe.lwe_decrypt(s, a, b, q, p)
+        # the closed form of Alg. 2 by brute force
+        assert x == brute.combine(1, b, sk.pk.N) * math.prod(
+            brute.modexp(c, (q - ai) % q, sk.pk.N ** 2) for c, ai in zip(ck, a)) % sk.pk.N ** 2
+
+
+def test_lwe_compress_binary_key_corollary():
+    # Corollary of Theorem 1: a binary key needs only m > q + n q; with a uniform key the same
+    # small modulus wraps and decryption fails.
+    q, p, n = 1 << 64, 16, 12
+    sk = _key(951, 96)
+    N = sk.pk.N
+    assert q + n * q < N < params.compression_bound(n, q)
+    g = np.random.default_rng(51)
+    s_bin = [int(x) for x in g.integers(0, 2, size=n)]
+    rs = wl.paillier_randomness(951, 0, n, N)
+    ck = [paillier.encrypt(sk.pk, s_bin[i], rs[i]) for i in range(n)]
+    for a, b, mu in _lwe_cts(g, s_bin, q, p, 8):
+        assert compress.modified_lwe_decrypt(sk, compress.lwe_compress(ck, a, b, q, N), q, p) == mu
+    s_uni = [int(x) for x in g.integers(0, q, size=n, dtype=np.uint64)]
+    ck_u = [paillier.encrypt(sk.pk, s_uni[i] % N, rs[i]) for i in range(n)]
+    bad = sum(compress.modified_lwe_decrypt(sk, compress.lwe_compress(ck_u, a, b, q, N), q, p) != mu
+              for a, b, mu in _lwe_cts(g, s_uni, q, p, 8))
+    assert bad >= 4
+
+
+def test_packed_key_round_trip():
+    # Alg. 9: unpacked keys scale the phase by delta^(t-1); the packed-key decryption recovers
+    # the plaintext when delta is a power of two above q + n q^2 (so q divides it) and
+    # t = floor(0.5 log2 m / log2 delta).
+    q, p, n = 1 << 32, 16, 20
+    sk = _key(952, 1024)
+    N = sk.pk.N
+    delta = 1 << params.compression_bound(n, q).bit_length()
+    t = compress.packed_digits_per_key(1024, delta)
+    assert t == 7 and delta ** (2 * t - 1) < N
+    g = np.random.default_rng(52)
+    s = [int(x) for x in g.integers(0, q, size=n, dtype=np.uint64)]
+    rs = wl.paillier_randomness(952, 0, -(-n // t), N)
+    pck = compress.generate_packed_key(sk.pk, s, delta, t, rs)
+    assert len(pck) == 3
+    ck = compress.unpack_compression_key(pck, delta, t, n, N)
+    # plaintext of ck[it+j] is delta^-j sum_l s[it+l] delta^l mod N
+    for k in range(n):
+        i, j = divmod(k, t)
+        want = sum(s[i * t + l] * delta ** l for l in range(t) if i * t + l < n) * pow(delta, -j, N) % N
+        assert paillier.decrypt(sk, ck[k]) == want
+    ok = 0
+    for a, b, mu in _lwe_cts(g, s, q, p, 10):
+        x = compress.lwe_compress(ck, a, b, q, N)
+        assert compress.modified_decrypt_packed_key(sk, x, delta, t, q, p) == mu
+        ok += compress.modified_lwe_decrypt(sk, x, q, p) == mu
+    assert ok <= 5, "the packed key must change the decryption"
+
+
+def test_packed_key_needs_half_width():
+    # With t twice as large (floor(log2 m / log2 delta)) the digits above delta^(t-1) wrap
+    # modulo m and the packed-key decryption fails for most ciphertexts.
+    q, p, n = 1 << 32, 16, 28
+    sk = _key(953, 1024)
+    N = sk.pk.N
+    delta = 1 << params.compression_bound(n, q).bit_length()
+    t = 2 * compress.packed_digits_per_key(1024, delta)
+    assert delta ** (2 * t - 1) > N
+    g = np.random.default_rng(53)
+    s = [int(x) for x in g.integers(0, q, size=n, dtype=np.uint64)]
+    rs = wl.paillier_randomness(953, 0, -(-n // t), N)
+    ck = compress.unpack_compression_key(compress.generate_packed_key(sk.pk, s, delta, t, rs), delta, t, n, N)
+    bad = sum(compress.modified_decrypt_packed_key(sk, compress.lwe_compress(ck, a, b, q, N), delta, t, q, p) != mu
+              for a, b, mu in _lwe_cts(g, s, q, p, 10))
+    assert bad >= 5
+
+
+def test_negacyclic_product_closed_form():
+    # X^Nr = -1: the product by X shifts and negates the top coefficient; numpy convolution
+    # folded at Nr gives the same product.
+    q, Nr = 1 << 32, 8
+    g = np.random.default_rng(54)
+    A = [int(x) for x in g.integers(0, q, size=Nr, dtype=np.uint64)]
+    X = [0, 1] + [0] * (Nr - 2)
+    assert compress.negacyclic_mul(A, X, q) == [(q - A[-1]) % q] + A[:-1]
+    S = [int(x) for x in g.integers(0, q, size=Nr, dtype=np.uint64)]
+    full = [0] * (2 * Nr - 1)
+    for i in range(Nr):
+        for j in range(Nr):
+            full[i + j] += A[i] * S[j]
+    folded = [(full[k] - (full[k + Nr] if k + Nr < 2 * Nr - 1 else 0)) % q for k in range(Nr)]
+    assert compress.negacyclic_mul(A, S, q) == folded
+
+
+def test_rlwe_coefficient_compression():
+    # Alg. 8 and the extracted LWE ciphertext agree, and both decrypt to coefficient k of the
+    # RLWE plaintext (Theorem of appendix B; needs m > q + Nr q^2).
+    q, p, Nr = 1 << 32, 16, 16
+    sk = _key(955, 512)
+    N = sk.pk.N
+    assert N > params.compression_bound(Nr, q)
+    g = np.random.default_rng(55)
+    S = [int(x) for x in g.integers(0, q, size=Nr, dtype=np.uint64)]
+    A = [int(x) for x in g.integers(0, q, size=Nr, dtype=np.uint64)]
+    E = [int(x) for x in np.rint(6.4 * g.standard_normal(Nr))]
+    mu = [int(x) for x in g.integers(0, p, size=Nr)]
+    B = compress.rlwe_encrypt(S, mu, A, E, q, p)
+    rs = wl.paillier_randomness(955, 0, Nr, N)
+    ck = [paillier.encrypt(sk.pk, S[i], rs[i]) for i in range(Nr)]
+    for k in (0, 1, Nr // 2, Nr - 1):
+        x = compress.rlwe_compress_coefficient(ck, A, B, k, q, N)
+        a, b = compress.rlwe_extract_lwe(A, B, k, q)
+        assert x == compress.lwe_compress(ck, a, b, q, N)
+        assert lwe.lwe_phase(S, a, b, q) == (B[k] - compress.negacyclic_mul(A, S, q)[k]) % q
+        assert compress.modified_lwe_decrypt(sk, x, q, p) == mu[k] == compress.rlwe_decrypt_coefficient(S, A, B, k, q, p)
