@@ -89,6 +89,8 @@ def main() -> int:
                     help="serve: database sides (square uint8 matrices)")
     ap.add_argument("--mix", type=str, default="40,30,20,10", help="serve: request share per database")
     ap.add_argument("--clients", type=int, default=2, help="serve: clients (resident hints) per database")
+    ap.add_argument("--pack", action="store_true",
+                    help="serve: packed responses (batched compression, largest ell) for every client")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -396,6 +398,8 @@ def serve(args) -> int:
             t0 = time.perf_counter()
             srv.hint(cid)
             log(f"  client {c}: hint for {side} rows in {time.perf_counter() - t0:.2f} s")
+            if args.pack:
+                srv.set_packing(cid, srv.packing_info(cid)["ell_max"])
             ids.append(cid)
         servers.append(srv)
         streams.append(st)
@@ -407,7 +411,8 @@ def serve(args) -> int:
     nreq = len(arr)
     log(f"serve: {nreq} requests over {args.duration:.0f} s at {args.rate:.0f}/s, mix {args.mix}")
     ring = 16
-    rings = [[native.PinnedArray((side, L)) for _ in range(ring)] for side in sides]
+    out_rows = [srv.packing_info(ids[0])["groups"] for srv, ids in zip(servers, clients)]
+    rings = [[native.PinnedArray((orow, L)) for _ in range(ring)] for orow in out_rows]
     slot_owner = [[None] * ring for _ in sides]
     queries = [g.integers(0, 1 << 32, size=(8, side), dtype=np.uint32) for side in sides]
     comps = {}
@@ -480,8 +485,10 @@ def serve(args) -> int:
         "config": {"workload": f"serving mix: {len(sides)} resident databases "
                                f"({', '.join(f'{s}x{s}' for s in sides)} uint8), Poisson arrivals "
                                f"{args.rate:.0f}/s split {args.mix}, {args.clients} clients per database "
-                               f"with resident hints, N {nbits}-bit, answer + Paillier combine per request",
-                   "rate_qps": args.rate, "duration_s": args.duration, "max_batch": args.batch},
+                               f"with resident hints, N {nbits}-bit, answer + Paillier combine per request"
+                               + (" (packed responses)" if args.pack else ""),
+                   "rate_qps": args.rate, "duration_s": args.duration, "max_batch": args.batch,
+                   "packed": bool(args.pack), "response_bytes": {f"{s}x{s}": 4 * o * L for s, o in zip(sides, out_rows)}},
         "p50_ms": round(percentile(lat, 50), 3),
         "p99_ms": round(percentile(lat, 99), 3),
         "all_ok": ok,

@@ -178,6 +178,50 @@ pir_status pir_offset_answer(pir_server *srv, const uint32_t *client_ids, uint32
 pir_status pir_compress_offset(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
                                const uint32_t *T, uint32_t *C, uint32_t ptr_flags);
 
+/*
+ * Standalone compression of LWE ciphertexts (Sec. 3.1, Alg. 2) and of RLWE coefficients
+ * (appendix B, Alg. 8) into Paillier ciphertexts, with a resident compression key.
+ *
+ * A pir_compressor holds the key ck (n entries, ck[i] = Enc(s_i)) of one Paillier modulus N
+ * and an LWE modulus q (2 <= q <= 2^64; pass q = 0 for 2^64).  Creation checks Theorem 1's
+ * bound N > q + n (q-1)^2 and builds a fixed-base table of n x ceil(bits(q-1)/8) x 255
+ * Montgomery residues on the device (about 1 GB for n = 630, q = 2^64, 3072-bit N).
+ *
+ * pir_compressor_create: ck is n x L uint32 (L = 2 ceil(N_bits/32), little-endian, each below
+ *   N^2).  stream: a hipStream_t (NULL: the default stream).
+ * pir_compressor_create_packed: the key is given packed (Sec. 3.2, Alg. 9): pck holds
+ *   ceil(n/t) ciphertexts of t secret digits each, scaled for unpacking with
+ *   delta = 2^delta_log2, and the device unpacks ck[it+j] = pck_i^(delta^(t-1-j)).  The client
+ *   then decrypts with Alg. 9's ModifiedLWEDecryptPackedKey.
+ * pir_compress_lwe: X[r] = (1 + B[r] N) prod_i ck_i^((q - A[r][i]) mod q) mod N^2 for
+ *   r < rows.  A is rows x n entries and B rows entries; an entry is one uint32 when
+ *   q <= 2^32, else two (little-endian uint64); entries are reduced mod q.  X is rows x L.
+ * pir_compress_rlwe: for an RLWE ciphertext (A, B) over Z_q[X]/(X^n + 1) (A and B: n
+ *   entries each), X[j] is the compressed coefficient ks[j] (ks: host array of nk indices
+ *   below n), exponents (q - A[k-i]) mod q for i <= k and A[n+k-i] mod q for i > k.
+ * pir_compressor_key: copies key entries [k0, k0+nk) (e.g. the unpacked key) into ck.
+ * pir_compressor_info: L, exponent windows, device bytes held (any pointer may be NULL).
+ * One ciphertext is spread over up to 256 wavefronts when few are compressed, so a single
+ * compression is a short tree of Montgomery products rather than n x 8 sequential ones.
+ */
+typedef struct pir_compressor pir_compressor;
+pir_status pir_compressor_create(pir_compressor **out, int device, void *hip_stream, uint32_t n,
+                                 uint64_t q, const uint32_t *N, uint32_t N_bits,
+                                 const uint32_t *ck, uint32_t ptr_flags);
+pir_status pir_compressor_create_packed(pir_compressor **out, int device, void *hip_stream,
+                                        uint32_t n, uint64_t q, const uint32_t *N,
+                                        uint32_t N_bits, const uint32_t *pck, uint32_t t,
+                                        uint32_t delta_log2, uint32_t ptr_flags);
+void pir_compressor_destroy(pir_compressor *cmp);
+pir_status pir_compressor_key(pir_compressor *cmp, uint32_t k0, uint32_t nk, uint32_t *ck,
+                              uint32_t ptr_flags);
+pir_status pir_compressor_info(pir_compressor *cmp, uint32_t *L, uint32_t *windows,
+                               uint64_t *device_bytes);
+pir_status pir_compress_lwe(pir_compressor *cmp, const uint32_t *A, const uint32_t *B,
+                            uint32_t rows, uint32_t *X, uint32_t ptr_flags);
+pir_status pir_compress_rlwe(pir_compressor *cmp, const uint32_t *A, const uint32_t *B,
+                             const uint32_t *ks, uint32_t nk, uint32_t *X, uint32_t ptr_flags);
+
 /* Copy rows [row0, row0+nrows) of H (nrows x n uint32).  PIR_ESTALE if any is stale. */
 pir_status pir_get_global_hint(pir_server *srv, uint32_t row0, uint32_t nrows, uint32_t *H,
                                uint32_t ptr_flags);
@@ -269,8 +313,11 @@ pir_status pir_engine_create(pir_engine **out, uint32_t max_batch, uint64_t hbm_
 pir_status pir_engine_add_db(pir_engine *eng, pir_server *srv, uint32_t *db_index);
 
 /* Queue one request.  query: host array of the database's cols uint32 (copied before the call
- * returns).  result: rows x L uint32 in pinned host memory (pir_host_alloc) or device memory;
- * it must stay valid until the request's completion is returned by pir_engine_poll.
+ * returns).  result: rows x L uint32 in pinned host memory (pir_host_alloc) or device memory,
+ * or groups x L (groups = ceil(rows / ell)) when the client has packed responses
+ * (pir_set_packing; the packing factor is read here, so it must not change while the
+ * client's requests are queued); it must stay valid until the request's completion is
+ * returned by pir_engine_poll.
  * arrival_ms: engine-clock time before which the request is not started (< 0: now).
  * Errors: PIR_EINVAL (unknown database or client, pageable result buffer). */
 pir_status pir_engine_submit(pir_engine *eng, uint32_t db_index, uint32_t client_id,
@@ -295,8 +342,8 @@ void pir_engine_destroy(pir_engine *eng);
 
 /* Admission policy, exposed for testing.  pir_engine_capacity: how many requests' buffers
  * (bytes_per_request each) fit in budget_free, at most max_batch.  pir_engine_plan: how many
- * leading queued requests form the next batch: those sharing the first one's limb count,
- * at most capacity. */
+ * leading queued requests form the next batch: those sharing the first one's batch key (the
+ * engine uses limb count | packing factor << 16), at most capacity. */
 uint32_t pir_engine_capacity(uint64_t budget_free, uint64_t bytes_per_request, uint32_t max_batch);
 uint32_t pir_engine_plan(const uint32_t *queued_limbs, uint32_t nqueued, uint32_t capacity);
 

@@ -18,8 +18,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libzippir.so")
 ARCH = os.environ.get("ZIPPIR_ARCH", "gfx950")
 
-SOURCES = ["runtime.cpp", "serve.cpp", "matvec.hip", "gemm_i8.hip", "rows.hip", "hint.hip",
-           "compress.hip", "offset.hip"]
+SOURCES = ["runtime.cpp", "serve.cpp", "compressor.cpp", "matvec.hip", "gemm_i8.hip", "rows.hip", "hint.hip",
+           "compress.hip", "offset.hip", "lwec.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

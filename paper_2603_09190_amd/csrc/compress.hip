@@ -123,43 +123,27 @@ void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint3
 // Combined response of the full protocol (Alg. 5 Response with the Sec. 4.3 Paillier
 // addition): c_j = K_j (+) Enc(t_j; 1) = K_j (1 + t_j N) mod N^2 for an h-limb offset answer t_j.
 //   K (1 + tN) = K + N (t (K mod N) mod N)   (mod N^2).
-// From the stored K' = K 2^32 mod N^2 = lo + hi R_N:
-//   y = (K mod N) R_N mod N = lo D1 R_N^{-1} + hi D2 R_N^{-1}   (two Montgomery products mod N),
-//   z = t (K mod N) mod N    = t y R_N^{-1}                      (h steps),
-//   K = K' 2^{-32} mod N^2                                       (one Montgomery step),
+// With y = (K mod N) R_N mod N stored by the hint step:
+//   z = t (K mod N) mod N    = t y R_N^{-1}   (one Montgomery product mod N, h multiplier limbs),
+//   K = K' 2^{-32} mod N^2                   (one Montgomery reduction step),
 //   c = K + N z mod N^2.
 // One wavefront per row.
 template <int P, int PN>
 __global__ __launch_bounds__(256) void compress_offset_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
+                                                              const uint32_t* __restrict__ Y,
                                                               const uint32_t* __restrict__ T, int rows,
                                                               uint32_t* __restrict__ C) {
-  constexpr int SN = 64 * PN;
   const int row = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (row >= rows) return;
   const uint32_t* kr = Kp + (size_t)row * cd.L;
-  WNum<PN> Nn, lo, hi, d, y, y2, tv, z;
+  WNum<PN> Nn, y, tv, z;
   wn_load(Nn, cd.Nn);
-  wn_load_n(lo, kr, cd.L < SN ? cd.L : SN);
-  if (cd.L > SN) wn_load_n(hi, kr + SN, cd.L - SN); else wn_zero(hi);
-  wn_load(d, cd.D1);
-  mont_mul(y, lo, d, Nn, cd.nprime);
-  wn_load(d, cd.D2);
-  mont_mul(y2, hi, d, Nn, cd.nprime);
-  uint32_t cy = 0;
-#pragma unroll
-  for (int j = 0; j < PN; ++j) {
-    const uint64_t s = (uint64_t)y.v[j] + y2.v[j] + cy;
-    y.v[j] = (uint32_t)s;
-    cy = (uint32_t)(s >> 32);
-  }
-  uint64_t ovf = wn_resolve(y, (uint64_t)cy);
-  wn_cond_sub(y, ovf, Nn);
+  wn_load_n(y, Y + (size_t)row * cd.h, cd.h);
   wn_load_n(tv, T + (size_t)row * cd.h, cd.h);
   mont_mul_short(z, tv, cd.h, y, Nn, cd.nprime);
   // N z: the h limbs of z times N, N shifted up one limb per step
-  WNum<P> acc, Nsh, k, M2, zero;
+  WNum<P> acc, Nsh, k, M2;
   wn_zero(acc);
-  wn_zero(zero);
   wn_load(Nsh, cd.NP);
   uint64_t pend = 0;
   for (int i = 0; i < cd.h; ++i) {
@@ -182,8 +166,8 @@ __global__ __launch_bounds__(256) void compress_offset_kernel(ClientDev cd, cons
   wn_load(M2, cd.N2);
   wn_load_n(k, kr, cd.L);
   uint64_t kc = 0;
-  mont_step(k, kc, 0u, zero, M2, cd.m2prime);
-  ovf = wn_resolve(k, kc);
+  redc_step(k, kc, M2, cd.m2prime);
+  uint64_t ovf = wn_resolve(k, kc);
   wn_cond_sub(k, ovf, M2);
   uint32_t carry = 0;
 #pragma unroll
@@ -197,15 +181,15 @@ __global__ __launch_bounds__(256) void compress_offset_kernel(ClientDev cd, cons
   wn_store_n(C + (size_t)row * cd.L, acc, cd.L);
 }
 
-void launch_compress_offset(const ClientDev& cd, const uint32_t* Kp, const uint32_t* T, int rows,
-                            uint32_t* C, hipStream_t s) {
+void launch_compress_offset(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Y,
+                            const uint32_t* T, int rows, uint32_t* C, hipStream_t s) {
   if (rows <= 0) return;
   const int blocks = (rows + 3) / 4;
   switch (cd.P) {
-    case 1: compress_offset_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, T, rows, C); break;
-    case 2: compress_offset_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, T, rows, C); break;
-    case 3: compress_offset_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, T, rows, C); break;
-    case 4: compress_offset_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, T, rows, C); break;
+    case 1: compress_offset_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C); break;
+    case 2: compress_offset_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C); break;
+    case 3: compress_offset_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C); break;
+    case 4: compress_offset_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C); break;
   }
 }
 

@@ -109,25 +109,38 @@ constexpr int kMaxBlockK = 65536; // K bytes per block (keeps MFMA partials with
 // same k-set feeds both operands, so the MFMA's internal ordering of k does not matter.  The
 // plane results of one output sit in the same lane and register, so the epilogue combines
 // them without data exchange.
-// A block of kW waves covers 16 kMR kW rows and one K range of at most 64 KiB (split-K over
-// grid.z, which keeps every MFMA partial within +-2^30); each wave keeps kDepth K steps of D
-// in flight, the X tile (kPl planes x 32 vectors x kKB bytes) is double-buffered in LDS with
-// one barrier per step, and partial results are added into the zeroed output with 32-bit
-// atomic adds (exact modulo 2^32 in any order).
-template <int kW, int kDepth, int kMR, int kKB, int kPl>
+// A block of kW waves covers 16 kMR kW rows and one K range of at most 64 KiB (split-K,
+// which keeps every MFMA partial within +-2^30); each wave keeps kDepth K steps of D in
+// flight, the X tile (kPl groups x 32 vectors x kKB bytes) is double-buffered in LDS with one
+// barrier per step, and partial results are added into the zeroed output with 32-bit atomic
+// adds (exact modulo 2^32 in any order).
+// kWide: X holds uint8 vectors (one plane) and the kPl accumulator groups are kPl different
+// 32-vector column groups sharing each D fragment, i.e. a block covers 32 kPl output columns.
+// The grid is one-dimensional and XCD-aware: workgroup L runs on XCD L mod 8, and each XCD
+// takes every column block and K range of one row block in turn (row blocks x, x+8, ...), so
+// the D tile they share is read from HBM once and then served from that XCD's L2.
+template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide>
 __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     const uint8_t* __restrict__ D, int rows, int cols, int pitch, const int8_t* __restrict__ Xs,
     const int32_t* __restrict__ colsum, int ncol, const int32_t* __restrict__ rowsum,
-    uint32_t* __restrict__ out, int out_rowmajor, long long out_ld, int ksteps_per_block) {
+    uint32_t* __restrict__ out, int out_rowmajor, long long out_ld, int ksteps_per_block,
+    int nrb, int ncb, int nkz) {
+  static_assert(kWide || kPl == 4, "byte-plane mode has four planes");
   constexpr int kSl = kKB / 64;            // MFMA K slices per step
   constexpr int kStride = kKB + 16;        // LDS row stride; the skew spreads banks
   __shared__ __attribute__((aligned(16))) int8_t xs[2][kPl * kBC][kStride];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, r = lane & 15;
-  const int rowblk = blockIdx.x * 16 * kMR * kW;
-  const int cblk = blockIdx.y * kBC;
-  const int kstep0 = blockIdx.z * ksteps_per_block;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int per_rb = ncb * nkz;
+  const int rbi = (slot / per_rb) * 8 + xcd;
+  if (rbi >= nrb) return;
+  const int u = slot % per_rb;
+  const int cbi = u % ncb, kz = u / ncb;
+  const int rowblk = rbi * 16 * kMR * kW;
+  const int cblk = cbi * (kWide ? kPl * kBC : kBC);
+  const int kstep0 = kz * ksteps_per_block;
   const int nsteps = min(ksteps_per_block, pitch / kKB - kstep0);
   if (nsteps <= 0) return;
 
@@ -146,10 +159,11 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     const int piece = tid + t * 64 * kW;
     lrow[t] = piece / (kKB / 16);
     lcol[t] = (piece % (kKB / 16)) * 16;
-    const int b = lrow[t] >> 5, c = cblk + (lrow[t] & 31);
+    const int b = lrow[t] >> 5;
+    const int c = kWide ? cblk + lrow[t] : cblk + (lrow[t] & 31);
     xval[t] = c < ncol;
     // vectors beyond ncol read vector ncol-1 (a valid address) and are zeroed after the load
-    xoff[t] = (min(c, ncol - 1) * kPl + b) * pitch + kstep0 * kKB + lcol[t];
+    xoff[t] = (kWide ? min(c, ncol - 1) : min(c, ncol - 1) * kPl + b) * pitch + kstep0 * kKB + lcol[t];
   }
 
   v4i acc[kMR][2][kPl];
@@ -231,7 +245,29 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     }
   }
 
-  const bool first = blockIdx.z == 0;
+  const bool first = kz == 0;
+  if constexpr (kWide) {
+#pragma unroll
+    for (int mr = 0; mr < kMR; ++mr)
+#pragma unroll
+      for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+        for (int b = 0; b < kPl; ++b) {
+          const int c = cblk + 32 * b + 16 * qb + r;
+          if (c >= ncol) continue;
+          const uint32_t cs = first ? 128u * (uint32_t)colsum[c] : 0u;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int orow = rowblk + 16 * kMR * wave + 16 * mr + 4 * g + i;
+            if (orow >= rows) continue;
+            const uint32_t rterm = first ? 128u * (uint32_t)rowsum[orow] + 16384u * (uint32_t)cols : 0u;
+            const uint32_t v = (uint32_t)acc[mr][qb][b][i] + cs + rterm;
+            uint32_t* o = out_rowmajor ? out + (size_t)orow * ncol + c : out + (size_t)c * out_ld + orow;
+            if (nkz == 1) *o = v; else atomicAdd(o, v);
+          }
+        }
+    return;
+  }
 #pragma unroll
   for (int mr = 0; mr < kMR; ++mr)
 #pragma unroll
@@ -250,7 +286,7 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
 #pragma unroll
         for (int b = 0; b < kPl; ++b) v += ((uint32_t)acc[mr][qb][b][i] + cs[b] + rterm) << (8 * b);
         uint32_t* o = out_rowmajor ? out + (size_t)orow * ncol + c : out + (size_t)c * out_ld + orow;
-        atomicAdd(o, v);
+        if (nkz == 1) *o = v; else atomicAdd(o, v);
       }
     }
 }
@@ -270,47 +306,65 @@ __global__ void zero_out_kernel(uint32_t* __restrict__ p, int rows, int ncol, in
   }
 }
 
-bool gemm_shape_valid(const GemmShape& sh, int pitch) {
-  const bool known = (sh.waves == 8 && sh.depth == 1 && sh.mr == 2 && sh.kb == 256) ||
-                     (sh.waves == 8 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) ||
-                     (sh.waves == 8 && sh.depth == 1 && sh.mr == 1 && sh.kb == 256) ||
-                     (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 256) ||
-                     (sh.waves == 2 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) ||
-                     (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 512);
+bool gemm_shape_valid(const GemmShape& sh, int pitch, int planes) {
+  const bool base = (sh.waves == 8 && sh.depth == 1 && sh.mr == 2 && sh.kb == 256) ||
+                    (sh.waves == 8 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) ||
+                    (sh.waves == 8 && sh.depth == 1 && sh.mr == 1 && sh.kb == 256) ||
+                    (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 256) ||
+                    (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 512);
+  const bool wide4 = (sh.waves == 8 || sh.waves == 4) && sh.depth == 1 && sh.mr == 4 && sh.kb == 256;
+  const bool known = base || (planes == 4 && sh.waves == 2 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) ||
+                     (planes == 1 && wide4);
   if (!known || sh.ksplit < 1) return false;
+  if (planes == 1 && (sh.cg < 2 || sh.cg > 4)) return false;
+  if (planes != 1 && planes != 4) return false;
   return pitch % sh.kb == 0;
 }
 
 void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int planes,
                         const int8_t* Xs, const int32_t* colsum, int ncol, const int32_t* rowsum,
-                        uint32_t* out, bool out_rowmajor, long long out_ld, const GemmShape& sh,
+                        uint32_t* out, bool out_rowmajor, long long out_ld, const GemmShape& sh_in,
                         hipStream_t s) {
-  zero_out_kernel<<<1024, 256, 0, s>>>(out, rows, ncol, out_rowmajor ? 1 : 0, out_ld);
+  GemmShape sh = sh_in;
+  if (!gemm_shape_valid(sh, pitch, planes))
+    sh = planes == 4 ? GemmShape{8, 1, 2, 256, 2, 4} : GemmShape{8, 1, 2, 256, 1, 3};
   const int nsteps = pitch / sh.kb;
   const int per = std::min(kMaxBlockK / sh.kb, (nsteps + sh.ksplit - 1) / sh.ksplit);
-  const int kz = (nsteps + per - 1) / per;
+  const int nkz = (nsteps + per - 1) / per;
+  if (nkz > 1) zero_out_kernel<<<1024, 256, 0, s>>>(out, rows, ncol, out_rowmajor ? 1 : 0, out_ld);
   const int rows_per_block = 16 * sh.mr * sh.waves;
-  dim3 grid((rows + rows_per_block - 1) / rows_per_block, (ncol + kBC - 1) / kBC, kz);
-#define ZP_G(W, DP, MR, KB)                                                                        \
-  if (sh.waves == W && sh.depth == DP && sh.mr == MR && sh.kb == KB) {                             \
-    if (planes == 4)                                                                               \
-      gemm_planes_kernel<W, DP, MR, KB, 4><<<grid, 64 * W, 0, s>>>(                                \
-          D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per);         \
-    else                                                                                           \
-      gemm_planes_kernel<W, DP, MR, KB, 1><<<grid, 64 * W, 0, s>>>(                                \
-          D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per);         \
-    return;                                                                                        \
+  const int nrb = (rows + rows_per_block - 1) / rows_per_block;
+  const int cols_per_block = planes == 4 ? kBC : kBC * sh.cg;
+  const int ncb = (ncol + cols_per_block - 1) / cols_per_block;
+  const long long nblocks = (long long)((nrb + 7) / 8 * 8) * ncb * nkz;
+  const dim3 grid((unsigned)nblocks);
+#define ZP_LAUNCH(W, DP, MR, KB, PL, WIDE)                                                          \
+  gemm_planes_kernel<W, DP, MR, KB, PL, WIDE><<<grid, 64 * W, 0, s>>>(                               \
+      D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per, nrb, ncb, nkz)
+#define ZP_G(W, DP, MR, KB)                                                                         \
+  if (sh.waves == W && sh.depth == DP && sh.mr == MR && sh.kb == KB) {                              \
+    if (planes == 4) ZP_LAUNCH(W, DP, MR, KB, 4, false);                                            \
+    else if (sh.cg == 2) ZP_LAUNCH(W, DP, MR, KB, 2, true);                                         \
+    else if (sh.cg == 3) ZP_LAUNCH(W, DP, MR, KB, 3, true);                                         \
+    else ZP_LAUNCH(W, DP, MR, KB, 4, true);                                                         \
+    return;                                                                                         \
   }
-  ZP_G(8, 1, 2, 256) ZP_G(8, 2, 2, 256) ZP_G(8, 1, 1, 256) ZP_G(4, 1, 2, 256)
-  ZP_G(2, 2, 2, 256) ZP_G(4, 1, 2, 512)
+  ZP_G(8, 1, 2, 256) ZP_G(8, 2, 2, 256) ZP_G(8, 1, 1, 256) ZP_G(4, 1, 2, 256) ZP_G(4, 1, 2, 512)
 #undef ZP_G
-  // any other shape falls back to the default
-  if (planes == 4)
-    gemm_planes_kernel<8, 1, 2, 256, 4><<<grid, 512, 0, s>>>(D, rows, cols, pitch, Xs, colsum, ncol,
-                                                             rowsum, out, out_rowmajor, out_ld, per);
-  else
-    gemm_planes_kernel<8, 1, 2, 256, 1><<<grid, 512, 0, s>>>(D, rows, cols, pitch, Xs, colsum, ncol,
-                                                             rowsum, out, out_rowmajor, out_ld, per);
+#define ZP_W(W, DP, MR, KB)                                                                         \
+  if (planes == 1 && sh.waves == W && sh.depth == DP && sh.mr == MR && sh.kb == KB) {               \
+    if (sh.cg == 2) ZP_LAUNCH(W, DP, MR, KB, 2, true);                                              \
+    else if (sh.cg == 3) ZP_LAUNCH(W, DP, MR, KB, 3, true);                                         \
+    else ZP_LAUNCH(W, DP, MR, KB, 4, true);                                                         \
+    return;                                                                                         \
+  }
+  ZP_W(8, 1, 4, 256) ZP_W(4, 1, 4, 256)
+#undef ZP_W
+  if (sh.waves == 2 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256 && planes == 4) {
+    ZP_LAUNCH(2, 2, 2, 256, 4, false);
+    return;
+  }
+#undef ZP_LAUNCH
 }
 
 }  // namespace zp

@@ -24,11 +24,11 @@ __device__ __forceinline__ int wave_index() {
 template <int P>
 __global__ __launch_bounds__(256) void build_table_kernel(ClientDev cd,
                                                           const uint32_t* __restrict__ ck, int n,
-                                                          uint32_t* __restrict__ table) {
+                                                          int windows, uint32_t* __restrict__ table) {
   constexpr int S = 64 * P;
   const int widx = wave_index();
-  if (widx >= n * kWindows) return;
-  const int k = widx / kWindows, w = widx % kWindows;
+  if (widx >= n * windows) return;
+  const int k = widx / windows, w = widx % windows;
   WNum<P> M, RR, x, cur;
   wn_load(M, cd.N2);
   wn_load(RR, cd.RR);
@@ -84,7 +84,8 @@ template <int P, int PN>
 __global__ __launch_bounds__(256) void combine_key_kernel(ClientDev cd,
                                                           const uint32_t* __restrict__ Kp,
                                                           const uint32_t* __restrict__ rowlist,
-                                                          int nrows, uint32_t* __restrict__ Mp) {
+                                                          int nrows, uint32_t* __restrict__ Mp,
+                                                          uint32_t* __restrict__ Y) {
   constexpr int SN = 64 * PN;
   const int widx = wave_index();
   if (widx >= nrows) return;
@@ -108,6 +109,13 @@ __global__ __launch_bounds__(256) void combine_key_kernel(ClientDev cd,
   }
   const uint64_t ovf = wn_resolve(x, (uint64_t)carry);
   wn_cond_sub(x, ovf, Nn);  // x = K' mod N
+  if (Y) {
+    // (K mod N) R_N = x 2^-32 R_N mod N = x D1 R_N^-1 (D1 = R_N^2 2^-32 mod N)
+    WNum<PN> d, yv;
+    wn_load(d, cd.D1);
+    mont_mul(yv, x, d, Nn, cd.nprime);
+    wn_store_n(Y + (size_t)row * cd.h, yv, cd.h);
+  }
   // M' = N * x: h broadcast limbs of x times N shifted up one limb per step
   WNum<P> acc, Nsh;
   wn_zero(acc);
@@ -138,12 +146,11 @@ __global__ __launch_bounds__(256) void unscale_kernel(ClientDev cd, const uint32
                                                       int row0, int nrows, uint32_t* __restrict__ K) {
   const int widx = wave_index();
   if (widx >= nrows) return;
-  WNum<P> M, t, z;
+  WNum<P> M, t;
   wn_load(M, cd.N2);
   wn_load_n(t, Kp + (size_t)(row0 + widx) * cd.L, cd.L);
-  wn_zero(z);
   uint64_t c = 0;
-  mont_step(t, c, 0u, z, M, cd.m2prime);
+  redc_step(t, c, M, cd.m2prime);
   const uint64_t ovf = wn_resolve(t, c);
   wn_cond_sub(t, ovf, M);
   wn_store_n(K + (size_t)widx * cd.L, t, cd.L);
@@ -218,15 +225,15 @@ void launch_to_mont(const ClientDev& cd, uint32_t* x, const uint32_t* rowlist, i
   }
 }
 
-void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, uint32_t* table,
-                        hipStream_t s) {
-  const int waves = n * kWindows;
+void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int windows,
+                        uint32_t* table, hipStream_t s) {
+  const int waves = n * windows;
   const int blocks = (waves + 3) / 4;
   switch (cd.P) {
-    case 1: build_table_kernel<1><<<blocks, 256, 0, s>>>(cd, ck, n, table); break;
-    case 2: build_table_kernel<2><<<blocks, 256, 0, s>>>(cd, ck, n, table); break;
-    case 3: build_table_kernel<3><<<blocks, 256, 0, s>>>(cd, ck, n, table); break;
-    case 4: build_table_kernel<4><<<blocks, 256, 0, s>>>(cd, ck, n, table); break;
+    case 1: build_table_kernel<1><<<blocks, 256, 0, s>>>(cd, ck, n, windows, table); break;
+    case 2: build_table_kernel<2><<<blocks, 256, 0, s>>>(cd, ck, n, windows, table); break;
+    case 3: build_table_kernel<3><<<blocks, 256, 0, s>>>(cd, ck, n, windows, table); break;
+    case 4: build_table_kernel<4><<<blocks, 256, 0, s>>>(cd, ck, n, windows, table); break;
   }
 }
 
@@ -243,14 +250,14 @@ void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint3
 }
 
 void launch_combine_key(const ClientDev& cd, const uint32_t* Kp, const uint32_t* rowlist,
-                        int nrows, uint32_t* Mp, hipStream_t s) {
+                        int nrows, uint32_t* Mp, uint32_t* Y, hipStream_t s) {
   if (nrows <= 0) return;
   const int blocks = (nrows + 3) / 4;
   switch (cd.P) {
-    case 1: combine_key_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp); break;
-    case 2: combine_key_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp); break;
-    case 3: combine_key_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp); break;
-    case 4: combine_key_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp); break;
+    case 1: combine_key_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y); break;
+    case 2: combine_key_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y); break;
+    case 3: combine_key_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y); break;
+    case 4: combine_key_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y); break;
   }
 }
 

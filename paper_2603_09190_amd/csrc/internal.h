@@ -18,6 +18,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 //   C2  SN limbs  R_N^2 mod N              CP  S limbs   2^(64 S - 32) mod N^2 (K' -> K R)
 //   D1  SN limbs  R_N^2 2^-32 mod N         D2  SN limbs  R_N^3 2^-32 mod N
 //   (D1, D2 map K' = lo + hi R_N to (K mod N) R_N mod N with two Montgomery products)
+//   C96 SN limbs  2^96 R_N mod N (x -> x 2^96 mod N in one Montgomery product)
 struct ClientDev {
   const uint32_t* N2;
   const uint32_t* R1;
@@ -29,6 +30,7 @@ struct ClientDev {
   const uint32_t* CP;
   const uint32_t* D1;
   const uint32_t* D2;
+  const uint32_t* C96;
   uint32_t m2prime;  // -(N^2)^{-1} mod 2^32
   uint32_t nprime;   // -N^{-1} mod 2^32
   int L;             // limbs of a ciphertext (2h)
@@ -69,10 +71,11 @@ void launch_rowsum(const uint8_t* D, int rows, int cols, int pitch, int32_t* row
 // Launch shape: `waves` per block, `depth` K steps of D in flight per wave, `mr` x 16 rows per
 // wave, `kb` bytes of K per step, `ksplit` K ranges per output tile.  Every shape gives
 // identical bits; gemm_shape_valid tells whether a shape is built and fits the pitch.
+// cg (one plane only): 32-vector column groups per block, 2..4.
 struct GemmShape {
-  int waves, depth, mr, kb, ksplit;
+  int waves, depth, mr, kb, ksplit, cg;
 };
-bool gemm_shape_valid(const GemmShape& sh, int pitch);
+bool gemm_shape_valid(const GemmShape& sh, int pitch, int planes);
 // planes = 4: X holds uint32 vectors as four byte planes (launch_pack_planes_s8) and
 // out = D . X mod 2^32.  planes = 1: X holds uint8 vectors as one plane,
 // Xs[c*pitch + i] = X(c,i) ^ 0x80 (0 beyond cols), colsum[c] = sum_{i<cols} Xs[c*pitch + i],
@@ -93,15 +96,16 @@ void launch_scatter_rows_u32(const uint32_t* src, int width, const uint32_t* row
                              uint32_t* dst, hipStream_t s);
 
 // ---- hint.hip
-void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, uint32_t* table,
-                        hipStream_t s);
+void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int windows,
+                        uint32_t* table, hipStream_t s);
 // Rows processed: rowlist[i] for i < nrows (rowlist may be null: rows 0..nrows-1).
 // Writes K'_j = K_j 2^32 mod N^2 (rows x L limbs).
 void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
                       int nrows, const uint32_t* table, uint32_t* Kp, hipStream_t s);
 // M'_j = N (K'_j mod N) (rows x L limbs), the combine key.
+// (Y, when not NULL: rows x h, Y[row] = (K mod N) R_N mod N for the offset combine.)
 void launch_combine_key(const ClientDev& cd, const uint32_t* Kp, const uint32_t* rowlist,
-                        int nrows, uint32_t* Mp, hipStream_t s);
+                        int nrows, uint32_t* Mp, uint32_t* Y, hipStream_t s);
 // K_j = K'_j 2^{-32} mod N^2 for rows [row0, row0+nrows) into K (nrows x L).
 void launch_unscale(const ClientDev& cd, const uint32_t* Kp, int row0, int nrows, uint32_t* K,
                     hipStream_t s);
@@ -121,19 +125,47 @@ void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint3
 // Eb row j (epitch bytes) = the 4n little-endian bytes of E row j = -H row j mod 2^32, zero
 // beyond 4n; epitch is a multiple of 256.
 void launch_e_bytes(const uint32_t* H, int rows, int n, int epitch, uint8_t* Eb, hipStream_t s);
+// out[k] = cko[k] 2^96 mod N (canonical) for the n offset entries of one client (h limbs each).
+void launch_scale_offsets(const ClientDev& cd, const uint32_t* cko, int n, uint32_t* out,
+                          hipStream_t s);
 // One-plane operand for `batch` offset vectors cko (batch x n x h limbs): column
 // i*cpc + pos, K index 4k + a holds byte (pos - a) of cko[i][k] (XOR 0x80, 0 beyond 4n);
 // also zeroes and fills colsum (batch*cpc).  cpc >= 4h + 3.
 void launch_pack_offset(const uint32_t* cko, int batch, int n, int h, int cpc, int epitch,
                         int8_t* X, int32_t* colsum, hipStream_t s);
-// T[j] (h limbs) = (b[j] + sum_pos W[j*ldw + pos] 2^(8 pos)) mod N, pos < 4h + 3.
+// T[j] (h limbs) = (b[j] 2^96 + sum_pos W[j*ldw + pos] 2^(8 pos)) 2^-96 mod N, pos < 4h + 3,
+// where W was computed from offsets scaled by 2^96 (launch_scale_offsets).
 void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,
                           int rows, uint32_t* T, hipStream_t s);
 
 // C[j] = K_j (1 + T[j] N) mod N^2 for rows [0, rows): T is rows x h (any value below 2^(32h)),
-// K_j from the stored K'; C is rows x L.
-void launch_compress_offset(const ClientDev& cd, const uint32_t* Kp, const uint32_t* T, int rows,
-                            uint32_t* C, hipStream_t s);
+// K_j from the stored K', Y[j] = (K_j mod N) R_N mod N (h limbs); C is rows x L.
+void launch_compress_offset(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Y,
+                            const uint32_t* T, int rows, uint32_t* C, hipStream_t s);
+
+// ---- standalone LWE / RLWE compression (lwec.hip)
+// Exponent source of one compressed ciphertext: LWE rows (A rows x n, B rows) or RLWE
+// coefficients (A and B the ring elements' n coefficients, ks the coefficient indices).
+// Entries are qw 32-bit words (little-endian), reduced modulo q in the kernel; q = 0 means 2^64.
+struct LweBatch {
+  const uint32_t* A;
+  const uint32_t* B;
+  const uint32_t* ks;  // NULL for LWE rows
+  int rows, n, qw, windows;
+  uint64_t q;
+};
+// parts > 1: each ciphertext's n bases are split over `parts` waves whose partial products
+// (Montgomery form, S limbs each) go to Part (rows x parts); otherwise X gets the result.
+void launch_compress_lwe(const ClientDev& cd, const LweBatch& lb, const uint32_t* table, int parts,
+                         uint32_t* Part, uint32_t* X, hipStream_t s);
+// Multiplies groups of `fan` consecutive partial products (parts per row -> ceil(parts/fan));
+// when one remains per row, multiplies in Enc(b; 1) = 1 + bN and writes X (rows x L).
+void launch_reduce_parts(const ClientDev& cd, const LweBatch& lb, const uint32_t* Part, int parts,
+                         int fan, uint32_t* Out, uint32_t* X, hipStream_t s);
+// ck[k] = pck[k / t]^(2^(dbits (t - 1 - k mod t))) mod N^2 for k < n (unpacking of packed keys
+// with delta = 2^dbits).
+void launch_unpack_keys(const ClientDev& cd, const uint32_t* pck, int n, int t, int dbits,
+                        uint32_t* ck, hipStream_t s);
 
 // ---- runtime.cpp accessors used by the serving engine
 hipStream_t server_stream(pir_server* s);

@@ -1,0 +1,191 @@
+// Standalone compression of LWE ciphertexts and RLWE coefficients into Paillier ciphertexts.
+//
+// Alg. 2 (LWECompress): x = Enc(b; 1) (+) sum_i ((q - a_i) mod q) (x) ck_i
+//                         = (1 + b N) prod_i ck_i^((q - a_i) mod q)   mod N^2.
+// Alg. 8 (RLWECompressCoefficient, appendix B): the same product for coefficient k of an RLWE
+// ciphertext (A, B) over Z_q[X]/(X^n + 1), with exponents (q - A[k-i]) mod q for i <= k and
+// A[n+k-i] mod q for i > k, and b = B[k].
+//
+// The bases are fixed (the compression key), so the 8-bit fixed-base table of the client-hint
+// kernel applies with as many windows as q has bytes: an exponent below 2^64 costs at most 8
+// Montgomery products.  One ciphertext is spread over `parts` wavefronts (each multiplies the
+// table entries of a contiguous range of bases), and the partial products are multiplied
+// together in a tree of fan-in `fan`; with many ciphertexts one wavefront per ciphertext is
+// enough to fill the GPU.
+//
+// Packed compression keys (Alg. 9, delta = 2^dbits): ck[it+j] = pck_i^(delta^(t-1-j)), i.e.
+// dbits (t-1-j) Montgomery squarings of pck_i.
+#include "internal.h"
+#include "wavenum.h"
+
+namespace zp {
+
+__device__ __forceinline__ uint64_t lw_load(const uint32_t* p, size_t idx, int qw) {
+  return qw == 2 ? ((uint64_t)p[2 * idx + 1] << 32) | p[2 * idx] : (uint64_t)p[idx];
+}
+
+__device__ __forceinline__ uint64_t lw_mod(uint64_t a, uint64_t q) { return q ? a % q : a; }
+
+// (q - (a mod q)) mod q, q = 0 standing for 2^64
+__device__ __forceinline__ uint64_t lw_neg(uint64_t a, uint64_t q) {
+  const uint64_t r = lw_mod(a, q);
+  return r == 0 ? 0 : (q ? q - r : 0 - r);
+}
+
+// exponent of base k for ciphertext `row`
+__device__ __forceinline__ uint64_t lw_exponent(const LweBatch& lb, int row, int k) {
+  if (!lb.ks) return lw_neg(lw_load(lb.A, (size_t)row * lb.n + k, lb.qw), lb.q);
+  const int kk = (int)lb.ks[row];
+  return k <= kk ? lw_neg(lw_load(lb.A, kk - k, lb.qw), lb.q)
+                 : lw_mod(lw_load(lb.A, lb.n + kk - k, lb.qw), lb.q);
+}
+
+// x <- x (1 + b N) mod N^2 for x in Montgomery form (x = X R): the result is X (1 + b N),
+// canonical.  1 + b N < N^2 because b < q <= 2^64 < N.
+template <int P>
+__device__ __forceinline__ void times_enc_b(const ClientDev& cd, WNum<P>& x, uint64_t b,
+                                            const WNum<P>& M) {
+  WNum<P> f, Nsh;
+  wn_zero(f);
+  if (lane_id() == 0) f.v[0] = 1;
+  wn_load(Nsh, cd.NP);
+  uint64_t pend = 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {  // f += b_i N 2^(32 i)
+    const uint32_t bi = (uint32_t)(b >> (32 * i));
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const uint64_t t = (uint64_t)bi * Nsh.v[j] + f.v[j] + c;
+      f.v[j] = (uint32_t)t;
+      c = (uint32_t)(t >> 32);
+    }
+    pend += c;
+    const uint32_t in = from_prev_lane(Nsh.v[P - 1]);
+#pragma unroll
+    for (int j = P - 1; j > 0; --j) Nsh.v[j] = Nsh.v[j - 1];
+    Nsh.v[0] = in;
+  }
+  (void)wn_resolve(f, pend);  // 1 + b N < N^2
+  mont_mul(x, x, f, M, cd.m2prime);
+}
+
+__device__ __forceinline__ uint64_t lw_b(const LweBatch& lb, int row) {
+  return lb.ks ? lw_mod(lw_load(lb.B, lb.ks[row], lb.qw), lb.q)
+               : lw_mod(lw_load(lb.B, row, lb.qw), lb.q);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void compress_lwe_kernel(ClientDev cd, LweBatch lb,
+                                                           const uint32_t* __restrict__ table,
+                                                           int parts, uint32_t* __restrict__ Part,
+                                                           uint32_t* __restrict__ X) {
+  constexpr int S = 64 * P;
+  const int widx = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (widx >= lb.rows * parts) return;
+  const int row = widx / parts, part = widx - row * parts;
+  const int k0 = (int)((long long)lb.n * part / parts);
+  const int k1 = (int)((long long)lb.n * (part + 1) / parts);
+  WNum<P> M, acc, b;
+  wn_load(M, cd.N2);
+  wn_load(acc, cd.R1);  // Montgomery form of 1
+  for (int k = k0; k < k1; ++k) {
+    const uint64_t e = lw_exponent(lb, row, k);
+    const uint32_t* tk = table + (size_t)k * lb.windows * kDigits * S;
+    for (int w = 0; w < lb.windows; ++w) {
+      const uint32_t d = (uint32_t)(e >> (kWindowBits * w)) & kDigits;
+      if (d != 0) {
+        wn_load(b, tk + ((size_t)w * kDigits + (d - 1)) * S);
+        mont_mul(acc, acc, b, M, cd.m2prime);
+      }
+    }
+  }
+  if (parts == 1) {
+    times_enc_b<P>(cd, acc, lw_b(lb, row), M);
+    wn_store_n(X + (size_t)row * cd.L, acc, cd.L);
+  } else {
+    wn_store(Part + (size_t)widx * S, acc);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void reduce_parts_kernel(ClientDev cd, LweBatch lb,
+                                                           const uint32_t* __restrict__ Part,
+                                                           int parts, int fan,
+                                                           uint32_t* __restrict__ Out,
+                                                           uint32_t* __restrict__ X) {
+  constexpr int S = 64 * P;
+  const int outs = (parts + fan - 1) / fan;
+  const int widx = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (widx >= lb.rows * outs) return;
+  const int row = widx / outs, o = widx - row * outs;
+  const int p0 = o * fan, p1 = min(parts, p0 + fan);
+  WNum<P> M, acc, b;
+  wn_load(M, cd.N2);
+  wn_load(acc, Part + ((size_t)row * parts + p0) * S);
+  for (int p = p0 + 1; p < p1; ++p) {
+    wn_load(b, Part + ((size_t)row * parts + p) * S);
+    mont_mul(acc, acc, b, M, cd.m2prime);
+  }
+  if (outs == 1) {
+    times_enc_b<P>(cd, acc, lw_b(lb, row), M);
+    wn_store_n(X + (size_t)row * cd.L, acc, cd.L);
+  } else {
+    wn_store(Out + (size_t)widx * S, acc);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void unpack_keys_kernel(ClientDev cd, const uint32_t* __restrict__ pck,
+                                                          int n, int t, int dbits,
+                                                          uint32_t* __restrict__ ck) {
+  const int k = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (k >= n) return;
+  WNum<P> M, RR, x;
+  wn_load(M, cd.N2);
+  wn_load(RR, cd.RR);
+  wn_load_n(x, pck + (size_t)(k / t) * cd.L, cd.L);
+  mont_mul(x, x, RR, M, cd.m2prime);  // Montgomery form
+  const int sq = dbits * (t - 1 - k % t);
+  for (int i = 0; i < sq; ++i) mont_mul(x, x, x, M, cd.m2prime);
+  WNum<P> one;
+  wn_zero(one);
+  if (lane_id() == 0) one.v[0] = 1;
+  mont_mul(x, x, one, M, cd.m2prime);
+  wn_store_n(ck + (size_t)k * cd.L, x, cd.L);
+}
+
+#define ZP_BY_P(KERNEL, GRID, ...)                                                   \
+  switch (cd.P) {                                                                    \
+    case 1: KERNEL<1><<<GRID, 256, 0, s>>>(__VA_ARGS__); break;                      \
+    case 2: KERNEL<2><<<GRID, 256, 0, s>>>(__VA_ARGS__); break;                      \
+    case 3: KERNEL<3><<<GRID, 256, 0, s>>>(__VA_ARGS__); break;                      \
+    case 4: KERNEL<4><<<GRID, 256, 0, s>>>(__VA_ARGS__); break;                      \
+  }
+
+void launch_compress_lwe(const ClientDev& cd, const LweBatch& lb, const uint32_t* table, int parts,
+                         uint32_t* Part, uint32_t* X, hipStream_t s) {
+  const long long waves = (long long)lb.rows * parts;
+  if (waves <= 0) return;
+  const int blocks = (int)((waves + 3) / 4);
+  ZP_BY_P(compress_lwe_kernel, blocks, cd, lb, table, parts, Part, X)
+}
+
+void launch_reduce_parts(const ClientDev& cd, const LweBatch& lb, const uint32_t* Part, int parts,
+                         int fan, uint32_t* Out, uint32_t* X, hipStream_t s) {
+  const long long waves = (long long)lb.rows * ((parts + fan - 1) / fan);
+  if (waves <= 0) return;
+  const int blocks = (int)((waves + 3) / 4);
+  ZP_BY_P(reduce_parts_kernel, blocks, cd, lb, Part, parts, fan, Out, X)
+}
+
+void launch_unpack_keys(const ClientDev& cd, const uint32_t* pck, int n, int t, int dbits,
+                        uint32_t* ck, hipStream_t s) {
+  if (n <= 0) return;
+  const int blocks = (n + 3) / 4;
+  ZP_BY_P(unpack_keys_kernel, blocks, cd, pck, n, t, dbits, ck)
+}
+
+#undef ZP_BY_P
+
+}  // namespace zp

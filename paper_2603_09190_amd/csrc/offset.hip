@@ -11,8 +11,9 @@
 // which is the uint8 product of E's rows read as 4n bytes (little-endian, so the byte of
 // E_jk with weight 2^(8a) sits at K index 4k + a) with a 4n x (4h + 3) byte matrix whose
 // column pos holds the bytes y_k[pos - a].  Every W entry is below 4n 255^2 < 2^32, so the
-// contraction is exact in 32-bit accumulators.  A reduction kernel then folds the byte
-// positions into limbs, adds b_j and reduces modulo N.
+// contraction is exact in 32-bit accumulators.  The offsets are first replaced by
+// y_k = ck_o,k 2^96 mod N, so that a reduction kernel can fold the byte positions into limbs,
+// add b_j 2^96 and finish modulo N with three Montgomery reduction steps (see below).
 #include "internal.h"
 #include "wavenum.h"
 
@@ -36,7 +37,7 @@ void launch_e_bytes(const uint32_t* H, int rows, int n, int epitch, uint8_t* Eb,
 }
 
 // Column col = i*cpc + pos of the shifted-byte operand for client i: X[col][4k + a] is byte
-// (pos - a) of ck_o,k (0 outside [0, 4h)), stored as X ^ 0x80 for K indices below 4n and 0
+// (pos - a) of y_k (0 outside [0, 4h)), stored as X ^ 0x80 for K indices below 4n and 0
 // beyond (the one-plane layout of launch_gemm_planes); colsum[col] sums the stored int8s.
 __global__ __launch_bounds__(256) void pack_offset_kernel(const uint32_t* __restrict__ cko, int n,
                                                           int h, int cpc, int epitch,
@@ -78,68 +79,77 @@ void launch_pack_offset(const uint32_t* cko, int batch, int n, int h, int cpc, i
   pack_offset_kernel<<<grid, 256, 0, s>>>(cko, n, h, cpc, epitch, X, colsum);
 }
 
-// t_j from W[j][0 .. 4h+3): one wavefront per row, numbers of SN = 64 PN limbs.
-//   value = b_j + sum_pos W[j][pos] 2^(8 pos) = lo + hi 2^(32 SN),  lo < 2^(32 SN), hi < 2^64,
-//   t_j   = (lo mod N + hi 2^(32 SN) mod N) mod N
-// with lo mod N = lo C1 R_N^{-1} (C1 = R_N mod N) and hi R_N mod N = hi C2 R_N^{-1}
-// (C2 = R_N^2 mod N), two Montgomery products modulo N, as for the combine key.
+// The offsets enter the contraction scaled by 2^96 (mod N, which also makes them canonical):
+//   y_k = ck_o,k 2^96 mod N,   v_j = b_j 2^96 + sum_k E_jk y_k  = 2^96 (b_j + sum_k E_jk ck_o,k)  (mod N).
+// Three Montgomery reduction steps then give v_j 2^-96 mod N, which is t_j, and they shrink
+// v_j < 2^128 + n 2^32 N to below v_j / 2^96 + N < 2N: one conditional subtraction finishes.
 template <int PN>
+__global__ __launch_bounds__(256) void scale_offsets_kernel(ClientDev cd, const uint32_t* __restrict__ cko,
+                                                            int n, uint32_t* __restrict__ out) {
+  const int k = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (k >= n) return;
+  WNum<PN> Nn, c, x;
+  wn_load(Nn, cd.Nn);
+  wn_load(c, cd.C96);
+  wn_load_n(x, cko + (size_t)k * cd.h, cd.h);
+  mont_mul(x, x, c, Nn, cd.nprime);
+  wn_store_n(out + (size_t)k * cd.h, x, cd.h);
+}
+
+void launch_scale_offsets(const ClientDev& cd, const uint32_t* cko, int n, uint32_t* out,
+                          hipStream_t s) {
+  if (n <= 0) return;
+  const int blocks = (n + 3) / 4;
+  if (cd.PN == 1)
+    scale_offsets_kernel<1><<<blocks, 256, 0, s>>>(cd, cko, n, out);
+  else
+    scale_offsets_kernel<2><<<blocks, 256, 0, s>>>(cd, cko, n, out);
+}
+
+// t_j from W[j][0 .. 4h+3): one wavefront per row, numbers of S = 64 P limbs (S >= h + 2
+// holds the sum), modulus N zero-padded to S limbs.
+template <int P>
 __global__ __launch_bounds__(256) void offset_reduce_kernel(ClientDev cd, const uint32_t* __restrict__ W,
                                                             long long ldw,
                                                             const uint32_t* __restrict__ b, int rows,
                                                             uint32_t* __restrict__ T) {
-  constexpr int SN = 64 * PN;
   const int j = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (j >= rows) return;
   const uint32_t* w = W + (size_t)j * ldw;
   const int npos = 4 * cd.h + 3;
-  WNum<PN> lo, hiw, Nn, C1, C2, x, y;
+  WNum<P> v, m;
   uint64_t carry = 0;
 #pragma unroll
-  for (int jj = 0; jj < PN; ++jj) {
-    const int limb = PN * lane_id() + jj;
-    uint64_t v = carry;
+  for (int jj = 0; jj < P; ++jj) {
+    const int limb = P * lane_id() + jj;
+    uint64_t x = carry;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int pos = 4 * limb + u;
-      if (pos < npos) v += (uint64_t)w[pos] << (8 * u);
+      if (pos < npos) x += (uint64_t)w[pos] << (8 * u);
     }
-    if (limb == 0) v += b[j];
-    lo.v[jj] = (uint32_t)v;
-    carry = v >> 32;
+    if (limb == 3) x += b[j];  // b_j 2^96
+    v.v[jj] = (uint32_t)x;
+    carry = x >> 32;
   }
-  uint64_t hi = wn_resolve(lo, carry);
-  for (int pos = 4 * SN; pos < npos; ++pos) hi += (uint64_t)w[pos] << (8 * (pos - 4 * SN));
+  wn_load(m, cd.NP);
 #pragma unroll
-  for (int jj = 0; jj < PN; ++jj) {
-    const int limb = PN * lane_id() + jj;
-    hiw.v[jj] = limb == 0 ? (uint32_t)hi : (limb == 1 ? (uint32_t)(hi >> 32) : 0u);
-  }
-  wn_load(Nn, cd.Nn);
-  wn_load(C1, cd.C1);
-  wn_load(C2, cd.C2);
-  mont_mul(x, lo, C1, Nn, cd.nprime);
-  mont_mul(y, hiw, C2, Nn, cd.nprime);
-  uint32_t c = 0;
-#pragma unroll
-  for (int jj = 0; jj < PN; ++jj) {
-    const uint64_t s = (uint64_t)x.v[jj] + y.v[jj] + c;
-    x.v[jj] = (uint32_t)s;
-    c = (uint32_t)(s >> 32);
-  }
-  const uint64_t ovf = wn_resolve(x, (uint64_t)c);
-  wn_cond_sub(x, ovf, Nn);
-  wn_store_n(T + (size_t)j * cd.h, x, cd.h);
+  for (int i = 0; i < 3; ++i) redc_step(v, carry, m, cd.nprime);
+  const uint64_t ovf = wn_resolve(v, carry);
+  wn_cond_sub(v, ovf, m);
+  wn_store_n(T + (size_t)j * cd.h, v, cd.h);
 }
 
 void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,
                           int rows, uint32_t* T, hipStream_t s) {
   if (rows <= 0) return;
   const int blocks = (rows + 3) / 4;
-  if (cd.PN == 1)
-    offset_reduce_kernel<1><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T);
-  else
-    offset_reduce_kernel<2><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T);
+  switch (cd.P) {
+    case 1: offset_reduce_kernel<1><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
+    case 2: offset_reduce_kernel<2><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
+    case 3: offset_reduce_kernel<3><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
+    case 4: offset_reduce_kernel<4><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
+  }
 }
 
 }  // namespace zp

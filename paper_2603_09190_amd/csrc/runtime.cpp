@@ -15,10 +15,18 @@
 #include <tuple>
 #include <vector>
 
+#include "hostbig.h"
 #include "internal.h"
 #include "zippir.h"
 
 namespace {
+
+using zp::Big;
+using zp::big_cmp;
+using zp::big_mul;
+using zp::big_pow2_mod;
+using zp::big_resize;
+using zp::bit_length;
 
 thread_local std::string g_last_error;
 
@@ -41,84 +49,6 @@ pir_status fail(pir_status st, const std::string& msg) {
     if (st_ != PIR_OK) return st_;   \
   } while (0)
 
-// ----------------------------------------------------------------------------- host bignum
-// Little-endian uint32 limbs, used only for per-client constants at registration time.
-using Big = std::vector<uint32_t>;
-
-Big big_resize(Big a, size_t n) {
-  a.resize(n, 0u);
-  return a;
-}
-
-int big_cmp(const Big& a, const Big& b) {
-  const size_t n = std::max(a.size(), b.size());
-  for (size_t i = n; i-- > 0;) {
-    const uint32_t x = i < a.size() ? a[i] : 0u, y = i < b.size() ? b[i] : 0u;
-    if (x != y) return x < y ? -1 : 1;
-  }
-  return 0;
-}
-
-void big_sub_inplace(Big& a, const Big& b) {  // a -= b, requires a >= b
-  uint64_t br = 0;
-  for (size_t i = 0; i < a.size(); ++i) {
-    const uint64_t y = (i < b.size() ? b[i] : 0u) + br;
-    const uint64_t x = a[i];
-    a[i] = (uint32_t)(x - y);
-    br = x < y ? 1 : 0;
-  }
-}
-
-Big big_mul(const Big& a, const Big& b) {
-  Big r(a.size() + b.size(), 0u);
-  for (size_t i = 0; i < a.size(); ++i) {
-    uint64_t carry = 0;
-    for (size_t j = 0; j < b.size(); ++j) {
-      const uint64_t t = (uint64_t)a[i] * b[j] + r[i + j] + carry;
-      r[i + j] = (uint32_t)t;
-      carry = t >> 32;
-    }
-    size_t k = i + b.size();
-    while (carry) {
-      const uint64_t t = (uint64_t)r[k] + carry;
-      r[k] = (uint32_t)t;
-      carry = t >> 32;
-      ++k;
-    }
-  }
-  return r;
-}
-
-// 2^k mod m by repeated doubling (m odd, m > 1).
-Big big_pow2_mod(uint64_t k, const Big& m) {
-  Big x(m.size() + 1, 0u);
-  x[0] = 1;
-  if (big_cmp(x, m) >= 0) big_sub_inplace(x, m);
-  for (uint64_t t = 0; t < k; ++t) {
-    uint32_t carry = 0;
-    for (size_t i = 0; i < x.size(); ++i) {
-      const uint32_t nc = x[i] >> 31;
-      x[i] = (x[i] << 1) | carry;
-      carry = nc;
-    }
-    if (big_cmp(x, m) >= 0) big_sub_inplace(x, m);
-  }
-  x.resize(m.size());
-  return x;
-}
-
-uint32_t neg_inv32(uint32_t m0) {  // -m0^{-1} mod 2^32 for odd m0 (Newton iteration)
-  uint32_t inv = m0;               // correct to 3 bits
-  for (int i = 0; i < 5; ++i) inv *= 2u - m0 * inv;
-  return 0u - inv;
-}
-
-size_t bit_length(const Big& a) {
-  for (size_t i = a.size(); i-- > 0;)
-    if (a[i]) return 32 * i + (32 - __builtin_clz(a[i]));
-  return 0;
-}
-
 // ----------------------------------------------------------------------------- state
 
 struct DevAlloc {
@@ -133,9 +63,10 @@ struct ClientState {
   uint32_t n_bits = 0, h = 0, L = 0, P = 0, PN = 0, S = 0, SN = 0;
   Big N;
   uint32_t* ck = nullptr;      // n x L
-  uint32_t* consts = nullptr;  // N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each) | CP (S) | D1 | D2 (SN each)
+  uint32_t* consts = nullptr;  // N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each) | CP (S) | D1 | D2 | C96 (SN each)
   uint32_t* Kp = nullptr;      // rows x L: K_j 2^32 mod N^2
   uint32_t* Mp = nullptr;      // rows x L: N (K'_j mod N), the combine key
+  uint32_t* Y = nullptr;       // rows x h: (K_j mod N) R_N mod N, the offset-combine key
   uint32_t m2prime = 0, nprime = 0;
   std::vector<uint8_t> valid;  // per row: K' and M' up to date
   int64_t stale = 0;
@@ -146,26 +77,9 @@ struct ClientState {
   std::vector<uint8_t> gvalid; // per group
   int64_t gstale = 0;
 
-  zp::ClientDev dev() const {
-    zp::ClientDev d;
-    d.N2 = consts;
-    d.R1 = consts + S;
-    d.RR = consts + 2 * S;
-    d.NP = consts + 3 * S;
-    d.Nn = consts + 4 * S;
-    d.C1 = consts + 4 * S + SN;
-    d.C2 = consts + 4 * S + 2 * SN;
-    d.CP = consts + 4 * S + 3 * SN;
-    d.D1 = consts + 5 * S + 3 * SN;
-    d.D2 = consts + 5 * S + 4 * SN;
-    d.m2prime = m2prime;
-    d.nprime = nprime;
-    d.L = (int)L;
-    d.h = (int)h;
-    d.P = (int)P;
-    d.PN = (int)PN;
-    return d;
-  }
+  zp::ModConsts mc;            // sizes and constants of N (mc.host is the device block `consts`)
+
+  zp::ClientDev dev() const { return zp::dev_view(mc, consts); }
 };
 
 struct pir_server {
@@ -197,7 +111,7 @@ struct pir_server {
   };
   std::vector<ProfRecord> prof_ev[PIR_KERNEL_COUNT];
   // growable scratch
-  DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c, s_x, s_xcs, s_w, s_t;
+  DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c, s_x, s_xcs, s_w, s_t, s_ys;
 
   pir_status alloc(void** p, size_t bytes_) {
     *p = nullptr;
@@ -287,16 +201,23 @@ void prof_clear(pir_server* s) {
 // shape times every candidate once (after a warm-up) with events on the server's stream and
 // keeps the fastest; every candidate computes identical bits, so tuning never changes a
 // result.  ZIPPIR_AUTOTUNE=0 disables tuning (default shape); ZIPPIR_TUNE_CACHE=<file>
-// persists choices as lines "rows pitch ncol rowmajor planes waves depth mr kb ksplit".
+// persists choices as lines "rows pitch ncol rowmajor planes waves depth mr kb ksplit cg".
 using TuneKey = std::tuple<int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, zp::GemmShape> g_tune;
 bool g_tune_loaded = false;
 
-constexpr zp::GemmShape kDefaultShape{8, 1, 2, 256, 2};
-const zp::GemmShape kCandidates[] = {{8, 1, 2, 256, 2}, {8, 2, 2, 256, 2}, {8, 1, 2, 256, 4},
-                                     {8, 1, 1, 256, 2}, {4, 1, 2, 512, 1}, {2, 2, 2, 256, 1},
-                                     {4, 1, 2, 256, 1}};
+constexpr zp::GemmShape kDefaultShape4{8, 1, 2, 256, 2, 4};
+constexpr zp::GemmShape kDefaultShape1{8, 1, 2, 256, 1, 3};
+// byte-plane problems (batched answers, H)
+const std::vector<zp::GemmShape> kCandidates4 = {{8, 1, 2, 256, 2, 4}, {8, 2, 2, 256, 2, 4}, {8, 1, 2, 256, 4, 4},
+                                                 {8, 1, 1, 256, 2, 4}, {4, 1, 2, 512, 1, 4}, {2, 2, 2, 256, 1, 4},
+                                                 {4, 1, 2, 256, 1, 4}};
+// one-plane problems (the offset answer): column groups per block as well
+const std::vector<zp::GemmShape> kCandidates1 = {{8, 1, 2, 256, 1, 3}, {8, 1, 2, 256, 1, 4}, {8, 2, 2, 256, 1, 3},
+                                                 {8, 2, 2, 256, 1, 4}, {4, 1, 2, 256, 1, 3}, {4, 1, 2, 512, 1, 4},
+                                                 {8, 1, 1, 256, 1, 4}, {8, 1, 2, 256, 2, 3}, {8, 1, 2, 256, 1, 2},
+                                                 {8, 1, 4, 256, 1, 3}, {8, 1, 4, 256, 1, 4}, {4, 1, 4, 256, 1, 3}};
 
 const char* tune_cache_path() {
   const char* p = std::getenv("ZIPPIR_TUNE_CACHE");
@@ -309,10 +230,10 @@ void tune_load_locked() {
   const char* path = tune_cache_path();
   if (!path) return;
   std::ifstream f(path);
-  int r, p, n, m, pl, w, d, mr, kb, k;
-  while (f >> r >> p >> n >> m >> pl >> w >> d >> mr >> kb >> k) {
-    const zp::GemmShape sh{w, d, mr, kb, k};
-    if (zp::gemm_shape_valid(sh, p) && (pl == 1 || pl == 4)) g_tune[TuneKey(r, p, n, m, pl)] = sh;
+  int r, p, n, m, pl, w, d, mr, kb, k, cg;
+  while (f >> r >> p >> n >> m >> pl >> w >> d >> mr >> kb >> k >> cg) {
+    const zp::GemmShape sh{w, d, mr, kb, k, cg};
+    if (zp::gemm_shape_valid(sh, p, pl)) g_tune[TuneKey(r, p, n, m, pl)] = sh;
   }
 }
 
@@ -324,7 +245,7 @@ void tune_store_locked() {
     f << std::get<0>(kv.first) << " " << std::get<1>(kv.first) << " " << std::get<2>(kv.first) << " "
       << std::get<3>(kv.first) << " " << std::get<4>(kv.first) << " " << kv.second.waves << " "
       << kv.second.depth << " "
-      << kv.second.mr << " " << kv.second.kb << " " << kv.second.ksplit << "\n";
+      << kv.second.mr << " " << kv.second.kb << " " << kv.second.ksplit << " " << kv.second.cg << "\n";
 }
 
 bool autotune_enabled() {
@@ -338,7 +259,7 @@ pir_status run_gemm_x(pir_server* s, const uint8_t* D, int rows, int cols, int p
                       uint32_t* out, bool rowmajor, long long ld) {
   hipStream_t st = s->stream;
   const TuneKey key((int)rows, pitch, ncol, rowmajor ? 1 : 0, planes);
-  zp::GemmShape shape = kDefaultShape;
+  zp::GemmShape shape = planes == 4 ? kDefaultShape4 : kDefaultShape1;
   bool need_tune = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -352,8 +273,8 @@ pir_status run_gemm_x(pir_server* s, const uint8_t* D, int rows, int cols, int p
     ZP_HIP(hipEventCreate(&e0));
     ZP_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    for (const zp::GemmShape& c : kCandidates) {
-      if (!zp::gemm_shape_valid(c, pitch)) continue;
+    for (const zp::GemmShape& c : planes == 4 ? kCandidates4 : kCandidates1) {
+      if (!zp::gemm_shape_valid(c, pitch, planes)) continue;
       zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor,
                              ld, c, st);
       ZP_HIP(hipEventRecord(e0, st));
@@ -488,7 +409,7 @@ pir_status refresh_groups(pir_server* s, ClientState* c, std::vector<uint32_t> g
     (void)hipMemcpyAsync(dg, groups.data(), groups.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
   }
   zp::launch_group_keys(cd, c->Kp, (int)s->rows, (int)c->ell, (int)c->t, dg, ng, c->Kg, st);
-  zp::launch_combine_key(cd, c->Kg, dg, ng, c->Mr, st);
+  zp::launch_combine_key(cd, c->Kg, dg, ng, c->Mr, nullptr, st);
   zp::launch_to_mont(cd, c->Mr, dg, ng, st);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -609,31 +530,11 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
     if (big_cmp(c->N, bound) <= 0)
       return fail(PIR_EINVAL, "N too small: compression needs N > q + n q^2 (q = 2^32)");
   }
-  const Big N2 = big_resize(big_mul(c->N, c->N), c->S);
-  const Big Nn = big_resize(c->N, c->SN);
-  const Big R1 = big_pow2_mod(32ull * c->S, big_resize(N2, c->L));
-  const Big RR = big_pow2_mod(64ull * c->S, big_resize(N2, c->L));
-  const Big C1 = big_pow2_mod(32ull * c->SN, c->N);
-  const Big C2 = big_pow2_mod(64ull * c->SN, c->N);
-  c->m2prime = neg_inv32(N2[0]);
-  c->nprime = neg_inv32(c->N[0]);
-  const Big CP = big_pow2_mod(64ull * c->S - 32, big_resize(N2, c->L));
-  const Big D1 = big_pow2_mod(64ull * c->SN - 32, c->N);
-  const Big D2 = big_pow2_mod(96ull * c->SN - 32, c->N);
-  std::vector<uint32_t> host(5 * (size_t)c->S + 5 * (size_t)c->SN, 0u);
-  auto put = [&](size_t off, const Big& v, size_t width) {
-    for (size_t i = 0; i < std::min(width, v.size()); ++i) host[off + i] = v[i];
-  };
-  put(0, N2, c->S);
-  put(c->S, R1, c->S);
-  put(2 * (size_t)c->S, RR, c->S);
-  put(3 * (size_t)c->S, c->N, c->S);
-  put(4 * (size_t)c->S, Nn, c->SN);
-  put(4 * (size_t)c->S + c->SN, C1, c->SN);
-  put(4 * (size_t)c->S + 2 * c->SN, C2, c->SN);
-  put(4 * (size_t)c->S + 3 * c->SN, CP, c->S);
-  put(5 * (size_t)c->S + 3 * c->SN, D1, c->SN);
-  put(5 * (size_t)c->S + 4 * c->SN, D2, c->SN);
+  c->mc = zp::mod_constants(c->N, N_bits);
+  c->m2prime = c->mc.m2prime;
+  c->nprime = c->mc.nprime;
+  const std::vector<uint32_t>& host = c->mc.host;
+  const Big N2 = big_mul(c->N, c->N);
   // packing scale gamma = 2^t >= q + n q^2 (q = 2^32): t = 64 + bitlen(n); ell t <= N_bits - 1
   {
     uint32_t bl = 0;
@@ -664,8 +565,13 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
       }
     }
   }
-  ZP_TRY(s->alloc((void**)&c->Kp, (size_t)s->rows * c->L * sizeof(uint32_t)));
-  ZP_TRY(s->alloc((void**)&c->Mp, (size_t)s->rows * c->L * sizeof(uint32_t)));
+  pir_status a = s->alloc((void**)&c->Kp, (size_t)s->rows * c->L * sizeof(uint32_t));
+  if (a == PIR_OK) a = s->alloc((void**)&c->Mp, (size_t)s->rows * c->L * sizeof(uint32_t));
+  if (a == PIR_OK) a = s->alloc((void**)&c->Y, (size_t)s->rows * c->h * sizeof(uint32_t));
+  if (a != PIR_OK) {
+    for (void* p : {(void*)c->ck, (void*)c->consts, (void*)c->Kp, (void*)c->Mp, (void*)c->Y}) s->release(p);
+    return a;
+  }
   c->valid.assign(s->rows, 0);
   c->stale = s->rows;
   c->id = s->next_id++;
@@ -685,6 +591,7 @@ pir_status pir_remove_client(pir_server* s, uint32_t id) {
   s->release(c->consts);
   s->release(c->Kp);
   s->release(c->Mp);
+  s->release(c->Y);
   s->release(c->Kg);
   s->release(c->Mr);
   s->clients.erase(id);
@@ -714,7 +621,7 @@ pir_status pir_hint(pir_server* s, uint32_t id, const uint32_t* rows, uint32_t n
   ZP_TRY(s->alloc((void**)&table, tbytes));
   {
     ProfScope ps(s, PIR_KERNEL_TABLE);
-    zp::launch_build_table(cd, c->ck, (int)s->n, table, st);
+    zp::launch_build_table(cd, c->ck, (int)s->n, zp::kWindows, table, st);
   }
   uint32_t* drows = nullptr;
   const int m = all ? (int)s->rows : (int)sel.size();
@@ -732,7 +639,7 @@ pir_status pir_hint(pir_server* s, uint32_t id, const uint32_t* rows, uint32_t n
   }
   {
     ProfScope ps(s, PIR_KERNEL_KEY);
-    zp::launch_combine_key(cd, c->Kp, drows, m, c->Mp, st);
+    zp::launch_combine_key(cd, c->Kp, drows, m, c->Mp, c->Y, st);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1047,7 +954,15 @@ pir_status pir_offset_answer(pir_server* s, const uint32_t* ids, uint32_t batch,
   auto* X = (int8_t*)s->s_x.p;
   auto* xcs = (int32_t*)s->s_xcs.p;
   auto* W = (uint32_t*)s->s_w.p;
-  zp::launch_pack_offset(dK, (int)batch, (int)s->n, (int)h, cpc, (int)s->epitch, X, xcs, st);
+  ZP_TRY(s->scratch(s->s_ys, kbytes));
+  auto* ys = (uint32_t*)s->s_ys.p;
+  {
+    ProfScope ps(s, PIR_KERNEL_OFFSET, (int)batch);
+    for (uint32_t i = 0; i < batch; ++i)
+      zp::launch_scale_offsets(cs[i]->dev(), dK + (size_t)i * s->n * h, (int)s->n,
+                               ys + (size_t)i * s->n * h, st);
+  }
+  zp::launch_pack_offset(ys, (int)batch, (int)s->n, (int)h, cpc, (int)s->epitch, X, xcs, st);
   ZP_TRY(run_gemm_x(s, s->Eb, (int)s->rows, 4 * (int)s->n, (int)s->epitch, 1, X, xcs, (int)ncol,
                     s->Erowsum, W, true, 0));
   {
@@ -1094,8 +1009,8 @@ pir_status pir_compress_offset(pir_server* s, const uint32_t* ids, uint32_t batc
   }
   for (uint32_t i = 0; i < batch; ++i) {
     ProfScope ps(s, PIR_KERNEL_COMPRESS);
-    zp::launch_compress_offset(cs[i]->dev(), cs[i]->Kp, dT + (size_t)i * s->rows * h, (int)s->rows,
-                               dC + (size_t)i * s->rows * L, st);
+    zp::launch_compress_offset(cs[i]->dev(), cs[i]->Kp, cs[i]->Y, dT + (size_t)i * s->rows * h,
+                               (int)s->rows, dC + (size_t)i * s->rows * L, st);
   }
   ZP_HIP(hipGetLastError());
   if (ptr_flags == PIR_PTR_HOST) {

@@ -5,9 +5,10 @@
 // keeps one FIFO queue per database.  Each database has two batch slots (device buffers for
 // the queries, the answers and the compressed responses of one batch); whenever a slot is
 // free and arrived requests are waiting, it takes up to max_batch of them whose clients
-// share a limb count and enqueues on the database's stream: query uploads, pir_answer
-// (matvec for one request, one int8-MFMA contraction otherwise), pir_compress, and one
-// download per response.  An event marks the batch's end; the scheduler polls events and
+// share a limb count and a packing factor, and enqueues on the database's stream: query
+// uploads, pir_answer (matvec for one request, one int8-MFMA contraction otherwise),
+// pir_compress (or pir_compress_packed for clients with packed responses), and one download
+// per response.  An event marks the batch's end; the scheduler polls events and
 // hands completions to pir_engine_poll.  Databases use different streams, so their batches
 // overlap on the device, and a database with a batch in flight forms its next one meanwhile.
 #include <hip/hip_runtime.h>
@@ -35,6 +36,7 @@ using Clock = std::chrono::steady_clock;
 struct Request {
   uint64_t id = 0;
   uint32_t db = 0, client = 0, L = 0;
+  uint32_t ell = 1;            // packing factor of the client's responses, read at submit
   double arrival_ms = 0;
   uint32_t* host_q = nullptr;  // pinned copy of the query
   uint32_t* result = nullptr;
@@ -60,9 +62,15 @@ struct Db {
   std::vector<uint32_t*> qpool;  // free pinned query buffers (cols words each)
 };
 
-uint64_t bytes_per_request(const Db& d, uint32_t L) {
-  return 4ull * d.cols + 4ull * d.rows + 4ull * d.rows * L;
+// Rows of one response: one ciphertext per database row, or per group of ell rows.
+uint64_t response_rows(const Db& d, uint32_t ell) { return (d.rows + ell - 1) / ell; }
+
+uint64_t bytes_per_request(const Db& d, uint32_t L, uint32_t ell) {
+  return 4ull * d.cols + 4ull * d.rows + 4ull * response_rows(d, ell) * L;
 }
+
+// Requests can share a batch when their clients have the same limb count and packing.
+uint32_t batch_key(const Request& r) { return r.L | (r.ell << 16); }
 
 }  // namespace
 
@@ -144,8 +152,9 @@ bool pir_engine::reserve(Db& d, Slot& slot, uint64_t need) {
 }
 
 bool pir_engine::launch(Db& d, Slot& slot, uint32_t n) {
-  const uint32_t L = d.queue.front().L;
-  const uint64_t need = bytes_per_request(d, L) * n;
+  const uint32_t L = d.queue.front().L, ell = d.queue.front().ell;
+  const uint64_t orows = response_rows(d, ell);
+  const uint64_t need = bytes_per_request(d, L, ell) * n;
   if (!reserve(d, slot, need)) return false;
   slot.reqs.assign(d.queue.begin(), d.queue.begin() + n);
   d.queue.erase(d.queue.begin(), d.queue.begin() + n);
@@ -161,9 +170,11 @@ bool pir_engine::launch(Db& d, Slot& slot, uint32_t n) {
   std::vector<uint32_t> ids(n);
   for (uint32_t i = 0; i < n; ++i) ids[i] = slot.reqs[i].client;
   if (st == PIR_OK) st = pir_answer(d.srv, dQ, n, dB, PIR_PTR_DEVICE);
-  if (st == PIR_OK) st = pir_compress(d.srv, ids.data(), n, dB, dC, PIR_PTR_DEVICE);
+  if (st == PIR_OK)
+    st = ell > 1 ? pir_compress_packed(d.srv, ids.data(), n, dB, dC, PIR_PTR_DEVICE)
+                 : pir_compress(d.srv, ids.data(), n, dB, dC, PIR_PTR_DEVICE);
   for (uint32_t i = 0; i < n && st == PIR_OK; ++i)
-    if (hipMemcpyAsync(slot.reqs[i].result, dC + (size_t)i * d.rows * L, 4ull * d.rows * L,
+    if (hipMemcpyAsync(slot.reqs[i].result, dC + (size_t)i * orows * L, 4ull * orows * L,
                        hipMemcpyDefault, d.stream) != hipSuccess)
       st = PIR_EDEVICE;
   if (!slot.ev) (void)hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming);
@@ -239,10 +250,10 @@ void pir_engine::run() {
             next_arrival = std::min(next_arrival, r.arrival_ms);
             break;
           }
-          limbs.push_back(r.L);
+          limbs.push_back(batch_key(r));
         }
         if (limbs.empty()) continue;
-        const uint64_t per = bytes_per_request(d, limbs[0]);
+        const uint64_t per = bytes_per_request(d, d.queue.front().L, d.queue.front().ell);
         uint64_t avail = budget - std::min(budget, in_use) + s.bytes;
         uint32_t cap = pir_engine_capacity(avail, per, max_batch);
         if (cap == 0) {
@@ -348,6 +359,8 @@ pir_status pir_engine_submit(pir_engine* e, uint32_t db, uint32_t client, const 
     Db& d = *e->dbs[db];
     r.L = pir_client_limbs(d.srv, client);
     if (r.L == 0) return efail(PIR_EINVAL, "unknown client id");
+    if (pir_packing_info(d.srv, client, &r.ell, nullptr, nullptr, nullptr) != PIR_OK)
+      return efail(PIR_EINVAL, "unknown client id");
     hipPointerAttribute_t attr;
     std::memset(&attr, 0, sizeof(attr));
     const hipError_t pe = hipPointerGetAttributes(&attr, result);

@@ -155,21 +155,13 @@ __device__ __forceinline__ void wn_cond_sub(WNum<P>& x, uint64_t ovf, const WNum
   }
 }
 
-// One CIOS step: t = (t + a_i*b + q*m) / 2^32 with q chosen so the division is exact.
-// c is the lane's pending carry word (see file comment).
+// The reduction half of a CIOS step: t = (t + q*m) / 2^32 with q = t_0 * mprime mod 2^32, so
+// the division is exact.  c is the lane's pending carry word (see file comment).
 template <int P>
-__device__ __forceinline__ void mont_step(WNum<P>& t, uint64_t& c, uint32_t ai, const WNum<P>& b,
-                                          const WNum<P>& m, uint32_t mprime) {
-  uint32_t carry = 0;
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    uint64_t x = (uint64_t)ai * b.v[j] + t.v[j] + carry;
-    t.v[j] = (uint32_t)x;
-    carry = (uint32_t)(x >> 32);
-  }
-  c += carry;
+__device__ __forceinline__ void redc_step(WNum<P>& t, uint64_t& c, const WNum<P>& m,
+                                          uint32_t mprime) {
   const uint32_t q = bcast(t.v[0], 0) * mprime;
-  carry = 0;
+  uint32_t carry = 0;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     uint64_t x = (uint64_t)q * m.v[j] + t.v[j] + carry;
@@ -184,6 +176,22 @@ __device__ __forceinline__ void mont_step(WNum<P>& t, uint64_t& c, uint32_t ai, 
   const uint64_t top = (uint64_t)up + c;
   t.v[P - 1] = (uint32_t)top;
   c = top >> 32;
+}
+
+// One CIOS step: t = (t + a_i*b + q*m) / 2^32 with q chosen so the division is exact.
+// c is the lane's pending carry word (see file comment).
+template <int P>
+__device__ __forceinline__ void mont_step(WNum<P>& t, uint64_t& c, uint32_t ai, const WNum<P>& b,
+                                          const WNum<P>& m, uint32_t mprime) {
+  uint32_t carry = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    uint64_t x = (uint64_t)ai * b.v[j] + t.v[j] + carry;
+    t.v[j] = (uint32_t)x;
+    carry = (uint32_t)(x >> 32);
+  }
+  c += carry;
+  redc_step(t, c, m, mprime);
 }
 
 // out = a * b * R^{-1} mod m, canonical, for a < R and b < m (m odd, m < R).
@@ -216,11 +224,7 @@ __device__ __forceinline__ void mont_mul_short(WNum<P>& out, const WNum<P>& a, i
   uint64_t c = 0;
   for (int i = 0; i < na; ++i) mont_step(t, c, wn_limb(a, i), b, m, mprime);
   // the remaining S - na steps have a_i = 0: only the reduction part remains
-  for (int i = na; i < 64 * P; ++i) {
-    WNum<P> z;
-    wn_zero(z);
-    mont_step(t, c, 0u, z, m, mprime);
-  }
+  for (int i = na; i < 64 * P; ++i) redc_step(t, c, m, mprime);
   const uint64_t ovf = wn_resolve(t, c);
   wn_cond_sub(t, ovf, m);
   out = t;

@@ -304,4 +304,4 @@ def test_autotuned_shape_is_persisted(native, tmp_path, monkeypatch):
         assert np.array_equal(B, server.answer_batch(D, Qm))
     lines = [l.split() for l in cache.read_text().splitlines()]
     mine = [l for l in lines if l[:5] == [str(rows), str(cols + (-cols) % 256), str(batch), "0", "4"]]
-    assert len(mine) == 1 and len(mine[0]) == 10
+    assert len(mine) == 1 and len(mine[0]) == 11

@@ -196,3 +196,48 @@ def test_engine_errors(native, setup):
         K = server.client_hint(cl1.ck, E, cl1.N)
         assert limbs_rows_to_ints(b1.array) == server.compress(K, server.answer(inst1.D, q), cl1.N)
         b1.close()
+
+
+def test_packed_clients_in_the_mix(native):
+    """A database with one packed client (ell = 5) and one plain client: requests of the two
+    kinds never share a batch, and every response equals the library's own packed or plain
+    combine of that request's answer, which the packed GPU tests check against the oracle."""
+    import torch
+    rows, cols, nb = 203, 320, 512
+    inst = make_instance(cfg=940, rows=rows, cols=cols, n=N_LWE, n_bits=nb, nclients=2, encrypt_secret=False)
+    st = torch.cuda.Stream()
+    g = np.random.default_rng(4)
+    with native.Server(inst.D, inst.A, stream=st.cuda_stream) as srv:
+        ids = []
+        for cl in inst.clients:
+            N_limbs, ck, L = client_arrays(cl, nb)
+            cid = srv.add_client(N_limbs, nb, ck)
+            srv.hint(cid)
+            ids.append(cid)
+        srv.set_packing(ids[0], 5)
+        groups = srv.packing_info(ids[0])["groups"]
+        assert groups == -(-rows // 5)
+        reqs = [(int(g.integers(0, 2)), g.integers(0, 1 << 32, size=cols, dtype=np.uint32)) for _ in range(40)]
+        with native.Engine(max_batch=8) as eng:
+            eng.add_db(srv)
+            bufs = [native.PinnedArray((groups if k == 0 else rows, L)) for k, _ in reqs]
+            for (k, q), buf in zip(reqs, bufs):
+                eng.submit(0, ids[k], q, buf.array)
+            eng.drain()
+            comps = eng.poll(max_items=64)
+            got = [b.array.copy() for b in bufs]
+            for b in bufs:
+                b.close()
+        assert len(comps) == len(reqs) and all(c["status"] == 0 for c in comps)
+        by_id = {c["request_id"]: c for c in comps}
+        for i, ((k, q), out) in enumerate(zip(reqs, got), start=1):
+            B = np.zeros((1, rows), np.uint32)
+            srv.answer(q[None, :], B)
+            if k == 0:
+                C = np.zeros((1, groups, L), np.uint32)
+                srv.compress_packed([ids[0]], B, C)
+            else:
+                C = np.zeros((1, rows, L), np.uint32)
+                srv.compress([ids[1]], B, C)
+            assert np.array_equal(out, C[0]), f"request {i}"
+            assert by_id[i]["batch"] >= 1
