@@ -80,9 +80,10 @@ def main() -> int:
     ap.add_argument("--nbits", type=int, default=2048)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--cpu-rows", type=int, default=32768, help="rows in the CPU-oracle sample (0: skip)")
-    ap.add_argument("--workload", choices=["answer", "serve"], default="answer",
+    ap.add_argument("--workload", choices=["answer", "serve", "compress"], default="answer",
                     help="answer: 1 GiB database, one query per step (default); "
-                         "serve: four resident databases under Poisson arrivals")
+                         "serve: four resident databases under Poisson arrivals; "
+                         "compress: standalone LWE/RLWE compression at the Table 2 parameters")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals")
     ap.add_argument("--sides", type=str, default="16384,32768,65536,131072",
@@ -108,6 +109,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "serve":
         return serve(args)
+    if args.workload == "compress":
+        return compress_bench(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -360,6 +363,120 @@ def main() -> int:
         "hint_kernel_ms": round(hintk_ms, 1),
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+# Table 2's parameter sets: LWE (n, log2 q) and RLWE (ring dimension, log2 q), 3072-bit N.
+# q is 2^64 / 2^11 for the LWE sets and the largest prime below 2^bits for the RLWE sets.
+TABLE2 = [("lwe", 630, 64), ("lwe", 742, 64), ("lwe", 870, 64), ("lwe", 1305, 11),
+          ("rlwe", 1024, 27), ("rlwe", 2048, 54), ("rlwe", 4096, 36), ("rlwe", 8192, 43)]
+TABLE2_PAPER_MS = [9.7, 11.0, 12.9, 16.6, 7.2, 23.8, 33.8, 83.3]
+
+
+def _prime_below(bits: int) -> int:
+    def probable_prime(x):
+        if x % 2 == 0:
+            return False
+        d, r = x - 1, 0
+        while d % 2 == 0:
+            d //= 2
+            r += 1
+        for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+            y = pow(a, d, x)
+            if y in (1, x - 1):
+                continue
+            for _ in range(r - 1):
+                y = y * y % x
+                if y == x - 1:
+                    break
+            else:
+                return False
+        return True
+    x = (1 << bits) - 1
+    while not probable_prime(x):
+        x -= 2
+    return x
+
+
+def compress_bench(args) -> int:
+    """Standalone compression at Table 2's parameters: one ciphertext (latency) and a batch."""
+    import torch
+    import workload as wl
+    from paper_2603_09190_amd import native
+
+    dev = torch.device("cuda:0")
+    nbits = 3072
+    h = nbits // 32
+    L = 2 * h
+    pr = wl.paillier_primes(77, 0, nbits)
+    N = pr.P * pr.Q
+    N_limbs = wl.int_to_limbs(N, h)
+    results = []
+    for (kind, n, qbits), paper_ms in zip(TABLE2, TABLE2_PAPER_MS):
+        q = (1 << qbits) if kind == "lwe" else _prime_below(qbits)
+        dt = np.uint32 if q <= 1 << 32 else np.uint64
+        log(f"compress: {kind} n={n} log2 q={qbits}")
+        ck = wl.ints_to_limbs(wl.uniform_ciphertexts(77, n, n, N), L)
+        g = wl.rng(77, "cipher", n)
+        t0 = time.perf_counter()
+        cmp = native.Compressor(n, q, N_limbs, nbits, ck=ck)
+        setup_s = time.perf_counter() - t0
+        batch = 4096 if kind == "lwe" else n
+        sv = np.int32 if dt == np.uint32 else np.int64   # torch holds the words as signed ints
+        A = torch.from_numpy(g.integers(0, q, size=(batch if kind == "lwe" else 1, n), dtype=np.uint64)
+                             .astype(dt).view(sv)).to(dev)
+        B = torch.from_numpy(g.integers(0, q, size=(batch if kind == "lwe" else n,), dtype=np.uint64)
+                             .astype(dt).view(sv)).to(dev)
+        X = torch.zeros((batch, L), dtype=torch.int32, device=dev)
+        ks = np.arange(n, dtype=np.uint32)
+
+        def one():
+            if kind == "lwe":
+                cmp.compress_lwe(A[:1], B[:1], X[:1])
+            else:
+                cmp.compress_rlwe(A[0], B, ks[:1], X[:1])
+
+        def many():
+            if kind == "lwe":
+                cmp.compress_lwe(A, B, X)
+            else:
+                cmp.compress_rlwe(A[0], B, ks, X)
+
+        one()
+        lat = []
+        for _ in range(20):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            one()
+            lat.append((time.perf_counter() - t) * 1e3)
+        many()
+        torch.cuda.synchronize()
+        reps = 3
+        t = time.perf_counter()
+        for _ in range(reps):
+            many()
+        torch.cuda.synchronize()
+        batch_ms = (time.perf_counter() - t) * 1e3 / reps
+        info = cmp.info()
+        cmp.close()
+        results.append({"kind": kind, "n": n, "log2_q": qbits, "q": q, "single_ms_p50": round(percentile(lat, 50), 4),
+                        "batch": batch, "batch_ms": round(batch_ms, 3),
+                        "per_ciphertext_us": round(batch_ms * 1e3 / batch, 3),
+                        "setup_s": round(setup_s, 3), "table_bytes": info["device_bytes"],
+                        "paper_cpu_ms": paper_ms})
+        log(f"  single {results[-1]['single_ms_p50']} ms, batch {batch} in {batch_ms:.2f} ms")
+        del A, B, X
+        torch.cuda.empty_cache()
+    out = {
+        "metric": "standalone ciphertext compression time, Table 2 parameters (single ciphertext)",
+        "value": results[0]["single_ms_p50"], "unit": "ms", "n_gpus": 1, "steps": 20, "warmup": 1,
+        "ms_per_step": results[0]["single_ms_p50"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "LWE/RLWE ciphertext compression into 3072-bit Paillier (Table 2 parameter sets); "
+                               "value = one (630, 2^64) LWE ciphertext", "N_bits": nbits},
+        "sets": results,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -86,6 +86,22 @@ _sig = {
     "pir_engine_destroy": (None, [ctypes.c_void_p]),
     "pir_engine_capacity": (ctypes.c_uint32, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]),
     "pir_engine_plan": (ctypes.c_uint32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
+    "pir_compressor_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p,
+                                               ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32,
+                                               ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_compressor_create_packed": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                                      ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64,
+                                                      ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]),
+    "pir_compressor_destroy": (None, [ctypes.c_void_p]),
+    "pir_compressor_key": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                            ctypes.c_uint32]),
+    "pir_compressor_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                             ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]),
+    "pir_compress_lwe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                          ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_compress_rlwe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_host_alloc": (ctypes.c_void_p, [ctypes.c_uint64]),
     "pir_host_free": (None, [ctypes.c_void_p]),
     "pir_strerror": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -280,6 +296,77 @@ class EngineStats(ctypes.Structure):
                 ("batches", ctypes.c_uint64), ("admission_waits", ctypes.c_uint64),
                 ("device_bytes_peak", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("mean_batch", ctypes.c_double)]
+
+
+class Compressor:
+    """Standalone LWE / RLWE ciphertext compressor with a resident compression key.
+
+    ``q`` is the LWE modulus (2 <= q <= 2^64).  Arrays of LWE entries are uint32 when
+    q <= 2^32 and uint64 otherwise; keys and outputs are uint32 limb arrays (L limbs each).
+    """
+
+    def __init__(self, n: int, q: int, N_limbs, N_bits: int, ck=None, packed=None, t: int = 0,
+                 delta_log2: int = 0, device: int = 0, stream=None):
+        if not (2 <= q <= 1 << 64):
+            raise ValueError("q must be in [2, 2^64]")
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream is not None else None
+        qarg = q % (1 << 64)
+        N_limbs = np.ascontiguousarray(N_limbs, dtype=np.uint32)
+        if packed is None:
+            key = np.ascontiguousarray(ck, dtype=np.uint32)
+            _check(_lib.pir_compressor_create(ctypes.byref(h), device, st, n, qarg, _ptr(N_limbs)[0], N_bits,
+                                              _ptr(key)[0], PIR_PTR_HOST), "pir_compressor_create")
+        else:
+            key = np.ascontiguousarray(packed, dtype=np.uint32)
+            _check(_lib.pir_compressor_create_packed(ctypes.byref(h), device, st, n, qarg, _ptr(N_limbs)[0],
+                                                     N_bits, _ptr(key)[0], t, delta_log2, PIR_PTR_HOST),
+                   "pir_compressor_create_packed")
+        self._h = h
+        self.n, self.q = n, q
+        self.dtype = np.uint32 if q <= 1 << 32 else np.uint64
+        L, w, b = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        _check(_lib.pir_compressor_info(self._h, ctypes.byref(L), ctypes.byref(w), ctypes.byref(b)),
+               "pir_compressor_info")
+        self.L, self.windows = L.value, w.value
+
+    def info(self) -> dict:
+        L, w, b = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        _check(_lib.pir_compressor_info(self._h, ctypes.byref(L), ctypes.byref(w), ctypes.byref(b)),
+               "pir_compressor_info")
+        return {"L": L.value, "windows": w.value, "device_bytes": b.value}
+
+    def key(self, k0: int = 0, nk: int | None = None) -> np.ndarray:
+        nk = self.n - k0 if nk is None else nk
+        out = np.zeros((nk, self.L), np.uint32)
+        _check(_lib.pir_compressor_key(self._h, k0, nk, _ptr(out)[0], PIR_PTR_HOST), "pir_compressor_key")
+        return out
+
+    def compress_lwe(self, A, B, X) -> None:
+        """A: rows x n, B: rows (entries of self.dtype); X: rows x L uint32 (host or device)."""
+        rows = int(np.shape(B)[0])
+        _check(_lib.pir_compress_lwe(self._h, _ptr(A)[0], _ptr(B)[0], rows, _ptr(X)[0], _flags(A, B, X)),
+               "pir_compress_lwe")
+
+    def compress_rlwe(self, A, B, ks, X) -> None:
+        """A, B: the n coefficients of an RLWE ciphertext; ks: coefficient indices; X: len(ks) x L."""
+        k = np.ascontiguousarray(np.asarray(ks, dtype=np.uint32))
+        _check(_lib.pir_compress_rlwe(self._h, _ptr(A)[0], _ptr(B)[0], ctypes.c_void_p(k.ctypes.data), len(k),
+                                      _ptr(X)[0], _flags(A, B, X)), "pir_compress_rlwe")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.pir_compressor_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class PinnedArray:
