@@ -32,6 +32,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA
+# 32x32 -> 64-bit integer multiply-add (v_mad_u64_u32) issues at half rate: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz / 2 word MACs per second.
+ALU_PEAK_MACS = 256 * 4 * 16 * 2.4e9 / 2
+
+
+def montmul_macs(n_limbs: int) -> int:
+    """32x32-bit multiply-adds of one Montgomery product of S = n_limbs words (CIOS)."""
+    return 2 * n_limbs * n_limbs + n_limbs
 
 # HBM bytes per launch of the matvec on the 1 GiB database, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (calibrated on a plain 1 GiB device copy), keyed by the SHA-256 of the matvec
@@ -147,6 +155,15 @@ def main() -> int:
     hintk_ms, _ = srv.profile_read("hint")
     srv.profile(False)
     log(f"offline hint {hint_s:.2f} s (H {gemm_ms:.2f} ms, table {table_ms:.1f} ms, rows {hintk_ms:.1f} ms)")
+    # expected Montgomery products of the hint rows: 4 windows per exponent, each nonzero with
+    # probability 255/256 for uniform exponents, plus one conversion per row
+    S = 64 * ((L + 63) // 64)
+    hint_mm = rows * (n * 4 * 255 / 256 + 1)
+    hint_rate = hint_mm / (hintk_ms * 1e-3)
+    hint_fig = {"kernel_ms": round(hintk_ms, 1), "montmuls": int(hint_mm), "montmul_per_s": round(hint_rate, 0),
+                "limbs": S, "word_mac_per_s": round(hint_rate * montmul_macs(S), 0),
+                "alu_peak_mac_per_s": ALU_PEAK_MACS,
+                "frac": round(hint_rate * montmul_macs(S) / ALU_PEAK_MACS, 4)}
 
     Qt = torch.from_numpy(Qh.view(np.int32)).to(dev)
     q1 = Qt[:1].contiguous()
@@ -312,6 +329,23 @@ def main() -> int:
             "kernel": "matvec_seg_kernel<2>", "kernel_avg_us": round(mv_avg_ms * 1e3, 2),
             "bytes_per_launch": mv_bytes, "step_matvec_event_us": round(mv_ms / max(1, mv_n) * 1e3, 2)}
 
+    # the device's streaming-read ceiling: a 1 GiB nontemporal read per launch, timed with
+    # events on the same stream
+    src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    sink = torch.empty(8192, dtype=torch.int32, device=dev)
+    for _ in range(3):
+        native.read_probe(src, sink, 8192, stream.cuda_stream)
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    for _ in range(10):
+        native.read_probe(src, sink, 8192, stream.cuda_stream)
+    p1.record(stream)
+    p1.synchronize()
+    probe_gbs = (1 << 30) / (p0.elapsed_time(p1) / 10 * 1e-3) / 1e9
+    del src, sink
+    roof["read_probe_gbs"] = round(probe_gbs, 1)
+    roof["frac_of_read_probe"] = round(achieved / probe_gbs, 4)
+
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -361,6 +395,7 @@ def main() -> int:
         "full_protocol": full,
         "offline_hint_s": round(hint_s, 3),
         "hint_kernel_ms": round(hintk_ms, 1),
+        "hint": hint_fig,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -461,7 +496,11 @@ def compress_bench(args) -> int:
         batch_ms = (time.perf_counter() - t) * 1e3 / reps
         info = cmp.info()
         cmp.close()
+        mm = batch * (n * info["windows"] * 255 / 256 + 2)   # + tree/conversion products per ciphertext
+        rate = mm / (batch_ms * 1e-3)
         results.append({"kind": kind, "n": n, "log2_q": qbits, "q": q, "single_ms_p50": round(percentile(lat, 50), 4),
+                        "batch_montmul_per_s": round(rate, 0),
+                        "batch_alu_frac": round(rate * montmul_macs(3 * 64) / ALU_PEAK_MACS, 4),
                         "batch": batch, "batch_ms": round(batch_ms, 3),
                         "per_ciphertext_us": round(batch_ms * 1e3 / batch, 3),
                         "setup_s": round(setup_s, 3), "table_bytes": info["device_bytes"],

@@ -347,6 +347,16 @@ void pir_engine_destroy(pir_engine *eng);
 uint32_t pir_engine_capacity(uint64_t budget_free, uint64_t bytes_per_request, uint32_t max_batch);
 uint32_t pir_engine_plan(const uint32_t *queued_limbs, uint32_t nqueued, uint32_t capacity);
 
+/*
+ * Streaming-read probe (measurement only): reads the first bytes - bytes mod 16 bytes of the
+ * device buffer buf (16-byte aligned) once with nontemporal loads, `blocks` workgroups of 256
+ * threads, and writes one word per workgroup to sink (a device array of `blocks` words).
+ * Enqueued on hip_stream; the time of this launch gives the device's achievable HBM read
+ * bandwidth, the practical ceiling of the one-query answer.
+ */
+pir_status pir_read_probe(const void *buf, uint64_t bytes, uint32_t *sink, uint32_t blocks,
+                          void *hip_stream);
+
 /* Pinned host memory for engine results (NULL on failure). */
 void *pir_host_alloc(uint64_t bytes);
 void pir_host_free(void *p);

@@ -120,7 +120,7 @@ constexpr int kMaxBlockK = 65536; // K bytes per block (keeps MFMA partials with
 // takes every column block and K range of one row block in turn (row blocks x, x+8, ...), so
 // the D tile they share is read from HBM once and then served from that XCD's L2.
 template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide>
-__global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
+__device__ __forceinline__ void gemm_planes_body(
     const uint8_t* __restrict__ D, int rows, int cols, int pitch, const int8_t* __restrict__ Xs,
     const int32_t* __restrict__ colsum, int ncol, const int32_t* __restrict__ rowsum,
     uint32_t* __restrict__ out, int out_rowmajor, long long out_ld, int ksteps_per_block,
@@ -209,16 +209,17 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
       const int cur = st + d;
       if (cur >= nsteps) break;
       const int buf = cur & 1;
-      u32x4 dc[kMR][kSl];
+      // With one step in flight the next load is issued before this step's MFMAs (from a
+      // copy of the ring slot); with two or more it is issued after them, which saves the
+      // copy's registers while the other slots keep HBM busy.
+      u32x4 dc[kDepth == 1 ? kMR : 1][kSl];
+      if constexpr (kDepth == 1) {
 #pragma unroll
-      for (int mr = 0; mr < kMR; ++mr)
+        for (int mr = 0; mr < kMR; ++mr)
 #pragma unroll
-        for (int s = 0; s < kSl; ++s) {
-          u32x4 v = ring[d][mr][s];
-          v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
-          dc[mr][s] = v;
-        }
-      if (cur + kDepth < nsteps) load_d(d, cur + kDepth);
+          for (int s = 0; s < kSl; ++s) dc[mr][s] = ring[d][mr][s];
+        if (cur + kDepth < nsteps) load_d(d, cur + kDepth);
+      }
 #pragma unroll
       for (int s = 0; s < kSl; ++s) {
         v4i xf[2][kPl];
@@ -229,13 +230,18 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
             xf[qb][b] = *reinterpret_cast<const v4i*>(&xs[buf][b * 32 + 16 * qb + r][16 * g + 64 * s]);
 #pragma unroll
         for (int mr = 0; mr < kMR; ++mr) {
-          const v4i a = v4i{(int)dc[mr][s].x, (int)dc[mr][s].y, (int)dc[mr][s].z, (int)dc[mr][s].w};
+          u32x4 v = kDepth == 1 ? dc[kDepth == 1 ? mr : 0][s] : ring[d][mr][s];
+          v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
+          const v4i a = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
 #pragma unroll
           for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
             for (int b = 0; b < kPl; ++b)
               acc[mr][qb][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, xf[qb][b], acc[mr][qb][b], 0, 0, 0);
         }
+      }
+      if constexpr (kDepth > 1) {
+        if (cur + kDepth < nsteps) load_d(d, cur + kDepth);
       }
       if (cur + 1 < nsteps) {
         stash(buf ^ 1);
@@ -291,6 +297,26 @@ __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(
     }
 }
 
+#define ZP_GEMM_ARGS                                                                              \
+  const uint8_t* __restrict__ D, int rows, int cols, int pitch, const int8_t* __restrict__ Xs,     \
+      const int32_t* __restrict__ colsum, int ncol, const int32_t* __restrict__ rowsum,            \
+      uint32_t* __restrict__ out, int out_rowmajor, long long out_ld, int ksteps_per_block,        \
+      int nrb, int ncb, int nkz
+#define ZP_GEMM_PASS D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, \
+                     ksteps_per_block, nrb, ncb, nkz
+
+template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide>
+__global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(ZP_GEMM_ARGS) {
+  gemm_planes_body<kW, kDepth, kMR, kKB, kPl, kWide>(ZP_GEMM_PASS);
+}
+
+// Four row tiles per wave need more than half the register file: at most two waves per SIMD.
+template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide>
+__global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void gemm_planes_kernel_wide_regs(ZP_GEMM_ARGS) {
+  gemm_planes_body<kW, kDepth, kMR, kKB, kPl, kWide>(ZP_GEMM_PASS);
+}
+
 // Clears the rows x ncol output block: out[j*ncol + c] (row-major) or out[c*ld + j].
 __global__ void zero_out_kernel(uint32_t* __restrict__ p, int rows, int ncol, int rowmajor,
                                 long long ld) {
@@ -312,9 +338,9 @@ bool gemm_shape_valid(const GemmShape& sh, int pitch, int planes) {
                     (sh.waves == 8 && sh.depth == 1 && sh.mr == 1 && sh.kb == 256) ||
                     (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 256) ||
                     (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 512);
-  const bool wide4 = (sh.waves == 8 || sh.waves == 4) && sh.depth == 1 && sh.mr == 4 && sh.kb == 256;
-  const bool known = base || (planes == 4 && sh.waves == 2 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) ||
-                     (planes == 1 && wide4);
+  const bool mr4 = (sh.waves == 8 || sh.waves == 4) && sh.mr == 4 && sh.kb == 256 &&
+                   (sh.depth == 2 || (planes == 1 && sh.depth == 1));
+  const bool known = base || (planes == 4 && sh.waves == 2 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) || mr4;
   if (!known || sh.ksplit < 1) return false;
   if (planes == 1 && (sh.cg < 2 || sh.cg > 4)) return false;
   if (planes != 1 && planes != 4) return false;
@@ -339,8 +365,12 @@ void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int pla
   const long long nblocks = (long long)((nrb + 7) / 8 * 8) * ncb * nkz;
   const dim3 grid((unsigned)nblocks);
 #define ZP_LAUNCH(W, DP, MR, KB, PL, WIDE)                                                          \
-  gemm_planes_kernel<W, DP, MR, KB, PL, WIDE><<<grid, 64 * W, 0, s>>>(                               \
-      D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per, nrb, ncb, nkz)
+  if constexpr (MR >= 4)                                                                            \
+    gemm_planes_kernel_wide_regs<W, DP, MR, KB, PL, WIDE><<<grid, 64 * W, 0, s>>>(                   \
+        D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per, nrb, ncb, nkz); \
+  else                                                                                              \
+    gemm_planes_kernel<W, DP, MR, KB, PL, WIDE><<<grid, 64 * W, 0, s>>>(                             \
+        D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per, nrb, ncb, nkz)
 #define ZP_G(W, DP, MR, KB)                                                                         \
   if (sh.waves == W && sh.depth == DP && sh.mr == MR && sh.kb == KB) {                              \
     if (planes == 4) ZP_LAUNCH(W, DP, MR, KB, 4, false);                                            \
@@ -350,7 +380,6 @@ void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int pla
     return;                                                                                         \
   }
   ZP_G(8, 1, 2, 256) ZP_G(8, 2, 2, 256) ZP_G(8, 1, 1, 256) ZP_G(4, 1, 2, 256) ZP_G(4, 1, 2, 512)
-#undef ZP_G
 #define ZP_W(W, DP, MR, KB)                                                                         \
   if (planes == 1 && sh.waves == W && sh.depth == DP && sh.mr == MR && sh.kb == KB) {               \
     if (sh.cg == 2) ZP_LAUNCH(W, DP, MR, KB, 2, true);                                              \
@@ -360,6 +389,8 @@ void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int pla
   }
   ZP_W(8, 1, 4, 256) ZP_W(4, 1, 4, 256)
 #undef ZP_W
+  ZP_G(8, 2, 4, 256) ZP_G(4, 2, 4, 256)
+#undef ZP_G
   if (sh.waves == 2 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256 && planes == 4) {
     ZP_LAUNCH(2, 2, 2, 256, 4, false);
     return;

@@ -1,0 +1,42 @@
+// Streaming-read probe: the device's achievable HBM read bandwidth, the practical ceiling for
+// the HBM-bound kernels (the one-query answer reads its database exactly once).  Every thread
+// xors nontemporal 16-byte loads, eight independent loads in flight, over a grid-stride loop.
+#include "internal.h"
+#include "zippir.h"
+
+namespace zp {
+
+__global__ __launch_bounds__(256) void read_probe_kernel(const u32x4* __restrict__ p, size_t n16,
+                                                         uint32_t* __restrict__ sink) {
+  constexpr int kU = 8;
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  uint32_t acc = 0;
+  for (size_t i = tid; i < n16; i += stride * kU) {
+    u32x4 v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const size_t j = i + (size_t)u * stride;
+      v[u] = j < n16 ? __builtin_nontemporal_load(p + j) : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  // one word per block keeps the loads alive
+  __shared__ uint32_t red[4];
+  for (int off = 32; off >= 1; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) sink[blockIdx.x] = red[0] ^ red[1] ^ red[2] ^ red[3];
+}
+
+}  // namespace zp
+
+extern "C" pir_status pir_read_probe(const void* buf, uint64_t bytes, uint32_t* sink, uint32_t blocks,
+                                     void* hip_stream) {
+  if (!buf || !sink || blocks == 0 || bytes < 16) return PIR_EINVAL;
+  if (((uintptr_t)buf & 15) != 0) return PIR_EINVAL;
+  zp::read_probe_kernel<<<blocks, 256, 0, (hipStream_t)hip_stream>>>(
+      reinterpret_cast<const zp::u32x4*>(buf), bytes / 16, sink);
+  return hipGetLastError() == hipSuccess ? PIR_OK : PIR_EDEVICE;
+}

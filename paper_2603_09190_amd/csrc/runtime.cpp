@@ -212,12 +212,13 @@ constexpr zp::GemmShape kDefaultShape1{8, 1, 2, 256, 1, 3};
 // byte-plane problems (batched answers, H)
 const std::vector<zp::GemmShape> kCandidates4 = {{8, 1, 2, 256, 2, 4}, {8, 2, 2, 256, 2, 4}, {8, 1, 2, 256, 4, 4},
                                                  {8, 1, 1, 256, 2, 4}, {4, 1, 2, 512, 1, 4}, {2, 2, 2, 256, 1, 4},
-                                                 {4, 1, 2, 256, 1, 4}};
+                                                 {4, 1, 2, 256, 1, 4}, {8, 2, 4, 256, 2, 4}, {4, 2, 4, 256, 1, 4}};
 // one-plane problems (the offset answer): column groups per block as well
 const std::vector<zp::GemmShape> kCandidates1 = {{8, 1, 2, 256, 1, 3}, {8, 1, 2, 256, 1, 4}, {8, 2, 2, 256, 1, 3},
                                                  {8, 2, 2, 256, 1, 4}, {4, 1, 2, 256, 1, 3}, {4, 1, 2, 512, 1, 4},
                                                  {8, 1, 1, 256, 1, 4}, {8, 1, 2, 256, 2, 3}, {8, 1, 2, 256, 1, 2},
-                                                 {8, 1, 4, 256, 1, 3}, {8, 1, 4, 256, 1, 4}, {4, 1, 4, 256, 1, 3}};
+                                                 {8, 1, 4, 256, 1, 3}, {8, 1, 4, 256, 1, 4}, {4, 1, 4, 256, 1, 3},
+                                                 {8, 2, 4, 256, 1, 3}, {8, 2, 4, 256, 1, 4}, {4, 2, 4, 256, 1, 4}};
 
 const char* tune_cache_path() {
   const char* p = std::getenv("ZIPPIR_TUNE_CACHE");

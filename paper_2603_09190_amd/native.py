@@ -102,6 +102,8 @@ _sig = {
                                           ctypes.c_void_p, ctypes.c_uint32]),
     "pir_compress_rlwe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_read_probe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32,
+                                        ctypes.c_void_p]),
     "pir_host_alloc": (ctypes.c_void_p, [ctypes.c_uint64]),
     "pir_host_free": (None, [ctypes.c_void_p]),
     "pir_strerror": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -367,6 +369,12 @@ class Compressor:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def read_probe(buf, sink, blocks: int = 8192, stream=None) -> None:
+    """One streaming read of the device tensor ``buf`` (measurement only; see pir_read_probe)."""
+    st = ctypes.c_void_p(stream) if stream is not None else None
+    _check(_lib.pir_read_probe(_ptr(buf)[0], _nbytes(buf), _ptr(sink)[0], blocks, st), "pir_read_probe")
 
 
 class PinnedArray:

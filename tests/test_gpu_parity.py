@@ -305,3 +305,18 @@ def test_autotuned_shape_is_persisted(native, tmp_path, monkeypatch):
     lines = [l.split() for l in cache.read_text().splitlines()]
     mine = [l for l in lines if l[:5] == [str(rows), str(cols + (-cols) % 256), str(batch), "0", "4"]]
     assert len(mine) == 1 and len(mine[0]) == 11
+
+
+def test_read_probe(native):
+    # measurement helper: reads the buffer once (the xor of the per-block words is the xor of
+    # every word read); a misaligned buffer is rejected
+    import torch
+    dev = torch.device("cuda:0")
+    src = torch.arange(1 << 20, dtype=torch.int32, device=dev)
+    sink = torch.zeros(64, dtype=torch.int32, device=dev)
+    native.read_probe(src, sink, 64)
+    torch.cuda.synchronize()
+    want = int(np.bitwise_xor.reduce(src.cpu().numpy().view(np.uint32)))
+    assert int(np.bitwise_xor.reduce(sink.cpu().numpy().view(np.uint32))) == want
+    st = native.lib().pir_read_probe(src.data_ptr() + 4, 1024, sink.data_ptr(), 64, None)
+    assert st == native.PIR_EINVAL
