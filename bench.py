@@ -145,7 +145,7 @@ def main() -> int:
     log("offline: pir_hint (H = D.A, then K for every row)")
     srv.profile(True)
     t0 = time.perf_counter()
-    chunk = max(1, rows // 8)
+    chunk = max(1, rows // 2)
     for r0 in range(0, rows, chunk):
         srv.hint(cid, rows=np.arange(r0, min(rows, r0 + chunk), dtype=np.uint32))
         log(f"  hint rows {r0}..{min(rows, r0 + chunk) - 1} done at {time.perf_counter() - t0:.1f} s")

@@ -77,6 +77,50 @@ __global__ __launch_bounds__(256) void hint_rows_kernel(ClientDev cd, const uint
   wn_store_n(K + (size_t)row * cd.L, acc, cd.L);
 }
 
+// Two rows per wavefront: the same products as hint_rows_kernel, with the two rows'
+// Montgomery chains interleaved (mont_mul2).  A zero digit multiplies by R mod N^2, the
+// Montgomery form of 1, so both chains stay in step.  With an odd row count the last wave
+// computes its single row twice and stores it once.
+template <int P>
+__global__ __launch_bounds__(256) void hint_rows_pair_kernel(ClientDev cd, const uint32_t* __restrict__ H,
+                                                             int n, const uint32_t* __restrict__ rowlist,
+                                                             int nrows, const uint32_t* __restrict__ table,
+                                                             uint32_t* __restrict__ K) {
+  constexpr int S = 64 * P;
+  const int widx = wave_index();
+  if (2 * widx >= nrows) return;
+  const int i1 = 2 * widx, i2 = min(nrows - 1, 2 * widx + 1);
+  const int row1 = rowlist ? (int)rowlist[i1] : i1;
+  const int row2 = rowlist ? (int)rowlist[i2] : i2;
+  WNum<P> M, one, acc1, acc2, b1, b2;
+  wn_load(M, cd.N2);
+  wn_load(one, cd.R1);  // Montgomery form of 1
+  acc1 = one;
+  acc2 = one;
+  const uint32_t* h1 = H + (size_t)row1 * n;
+  const uint32_t* h2 = H + (size_t)row2 * n;
+  for (int k = 0; k < n; ++k) {
+    const uint32_t e1 = 0u - h1[k], e2 = 0u - h2[k];
+    const uint32_t* tk = table + (size_t)k * kWindows * kDigits * S;
+#pragma unroll
+    for (int w = 0; w < kWindows; ++w) {
+      const uint32_t d1 = (e1 >> (kWindowBits * w)) & kDigits;
+      const uint32_t d2 = (e2 >> (kWindowBits * w)) & kDigits;
+      if (d1 == 0 && d2 == 0) continue;
+      if (d1) wn_load(b1, tk + ((size_t)w * kDigits + (d1 - 1)) * S); else b1 = one;
+      if (d2) wn_load(b2, tk + ((size_t)w * kDigits + (d2 - 1)) * S); else b2 = one;
+      mont_mul2(acc1, acc1, b1, acc2, acc2, b2, M, cd.m2prime);
+    }
+  }
+  // leave Montgomery form scaled by 2^32: acc * 2^32 * R^{-1} = K_j * 2^32 mod N^2
+  WNum<P> two32;
+  wn_zero(two32);
+  if (lane_id() == 1 / P) two32.v[1 % P] = 1;
+  mont_mul2(acc1, acc1, two32, acc2, acc2, two32, M, cd.m2prime);
+  wn_store_n(K + (size_t)row1 * cd.L, acc1, cd.L);
+  if (i2 != i1) wn_store_n(K + (size_t)row2 * cd.L, acc2, cd.L);
+}
+
 // The per-row key of the online combine: M'_j = N * (K'_j mod N), with K'_j = K_j 2^32 mod N^2.
 // It is a plain product below N^2 and satisfies M'_j = N K_j 2^32 (mod N^2), so that
 // K_j (1 + b N) 2^32 = K'_j + b M'_j (mod N^2).
@@ -240,6 +284,17 @@ void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int wind
 void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
                       int nrows, const uint32_t* table, uint32_t* K, hipStream_t s) {
   if (nrows <= 0) return;
+  // two rows per wavefront while that still leaves several wavefronts per SIMD
+  if (nrows >= 16384) {
+    const int blocks = ((nrows + 1) / 2 + 3) / 4;
+    switch (cd.P) {
+      case 1: hint_rows_pair_kernel<1><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
+      case 2: hint_rows_pair_kernel<2><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
+      case 3: hint_rows_pair_kernel<3><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
+      case 4: hint_rows_pair_kernel<4><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
+    }
+    return;
+  }
   const int blocks = (nrows + 3) / 4;
   switch (cd.P) {
     case 1: hint_rows_kernel<1><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;

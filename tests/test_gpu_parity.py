@@ -320,3 +320,22 @@ def test_read_probe(native):
     assert int(np.bitwise_xor.reduce(sink.cpu().numpy().view(np.uint32))) == want
     st = native.lib().pir_read_probe(src.data_ptr() + 4, 1024, sink.data_ptr(), 64, None)
     assert st == native.PIR_EINVAL
+
+
+def test_hint_two_rows_per_wave_odd_count(native):
+    # 16385 rows take the two-rows-per-wavefront hint kernel, the last wavefront holding a
+    # single row; every row of K matches the oracle.
+    rows, cols, n, n_bits = 16385, 64, 4, 256
+    inst = make_instance(cfg=931, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False, zero_row=rows - 1)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, n_bits)
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ck)
+        srv.hint(cid)
+        K = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K)
+    with Pool(pool_size()) as pool:
+        K_or = oracle_client_hint(cl.ck, E, cl.N, pool=pool)
+    assert limbs_rows_to_ints(K) == [K_or[j] for j in range(rows)]
+    assert K_or[rows - 1] == 1
