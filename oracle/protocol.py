@@ -13,8 +13,14 @@ encryption of the LWE secret, and the secret enters online through an offset vec
                        c_j = k_j (+) Enc(t_j; 1) = k_j (1 + t_j N) mod N^2
   instead of (k_j, t_j); then mu = Dec(c_j).
 
+* Sec. 4.3, "Batched compression for smaller responses", applied to this protocol: the rows
+  of a group of ell share one key k_g = prod_j k_{g ell + j}^{gamma^j} and one offset answer
+  t_g = sum_j gamma^j t_{g ell + j} mod N (scaling is linear, so it splits into the offline
+  key and the online answer); the client splits (t_g + Dec(k_g)) mod N into base-gamma digits.
+
 Correctness (appendix proof of the ZipPIR correctness theorem): t_j + Dec(k_j) equals
-b_j + sum_k E_jk s_k mod N, which is the integer itself while it stays below N.
+b_j + sum_k E_jk s_k mod N, which is the integer itself while it stays below N; packed, the
+digits are these integers when gamma exceeds each of them and gamma^ell < N (Theorem 2).
 Orientation as in ``oracle.server``: rows of D, H, E, k and t are database rows.
 """
 from __future__ import annotations
@@ -63,3 +69,28 @@ def extract(sk: paillier.SecretKey, k_j: int, t_j: int, p: int = 256, q: int = 1
 def extract_combined(sk: paillier.SecretKey, c_j: int, p: int = 256, q: int = 1 << 32) -> int:
     """f from one combined ciphertext c_j (Sec. 4.3)."""
     return lwe.pir_extract_value(paillier.decrypt(sk, int(c_j)), p, q)
+
+
+def offset_answer_packed(t, ell: int, gamma: int, N: int) -> list[int]:
+    """t_g = sum_{j<ell} gamma^j t_{g ell + j} mod N (the last group may be short)."""
+    return [sum(gamma ** j * int(t[g0 + j]) for j in range(min(ell, len(t) - g0))) % N
+            for g0 in range(0, len(t), ell)]
+
+
+def packed_keys(k, ell: int, gamma: int, N: int) -> list[int]:
+    """k_g = prod_{j<ell} k_{g ell + j}^(gamma^j) mod N^2."""
+    N2 = N * N
+    out = []
+    for g0 in range(0, len(k), ell):
+        acc = 1
+        for j in range(min(ell, len(k) - g0)):
+            acc = acc * pow(int(k[g0 + j]), gamma ** j, N2) % N2
+        out.append(acc)
+    return out
+
+
+def extract_packed(sk: paillier.SecretKey, k_g: int, t_g: int, rows: int, gamma: int,
+                   p: int = 256, q: int = 1 << 32) -> list[int]:
+    """The `rows` values of one group: base-gamma digits of (t_g + Dec(k_g)) mod N."""
+    mu = (int(t_g) + paillier.decrypt(sk, int(k_g))) % sk.pk.N
+    return [lwe.pir_extract_value((mu // gamma ** j) % gamma, p, q) for j in range(rows)]

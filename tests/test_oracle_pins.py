@@ -648,3 +648,35 @@ def test_rlwe_coefficient_compression():
         assert x == compress.lwe_compress(ck, a, b, q, N)
         assert lwe.lwe_phase(S, a, b, q) == (B[k] - compress.negacyclic_mul(A, S, q)[k]) % q
         assert compress.modified_lwe_decrypt(sk, x, q, p) == mu[k] == compress.rlwe_decrypt_coefficient(S, A, B, k, q, p)
+
+
+@pytest.fixture(scope="module")
+def full_wide():
+    # 640-bit N: room for up to 9 packed rows of 67 bits
+    return make_instance(cfg=906, rows=20, cols=32, n=6, n_bits=640, encrypt_secret=False)
+
+
+@pytest.mark.parametrize("ell", [3, 7])
+def test_full_protocol_packed_round_trip(full_wide, ell):
+    # Batched compression in the full protocol: per group, t_g + Dec(k_g) is the base-gamma
+    # number whose digits are the rows' plaintexts b_j + E_j.s (Theorem 2), so the client
+    # recovers every row, the short last group included; the combined form decrypts the same.
+    inst = full_wide
+    cl = inst.clients[0]
+    E, b, k, pt_r, cko, t = _full_protocol(inst, cl)
+    gamma = 1 << (server.packing_scale_min(inst.n) - 1).bit_length()
+    assert gamma ** ell < cl.N
+    tg = protocol.offset_answer_packed(t, ell, gamma, cl.N)
+    kg = protocol.packed_keys(k, ell, gamma, cl.N)
+    assert len(tg) == len(kg) == -(-inst.rows // ell)
+    got = []
+    for g, (x, y) in enumerate(zip(kg, tg)):
+        r0 = g * ell
+        nj = min(ell, inst.rows - r0)
+        mu = (y + paillier.decrypt(cl.sk, x)) % cl.N
+        assert mu == sum(gamma ** j * (int(b[r0 + j]) + server.hint_plaintext_row(E[r0 + j], cl.s))
+                         for j in range(nj))
+        got += protocol.extract_packed(cl.sk, x, y, nj, gamma)
+        c = protocol.combine_offset(x, y, cl.N)
+        assert paillier.decrypt(cl.sk, c) == mu
+    assert got == inst.D[:, cl.col].tolist()
