@@ -179,6 +179,25 @@ pir_status pir_compress_offset(pir_server *srv, const uint32_t *client_ids, uint
                                const uint32_t *T, uint32_t *C, uint32_t ptr_flags);
 
 /*
+ * The full protocol with batched compression (Sec. 4.3 "Batched compression for smaller
+ * responses", Theorem 2): for clients with packing factor ell > 1 (pir_set_packing), the
+ * rows of a group share the key k_g = prod_j k_{g ell + j}^(gamma^j) (the packed group key) and
+ * one offset answer
+ *     Tg[c][g] = sum_j gamma^j t_{g ell + j} mod N_c,   gamma = 2^t (pir_packing_info),
+ * where t_j is pir_offset_answer's row value.  The client computes (Tg + Dec(k_g)) mod N and
+ * splits it into base-gamma digits, one per row.
+ * pir_offset_answer_packed: CKO and B as for pir_offset_answer; Tg is batch x groups x h.
+ *   Every client in one call must have the same ell > 1 and h.
+ * pir_compress_offset_packed: Cg[c][g] = k_g (1 + Tg[c][g] N) mod N^2 (batch x groups x L);
+ *   PIR_ESTALE if a hint row or group is stale.
+ */
+pir_status pir_offset_answer_packed(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
+                                    const uint32_t *CKO, const uint32_t *B, uint32_t *Tg,
+                                    uint32_t ptr_flags);
+pir_status pir_compress_offset_packed(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
+                                      const uint32_t *Tg, uint32_t *Cg, uint32_t ptr_flags);
+
+/*
  * Standalone compression of LWE ciphertexts (Sec. 3.1, Alg. 2) and of RLWE coefficients
  * (appendix B, Alg. 8) into Paillier ciphertexts, with a resident compression key.
  *

@@ -125,14 +125,15 @@ void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint3
 //   K (1 + tN) = K + N (t (K mod N) mod N)   (mod N^2).
 // With y = (K mod N) R_N mod N stored by the hint step:
 //   z = t (K mod N) mod N    = t y R_N^{-1}   (one Montgomery product mod N, h multiplier limbs),
-//   K = K' 2^{-32} mod N^2                   (one Montgomery reduction step),
+//   K = K' 2^{-32} mod N^2                   (one Montgomery reduction step; packed group
+//                                             keys are stored as K itself),
 //   c = K + N z mod N^2.
 // One wavefront per row.
 template <int P, int PN>
 __global__ __launch_bounds__(256) void compress_offset_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
                                                               const uint32_t* __restrict__ Y,
                                                               const uint32_t* __restrict__ T, int rows,
-                                                              uint32_t* __restrict__ C) {
+                                                              uint32_t* __restrict__ C, int scaled) {
   const int row = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (row >= rows) return;
   const uint32_t* kr = Kp + (size_t)row * cd.L;
@@ -165,10 +166,13 @@ __global__ __launch_bounds__(256) void compress_offset_kernel(ClientDev cd, cons
   // K = K' 2^{-32} mod N^2
   wn_load(M2, cd.N2);
   wn_load_n(k, kr, cd.L);
-  uint64_t kc = 0;
-  redc_step(k, kc, M2, cd.m2prime);
-  uint64_t ovf = wn_resolve(k, kc);
-  wn_cond_sub(k, ovf, M2);
+  uint64_t ovf;
+  if (scaled) {
+    uint64_t kc = 0;
+    redc_step(k, kc, M2, cd.m2prime);
+    ovf = wn_resolve(k, kc);
+    wn_cond_sub(k, ovf, M2);
+  }
   uint32_t carry = 0;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -182,14 +186,14 @@ __global__ __launch_bounds__(256) void compress_offset_kernel(ClientDev cd, cons
 }
 
 void launch_compress_offset(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Y,
-                            const uint32_t* T, int rows, uint32_t* C, hipStream_t s) {
+                            const uint32_t* T, int rows, uint32_t* C, hipStream_t s, bool scaled) {
   if (rows <= 0) return;
   const int blocks = (rows + 3) / 4;
   switch (cd.P) {
-    case 1: compress_offset_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C); break;
-    case 2: compress_offset_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C); break;
-    case 3: compress_offset_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C); break;
-    case 4: compress_offset_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C); break;
+    case 1: compress_offset_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, scaled ? 1 : 0); break;
+    case 2: compress_offset_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, scaled ? 1 : 0); break;
+    case 3: compress_offset_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, scaled ? 1 : 0); break;
+    case 4: compress_offset_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, scaled ? 1 : 0); break;
   }
 }
 

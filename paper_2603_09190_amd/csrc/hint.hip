@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void combine_key_kernel(ClientDev cd,
                                                           const uint32_t* __restrict__ Kp,
                                                           const uint32_t* __restrict__ rowlist,
                                                           int nrows, uint32_t* __restrict__ Mp,
-                                                          uint32_t* __restrict__ Y) {
+                                                          uint32_t* __restrict__ Y, int scaled) {
   constexpr int SN = 64 * PN;
   const int widx = wave_index();
   if (widx >= nrows) return;
@@ -154,9 +154,10 @@ __global__ __launch_bounds__(256) void combine_key_kernel(ClientDev cd,
   const uint64_t ovf = wn_resolve(x, (uint64_t)carry);
   wn_cond_sub(x, ovf, Nn);  // x = K' mod N
   if (Y) {
-    // (K mod N) R_N = x 2^-32 R_N mod N = x D1 R_N^-1 (D1 = R_N^2 2^-32 mod N)
+    // scaled: (K mod N) R_N = x 2^-32 R_N mod N = x D1 R_N^-1 (D1 = R_N^2 2^-32 mod N);
+    // otherwise x R_N = x C2 R_N^-1 (C2 = R_N^2 mod N)
     WNum<PN> d, yv;
-    wn_load(d, cd.D1);
+    wn_load(d, scaled ? cd.D1 : cd.C2);
     mont_mul(yv, x, d, Nn, cd.nprime);
     wn_store_n(Y + (size_t)row * cd.h, yv, cd.h);
   }
@@ -305,14 +306,14 @@ void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint3
 }
 
 void launch_combine_key(const ClientDev& cd, const uint32_t* Kp, const uint32_t* rowlist,
-                        int nrows, uint32_t* Mp, uint32_t* Y, hipStream_t s) {
+                        int nrows, uint32_t* Mp, uint32_t* Y, hipStream_t s, bool scaled) {
   if (nrows <= 0) return;
   const int blocks = (nrows + 3) / 4;
   switch (cd.P) {
-    case 1: combine_key_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y); break;
-    case 2: combine_key_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y); break;
-    case 3: combine_key_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y); break;
-    case 4: combine_key_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y); break;
+    case 1: combine_key_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y, scaled ? 1 : 0); break;
+    case 2: combine_key_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y, scaled ? 1 : 0); break;
+    case 3: combine_key_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y, scaled ? 1 : 0); break;
+    case 4: combine_key_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, rowlist, nrows, Mp, Y, scaled ? 1 : 0); break;
   }
 }
 

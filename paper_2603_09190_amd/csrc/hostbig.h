@@ -89,7 +89,7 @@ inline size_t bit_length(const Big& a) {
 
 // Sizes and constants of one Paillier modulus N (h limbs): L = 2h limbs modulo N^2, numbers
 // of S = 64 P limbs modulo N^2 and SN = 64 PN limbs modulo N.  `host` is the device block
-//   N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each) | CP (S) | D1 | D2 | C96 (SN each)
+//   N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each) | CP (S) | D1 | D2 | C96 | CT (SN each)
 // (the meaning of each is listed at zp::ClientDev).
 struct ModConsts {
   uint32_t n_bits = 0, h = 0, L = 0, P = 0, PN = 0, S = 0, SN = 0;
@@ -98,7 +98,8 @@ struct ModConsts {
   std::vector<uint32_t> host;
 };
 
-inline ModConsts mod_constants(const Big& N_in, uint32_t n_bits) {
+// t_bits: the packing shift t of packed offset answers (CT = 2^t R_N mod N); 0 if unused.
+inline ModConsts mod_constants(const Big& N_in, uint32_t n_bits, uint32_t t_bits = 0) {
   ModConsts c;
   c.n_bits = n_bits;
   c.h = (n_bits + 31) / 32;
@@ -119,9 +120,10 @@ inline ModConsts mod_constants(const Big& N_in, uint32_t n_bits) {
   const Big D1 = big_pow2_mod(64ull * c.SN - 32, c.N);
   const Big D2 = big_pow2_mod(96ull * c.SN - 32, c.N);
   const Big C96 = big_pow2_mod(32ull * c.SN + 96, c.N);
+  const Big CT = big_pow2_mod(32ull * c.SN + t_bits, c.N);
   c.m2prime = neg_inv32(N2[0]);
   c.nprime = neg_inv32(c.N[0]);
-  c.host.assign(5 * (size_t)c.S + 6 * (size_t)c.SN, 0u);
+  c.host.assign(5 * (size_t)c.S + 7 * (size_t)c.SN, 0u);
   auto put = [&](size_t off, const Big& v, size_t width) {
     for (size_t i = 0; i < std::min(width, v.size()); ++i) c.host[off + i] = v[i];
   };
@@ -136,6 +138,7 @@ inline ModConsts mod_constants(const Big& N_in, uint32_t n_bits) {
   put(5 * (size_t)c.S + 3 * c.SN, D1, c.SN);
   put(5 * (size_t)c.S + 4 * c.SN, D2, c.SN);
   put(5 * (size_t)c.S + 5 * c.SN, C96, c.SN);
+  put(5 * (size_t)c.S + 6 * c.SN, CT, c.SN);
   return c;
 }
 
@@ -154,6 +157,7 @@ inline ClientDev dev_view(const ModConsts& c, const uint32_t* consts) {
   d.D1 = consts + 5 * S + 3 * SN;
   d.D2 = consts + 5 * S + 4 * SN;
   d.C96 = consts + 5 * S + 5 * SN;
+  d.CT = consts + 5 * S + 6 * SN;
   d.m2prime = c.m2prime;
   d.nprime = c.nprime;
   d.L = (int)c.L;

@@ -19,6 +19,8 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 //   D1  SN limbs  R_N^2 2^-32 mod N         D2  SN limbs  R_N^3 2^-32 mod N
 //   (D1, D2 map K' = lo + hi R_N to (K mod N) R_N mod N with two Montgomery products)
 //   C96 SN limbs  2^96 R_N mod N (x -> x 2^96 mod N in one Montgomery product)
+//   CT  SN limbs  2^t R_N mod N (x -> x 2^t mod N, t the packing shift; unused by the kernels
+//                 since the packed offset answer takes per-row powers PJ)
 struct ClientDev {
   const uint32_t* N2;
   const uint32_t* R1;
@@ -31,6 +33,7 @@ struct ClientDev {
   const uint32_t* D1;
   const uint32_t* D2;
   const uint32_t* C96;
+  const uint32_t* CT;
   uint32_t m2prime;  // -(N^2)^{-1} mod 2^32
   uint32_t nprime;   // -N^{-1} mod 2^32
   int L;             // limbs of a ciphertext (2h)
@@ -103,9 +106,10 @@ void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int wind
 void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
                       int nrows, const uint32_t* table, uint32_t* Kp, hipStream_t s);
 // M'_j = N (K'_j mod N) (rows x L limbs), the combine key.
-// (Y, when not NULL: rows x h, Y[row] = (K mod N) R_N mod N for the offset combine.)
+// (Y, when not NULL: rows x h, Y[row] = (K mod N) R_N mod N for the offset combine, where
+// K = Kp 2^-32 when `scaled` and K = Kp otherwise.)
 void launch_combine_key(const ClientDev& cd, const uint32_t* Kp, const uint32_t* rowlist,
-                        int nrows, uint32_t* Mp, uint32_t* Y, hipStream_t s);
+                        int nrows, uint32_t* Mp, uint32_t* Y, hipStream_t s, bool scaled = true);
 // K_j = K'_j 2^{-32} mod N^2 for rows [row0, row0+nrows) into K (nrows x L).
 void launch_unscale(const ClientDev& cd, const uint32_t* Kp, int row0, int nrows, uint32_t* K,
                     hipStream_t s);
@@ -140,8 +144,14 @@ void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw,
 
 // C[j] = K_j (1 + T[j] N) mod N^2 for rows [0, rows): T is rows x h (any value below 2^(32h)),
 // K_j from the stored K', Y[j] = (K_j mod N) R_N mod N (h limbs); C is rows x L.
+// scaled = false: Kp holds K itself (canonical), as the packed group keys do.
 void launch_compress_offset(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Y,
-                            const uint32_t* T, int rows, uint32_t* C, hipStream_t s);
+                            const uint32_t* T, int rows, uint32_t* C, hipStream_t s,
+                            bool scaled = true);
+// Tg[g] = sum_j 2^(t j) T[g ell + j] mod N for the groups of ell rows (T rows x h, canonical);
+// PJ holds 2^(t j) R_N mod N for j < ell (SN limbs each); Tmp is rows x h scratch.
+void launch_offset_pack(const ClientDev& cd, const uint32_t* T, int rows, int ell,
+                        const uint32_t* PJ, uint32_t* Tmp, uint32_t* Tg, hipStream_t s);
 
 // ---- standalone LWE / RLWE compression (lwec.hip)
 // Exponent source of one compressed ciphertext: LWE rows (A rows x n, B rows) or RLWE

@@ -152,4 +152,62 @@ void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw,
   }
 }
 
+// Packed offset answer (batched compression, Sec. 4.3): for the group of rows
+// g ell .. g ell + ell - 1, Tg = sum_j 2^(t j) t_{g ell + j} mod N.  The terms are independent:
+// one wavefront per (group, j) forms 2^(t j) t mod N as one Montgomery product by
+// PJ[j] = 2^(t j) R_N mod N, and a second kernel adds each group's terms modulo N.
+template <int PN>
+__global__ __launch_bounds__(256) void offset_terms_kernel(ClientDev cd, const uint32_t* __restrict__ T,
+                                                           int rows, int ell,
+                                                           const uint32_t* __restrict__ PJ,
+                                                           uint32_t* __restrict__ Tmp) {
+  const int w = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= rows) return;
+  const int j = w % ell;
+  WNum<PN> Nn, c, x;
+  wn_load(Nn, cd.Nn);
+  wn_load(c, PJ + (size_t)j * 64 * PN);
+  wn_load_n(x, T + (size_t)w * cd.h, cd.h);
+  mont_mul(x, x, c, Nn, cd.nprime);
+  wn_store_n(Tmp + (size_t)w * cd.h, x, cd.h);
+}
+
+template <int PN>
+__global__ __launch_bounds__(256) void offset_sum_kernel(ClientDev cd, const uint32_t* __restrict__ Tmp,
+                                                         int rows, int ell, uint32_t* __restrict__ Tg) {
+  const int g = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = g * ell;
+  if (r0 >= rows) return;
+  const int r1 = min(rows, r0 + ell);
+  WNum<PN> Nn, acc, x;
+  wn_load(Nn, cd.Nn);
+  wn_load_n(acc, Tmp + (size_t)r0 * cd.h, cd.h);
+  for (int r = r0 + 1; r < r1; ++r) {
+    wn_load_n(x, Tmp + (size_t)r * cd.h, cd.h);
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < PN; ++k) {
+      const uint64_t s = (uint64_t)acc.v[k] + x.v[k] + c;
+      acc.v[k] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    const uint64_t ovf = wn_resolve(acc, (uint64_t)c);
+    wn_cond_sub(acc, ovf, Nn);
+  }
+  wn_store_n(Tg + (size_t)g * cd.h, acc, cd.h);
+}
+
+void launch_offset_pack(const ClientDev& cd, const uint32_t* T, int rows, int ell,
+                        const uint32_t* PJ, uint32_t* Tmp, uint32_t* Tg, hipStream_t s) {
+  if (rows <= 0) return;
+  const int groups = (rows + ell - 1) / ell;
+  if (cd.PN == 1) {
+    offset_terms_kernel<1><<<(rows + 3) / 4, 256, 0, s>>>(cd, T, rows, ell, PJ, Tmp);
+    offset_sum_kernel<1><<<(groups + 3) / 4, 256, 0, s>>>(cd, Tmp, rows, ell, Tg);
+  } else {
+    offset_terms_kernel<2><<<(rows + 3) / 4, 256, 0, s>>>(cd, T, rows, ell, PJ, Tmp);
+    offset_sum_kernel<2><<<(groups + 3) / 4, 256, 0, s>>>(cd, Tmp, rows, ell, Tg);
+  }
+}
+
 }  // namespace zp

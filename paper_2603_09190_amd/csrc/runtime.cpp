@@ -63,7 +63,7 @@ struct ClientState {
   uint32_t n_bits = 0, h = 0, L = 0, P = 0, PN = 0, S = 0, SN = 0;
   Big N;
   uint32_t* ck = nullptr;      // n x L
-  uint32_t* consts = nullptr;  // N2 | R1 | RR | NP (S each) | Nn | C1 | C2 (SN each) | CP (S) | D1 | D2 | C96 (SN each)
+  uint32_t* consts = nullptr;  // the device copy of mc.host (layout at zp::mod_constants)
   uint32_t* Kp = nullptr;      // rows x L: K_j 2^32 mod N^2
   uint32_t* Mp = nullptr;      // rows x L: N (K'_j mod N), the combine key
   uint32_t* Y = nullptr;       // rows x h: (K_j mod N) R_N mod N, the offset-combine key
@@ -74,6 +74,8 @@ struct ClientState {
   uint32_t ell = 1, t = 0, ell_max = 1;
   uint32_t* Kg = nullptr;      // groups x L: group keys K_g
   uint32_t* Mr = nullptr;      // groups x L: N (K_g mod N) R mod N^2
+  uint32_t* Yg = nullptr;      // groups x h: (K_g mod N) R_N mod N, the packed offset-combine key
+  uint32_t* PJ = nullptr;      // ell_max x SN: 2^(t j) R_N mod N, the packed offset-answer weights
   std::vector<uint8_t> gvalid; // per group
   int64_t gstale = 0;
 
@@ -111,7 +113,7 @@ struct pir_server {
   };
   std::vector<ProfRecord> prof_ev[PIR_KERNEL_COUNT];
   // growable scratch
-  DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c, s_x, s_xcs, s_w, s_t, s_ys;
+  DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c, s_x, s_xcs, s_w, s_t, s_ys, s_tmp;
 
   pir_status alloc(void** p, size_t bytes_) {
     *p = nullptr;
@@ -410,7 +412,7 @@ pir_status refresh_groups(pir_server* s, ClientState* c, std::vector<uint32_t> g
     (void)hipMemcpyAsync(dg, groups.data(), groups.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
   }
   zp::launch_group_keys(cd, c->Kp, (int)s->rows, (int)c->ell, (int)c->t, dg, ng, c->Kg, st);
-  zp::launch_combine_key(cd, c->Kg, dg, ng, c->Mr, nullptr, st);
+  zp::launch_combine_key(cd, c->Kg, dg, ng, c->Mr, c->Yg, st, false);
   zp::launch_to_mont(cd, c->Mr, dg, ng, st);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -531,11 +533,6 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
     if (big_cmp(c->N, bound) <= 0)
       return fail(PIR_EINVAL, "N too small: compression needs N > q + n q^2 (q = 2^32)");
   }
-  c->mc = zp::mod_constants(c->N, N_bits);
-  c->m2prime = c->mc.m2prime;
-  c->nprime = c->mc.nprime;
-  const std::vector<uint32_t>& host = c->mc.host;
-  const Big N2 = big_mul(c->N, c->N);
   // packing scale gamma = 2^t >= q + n q^2 (q = 2^32): t = 64 + bitlen(n); ell t <= N_bits - 1
   {
     uint32_t bl = 0;
@@ -543,8 +540,22 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
     c->t = 64 + bl;
     c->ell_max = std::max<uint32_t>(1, (N_bits - 1) / c->t);
   }
+  c->mc = zp::mod_constants(c->N, N_bits, c->t);
+  c->m2prime = c->mc.m2prime;
+  c->nprime = c->mc.nprime;
+  const std::vector<uint32_t>& host = c->mc.host;
+  const Big N2 = big_mul(c->N, c->N);
 
   hipStream_t st = s->stream;
+  {
+    std::vector<uint32_t> pj((size_t)c->ell_max * c->SN, 0u);
+    for (uint32_t j = 0; j < c->ell_max; ++j) {
+      const Big v = big_pow2_mod((uint64_t)c->t * j + 32ull * c->SN, c->N);
+      std::copy(v.begin(), v.begin() + std::min<size_t>(v.size(), c->SN), pj.begin() + (size_t)j * c->SN);
+    }
+    ZP_TRY(s->alloc((void**)&c->PJ, pj.size() * sizeof(uint32_t)));
+    ZP_HIP(hipMemcpy(c->PJ, pj.data(), pj.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  }
   ZP_TRY(s->alloc((void**)&c->consts, host.size() * sizeof(uint32_t)));
   ZP_HIP(hipMemcpyAsync(c->consts, host.data(), host.size() * sizeof(uint32_t),
                         hipMemcpyHostToDevice, st));
@@ -562,6 +573,7 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
       if (big_cmp(v, N2L) >= 0) {
         s->release(c->ck);
         s->release(c->consts);
+        s->release(c->PJ);
         return fail(PIR_EINVAL, "ck[" + std::to_string(k) + "] is not below N^2");
       }
     }
@@ -570,7 +582,8 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
   if (a == PIR_OK) a = s->alloc((void**)&c->Mp, (size_t)s->rows * c->L * sizeof(uint32_t));
   if (a == PIR_OK) a = s->alloc((void**)&c->Y, (size_t)s->rows * c->h * sizeof(uint32_t));
   if (a != PIR_OK) {
-    for (void* p : {(void*)c->ck, (void*)c->consts, (void*)c->Kp, (void*)c->Mp, (void*)c->Y}) s->release(p);
+    for (void* p : {(void*)c->ck, (void*)c->consts, (void*)c->Kp, (void*)c->Mp, (void*)c->Y, (void*)c->PJ})
+      s->release(p);
     return a;
   }
   c->valid.assign(s->rows, 0);
@@ -595,6 +608,8 @@ pir_status pir_remove_client(pir_server* s, uint32_t id) {
   s->release(c->Y);
   s->release(c->Kg);
   s->release(c->Mr);
+  s->release(c->Yg);
+  s->release(c->PJ);
   s->clients.erase(id);
   return PIR_OK;
 }
@@ -843,7 +858,8 @@ pir_status pir_set_packing(pir_server* s, uint32_t id, uint32_t ell) {
   ZP_HIP(hipStreamSynchronize(s->stream));
   s->release(c->Kg);
   s->release(c->Mr);
-  c->Kg = c->Mr = nullptr;
+  s->release(c->Yg);
+  c->Kg = c->Mr = c->Yg = nullptr;
   c->ell = ell;
   c->gvalid.clear();
   c->gstale = 0;
@@ -851,6 +867,7 @@ pir_status pir_set_packing(pir_server* s, uint32_t id, uint32_t ell) {
   const uint32_t G = (s->rows + ell - 1) / ell;
   ZP_TRY(s->alloc((void**)&c->Kg, (size_t)G * c->L * sizeof(uint32_t)));
   ZP_TRY(s->alloc((void**)&c->Mr, (size_t)G * c->L * sizeof(uint32_t)));
+  ZP_TRY(s->alloc((void**)&c->Yg, (size_t)G * c->h * sizeof(uint32_t)));
   c->gvalid.assign(G, 0);
   c->gstale = G;
   if (c->stale == 0) ZP_TRY(refresh_groups(s, c, {}));
@@ -913,20 +930,26 @@ pir_status pir_compress_packed(pir_server* s, const uint32_t* ids, uint32_t batc
   return PIR_OK;
 }
 
-pir_status pir_offset_answer(pir_server* s, const uint32_t* ids, uint32_t batch, const uint32_t* CKO,
-                             const uint32_t* B, uint32_t* T, uint32_t ptr_flags) {
-  g_last_error.clear();
-  if (!s || !ids || !CKO || !B || !T) return fail(PIR_EINVAL, "NULL argument");
-  ZP_TRY(check_flags(ptr_flags));
+// Shared by the plain and the packed offset answer: checks, then T (batch x rows x h on the
+// device) from device offsets and answers.  `packed`: every client must have the same ell > 1.
+static pir_status offset_clients(pir_server* s, const uint32_t* ids, uint32_t batch, bool packed,
+                                 std::vector<ClientState*>& cs) {
   if (batch < 1 || batch > 128) return fail(PIR_EINVAL, "batch must be in [1, 128]");
   if (s->n > 16384) return fail(PIR_EINVAL, "the offset answer needs n <= 16384");
-  std::vector<ClientState*> cs(batch);
+  cs.assign(batch, nullptr);
   for (uint32_t i = 0; i < batch; ++i) {
     cs[i] = find_client(s, ids[i]);
     if (!cs[i]) return fail(PIR_EINVAL, "unknown client id " + std::to_string(ids[i]));
     if (cs[i]->h != cs[0]->h) return fail(PIR_EINVAL, "clients in one call must share the limb count");
+    if (packed && (cs[i]->ell <= 1 || cs[i]->ell != cs[0]->ell))
+      return fail(PIR_EINVAL, "clients in one packed call must share a packing factor ell > 1");
   }
-  ZP_TRY(use_device(s));
+  return PIR_OK;
+}
+
+static pir_status offset_answer_dev(pir_server* s, const std::vector<ClientState*>& cs,
+                                    const uint32_t* dK, const uint32_t* dB, uint32_t* dT) {
+  const uint32_t batch = (uint32_t)cs.size();
   ZP_TRY(refresh_all_stale_H(s));
   ZP_TRY(ensure_E(s));
   hipStream_t st = s->stream;
@@ -934,21 +957,6 @@ pir_status pir_offset_answer(pir_server* s, const uint32_t* ids, uint32_t batch,
   const int cpc = (int)(4 * h + 4);
   const long long ncol = (long long)batch * cpc;
   const size_t kbytes = (size_t)batch * s->n * h * sizeof(uint32_t);
-  const size_t bbytes = (size_t)batch * s->rows * sizeof(uint32_t);
-  const size_t tbytes = (size_t)batch * s->rows * h * sizeof(uint32_t);
-  const uint32_t* dK = CKO;
-  const uint32_t* dB = B;
-  uint32_t* dT = T;
-  if (ptr_flags == PIR_PTR_HOST) {
-    ZP_TRY(s->scratch(s->s_q, kbytes));
-    ZP_TRY(s->scratch(s->s_b, bbytes));
-    ZP_TRY(s->scratch(s->s_t, tbytes));
-    ZP_HIP(hipMemcpyAsync(s->s_q.p, CKO, kbytes, hipMemcpyHostToDevice, st));
-    ZP_HIP(hipMemcpyAsync(s->s_b.p, B, bbytes, hipMemcpyHostToDevice, st));
-    dK = (const uint32_t*)s->s_q.p;
-    dB = (const uint32_t*)s->s_b.p;
-    dT = (uint32_t*)s->s_t.p;
-  }
   ZP_TRY(s->scratch(s->s_x, (size_t)ncol * s->epitch));
   ZP_TRY(s->scratch(s->s_xcs, (size_t)ncol * sizeof(int32_t)));
   ZP_TRY(s->scratch(s->s_w, (size_t)s->rows * ncol * sizeof(uint32_t)));
@@ -973,8 +981,114 @@ pir_status pir_offset_answer(pir_server* s, const uint32_t* ids, uint32_t batch,
                                (int)s->rows, dT + (size_t)i * s->rows * h, st);
   }
   ZP_HIP(hipGetLastError());
+  return PIR_OK;
+}
+
+static pir_status offset_answer_common(pir_server* s, const uint32_t* ids, uint32_t batch,
+                                      const uint32_t* CKO, const uint32_t* B, uint32_t* T,
+                                      uint32_t ptr_flags, bool packed) {
+  g_last_error.clear();
+  if (!s || !ids || !CKO || !B || !T) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  std::vector<ClientState*> cs;
+  ZP_TRY(offset_clients(s, ids, batch, packed, cs));
+  ZP_TRY(use_device(s));
+  hipStream_t st = s->stream;
+  const uint32_t h = cs[0]->h;
+  const uint32_t ell = packed ? cs[0]->ell : 1;
+  const uint32_t G = (s->rows + ell - 1) / ell;
+  const size_t kbytes = (size_t)batch * s->n * h * sizeof(uint32_t);
+  const size_t bbytes = (size_t)batch * s->rows * sizeof(uint32_t);
+  const size_t tbytes = (size_t)batch * s->rows * h * sizeof(uint32_t);
+  const size_t obytes = (size_t)batch * G * h * sizeof(uint32_t);
+  const uint32_t* dK = CKO;
+  const uint32_t* dB = B;
+  uint32_t* dOut = T;
   if (ptr_flags == PIR_PTR_HOST) {
-    ZP_HIP(hipMemcpyAsync(T, dT, tbytes, hipMemcpyDeviceToHost, st));
+    ZP_TRY(s->scratch(s->s_q, kbytes));
+    ZP_TRY(s->scratch(s->s_b, bbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_q.p, CKO, kbytes, hipMemcpyHostToDevice, st));
+    ZP_HIP(hipMemcpyAsync(s->s_b.p, B, bbytes, hipMemcpyHostToDevice, st));
+    dK = (const uint32_t*)s->s_q.p;
+    dB = (const uint32_t*)s->s_b.p;
+  }
+  uint32_t* dT = nullptr;
+  if (packed || ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_t, tbytes));
+    dT = (uint32_t*)s->s_t.p;
+  } else {
+    dT = T;
+  }
+  ZP_TRY(offset_answer_dev(s, cs, dK, dB, dT));
+  if (packed) {
+    if (ptr_flags == PIR_PTR_HOST) {
+      ZP_TRY(s->scratch(s->s_c, obytes));
+      dOut = (uint32_t*)s->s_c.p;
+    }
+    ZP_TRY(s->scratch(s->s_tmp, (size_t)s->rows * h * sizeof(uint32_t)));
+    ProfScope ps(s, PIR_KERNEL_OFFSET, (int)batch);
+    for (uint32_t i = 0; i < batch; ++i)
+      zp::launch_offset_pack(cs[i]->dev(), dT + (size_t)i * s->rows * h, (int)s->rows, (int)ell, cs[i]->PJ,
+                             (uint32_t*)s->s_tmp.p, dOut + (size_t)i * G * h, st);
+  } else {
+    dOut = dT;
+  }
+  ZP_HIP(hipGetLastError());
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(T, dOut, obytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_offset_answer(pir_server* s, const uint32_t* ids, uint32_t batch, const uint32_t* CKO,
+                             const uint32_t* B, uint32_t* T, uint32_t ptr_flags) {
+  return offset_answer_common(s, ids, batch, CKO, B, T, ptr_flags, false);
+}
+
+pir_status pir_offset_answer_packed(pir_server* s, const uint32_t* ids, uint32_t batch,
+                                    const uint32_t* CKO, const uint32_t* B, uint32_t* Tg,
+                                    uint32_t ptr_flags) {
+  return offset_answer_common(s, ids, batch, CKO, B, Tg, ptr_flags, true);
+}
+
+pir_status pir_compress_offset_packed(pir_server* s, const uint32_t* ids, uint32_t batch,
+                                      const uint32_t* Tg, uint32_t* Cg, uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !ids || !Tg || !Cg) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  if (batch < 1 || batch > 1024) return fail(PIR_EINVAL, "batch must be in [1, 1024]");
+  std::vector<ClientState*> cs(batch);
+  for (uint32_t i = 0; i < batch; ++i) {
+    cs[i] = find_client(s, ids[i]);
+    if (!cs[i]) return fail(PIR_EINVAL, "unknown client id " + std::to_string(ids[i]));
+    if (cs[i]->ell <= 1 || cs[i]->ell != cs[0]->ell || cs[i]->L != cs[0]->L)
+      return fail(PIR_EINVAL, "clients in one packed call must share L and a packing factor ell > 1");
+    if (cs[i]->stale != 0 || cs[i]->gstale != 0)
+      return fail(PIR_ESTALE, "client " + std::to_string(ids[i]) + " has stale hint rows or groups");
+  }
+  ZP_TRY(use_device(s));
+  hipStream_t st = s->stream;
+  const uint32_t L = cs[0]->L, h = cs[0]->h, G = (s->rows + cs[0]->ell - 1) / cs[0]->ell;
+  const size_t tbytes = (size_t)batch * G * h * sizeof(uint32_t);
+  const size_t cbytes = (size_t)batch * G * L * sizeof(uint32_t);
+  const uint32_t* dT = Tg;
+  uint32_t* dC = Cg;
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_t, tbytes));
+    ZP_TRY(s->scratch(s->s_c, cbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_t.p, Tg, tbytes, hipMemcpyHostToDevice, st));
+    dT = (const uint32_t*)s->s_t.p;
+    dC = (uint32_t*)s->s_c.p;
+  }
+  for (uint32_t i = 0; i < batch; ++i) {
+    ProfScope ps(s, PIR_KERNEL_COMPRESS);
+    zp::launch_compress_offset(cs[i]->dev(), cs[i]->Kg, cs[i]->Yg, dT + (size_t)i * G * h, (int)G,
+                               dC + (size_t)i * G * L, st, false);
+  }
+  ZP_HIP(hipGetLastError());
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(Cg, dC, cbytes, hipMemcpyDeviceToHost, st));
     ZP_HIP(hipStreamSynchronize(st));
   }
   return PIR_OK;

@@ -61,6 +61,11 @@ _sig = {
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_compress_offset": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_offset_answer_packed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_uint32]),
+    "pir_compress_offset_packed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_get_global_hint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                              ctypes.c_void_p, ctypes.c_uint32]),
     "pir_get_client_hint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
@@ -255,6 +260,16 @@ class Server:
         ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
         _check(_lib.pir_compress_offset(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(T)[0],
                                         _ptr(C)[0], _flags(T, C)), "pir_compress_offset")
+
+    def offset_answer_packed(self, ids, CKO, B, Tg) -> None:
+        ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        _check(_lib.pir_offset_answer_packed(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(CKO)[0],
+                                             _ptr(B)[0], _ptr(Tg)[0], _flags(CKO, B, Tg)), "pir_offset_answer_packed")
+
+    def compress_offset_packed(self, ids, Tg, Cg) -> None:
+        ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        _check(_lib.pir_compress_offset_packed(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a),
+                                               _ptr(Tg)[0], _ptr(Cg)[0], _flags(Tg, Cg)), "pir_compress_offset_packed")
 
     # -- introspection
     def global_hint(self, row0: int, nrows: int, out) -> None:

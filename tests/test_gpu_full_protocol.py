@@ -185,3 +185,44 @@ def test_offset_full_size(native):
         assert wl.limbs_to_int(Cn[j]) == c_or, f"c row {j}"
         assert protocol.extract(cl.sk, k_or[i], t_or) == int(D[j, cl.col])
         assert protocol.extract_combined(cl.sk, c_or) == int(D[j, cl.col])
+
+
+@pytest.mark.parametrize("n_bits,rows,ell", [(1024, 45, 13), (2048, 61, 29)])
+def test_packed_full_protocol(native, n_bits, rows, ell):
+    """Batched compression in the full protocol: packed offset answers and their Paillier-
+    added form against the oracle on every group (ragged last group), and the client's digits
+    recover the column on every row."""
+    n = 16
+    inst = make_instance(cfg=985 + n_bits, rows=rows, cols=48, n=n, n_bits=n_bits, encrypt_secret=False)
+    cl = inst.clients[0]
+    N_limbs, ckr, L = client_arrays(cl, n_bits)
+    h = L // 2
+    cko, CKO = _offsets(cl)
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    b = server.answer(inst.D, cl.qu)
+    k_or = server.client_hint(cl.ck, E, cl.N)
+    t_or = protocol.offset_answer(b, E, cko, cl.N)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ckr)
+        srv.hint(cid)
+        srv.set_packing(cid, ell)
+        info = srv.packing_info(cid)
+        G, gamma = info["groups"], 1 << info["log2_gamma"]
+        B = np.zeros((1, rows), np.uint32)
+        srv.answer(cl.qu[None, :], B)
+        Tg = np.zeros((1, G, h), np.uint32)
+        srv.offset_answer_packed([cid], CKO[None], B, Tg)
+        Cg = np.zeros((1, G, L), np.uint32)
+        srv.compress_offset_packed([cid], Tg, Cg)
+        srv.set_packing(cid, 1)
+        with pytest.raises(native.ZipPIRError) as ei:
+            srv.offset_answer_packed([cid], CKO[None], B, Tg)
+        assert ei.value.status == native.PIR_EINVAL
+    tg_or = protocol.offset_answer_packed(t_or, ell, gamma, cl.N)
+    kg_or = protocol.packed_keys(k_or, ell, gamma, cl.N)
+    assert limbs_rows_to_ints(Tg[0]) == tg_or
+    assert limbs_rows_to_ints(Cg[0]) == [protocol.combine_offset(x, y, cl.N) for x, y in zip(kg_or, tg_or)]
+    got = []
+    for g in range(G):
+        got += protocol.extract_packed(cl.sk, kg_or[g], tg_or[g], min(ell, rows - g * ell), gamma)
+    assert got == inst.D[:, cl.col].tolist()

@@ -339,3 +339,42 @@ def test_hint_two_rows_per_wave_odd_count(native):
         K_or = oracle_client_hint(cl.ck, E, cl.N, pool=pool)
     assert limbs_rows_to_ints(K) == [K_or[j] for j in range(rows)]
     assert K_or[rows - 1] == 1
+
+
+def test_empty_and_degenerate_inputs(native):
+    # empty shapes are rejected; a 1 x 1 database answers and compresses; empty row lists
+    # of an update are a no-op; an empty compressor batch does nothing
+    for shape in ((0, 64), (8, 0)):
+        D = np.zeros(shape, np.uint8)
+        A = np.zeros((shape[1], 4), np.uint32)
+        with pytest.raises(native.ZipPIRError) as ei:
+            native.Server(D, A)
+        assert ei.value.status == native.PIR_EINVAL
+    with pytest.raises(native.ZipPIRError) as ei:
+        native.Server(np.zeros((8, 8), np.uint8), np.zeros((8, 0), np.uint32))
+    assert ei.value.status == native.PIR_EINVAL
+    inst = make_instance(cfg=933, rows=1, cols=1, n=2, n_bits=256)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, 256)
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    K_or = server.client_hint(cl.ck, E, cl.N)
+    with native.Server(inst.D, inst.A) as srv:
+        B = np.zeros((1, 1), np.uint32)
+        with pytest.raises(native.ZipPIRError) as ei:
+            srv.answer(np.zeros((0, 1), np.uint32), np.zeros((0, 1), np.uint32))
+        assert ei.value.status == native.PIR_EINVAL
+        srv.answer(cl.qu[None, :], B)
+        assert np.array_equal(B[0], server.answer(inst.D, cl.qu))
+        cid = srv.add_client(N_limbs, 256, ck)
+        srv.hint(cid)
+        srv.update_rows(np.zeros(0, np.uint32), np.zeros((0, 1), np.uint8))
+        assert srv.stale_rows(cid) == 0
+        C = np.zeros((1, 1, L), np.uint32)
+        srv.compress([cid], B, C)
+        assert limbs_rows_to_ints(C[0]) == server.compress(K_or, B[0], cl.N)
+    sk_pr = wl.paillier_primes(934, 0, 256)
+    N = sk_pr.P * sk_pr.Q
+    with native.Compressor(4, 1 << 16, wl.int_to_limbs(N, 8), 256,
+                           ck=wl.ints_to_limbs(wl.uniform_ciphertexts(934, 0, 4, N), 16)) as cmp:
+        X = np.zeros((0, 16), np.uint32)
+        cmp.compress_lwe(np.zeros((0, 4), np.uint32), np.zeros(0, np.uint32), X)
