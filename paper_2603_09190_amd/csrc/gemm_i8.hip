@@ -127,7 +127,7 @@ __device__ __forceinline__ void gemm_planes_body(
     int nrb, int ncb, int nkz) {
   static_assert(kWide || kPl == 4, "byte-plane mode has four planes");
   constexpr int kSl = kKB / 64;            // MFMA K slices per step
-  constexpr int kStride = kKB + 16;        // LDS row stride; the skew spreads banks
+  constexpr int kStride = kKB + 32;        // LDS row stride; a 32-byte skew makes the fragment reads conflict-free
   __shared__ __attribute__((aligned(16))) int8_t xs[2][kPl * kBC][kStride];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
