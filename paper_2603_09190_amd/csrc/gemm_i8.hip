@@ -162,7 +162,7 @@ __device__ __forceinline__ void gemm_planes_body(
     const int b = lrow[t] >> 5;
     const int c = kWide ? cblk + lrow[t] : cblk + (lrow[t] & 31);
     xval[t] = c < ncol;
-    // vectors beyond ncol read vector ncol-1 (a valid address) and are zeroed after the load
+    // vectors beyond ncol read vector ncol-1 (a valid address) and are zeroed in the stash
     xoff[t] = (kWide ? min(c, ncol - 1) : min(c, ncol - 1) * kPl + b) * pitch + kstep0 * kKB + lcol[t];
   }
 
@@ -174,81 +174,105 @@ __device__ __forceinline__ void gemm_planes_body(
 #pragma unroll
       for (int b = 0; b < kPl; ++b) acc[mr][qb][b] = v4i{0, 0, 0, 0};
 
+  // X steps are loaded kXA steps ahead into kNX register buffers (step j in buffer j % kNX)
+  // and stashed into LDS one step ahead.  With two or more D steps in flight, X runs three
+  // steps ahead and each step issues its X load before its D load: the in-order load counter
+  // then lets the wait for X(i+1) pass while the younger D loads are still in flight.
+  constexpr int kXA = kDepth >= 2 ? 3 : 2;
+  constexpr int kNX = kXA - 1;
+  // unroll so that ring slots and X buffers are static register indices
+  constexpr int kU = kDepth == 1 ? 1 : (kDepth % 2 == 0 ? kDepth : 2 * kDepth);
   u32x4 ring[kDepth][kMR][kSl];
-  u32x4 xn[kPieces];
-  auto load_d = [&](int slot, int st) {
+  u32x4 xn[kNX][kPieces];
+  auto load_d = [&](int slot_, int st) {
 #pragma unroll
     for (int mr = 0; mr < kMR; ++mr)
 #pragma unroll
       for (int s = 0; s < kSl; ++s)
-        ring[slot][mr][s] = __builtin_nontemporal_load(
+        ring[slot_][mr][s] = __builtin_nontemporal_load(
             reinterpret_cast<const u32x4*>(dp[mr] + (size_t)st * kKB + 64 * s));
   };
-  auto load_x = [&](int st) {
+  auto load_x = [&](int xb, int st) {
 #pragma unroll
-    for (int t = 0; t < kPieces; ++t) {
-      const u32x4 v = *reinterpret_cast<const u32x4*>(Xs + (size_t)xoff[t] + (size_t)st * kKB);
-      xn[t] = xval[t] ? v : u32x4{0u, 0u, 0u, 0u};
-    }
+    for (int t = 0; t < kPieces; ++t)
+      xn[xb][t] = *reinterpret_cast<const u32x4*>(Xs + (size_t)xoff[t] + (size_t)st * kKB);
   };
-  auto stash = [&](int buf) {
+  // Vectors beyond ncol are zeroed here, when the data is consumed: a select right after the
+  // load would make the wave wait for it (and, the load counter being in order, for every
+  // older load) in the step that issued it.
+  auto stash = [&](int xb, int buf) {
 #pragma unroll
-    for (int t = 0; t < kPieces; ++t) *reinterpret_cast<u32x4*>(&xs[buf][lrow[t]][lcol[t]]) = xn[t];
+    for (int t = 0; t < kPieces; ++t)
+      *reinterpret_cast<u32x4*>(&xs[buf][lrow[t]][lcol[t]]) = xval[t] ? xn[xb][t] : u32x4{0u, 0u, 0u, 0u};
   };
 
+  // Every load is issued unconditionally, with its step clamped to the last one (the
+  // surplus loads near the end re-read that step and are never consumed), and the main loop
+  // runs whole unrolled trips only: with loads under branches, or loop back edges from
+  // several points, the compiler cannot count how many loads are younger than the one it
+  // needs and waits for all of them, which would expose the full load latency every step.
+  // The prologue issues its loads in the steady state's order for the same reason.
+  const int last = nsteps - 1;
+  load_x(0, 0);
+  if constexpr (kXA == 3) load_x(1, min(1, last));
+  load_d(0, 0);
+  if constexpr (kDepth >= 2) load_d(1, min(1, last));
+  stash(0, 0);
+  load_x((kXA - 1) % kNX, min(kXA - 1, last));
 #pragma unroll
-  for (int d = 0; d < kDepth; ++d)
-    if (d < nsteps) load_d(d, d);
-  load_x(0);
-  stash(0);
-  if (nsteps > 1) load_x(1);
+  for (int d = 2; d < kDepth; ++d) load_d(d, min(d, last));
   lds_barrier();
-  for (int st = 0; st < nsteps; st += kDepth) {
+
+  auto step = [&](int cur, int d) {
+    const int buf = cur & 1;
+    const int rs = d % kDepth;
+    // With one step in flight the next load is issued before this step's MFMAs (from a
+    // copy of the ring slot); with two or more it is issued after them, which saves the
+    // copy's registers while the other slots keep HBM busy.
+    u32x4 dc[kDepth == 1 ? kMR : 1][kSl];
+    if constexpr (kDepth == 1) {
 #pragma unroll
-    for (int d = 0; d < kDepth; ++d) {
-      const int cur = st + d;
-      if (cur >= nsteps) break;
-      const int buf = cur & 1;
-      // With one step in flight the next load is issued before this step's MFMAs (from a
-      // copy of the ring slot); with two or more it is issued after them, which saves the
-      // copy's registers while the other slots keep HBM busy.
-      u32x4 dc[kDepth == 1 ? kMR : 1][kSl];
-      if constexpr (kDepth == 1) {
+      for (int mr = 0; mr < kMR; ++mr)
 #pragma unroll
-        for (int mr = 0; mr < kMR; ++mr)
+        for (int s = 0; s < kSl; ++s) dc[mr][s] = ring[0][mr][s];
+      load_d(0, min(cur + 1, last));
+    }
 #pragma unroll
-          for (int s = 0; s < kSl; ++s) dc[mr][s] = ring[d][mr][s];
-        if (cur + kDepth < nsteps) load_d(d, cur + kDepth);
-      }
+    for (int s = 0; s < kSl; ++s) {
+      v4i xf[2][kPl];
 #pragma unroll
-      for (int s = 0; s < kSl; ++s) {
-        v4i xf[2][kPl];
+      for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+        for (int b = 0; b < kPl; ++b)
+          xf[qb][b] = *reinterpret_cast<const v4i*>(&xs[buf][b * 32 + 16 * qb + r][16 * g + 64 * s]);
+#pragma unroll
+      for (int mr = 0; mr < kMR; ++mr) {
+        u32x4 v = kDepth == 1 ? dc[kDepth == 1 ? mr : 0][s] : ring[rs][mr][s];
+        v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
+        const v4i a = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
           for (int b = 0; b < kPl; ++b)
-            xf[qb][b] = *reinterpret_cast<const v4i*>(&xs[buf][b * 32 + 16 * qb + r][16 * g + 64 * s]);
-#pragma unroll
-        for (int mr = 0; mr < kMR; ++mr) {
-          u32x4 v = kDepth == 1 ? dc[kDepth == 1 ? mr : 0][s] : ring[d][mr][s];
-          v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
-          const v4i a = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
-#pragma unroll
-          for (int qb = 0; qb < 2; ++qb)
-#pragma unroll
-            for (int b = 0; b < kPl; ++b)
-              acc[mr][qb][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, xf[qb][b], acc[mr][qb][b], 0, 0, 0);
-        }
+            acc[mr][qb][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, xf[qb][b], acc[mr][qb][b], 0, 0, 0);
       }
-      if constexpr (kDepth > 1) {
-        if (cur + kDepth < nsteps) load_d(d, cur + kDepth);
-      }
-      if (cur + 1 < nsteps) {
-        stash(buf ^ 1);
-        if (cur + 2 < nsteps) load_x(cur + 2);
-      }
-      lds_barrier();
     }
+    // the other LDS buffer was last read in the previous step, before its barrier; after the
+    // final step this stash writes surplus data that nothing reads
+    stash((d + 1) % kNX, buf ^ 1);
+    load_x((d + kXA) % kNX, min(cur + kXA, last));
+    if constexpr (kDepth > 1) load_d(rs, min(cur + kDepth, last));
+    lds_barrier();
+  };
+  int st = 0;
+  for (; st + kU <= nsteps; st += kU) {
+#pragma unroll
+    for (int d = 0; d < kU; ++d) step(st + d, d);
+  }
+#pragma unroll
+  for (int d = 0; d < kU - 1; ++d) {
+    if (st + d >= nsteps) break;
+    step(st + d, d);
   }
 
   const bool first = kz == 0;
@@ -332,14 +356,45 @@ __global__ void zero_out_kernel(uint32_t* __restrict__ p, int rows, int ncol, in
   }
 }
 
+// compare == 0: ref[c*rows + j] = element (j, c) of the output block (a snapshot);
+// compare == 1: adds the number of elements that differ from the snapshot to *mism.
+__global__ void gemm_snapshot_kernel(const uint32_t* __restrict__ out, int rows, int ncol,
+                                     int rowmajor, long long ld, uint32_t* __restrict__ ref,
+                                     int compare, unsigned* __restrict__ mism) {
+  const long long n = (long long)rows * ncol;
+  unsigned bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long c = i / rows, j = i - c * rows;
+    const uint32_t v = rowmajor ? out[j * ncol + c] : out[c * ld + j];
+    if (compare) bad += v != ref[i] ? 1u : 0u;
+    else ref[i] = v;
+  }
+  if (compare && bad) atomicAdd(mism, bad);
+}
+
+void launch_gemm_snapshot(const uint32_t* out, int rows, int ncol, bool out_rowmajor,
+                          long long out_ld, uint32_t* ref, bool compare, unsigned* mism,
+                          hipStream_t s) {
+  if ((long long)rows * ncol == 0) return;
+  gemm_snapshot_kernel<<<1024, 256, 0, s>>>(out, rows, ncol, out_rowmajor ? 1 : 0, out_ld, ref,
+                                            compare ? 1 : 0, mism);
+}
+
 bool gemm_shape_valid(const GemmShape& sh, int pitch, int planes) {
   const bool base = (sh.waves == 8 && sh.depth == 1 && sh.mr == 2 && sh.kb == 256) ||
                     (sh.waves == 8 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) ||
+                    (sh.waves == 8 && sh.depth == 3 && sh.mr == 2 && sh.kb == 256) ||
                     (sh.waves == 8 && sh.depth == 1 && sh.mr == 1 && sh.kb == 256) ||
                     (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 256) ||
+                    (sh.waves == 4 && sh.depth == 4 && sh.mr == 2 && sh.kb == 256) ||
                     (sh.waves == 4 && sh.depth == 1 && sh.mr == 2 && sh.kb == 512);
   const bool mr4 = (sh.waves == 8 || sh.waves == 4) && sh.mr == 4 && sh.kb == 256 &&
                    (sh.depth == 2 || (planes == 1 && sh.depth == 1));
+  // one plane, all nine 32-vector groups of a 260-column offset operand in one block
+  const bool wide9 = planes == 1 && sh.cg == 9 && sh.mr == 2 && sh.depth >= 2 && sh.depth <= 4 &&
+                     ((sh.waves == 4 && sh.kb == 128) || (sh.waves == 2 && sh.kb == 64));
+  if (wide9) return sh.ksplit >= 1 && pitch % sh.kb == 0;
   const bool known = base || (planes == 4 && sh.waves == 2 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256) || mr4;
   if (!known || sh.ksplit < 1) return false;
   if (planes == 1 && (sh.cg < 2 || sh.cg > 4)) return false;
@@ -379,7 +434,20 @@ void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int pla
     else ZP_LAUNCH(W, DP, MR, KB, 4, true);                                                         \
     return;                                                                                         \
   }
-  ZP_G(8, 1, 2, 256) ZP_G(8, 2, 2, 256) ZP_G(8, 1, 1, 256) ZP_G(4, 1, 2, 256) ZP_G(4, 1, 2, 512)
+  ZP_G(8, 1, 2, 256) ZP_G(8, 2, 2, 256) ZP_G(8, 3, 2, 256) ZP_G(8, 1, 1, 256) ZP_G(4, 1, 2, 256)
+  ZP_G(4, 4, 2, 256) ZP_G(4, 1, 2, 512)
+  if (planes == 1 && sh.cg == 9 && sh.waves == 4) {
+    if (sh.depth == 2) ZP_LAUNCH(4, 2, 2, 128, 9, true);
+    else if (sh.depth == 3) ZP_LAUNCH(4, 3, 2, 128, 9, true);
+    else ZP_LAUNCH(4, 4, 2, 128, 9, true);
+    return;
+  }
+  if (planes == 1 && sh.cg == 9 && sh.waves == 2) {
+    if (sh.depth == 2) ZP_LAUNCH(2, 2, 2, 64, 9, true);
+    else if (sh.depth == 3) ZP_LAUNCH(2, 3, 2, 64, 9, true);
+    else ZP_LAUNCH(2, 4, 2, 64, 9, true);
+    return;
+  }
 #define ZP_W(W, DP, MR, KB)                                                                         \
   if (planes == 1 && sh.waves == W && sh.depth == DP && sh.mr == MR && sh.kb == KB) {               \
     if (sh.cg == 2) ZP_LAUNCH(W, DP, MR, KB, 2, true);                                              \

@@ -88,6 +88,13 @@ void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int pla
                         uint32_t* out, bool out_rowmajor, long long out_ld, const GemmShape& sh,
                         hipStream_t s);
 
+// Tuning cross-check: with compare false, ref (rows x ncol, column c at ref + c*rows) receives
+// a copy of the output block; with compare true, *mism is increased by the number of
+// elements that differ from that copy.
+void launch_gemm_snapshot(const uint32_t* out, int rows, int ncol, bool out_rowmajor,
+                          long long out_ld, uint32_t* ref, bool compare, unsigned* mism,
+                          hipStream_t s);
+
 // ---- rows.hip (row gather/scatter for updates and partial recomputation)
 void launch_gather_rows_u8(const uint8_t* src, int pitch, const uint32_t* rows, int nrows,
                            uint8_t* dst, hipStream_t s);

@@ -200,27 +200,29 @@ void prof_clear(pir_server* s) {
 
 // ----------------------------------------------------------------------------- autotuner
 // Launch shape of the byte-plane contraction per problem shape.  The first contraction of a
-// shape times every candidate once (after a warm-up) with events on the server's stream and
-// keeps the fastest; every candidate computes identical bits, so tuning never changes a
-// result.  ZIPPIR_AUTOTUNE=0 disables tuning (default shape); ZIPPIR_TUNE_CACHE=<file>
-// persists choices as lines "rows pitch ncol rowmajor planes waves depth mr kb ksplit cg".
+// shape runs every candidate once as a warm-up, checks that its output equals the first
+// candidate's element for element (every shape must compute identical bits; a difference is
+// reported as PIR_EDEVICE), times three more launches with events on the server's stream and
+// keeps the fastest.  ZIPPIR_AUTOTUNE=0 disables tuning (default shape);
+// ZIPPIR_TUNE_CACHE=<file> persists choices as lines
+// "rows pitch ncol rowmajor planes waves depth mr kb ksplit cg".
 using TuneKey = std::tuple<int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, zp::GemmShape> g_tune;
 bool g_tune_loaded = false;
 
-constexpr zp::GemmShape kDefaultShape4{8, 1, 2, 256, 2, 4};
-constexpr zp::GemmShape kDefaultShape1{8, 1, 2, 256, 1, 3};
+constexpr zp::GemmShape kDefaultShape4{8, 2, 2, 256, 2, 4};
+constexpr zp::GemmShape kDefaultShape1{4, 2, 2, 128, 1, 9};
 // byte-plane problems (batched answers, H)
-const std::vector<zp::GemmShape> kCandidates4 = {{8, 1, 2, 256, 2, 4}, {8, 2, 2, 256, 2, 4}, {8, 1, 2, 256, 4, 4},
-                                                 {8, 1, 1, 256, 2, 4}, {4, 1, 2, 512, 1, 4}, {2, 2, 2, 256, 1, 4},
-                                                 {4, 1, 2, 256, 1, 4}, {8, 2, 4, 256, 2, 4}, {4, 2, 4, 256, 1, 4}};
+const std::vector<zp::GemmShape> kCandidates4 = {{8, 2, 2, 256, 2, 4}, {8, 1, 2, 256, 2, 4}, {8, 1, 2, 256, 4, 4},
+                                                 {8, 2, 2, 256, 4, 4}, {8, 1, 1, 256, 2, 4}, {4, 1, 2, 512, 1, 4},
+                                                 {4, 4, 2, 256, 1, 4}, {4, 1, 2, 256, 1, 4}, {2, 2, 2, 256, 1, 4},
+                                                 {4, 2, 4, 256, 1, 4}};
 // one-plane problems (the offset answer): column groups per block as well
-const std::vector<zp::GemmShape> kCandidates1 = {{8, 1, 2, 256, 1, 3}, {8, 1, 2, 256, 1, 4}, {8, 2, 2, 256, 1, 3},
-                                                 {8, 2, 2, 256, 1, 4}, {4, 1, 2, 256, 1, 3}, {4, 1, 2, 512, 1, 4},
-                                                 {8, 1, 1, 256, 1, 4}, {8, 1, 2, 256, 2, 3}, {8, 1, 2, 256, 1, 2},
-                                                 {8, 1, 4, 256, 1, 3}, {8, 1, 4, 256, 1, 4}, {4, 1, 4, 256, 1, 3},
-                                                 {8, 2, 4, 256, 1, 3}, {8, 2, 4, 256, 1, 4}, {4, 2, 4, 256, 1, 4}};
+const std::vector<zp::GemmShape> kCandidates1 = {{4, 2, 2, 128, 1, 9}, {4, 3, 2, 128, 1, 9}, {4, 4, 2, 128, 1, 9},
+                                                 {2, 4, 2, 64, 1, 9},  {8, 1, 2, 256, 1, 3}, {8, 1, 1, 256, 1, 4},
+                                                 {8, 2, 2, 256, 1, 3}, {4, 1, 2, 256, 1, 3}, {4, 4, 2, 256, 1, 3},
+                                                 {8, 1, 2, 256, 1, 2}, {4, 1, 4, 256, 1, 3}, {4, 2, 4, 256, 1, 4}};
 
 const char* tune_cache_path() {
   const char* p = std::getenv("ZIPPIR_TUNE_CACHE");
@@ -272,28 +274,55 @@ pir_status run_gemm_x(pir_server* s, const uint8_t* D, int rows, int cols, int p
     else need_tune = autotune_enabled();
   }
   if (need_tune) {
+    const size_t nout = (size_t)rows * (size_t)ncol;
+    const size_t refbytes = (nout * sizeof(uint32_t) + 255) / 256 * 256;
+    void* tmp = nullptr;
+    ZP_TRY(s->alloc(&tmp, refbytes + 256));
+    auto* ref = static_cast<uint32_t*>(tmp);
+    auto* mism = reinterpret_cast<unsigned*>(static_cast<char*>(tmp) + refbytes);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    ZP_HIP(hipEventCreate(&e0));
-    ZP_HIP(hipEventCreate(&e1));
+    pir_status rc = PIR_OK;
+    auto check = [&](hipError_t e) {
+      if (e != hipSuccess && rc == PIR_OK) rc = fail(PIR_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    };
+    check(hipEventCreate(&e0));
+    check(hipEventCreate(&e1));
+    check(hipMemsetAsync(mism, 0, sizeof(unsigned), st));
     float best = 1e30f;
+    bool have_ref = false;
     for (const zp::GemmShape& c : planes == 4 ? kCandidates4 : kCandidates1) {
+      if (rc != PIR_OK) break;
       if (!zp::gemm_shape_valid(c, pitch, planes)) continue;
       zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor,
                              ld, c, st);
-      ZP_HIP(hipEventRecord(e0, st));
-      zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor,
-                             ld, c, st);
-      ZP_HIP(hipEventRecord(e1, st));
-      ZP_HIP(hipEventSynchronize(e1));
-      float ms = 0;
-      ZP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      zp::launch_gemm_snapshot(out, rows, ncol, rowmajor, ld, ref, have_ref, mism, st);
+      have_ref = true;
+      float ms = 1e30f;
+      for (int rep = 0; rep < 3 && rc == PIR_OK; ++rep) {
+        check(hipEventRecord(e0, st));
+        zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor,
+                               ld, c, st);
+        check(hipEventRecord(e1, st));
+        check(hipEventSynchronize(e1));
+        float t = 0;
+        check(hipEventElapsedTime(&t, e0, e1));
+        ms = std::min(ms, t);
+      }
       if (ms < best) {
         best = ms;
         shape = c;
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    unsigned bad = 0;
+    check(hipMemcpyAsync(&bad, mism, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    check(hipStreamSynchronize(st));
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    s->release(tmp);
+    ZP_TRY(rc);
+    if (bad != 0)
+      return fail(PIR_EDEVICE, "autotune: launch shapes disagree on " + std::to_string(bad) +
+                                   " output elements");
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = shape;
     tune_store_locked();

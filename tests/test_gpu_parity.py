@@ -76,6 +76,22 @@ def test_mfma_batch_matches_oracle(native, batch):
         assert np.array_equal(B2, B)
 
 
+@pytest.mark.parametrize("cols", [1, 300, 700, 1100, 2200, 70000])
+def test_mfma_k_lengths(native, cols):
+    # From one K step per block to several, and a K range beyond 64 KiB (split over blocks that
+    # add into the output).  The first contraction of each problem shape also runs every
+    # candidate launch shape, and the library checks each one's output against the first.
+    rows, batch = 37, 3
+    log(f"mfma cols={cols}")
+    D = _rand(40 + cols, (rows, cols), 256, np.uint8)
+    A = _rand(41, (cols, 4), Q32, np.uint32)
+    Qm = _rand(42 + cols, (batch, cols), Q32, np.uint32)
+    with native.Server(D, A) as srv:
+        B = np.zeros((batch, rows), np.uint32)
+        srv.answer(Qm, B, native.PATH_MFMA)
+        assert np.array_equal(B, server.answer_batch(D, Qm))
+
+
 @pytest.mark.parametrize("dval,qval", [(0, 0), (255, Q32 - 1), (0, Q32 - 1), (255, 0), (128, 0x80808080)])
 def test_mfma_extreme_values(native, dval, qval):
     # D = 0 and Q = 0 both shift to -128 in every plane: the largest MFMA partial sums.
