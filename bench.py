@@ -145,22 +145,24 @@ def main() -> int:
     log("offline: pir_hint (H = D.A, then K for every row)")
     srv.profile(True)
     t0 = time.perf_counter()
-    chunk = max(1, rows // 2)
-    for r0 in range(0, rows, chunk):
-        srv.hint(cid, rows=np.arange(r0, min(rows, r0 + chunk), dtype=np.uint32))
-        log(f"  hint rows {r0}..{min(rows, r0 + chunk) - 1} done at {time.perf_counter() - t0:.1f} s")
+    srv.hint(cid)
     hint_s = time.perf_counter() - t0
+    wbits = srv.hint_window_bits(cid)
     gemm_ms, _ = srv.profile_read("gemm")
     table_ms, _ = srv.profile_read("table")
     hintk_ms, _ = srv.profile_read("hint")
     srv.profile(False)
-    log(f"offline hint {hint_s:.2f} s (H {gemm_ms:.2f} ms, table {table_ms:.1f} ms, rows {hintk_ms:.1f} ms)")
-    # expected Montgomery products of the hint rows: 4 windows per exponent, each nonzero with
-    # probability 255/256 for uniform exponents, plus one conversion per row
+    log(f"offline hint {hint_s:.2f} s (H {gemm_ms:.2f} ms, table {table_ms:.1f} ms, rows {hintk_ms:.1f} ms, "
+        f"{wbits}-bit windows)")
+    # expected Montgomery products of the hint rows: one per nonzero window digit of a uniform
+    # 32-bit exponent (a digit of b bits is nonzero with probability 1 - 2^-b), plus one
+    # conversion per row
     S = 64 * ((L + 63) // 64)
-    hint_mm = rows * (n * 4 * 255 / 256 + 1)
+    digit_bits = [min(wbits, 32 - wbits * w) for w in range(-(-32 // wbits))]
+    hint_mm = rows * (n * sum(1 - 2.0 ** -b for b in digit_bits) + 1)
     hint_rate = hint_mm / (hintk_ms * 1e-3)
-    hint_fig = {"kernel_ms": round(hintk_ms, 1), "montmuls": int(hint_mm), "montmul_per_s": round(hint_rate, 0),
+    hint_fig = {"kernel_ms": round(hintk_ms, 1), "table_ms": round(table_ms, 1), "window_bits": wbits,
+                "montmuls": int(hint_mm), "montmul_per_s": round(hint_rate, 0),
                 "limbs": S, "word_mac_per_s": round(hint_rate * montmul_macs(S), 0),
                 "alu_peak_mac_per_s": ALU_PEAK_MACS,
                 "frac": round(hint_rate * montmul_macs(S) / ALU_PEAK_MACS, 4)}

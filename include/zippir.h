@@ -253,6 +253,11 @@ pir_status pir_get_client_hint(pir_server *srv, uint32_t client_id, uint32_t row
 /* Limb count L of a client's ciphertexts (0 for an unknown id). */
 uint32_t pir_client_limbs(pir_server *srv, uint32_t client_id);
 
+/* Window width in bits of the fixed-base table used by the client's last pir_hint (the
+   exponentiation method of the Alg. 4 precomputation taken to wider windows: 8 or 11),
+   0 before the first pir_hint or for an unknown id.  The result does not depend on it. */
+uint32_t pir_hint_window_bits(pir_server *srv, uint32_t client_id);
+
 /* Number of stale rows in H (client_id == UINT32_MAX) or in a client's hint. */
 int64_t pir_stale_rows(pir_server *srv, uint32_t client_id);
 

@@ -224,6 +224,9 @@ __device__ __forceinline__ void gemm_planes_body(
   lds_barrier();
 
   auto step = [&](int cur, int d) {
+    // Keep the scheduler from hoisting work on later ring slots (their sign flips) into this
+    // step, which would wait for those slots' loads here.
+    __builtin_amdgcn_sched_barrier(0);
     const int buf = cur & 1;
     const int rs = d % kDepth;
     // With one step in flight the next load is issued before this step's MFMAs (from a

@@ -4,9 +4,11 @@
 //
 // Alg. 4 precomputes ck^(2^j) so that each plaintext multiplication becomes at most 32
 // ciphertext multiplications selected by the exponent's bits.  Here the same fixed-base
-// idea is taken to 8-bit windows: for every base k and window w the table holds
-// ck_k^(v * 2^(8w)) for v = 1..255, so one 32-bit exponent costs at most 4 Montgomery
-// multiplications, all bases being shared by every row of the database.  Any order of
+// idea is taken to windows of wb bits: for every base k and window w the table holds
+// ck_k^(v * 2^(wb w)) for v = 1..2^wb - 1, so one 32-bit exponent costs at most
+// ceil(32 / wb) Montgomery multiplications, all bases being shared by every row of the
+// database.  wb = 8 (4 windows, 255 entries each) suits a few rows; wb = 11 (3 windows, 2047
+// entries each) costs a larger table and saves a quarter of the row products.  Any order of
 // the multiplications gives the same residue.
 //
 // One wavefront computes one row; every value stays in Montgomery form (x R mod N^2) until
@@ -21,24 +23,37 @@ __device__ __forceinline__ int wave_index() {
   return blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+// One wavefront per (base k, window w, segment): with digits = 2^wbits - 1 entries per window
+// cut into `segs` runs, segment s computes x^v for v in its run, x = ck_k^(2^(wbits w)),
+// starting from x^v0 by square-and-multiply and continuing by multiplications by x.
 template <int P>
 __global__ __launch_bounds__(256) void build_table_kernel(ClientDev cd,
                                                           const uint32_t* __restrict__ ck, int n,
-                                                          int windows, uint32_t* __restrict__ table) {
+                                                          int windows, int wbits, int segs,
+                                                          uint32_t* __restrict__ table) {
   constexpr int S = 64 * P;
   const int widx = wave_index();
-  if (widx >= n * windows) return;
-  const int k = widx / windows, w = widx % windows;
+  if (widx >= n * windows * segs) return;
+  const int seg = widx % segs, kw = widx / segs;
+  const int k = kw / windows, w = kw % windows;
+  const int digits = (1 << wbits) - 1;
+  const int v0 = 1 + (int)((long long)digits * seg / segs);
+  const int v1 = (int)((long long)digits * (seg + 1) / segs);  // inclusive
   WNum<P> M, RR, x, cur;
   wn_load(M, cd.N2);
   wn_load(RR, cd.RR);
   wn_load_n(x, ck + (size_t)k * cd.L, cd.L);
   mont_mul(x, x, RR, M, cd.m2prime);  // ck * R mod N^2
-  for (int t = 0; t < kWindowBits * w; ++t) mont_mul(x, x, x, M, cd.m2prime);
-  uint32_t* T = table + (size_t)widx * kDigits * S;
-  wn_store(T, x);
+  for (int t = 0; t < wbits * w; ++t) mont_mul(x, x, x, M, cd.m2prime);
+  // cur = x^v0: left-to-right binary exponentiation
   cur = x;
-  for (int v = 2; v <= kDigits; ++v) {
+  for (int bit = 30 - __builtin_clz((unsigned)v0); bit >= 0; --bit) {
+    mont_mul(cur, cur, cur, M, cd.m2prime);
+    if ((v0 >> bit) & 1) mont_mul(cur, cur, x, M, cd.m2prime);
+  }
+  uint32_t* T = table + (size_t)kw * digits * S;
+  wn_store(T + (size_t)(v0 - 1) * S, cur);
+  for (int v = v0 + 1; v <= v1; ++v) {
     mont_mul(cur, cur, x, M, cd.m2prime);
     wn_store(T + (size_t)(v - 1) * S, cur);
   }
@@ -48,10 +63,12 @@ template <int P>
 __global__ __launch_bounds__(256) void hint_rows_kernel(ClientDev cd, const uint32_t* __restrict__ H,
                                                         int n, const uint32_t* __restrict__ rowlist,
                                                         int nrows, const uint32_t* __restrict__ table,
-                                                        uint32_t* __restrict__ K) {
+                                                        int wbits, uint32_t* __restrict__ K) {
   constexpr int S = 64 * P;
   const int widx = wave_index();
   if (widx >= nrows) return;
+  const int windows = (32 + wbits - 1) / wbits;
+  const uint32_t digits = (1u << wbits) - 1;
   const int row = rowlist ? (int)rowlist[widx] : widx;
   WNum<P> M, acc, b;
   wn_load(M, cd.N2);
@@ -59,12 +76,11 @@ __global__ __launch_bounds__(256) void hint_rows_kernel(ClientDev cd, const uint
   const uint32_t* hrow = H + (size_t)row * n;
   for (int k = 0; k < n; ++k) {
     const uint32_t e = 0u - hrow[k];  // (-H_jk) mod 2^32
-    const uint32_t* tk = table + (size_t)k * kWindows * kDigits * S;
-#pragma unroll
-    for (int w = 0; w < kWindows; ++w) {
-      const uint32_t d = (e >> (kWindowBits * w)) & kDigits;
+    const uint32_t* tk = table + (size_t)k * windows * digits * S;
+    for (int w = 0; w < windows; ++w) {
+      const uint32_t d = (e >> (wbits * w)) & digits;
       if (d != 0) {
-        wn_load(b, tk + ((size_t)w * kDigits + (d - 1)) * S);
+        wn_load(b, tk + ((size_t)w * digits + (d - 1)) * S);
         mont_mul(acc, acc, b, M, cd.m2prime);
       }
     }
@@ -85,10 +101,12 @@ template <int P>
 __global__ __launch_bounds__(256) void hint_rows_pair_kernel(ClientDev cd, const uint32_t* __restrict__ H,
                                                              int n, const uint32_t* __restrict__ rowlist,
                                                              int nrows, const uint32_t* __restrict__ table,
-                                                             uint32_t* __restrict__ K) {
+                                                             int wbits, uint32_t* __restrict__ K) {
   constexpr int S = 64 * P;
   const int widx = wave_index();
   if (2 * widx >= nrows) return;
+  const int windows = (32 + wbits - 1) / wbits;
+  const uint32_t digits = (1u << wbits) - 1;
   const int i1 = 2 * widx, i2 = min(nrows - 1, 2 * widx + 1);
   const int row1 = rowlist ? (int)rowlist[i1] : i1;
   const int row2 = rowlist ? (int)rowlist[i2] : i2;
@@ -101,14 +119,13 @@ __global__ __launch_bounds__(256) void hint_rows_pair_kernel(ClientDev cd, const
   const uint32_t* h2 = H + (size_t)row2 * n;
   for (int k = 0; k < n; ++k) {
     const uint32_t e1 = 0u - h1[k], e2 = 0u - h2[k];
-    const uint32_t* tk = table + (size_t)k * kWindows * kDigits * S;
-#pragma unroll
-    for (int w = 0; w < kWindows; ++w) {
-      const uint32_t d1 = (e1 >> (kWindowBits * w)) & kDigits;
-      const uint32_t d2 = (e2 >> (kWindowBits * w)) & kDigits;
+    const uint32_t* tk = table + (size_t)k * windows * digits * S;
+    for (int w = 0; w < windows; ++w) {
+      const uint32_t d1 = (e1 >> (wbits * w)) & digits;
+      const uint32_t d2 = (e2 >> (wbits * w)) & digits;
       if (d1 == 0 && d2 == 0) continue;
-      if (d1) wn_load(b1, tk + ((size_t)w * kDigits + (d1 - 1)) * S); else b1 = one;
-      if (d2) wn_load(b2, tk + ((size_t)w * kDigits + (d2 - 1)) * S); else b2 = one;
+      if (d1) wn_load(b1, tk + ((size_t)w * digits + (d1 - 1)) * S); else b1 = one;
+      if (d2) wn_load(b2, tk + ((size_t)w * digits + (d2 - 1)) * S); else b2 = one;
       mont_mul2(acc1, acc1, b1, acc2, acc2, b2, M, cd.m2prime);
     }
   }
@@ -271,37 +288,40 @@ void launch_to_mont(const ClientDev& cd, uint32_t* x, const uint32_t* rowlist, i
 }
 
 void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int windows,
-                        uint32_t* table, hipStream_t s) {
-  const int waves = n * windows;
+                        uint32_t* table, hipStream_t s, int wbits) {
+  // wide windows: four segments per (base, window) keep enough wavefronts in flight
+  const int segs = wbits > 8 ? 4 : 1;
+  const int waves = n * windows * segs;
+  if (waves <= 0) return;
   const int blocks = (waves + 3) / 4;
   switch (cd.P) {
-    case 1: build_table_kernel<1><<<blocks, 256, 0, s>>>(cd, ck, n, windows, table); break;
-    case 2: build_table_kernel<2><<<blocks, 256, 0, s>>>(cd, ck, n, windows, table); break;
-    case 3: build_table_kernel<3><<<blocks, 256, 0, s>>>(cd, ck, n, windows, table); break;
-    case 4: build_table_kernel<4><<<blocks, 256, 0, s>>>(cd, ck, n, windows, table); break;
+    case 1: build_table_kernel<1><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
+    case 2: build_table_kernel<2><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
+    case 3: build_table_kernel<3><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
+    case 4: build_table_kernel<4><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
   }
 }
 
 void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
-                      int nrows, const uint32_t* table, uint32_t* K, hipStream_t s) {
+                      int nrows, const uint32_t* table, int wbits, uint32_t* K, hipStream_t s) {
   if (nrows <= 0) return;
   // two rows per wavefront while that still leaves several wavefronts per SIMD
   if (nrows >= 16384) {
     const int blocks = ((nrows + 1) / 2 + 3) / 4;
     switch (cd.P) {
-      case 1: hint_rows_pair_kernel<1><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
-      case 2: hint_rows_pair_kernel<2><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
-      case 3: hint_rows_pair_kernel<3><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
-      case 4: hint_rows_pair_kernel<4><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
+      case 1: hint_rows_pair_kernel<1><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+      case 2: hint_rows_pair_kernel<2><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+      case 3: hint_rows_pair_kernel<3><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+      case 4: hint_rows_pair_kernel<4><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
     }
     return;
   }
   const int blocks = (nrows + 3) / 4;
   switch (cd.P) {
-    case 1: hint_rows_kernel<1><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
-    case 2: hint_rows_kernel<2><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
-    case 3: hint_rows_kernel<3><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
-    case 4: hint_rows_kernel<4><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, K); break;
+    case 1: hint_rows_kernel<1><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+    case 2: hint_rows_kernel<2><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+    case 3: hint_rows_kernel<3><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+    case 4: hint_rows_kernel<4><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
   }
 }
 

@@ -46,7 +46,8 @@ struct ClientDev {
 // into row chunks), bounding how long one database's launch holds the device.
 constexpr long long kLaunchBytes = 2LL << 30;
 
-// Number of table entries per (base, window) for 8-bit fixed-base windows.
+// 8-bit fixed-base windows: the standalone compressor's table, and the client hint's for
+// few rows.
 constexpr int kWindowBits = 8;
 constexpr int kWindows = 32 / kWindowBits;
 constexpr int kDigits = (1 << kWindowBits) - 1;
@@ -106,12 +107,14 @@ void launch_scatter_rows_u32(const uint32_t* src, int width, const uint32_t* row
                              uint32_t* dst, hipStream_t s);
 
 // ---- hint.hip
+// Fixed-base table of windows of wbits bits: entry (k, w, v) at table + ((k windows + w)
+// (2^wbits - 1) + v - 1) S holds ck_k^(v 2^(wbits w)) R mod N^2, v = 1 .. 2^wbits - 1.
 void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int windows,
-                        uint32_t* table, hipStream_t s);
-// Rows processed: rowlist[i] for i < nrows (rowlist may be null: rows 0..nrows-1).
-// Writes K'_j = K_j 2^32 mod N^2 (rows x L limbs).
+                        uint32_t* table, hipStream_t s, int wbits = kWindowBits);
+// Rows processed: rowlist[i] for i < nrows (rowlist may be null: rows 0..nrows-1), with a
+// table of ceil(32 / wbits) windows.  Writes K'_j = K_j 2^32 mod N^2 (rows x L limbs).
 void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
-                      int nrows, const uint32_t* table, uint32_t* Kp, hipStream_t s);
+                      int nrows, const uint32_t* table, int wbits, uint32_t* Kp, hipStream_t s);
 // M'_j = N (K'_j mod N) (rows x L limbs), the combine key.
 // (Y, when not NULL: rows x h, Y[row] = (K mod N) R_N mod N for the offset combine, where
 // K = Kp 2^-32 when `scaled` and K = Kp otherwise.)

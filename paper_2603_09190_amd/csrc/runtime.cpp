@@ -68,6 +68,7 @@ struct ClientState {
   uint32_t* Mp = nullptr;      // rows x L: N (K'_j mod N), the combine key
   uint32_t* Y = nullptr;       // rows x h: (K_j mod N) R_N mod N, the offset-combine key
   uint32_t m2prime = 0, nprime = 0;
+  uint32_t hint_wbits = 0;     // window width of the last pir_hint's table (0: none yet)
   std::vector<uint8_t> valid;  // per row: K' and M' up to date
   int64_t stale = 0;
   // packed responses (batched compression): ell rows per ciphertext, gamma = 2^t
@@ -661,15 +662,31 @@ pir_status pir_hint(pir_server* s, uint32_t id, const uint32_t* rows, uint32_t n
   ZP_TRY(refresh_all_stale_H(s));
   hipStream_t st = s->stream;
   const zp::ClientDev cd = c->dev();
+  const int m = all ? (int)s->rows : (int)sel.size();
+  // Window width of the fixed-base table: building it costs n W (2^wb - 1) products (each
+  // about 1.5 row products, one chain per wavefront), the rows m n W with W = ceil(32 / wb).
+  // 11-bit windows (W = 3) win once there are a few thousand rows; if their table does not
+  // fit, 8-bit windows (W = 4) are used.
+  auto cost = [&](int wb) {
+    const double W = (32 + wb - 1) / wb;
+    return 1.5 * s->n * W * ((1 << wb) - 1) + (double)m * s->n * W;
+  };
+  int wbits = cost(11) < cost(zp::kWindowBits) ? 11 : zp::kWindowBits;
   uint32_t* table = nullptr;
-  const size_t tbytes = (size_t)s->n * zp::kWindows * zp::kDigits * c->S * sizeof(uint32_t);
-  ZP_TRY(s->alloc((void**)&table, tbytes));
+  auto table_bytes = [&](int wb) {
+    return (size_t)s->n * ((32 + wb - 1) / wb) * (((size_t)1 << wb) - 1) * c->S * sizeof(uint32_t);
+  };
+  if (wbits != zp::kWindowBits && s->alloc((void**)&table, table_bytes(wbits)) != PIR_OK) {
+    g_last_error.clear();
+    wbits = zp::kWindowBits;
+  }
+  if (!table) ZP_TRY(s->alloc((void**)&table, table_bytes(wbits)));
   {
     ProfScope ps(s, PIR_KERNEL_TABLE);
-    zp::launch_build_table(cd, c->ck, (int)s->n, zp::kWindows, table, st);
+    zp::launch_build_table(cd, c->ck, (int)s->n, (32 + wbits - 1) / wbits, table, st, wbits);
   }
+  c->hint_wbits = (uint32_t)wbits;
   uint32_t* drows = nullptr;
-  const int m = all ? (int)s->rows : (int)sel.size();
   if (!all) {
     pir_status a = s->alloc((void**)&drows, sel.size() * sizeof(uint32_t));
     if (a != PIR_OK) {
@@ -680,7 +697,7 @@ pir_status pir_hint(pir_server* s, uint32_t id, const uint32_t* rows, uint32_t n
   }
   {
     ProfScope ps(s, PIR_KERNEL_HINT);
-    zp::launch_hint_rows(cd, s->H, (int)s->n, drows, m, table, c->Kp, st);
+    zp::launch_hint_rows(cd, s->H, (int)s->n, drows, m, table, wbits, c->Kp, st);
   }
   {
     ProfScope ps(s, PIR_KERNEL_KEY);
@@ -1210,6 +1227,12 @@ uint32_t pir_client_limbs(pir_server* s, uint32_t id) {
   if (!s) return 0;
   ClientState* c = find_client(s, id);
   return c ? c->L : 0;
+}
+
+uint32_t pir_hint_window_bits(pir_server* s, uint32_t id) {
+  if (!s) return 0;
+  ClientState* c = find_client(s, id);
+  return c ? c->hint_wbits : 0;
 }
 
 int64_t pir_stale_rows(pir_server* s, uint32_t id) {

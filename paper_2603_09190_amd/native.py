@@ -72,6 +72,7 @@ _sig = {
                                              ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_client_limbs": (ctypes.c_uint32, [ctypes.c_void_p, ctypes.c_uint32]),
     "pir_stale_rows": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_hint_window_bits": (ctypes.c_uint32, [ctypes.c_void_p, ctypes.c_uint32]),
     "pir_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
                                    ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                                    ctypes.POINTER(ctypes.c_uint64)]),
@@ -216,6 +217,10 @@ class Server:
 
     def stale_rows(self, cid: int | None = None) -> int:
         return _lib.pir_stale_rows(self._h, 0xFFFFFFFF if cid is None else cid)
+
+    def hint_window_bits(self, cid: int) -> int:
+        """Window width of the fixed-base table the client's last hint used (8 or 11)."""
+        return _lib.pir_hint_window_bits(self._h, cid)
 
     def hint(self, cid: int, rows=None) -> None:
         p, n, _keep = _rows_arg(rows)

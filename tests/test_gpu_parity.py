@@ -340,7 +340,8 @@ def test_read_probe(native):
 
 def test_hint_two_rows_per_wave_odd_count(native):
     # 16385 rows take the two-rows-per-wavefront hint kernel, the last wavefront holding a
-    # single row; every row of K matches the oracle.
+    # single row, and the 11-bit window table (a pir_hint over few rows takes 8-bit windows);
+    # every row of K matches the oracle.
     rows, cols, n, n_bits = 16385, 64, 4, 256
     inst = make_instance(cfg=931, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False, zero_row=rows - 1)
     cl = inst.clients[0]
@@ -348,12 +349,19 @@ def test_hint_two_rows_per_wave_odd_count(native):
     E = server.exponents(server.global_hint(inst.D, inst.A))
     with native.Server(inst.D, inst.A) as srv:
         cid = srv.add_client(N_limbs, n_bits, ck)
+        assert srv.hint_window_bits(cid) == 0
         srv.hint(cid)
+        assert srv.hint_window_bits(cid) == 11
         K = np.zeros((rows, L), np.uint32)
         srv.client_hint(cid, 0, rows, K)
+        K8 = K.copy()
+        srv.hint(cid, rows=[0, 5, rows - 1])
+        assert srv.hint_window_bits(cid) == 8
+        srv.client_hint(cid, 0, rows, K8)
     with Pool(pool_size()) as pool:
         K_or = oracle_client_hint(cl.ck, E, cl.N, pool=pool)
     assert limbs_rows_to_ints(K) == [K_or[j] for j in range(rows)]
+    assert np.array_equal(K8, K)
     assert K_or[rows - 1] == 1
 
 
