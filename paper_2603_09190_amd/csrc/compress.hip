@@ -10,6 +10,7 @@
 // followed by one conditional subtraction of N^2.  About 2 L word products per row; the
 // kernel is bound by reading K' and M' and writing c.
 #include "internal.h"
+#include "rownum.h"
 #include "wavenum.h"
 
 namespace zp {
@@ -185,15 +186,93 @@ __global__ __launch_bounds__(256) void compress_offset_kernel(ClientDev cd, cons
   wn_store_n(C + (size_t)row * cd.L, acc, cd.L);
 }
 
+// The same combine with four rows per wavefront, one per 16-lane row (rownum.h): Q = 4 P limbs
+// per lane for numbers mod N^2 and QN = 4 PN for numbers mod N, so R and R_N are those of the
+// one-row layout.  Spare rows of the last wavefront repeat its last row and store nothing.
+template <int P, int PN>
+__global__ __launch_bounds__(256) void compress_offset_quad_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
+                                                                   const uint32_t* __restrict__ Y,
+                                                                   const uint32_t* __restrict__ T, int rows,
+                                                                   uint32_t* __restrict__ C, int scaled) {
+  constexpr int Q = 4 * P, QN = 4 * PN;
+  const int widx = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (4 * widx >= rows) return;
+  const int mine = 4 * widx + row_index();
+  const int row = min(rows - 1, mine);
+  RNum<QN> Nn, y, tv, z;
+  rn_load(Nn, cd.Nn);
+  rn_load_n(y, Y + (size_t)row * cd.h, cd.h);
+  rn_load_n(tv, T + (size_t)row * cd.h, cd.h);
+  rn_mont_mul(z, tv, y, Nn, cd.nprime);  // z = t (K mod N) mod N
+  // N z: the limbs of z (broadcast from their lane) times N, N shifted up one limb per step
+  RNum<Q> acc, Nsh, k, M2;
+  rn_zero(acc);
+  rn_load(Nsh, cd.NP);
+  uint64_t pend = 0;
+  for (int src = 0; src < 16; ++src) {
+    const int addr = row_src_addr(src);
+    uint32_t zl[QN];
+#pragma unroll
+    for (int jj = 0; jj < QN; ++jj) zl[jj] = row_pick(addr, z.v[jj]);
+#pragma unroll
+    for (int jj = 0; jj < QN; ++jj) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const uint64_t t = (uint64_t)zl[jj] * Nsh.v[j] + acc.v[j] + c;
+        acc.v[j] = (uint32_t)t;
+        c = (uint32_t)(t >> 32);
+      }
+      pend += c;
+      const uint32_t in = row_from_prev(Nsh.v[Q - 1]);
+#pragma unroll
+      for (int j = Q - 1; j > 0; --j) Nsh.v[j] = Nsh.v[j - 1];
+      Nsh.v[0] = in;
+    }
+  }
+  (void)rn_resolve(acc, pend);  // N z < N^2
+  rn_load(M2, cd.N2);
+  rn_load_n(k, Kp + (size_t)row * cd.L, cd.L);
+  uint64_t ovf;
+  if (scaled) {  // K = K' 2^{-32} mod N^2
+    uint64_t kc = 0;
+    rn_redc_step(k, kc, M2, cd.m2prime);
+    ovf = rn_resolve(k, kc);
+    rn_cond_sub(k, ovf, M2);
+  }
+  uint32_t carry = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const uint64_t sum = (uint64_t)acc.v[j] + k.v[j] + carry;
+    acc.v[j] = (uint32_t)sum;
+    carry = (uint32_t)(sum >> 32);
+  }
+  ovf = rn_resolve(acc, (uint64_t)carry);
+  rn_cond_sub(acc, ovf, M2);
+  if (mine < rows) rn_store_n(C + (size_t)row * cd.L, acc, cd.L);
+}
+
 void launch_compress_offset(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Y,
                             const uint32_t* T, int rows, uint32_t* C, hipStream_t s, bool scaled) {
   if (rows <= 0) return;
+  const int sc = scaled ? 1 : 0;
+  // four rows per wavefront while that still leaves several wavefronts per SIMD
+  if (rows >= 16384) {
+    const int blocks = ((rows + 3) / 4 + 3) / 4;
+    switch (cd.P) {
+      case 1: compress_offset_quad_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, sc); break;
+      case 2: compress_offset_quad_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, sc); break;
+      case 3: compress_offset_quad_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, sc); break;
+      case 4: compress_offset_quad_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, sc); break;
+    }
+    return;
+  }
   const int blocks = (rows + 3) / 4;
   switch (cd.P) {
-    case 1: compress_offset_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, scaled ? 1 : 0); break;
-    case 2: compress_offset_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, scaled ? 1 : 0); break;
-    case 3: compress_offset_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, scaled ? 1 : 0); break;
-    case 4: compress_offset_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, scaled ? 1 : 0); break;
+    case 1: compress_offset_kernel<1, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, sc); break;
+    case 2: compress_offset_kernel<2, 1><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, sc); break;
+    case 3: compress_offset_kernel<3, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, sc); break;
+    case 4: compress_offset_kernel<4, 2><<<blocks, 256, 0, s>>>(cd, Kp, Y, T, rows, C, sc); break;
   }
 }
 

@@ -11,10 +11,12 @@
 // entries each) costs a larger table and saves a quarter of the row products.  Any order of
 // the multiplications gives the same residue.
 //
-// One wavefront computes one row; every value stays in Montgomery form (x R mod N^2) until
-// the final conversion, which stores K'_j = K_j 2^32 mod N^2 (the form the online combine
-// consumes; pir_get_client_hint converts back to K_j).
+// One wavefront computes one row (four rows, one per 16-lane row, when there are many rows);
+// every value stays in Montgomery form (x R mod N^2) until the final conversion, which stores
+// K'_j = K_j 2^32 mod N^2 (the form the online combine consumes; pir_get_client_hint converts
+// back to K_j).
 #include "internal.h"
+#include "rownum.h"
 #include "wavenum.h"
 
 namespace zp {
@@ -93,49 +95,45 @@ __global__ __launch_bounds__(256) void hint_rows_kernel(ClientDev cd, const uint
   wn_store_n(K + (size_t)row * cd.L, acc, cd.L);
 }
 
-// Two rows per wavefront: the same products as hint_rows_kernel, with the two rows'
-// Montgomery chains interleaved (mont_mul2).  A zero digit multiplies by R mod N^2, the
-// Montgomery form of 1, so both chains stay in step.  With an odd row count the last wave
-// computes its single row twice and stores it once.
+// Four rows per wavefront, one per 16-lane row (rownum.h): the same products as
+// hint_rows_kernel, each row with its own table entries.  A zero digit multiplies by R mod N^2,
+// the Montgomery form of 1, so the four rows stay in step.  When nrows is not a multiple of
+// four, the last wavefront's spare rows repeat its last row and store nothing.
 template <int P>
-__global__ __launch_bounds__(256) void hint_rows_pair_kernel(ClientDev cd, const uint32_t* __restrict__ H,
+__global__ __launch_bounds__(256) void hint_rows_quad_kernel(ClientDev cd, const uint32_t* __restrict__ H,
                                                              int n, const uint32_t* __restrict__ rowlist,
                                                              int nrows, const uint32_t* __restrict__ table,
                                                              int wbits, uint32_t* __restrict__ K) {
   constexpr int S = 64 * P;
+  constexpr int Q = 4 * P;  // limbs per lane, S = 16 Q
   const int widx = wave_index();
-  if (2 * widx >= nrows) return;
+  if (4 * widx >= nrows) return;
+  const int mine = 4 * widx + row_index();
+  const int i = min(nrows - 1, mine);
+  const int row = rowlist ? (int)rowlist[i] : i;
   const int windows = (32 + wbits - 1) / wbits;
   const uint32_t digits = (1u << wbits) - 1;
-  const int i1 = 2 * widx, i2 = min(nrows - 1, 2 * widx + 1);
-  const int row1 = rowlist ? (int)rowlist[i1] : i1;
-  const int row2 = rowlist ? (int)rowlist[i2] : i2;
-  WNum<P> M, one, acc1, acc2, b1, b2;
-  wn_load(M, cd.N2);
-  wn_load(one, cd.R1);  // Montgomery form of 1
-  acc1 = one;
-  acc2 = one;
-  const uint32_t* h1 = H + (size_t)row1 * n;
-  const uint32_t* h2 = H + (size_t)row2 * n;
+  RNum<Q> M, one, acc, b;
+  rn_load(M, cd.N2);
+  rn_load(one, cd.R1);  // Montgomery form of 1
+  acc = one;
+  const uint32_t* hrow = H + (size_t)row * n;
   for (int k = 0; k < n; ++k) {
-    const uint32_t e1 = 0u - h1[k], e2 = 0u - h2[k];
+    const uint32_t e = 0u - hrow[k];  // (-H_jk) mod 2^32
     const uint32_t* tk = table + (size_t)k * windows * digits * S;
     for (int w = 0; w < windows; ++w) {
-      const uint32_t d1 = (e1 >> (wbits * w)) & digits;
-      const uint32_t d2 = (e2 >> (wbits * w)) & digits;
-      if (d1 == 0 && d2 == 0) continue;
-      if (d1) wn_load(b1, tk + ((size_t)w * digits + (d1 - 1)) * S); else b1 = one;
-      if (d2) wn_load(b2, tk + ((size_t)w * digits + (d2 - 1)) * S); else b2 = one;
-      mont_mul2(acc1, acc1, b1, acc2, acc2, b2, M, cd.m2prime);
+      const uint32_t d = (e >> (wbits * w)) & digits;
+      if (d != 0) rn_load(b, tk + ((size_t)w * digits + (d - 1)) * S);
+      else b = one;
+      rn_mont_mul(acc, acc, b, M, cd.m2prime);
     }
   }
   // leave Montgomery form scaled by 2^32: acc * 2^32 * R^{-1} = K_j * 2^32 mod N^2
-  WNum<P> two32;
-  wn_zero(two32);
-  if (lane_id() == 1 / P) two32.v[1 % P] = 1;
-  mont_mul2(acc1, acc1, two32, acc2, acc2, two32, M, cd.m2prime);
-  wn_store_n(K + (size_t)row1 * cd.L, acc1, cd.L);
-  if (i2 != i1) wn_store_n(K + (size_t)row2 * cd.L, acc2, cd.L);
+  RNum<Q> two32;
+  rn_zero(two32);
+  if (row_lane() == 0) two32.v[1] = 1;
+  rn_mont_mul(acc, acc, two32, M, cd.m2prime);
+  if (mine < nrows) rn_store_n(K + (size_t)row * cd.L, acc, cd.L);
 }
 
 // The per-row key of the online combine: M'_j = N * (K'_j mod N), with K'_j = K_j 2^32 mod N^2.
@@ -305,14 +303,14 @@ void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int wind
 void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
                       int nrows, const uint32_t* table, int wbits, uint32_t* K, hipStream_t s) {
   if (nrows <= 0) return;
-  // two rows per wavefront while that still leaves several wavefronts per SIMD
+  // four rows per wavefront while that still leaves several wavefronts per SIMD
   if (nrows >= 16384) {
-    const int blocks = ((nrows + 1) / 2 + 3) / 4;
+    const int blocks = ((nrows + 3) / 4 + 3) / 4;
     switch (cd.P) {
-      case 1: hint_rows_pair_kernel<1><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
-      case 2: hint_rows_pair_kernel<2><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
-      case 3: hint_rows_pair_kernel<3><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
-      case 4: hint_rows_pair_kernel<4><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+      case 1: hint_rows_quad_kernel<1><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+      case 2: hint_rows_quad_kernel<2><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+      case 3: hint_rows_quad_kernel<3><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
+      case 4: hint_rows_quad_kernel<4><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, K); break;
     }
     return;
   }

@@ -213,33 +213,6 @@ __device__ __forceinline__ void mont_mul(WNum<P>& out, const WNum<P>& a, const W
   out = t;
 }
 
-// Two independent Montgomery products, a1*b1 and a2*b2 (same modulus), interleaved step by
-// step so that each step's dependency chain overlaps the other's.
-template <int P>
-__device__ __forceinline__ void mont_mul2(WNum<P>& out1, const WNum<P>& a1, const WNum<P>& b1,
-                                          WNum<P>& out2, const WNum<P>& a2, const WNum<P>& b2,
-                                          const WNum<P>& m, uint32_t mprime) {
-  WNum<P> t1, t2;
-  wn_zero(t1);
-  wn_zero(t2);
-  uint64_t c1 = 0, c2 = 0;
-  for (int src = 0; src < 64; ++src) {
-#pragma unroll
-    for (int jj = 0; jj < P; ++jj) {
-      const uint32_t x1 = bcast(a1.v[jj], src);
-      const uint32_t x2 = bcast(a2.v[jj], src);
-      mont_step(t1, c1, x1, b1, m, mprime);
-      mont_step(t2, c2, x2, b2, m, mprime);
-    }
-  }
-  const uint64_t o1 = wn_resolve(t1, c1);
-  wn_cond_sub(t1, o1, m);
-  const uint64_t o2 = wn_resolve(t2, c2);
-  wn_cond_sub(t2, o2, m);
-  out1 = t1;
-  out2 = t2;
-}
-
 // Montgomery multiplication by a number given only through its first `na` limbs
 // (the remaining limbs are zero): skips the zero limbs of a.
 template <int P>

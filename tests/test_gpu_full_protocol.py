@@ -76,6 +76,45 @@ def test_offset_answer_and_combine(native, n_bits, rows, cols, n):
     assert [protocol.extract_combined(cl.sk, x) for x in c_gpu] == want
 
 
+@pytest.mark.parametrize("n_bits", [256, 2048])
+def test_offset_many_rows_four_per_wave(native, n_bits):
+    # 16390 rows take the four-rows-per-wavefront kernels (one row per 16 lanes) for the hint
+    # and the combine, the last wavefront holding two rows; every row matches the oracle.
+    rows, cols, n = 16390, 24, 3
+    log(f"full protocol, four rows per wavefront: N {n_bits} rows {rows}")
+    inst = make_instance(cfg=975 + n_bits, rows=rows, cols=cols, n=n, n_bits=n_bits,
+                         encrypt_secret=False, zero_row=rows - 1)
+    cl = inst.clients[0]
+    N_limbs, ckr, L = client_arrays(cl, n_bits)
+    h = L // 2
+    cko, CKO = _offsets(cl)
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    b = server.answer(inst.D, cl.qu)
+    with Pool(pool_size()) as pool:
+        k_or = oracle_client_hint(cl.ck, E, cl.N, pool=pool)
+    t_or = protocol.offset_answer(b, E, cko, cl.N)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ckr)
+        srv.hint(cid)
+        B = np.zeros((1, rows), np.uint32)
+        srv.answer(cl.qu[None, :], B)
+        T = np.zeros((1, rows, h), np.uint32)
+        srv.offset_answer([cid], CKO[None], B, T)
+        C = np.zeros((1, rows, L), np.uint32)
+        srv.compress_offset([cid], T, C)
+        K = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K)
+    assert limbs_rows_to_ints(K) == [k_or[j] for j in range(rows)]
+    assert limbs_rows_to_ints(T[0]) == t_or
+    # combine_offset's (N+1)^t equals 1 + t N mod N^2 (binomial theorem); the closed form
+    # keeps 16390 rows of 2048-bit exponents off the CPU, and a few rows use the oracle itself
+    N2 = cl.N * cl.N
+    c_gpu = limbs_rows_to_ints(C[0])
+    assert c_gpu == [k_or[j] * (1 + t_or[j] * cl.N) % N2 for j in range(rows)]
+    for j in (0, 1, rows // 2, rows - 2, rows - 1):
+        assert c_gpu[j] == protocol.combine_offset(k_or[j], t_or[j], cl.N)
+
+
 def test_offset_answer_extremes(native):
     # ck_o entries at 0, N - 1 and 2^(32h) - 1 (the largest the layout holds), E rows from an
     # all-zero and an all-255 database row, b at 0 and 2^32 - 1.

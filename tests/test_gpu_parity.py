@@ -338,10 +338,10 @@ def test_read_probe(native):
     assert st == native.PIR_EINVAL
 
 
-def test_hint_two_rows_per_wave_odd_count(native):
-    # 16385 rows take the two-rows-per-wavefront hint kernel, the last wavefront holding a
-    # single row, and the 11-bit window table (a pir_hint over few rows takes 8-bit windows);
-    # every row of K matches the oracle.
+def test_hint_four_rows_per_wave_ragged_count(native):
+    # 16385 rows take the four-rows-per-wavefront hint kernel (one row per 16 lanes), the last
+    # wavefront holding a single row, and the 11-bit window table (a pir_hint over few rows
+    # takes the one-row kernel and 8-bit windows); every row of K matches the oracle.
     rows, cols, n, n_bits = 16385, 64, 4, 256
     inst = make_instance(cfg=931, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False, zero_row=rows - 1)
     cl = inst.clients[0]
