@@ -173,7 +173,7 @@ pir_status check_key(pir_compressor* c) {
 
 // Parts per ciphertext: enough wavefronts to fill the GPU when few ciphertexts are compressed.
 int choose_parts(uint32_t rows, uint32_t n) {
-  const long long target = 8192;
+  const long long target = zp::kQuadItems;
   long long p = (target + rows - 1) / rows;
   p = std::min<long long>(p, 256);
   p = std::min<long long>(p, std::max<uint32_t>(1, n / 4));

@@ -176,6 +176,8 @@ struct LweBatch {
 };
 // parts > 1: each ciphertext's n bases are split over `parts` waves whose partial products
 // (Montgomery form, S limbs each) go to Part (rows x parts); otherwise X gets the result.
+// (rows x parts) work items; from kQuadItems items on, four items share a wavefront.
+constexpr long long kQuadItems = 16384;
 void launch_compress_lwe(const ClientDev& cd, const LweBatch& lb, const uint32_t* table, int parts,
                          uint32_t* Part, uint32_t* X, hipStream_t s);
 // Multiplies groups of `fan` consecutive partial products (parts per row -> ceil(parts/fan));

@@ -16,6 +16,7 @@
 // Packed compression keys (Alg. 9, delta = 2^dbits): ck[it+j] = pck_i^(delta^(t-1-j)), i.e.
 // dbits (t-1-j) Montgomery squarings of pck_i.
 #include "internal.h"
+#include "rownum.h"
 #include "wavenum.h"
 
 namespace zp {
@@ -108,6 +109,79 @@ __global__ __launch_bounds__(256) void compress_lwe_kernel(ClientDev cd, LweBatc
   }
 }
 
+// x <- x (1 + b N) mod N^2 per row, x in Montgomery form (the row layout of times_enc_b).
+template <int Q>
+__device__ __forceinline__ void rn_times_enc_b(const ClientDev& cd, RNum<Q>& x, uint64_t b,
+                                               const RNum<Q>& M) {
+  RNum<Q> f, Nsh;
+  rn_zero(f);
+  if (row_lane() == 0) f.v[0] = 1;
+  rn_load(Nsh, cd.NP);
+  uint64_t pend = 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {  // f += b_i N 2^(32 i)
+    const uint32_t bi = (uint32_t)(b >> (32 * i));
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const uint64_t t = (uint64_t)bi * Nsh.v[j] + f.v[j] + c;
+      f.v[j] = (uint32_t)t;
+      c = (uint32_t)(t >> 32);
+    }
+    pend += c;
+    const uint32_t in = row_from_prev(Nsh.v[Q - 1]);
+#pragma unroll
+    for (int j = Q - 1; j > 0; --j) Nsh.v[j] = Nsh.v[j - 1];
+    Nsh.v[0] = in;
+  }
+  (void)rn_resolve(f, pend);  // 1 + b N < N^2
+  rn_mont_mul(x, x, f, M, cd.m2prime);
+}
+
+// compress_lwe_kernel with four work items (ciphertext, part) per wavefront, one per 16-lane
+// row (rownum.h).  Every row runs the longest part's base count; a row past its own range
+// multiplies by R mod N^2 (the Montgomery form of 1).  Spare rows of the last wavefront repeat
+// its last item and store nothing.
+template <int P>
+__global__ __launch_bounds__(256) void compress_lwe_quad_kernel(ClientDev cd, LweBatch lb,
+                                                                const uint32_t* __restrict__ table,
+                                                                int parts, uint32_t* __restrict__ Part,
+                                                                uint32_t* __restrict__ X) {
+  constexpr int S = 64 * P;
+  constexpr int Q = 4 * P;
+  const int items = lb.rows * parts;
+  const int widx = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (4 * widx >= items) return;
+  const int mine = 4 * widx + row_index();
+  const int item = min(items - 1, mine);
+  const int row = item / parts, part = item - row * parts;
+  const int k0 = (int)((long long)lb.n * part / parts);
+  const int k1 = (int)((long long)lb.n * (part + 1) / parts);
+  const int span = (lb.n + parts - 1) / parts;  // the longest part, the same for every row
+  RNum<Q> M, one, acc, b;
+  rn_load(M, cd.N2);
+  rn_load(one, cd.R1);
+  acc = one;
+  for (int i = 0; i < span; ++i) {
+    const int k = k0 + i;
+    const bool live = k < k1;
+    const uint64_t e = live ? lw_exponent(lb, row, k) : 0;
+    const uint32_t* tk = table + (size_t)(live ? k : 0) * lb.windows * kDigits * S;
+    for (int w = 0; w < lb.windows; ++w) {
+      const uint32_t d = (uint32_t)(e >> (kWindowBits * w)) & kDigits;
+      if (d != 0) rn_load(b, tk + ((size_t)w * kDigits + (d - 1)) * S);
+      else b = one;
+      rn_mont_mul(acc, acc, b, M, cd.m2prime);
+    }
+  }
+  if (parts == 1) {
+    rn_times_enc_b<Q>(cd, acc, lw_b(lb, row), M);
+    if (mine < items) rn_store_n(X + (size_t)row * cd.L, acc, cd.L);
+  } else if (mine < items) {
+    rn_store_n(Part + (size_t)item * S, acc, S);
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void reduce_parts_kernel(ClientDev cd, LweBatch lb,
                                                            const uint32_t* __restrict__ Part,
@@ -165,9 +239,15 @@ __global__ __launch_bounds__(256) void unpack_keys_kernel(ClientDev cd, const ui
 
 void launch_compress_lwe(const ClientDev& cd, const LweBatch& lb, const uint32_t* table, int parts,
                          uint32_t* Part, uint32_t* X, hipStream_t s) {
-  const long long waves = (long long)lb.rows * parts;
-  if (waves <= 0) return;
-  const int blocks = (int)((waves + 3) / 4);
+  const long long items = (long long)lb.rows * parts;
+  if (items <= 0) return;
+  // four items per wavefront once that still leaves about four wavefronts per SIMD
+  if (items >= kQuadItems) {
+    const int blocks = (int)(((items + 3) / 4 + 3) / 4);
+    ZP_BY_P(compress_lwe_quad_kernel, blocks, cd, lb, table, parts, Part, X)
+    return;
+  }
+  const int blocks = (int)((items + 3) / 4);
   ZP_BY_P(compress_lwe_kernel, blocks, cd, lb, table, parts, Part, X)
 }
 

@@ -109,6 +109,31 @@ def test_lwe_compress_many_rows_one_wave_each(native):
     assert got[0] == (1 + int(B[0]) * sk.pk.N) % sk.pk.N ** 2
 
 
+@pytest.mark.parametrize("rows,n", [(16390, 6), (400, 400)])
+def test_lwe_compress_four_items_per_wave(native, rows, n):
+    # From 16384 work items (ciphertext x part) on, four share a wavefront (one per 16 lanes):
+    # 16390 ciphertexts of one part each, and 400 ciphertexts cut into 41 parts of 9 or 10
+    # bases (then reduced in a tree); every ciphertext matches the oracle.
+    q, p, N_bits = 1 << 64, 16, 256
+    log(f"lwe compress, four items per wave: rows {rows} n {n}")
+    sk = _key(975 + n, N_bits)
+    g = np.random.default_rng(975 + n)
+    s = [int(x) for x in g.integers(0, q, size=n, dtype=np.uint64)]
+    ck = _enc_key(sk, s, 975 + n)
+    A = g.integers(0, 1 << 64, size=(rows, n), dtype=np.uint64)
+    B = g.integers(0, 1 << 64, size=rows, dtype=np.uint64)
+    A[0] = 0
+    N_limbs, L = _limbs(sk, N_bits)
+    with native.Compressor(n, q, N_limbs, N_bits, ck=wl.ints_to_limbs(ck, L)) as cmp:
+        X = np.zeros((rows, L), np.uint32)
+        cmp.compress_lwe(A, B, X)
+    got = limbs_rows_to_ints(X)
+    with Pool(pool_size()) as pool:
+        want = pool.map(_compress_job, [(ck, [int(x) for x in A[r]], int(B[r]), q, sk.pk.N) for r in range(rows)],
+                        chunksize=256)
+    assert got == want
+
+
 def test_table2_parameters(native):
     """Table 2's LWE parameter sets (n, q) = (630, 2^64) and (1305, 2^11) with a 3072-bit
     modulus: two ciphertexts each, bit-exact, and decryption recovers the message."""
