@@ -171,12 +171,13 @@ pir_status check_key(pir_compressor* c) {
   return PIR_OK;
 }
 
-// Parts per ciphertext: enough wavefronts to fill the GPU when few ciphertexts are compressed.
+// Parts per ciphertext: enough work items to fill the GPU when few ciphertexts are
+// compressed, down to one base per part (a lone ciphertext's latency is then the window
+// products of one base plus a tree of fan-in kFan).
 int choose_parts(uint32_t rows, uint32_t n) {
   const long long target = zp::kQuadItems;
   long long p = (target + rows - 1) / rows;
-  p = std::min<long long>(p, 256);
-  p = std::min<long long>(p, std::max<uint32_t>(1, n / 4));
+  p = std::min<long long>(p, std::max<uint32_t>(1, n));
   return (int)std::max<long long>(1, p);
 }
 
@@ -217,7 +218,7 @@ pir_status run(pir_compressor* c, zp::LweBatch lb, uint32_t* X, uint32_t ptr_fla
     ZC_TRY(c->grow(c->s_part[1], c->s_part_bytes[1], pbytes));
     zp::launch_compress_lwe(cd, lb, c->table, parts, (uint32_t*)c->s_part[0], dX, st);
     int cur = 0, p = parts;
-    constexpr int kFan = 8;
+    constexpr int kFan = 4;
     while (true) {
       const int outs = (p + kFan - 1) / kFan;
       zp::launch_reduce_parts(cd, lb, (const uint32_t*)c->s_part[cur], p, kFan,
