@@ -119,6 +119,13 @@ constexpr int kMaxBlockK = 65536; // K bytes per block (keeps MFMA partials with
 // The grid is one-dimensional and XCD-aware: workgroup L runs on XCD L mod 8, and each XCD
 // takes every column block and K range of one row block in turn (row blocks x, x+8, ...), so
 // the D tile they share is read from HBM once and then served from that XCD's L2.
+// Steps by which the X tile's global loads run ahead of its use (kNX = x_ahead - 1 register
+// buffers): three with two or more D steps in flight, two with one.
+constexpr int x_ahead(int waves, int depth, int mr, int kb, int pl) {
+  (void)waves; (void)mr; (void)kb; (void)pl;
+  return depth >= 2 ? 3 : 2;
+}
+
 template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide>
 __device__ __forceinline__ void gemm_planes_body(
     const uint8_t* __restrict__ D, int rows, int cols, int pitch, const int8_t* __restrict__ Xs,
@@ -178,8 +185,10 @@ __device__ __forceinline__ void gemm_planes_body(
   // and stashed into LDS one step ahead.  With two or more D steps in flight, X runs three
   // steps ahead and each step issues its X load before its D load: the in-order load counter
   // then lets the wait for X(i+1) pass while the younger D loads are still in flight.
-  constexpr int kXA = kDepth >= 2 ? 3 : 2;
+  constexpr int kXA = x_ahead(kW, kDepth, kMR, kKB, kPl);
   constexpr int kNX = kXA - 1;
+  static_assert(kDepth == 1 || (kDepth % 2 == 0 ? kDepth : 2 * kDepth) % kNX == 0,
+                "X buffers must be static in the unrolled trip");
   // unroll so that ring slots and X buffers are static register indices
   constexpr int kU = kDepth == 1 ? 1 : (kDepth % 2 == 0 ? kDepth : 2 * kDepth);
   u32x4 ring[kDepth][kMR][kSl];
@@ -214,11 +223,12 @@ __device__ __forceinline__ void gemm_planes_body(
   // The prologue issues its loads in the steady state's order for the same reason.
   const int last = nsteps - 1;
   load_x(0, 0);
-  if constexpr (kXA == 3) load_x(1, min(1, last));
+#pragma unroll
+  for (int a = 1; a < kNX; ++a) load_x(a, min(a, last));
   load_d(0, 0);
   if constexpr (kDepth >= 2) load_d(1, min(1, last));
   stash(0, 0);
-  load_x((kXA - 1) % kNX, min(kXA - 1, last));
+  load_x(0, min(kNX, last));  // X(kXA - 1) into the buffer just stashed
 #pragma unroll
   for (int d = 2; d < kDepth; ++d) load_d(d, min(d, last));
   lds_barrier();

@@ -15,6 +15,7 @@
 // y_k = ck_o,k 2^96 mod N, so that a reduction kernel can fold the byte positions into limbs,
 // add b_j 2^96 and finish modulo N with three Montgomery reduction steps (see below).
 #include "internal.h"
+#include "rownum.h"
 #include "wavenum.h"
 
 namespace zp {
@@ -172,6 +173,28 @@ __global__ __launch_bounds__(256) void offset_terms_kernel(ClientDev cd, const u
   wn_store_n(Tmp + (size_t)w * cd.h, x, cd.h);
 }
 
+// offset_terms_kernel with four rows per wavefront, one per 16-lane row (rownum.h; QN = 4 PN
+// limbs per lane, the same R_N).  Spare rows of the last wavefront repeat its last row and
+// store nothing.
+template <int PN>
+__global__ __launch_bounds__(256) void offset_terms_quad_kernel(ClientDev cd, const uint32_t* __restrict__ T,
+                                                                int rows, int ell,
+                                                                const uint32_t* __restrict__ PJ,
+                                                                uint32_t* __restrict__ Tmp) {
+  constexpr int QN = 4 * PN;
+  const int widx = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (4 * widx >= rows) return;
+  const int mine = 4 * widx + row_index();
+  const int w = min(rows - 1, mine);
+  const int j = w % ell;
+  RNum<QN> Nn, c, x;
+  rn_load(Nn, cd.Nn);
+  rn_load(c, PJ + (size_t)j * 64 * PN);
+  rn_load_n(x, T + (size_t)w * cd.h, cd.h);
+  rn_mont_mul(x, x, c, Nn, cd.nprime);
+  if (mine < rows) rn_store_n(Tmp + (size_t)w * cd.h, x, cd.h);
+}
+
 template <int PN>
 __global__ __launch_bounds__(256) void offset_sum_kernel(ClientDev cd, const uint32_t* __restrict__ Tmp,
                                                          int rows, int ell, uint32_t* __restrict__ Tg) {
@@ -201,11 +224,16 @@ void launch_offset_pack(const ClientDev& cd, const uint32_t* T, int rows, int el
                         const uint32_t* PJ, uint32_t* Tmp, uint32_t* Tg, hipStream_t s) {
   if (rows <= 0) return;
   const int groups = (rows + ell - 1) / ell;
+  // four rows per wavefront while that still leaves several wavefronts per SIMD
+  const bool quad = rows >= 16384;
+  const int tblocks = quad ? ((rows + 3) / 4 + 3) / 4 : (rows + 3) / 4;
   if (cd.PN == 1) {
-    offset_terms_kernel<1><<<(rows + 3) / 4, 256, 0, s>>>(cd, T, rows, ell, PJ, Tmp);
+    if (quad) offset_terms_quad_kernel<1><<<tblocks, 256, 0, s>>>(cd, T, rows, ell, PJ, Tmp);
+    else offset_terms_kernel<1><<<tblocks, 256, 0, s>>>(cd, T, rows, ell, PJ, Tmp);
     offset_sum_kernel<1><<<(groups + 3) / 4, 256, 0, s>>>(cd, Tmp, rows, ell, Tg);
   } else {
-    offset_terms_kernel<2><<<(rows + 3) / 4, 256, 0, s>>>(cd, T, rows, ell, PJ, Tmp);
+    if (quad) offset_terms_quad_kernel<2><<<tblocks, 256, 0, s>>>(cd, T, rows, ell, PJ, Tmp);
+    else offset_terms_kernel<2><<<tblocks, 256, 0, s>>>(cd, T, rows, ell, PJ, Tmp);
     offset_sum_kernel<2><<<(groups + 3) / 4, 256, 0, s>>>(cd, Tmp, rows, ell, Tg);
   }
 }

@@ -265,3 +265,29 @@ def test_packed_full_protocol(native, n_bits, rows, ell):
     for g in range(G):
         got += protocol.extract_packed(cl.sk, kg_or[g], tg_or[g], min(ell, rows - g * ell), gamma)
     assert got == inst.D[:, cl.col].tolist()
+
+
+def test_packed_offset_answer_many_rows(native):
+    """16390 rows: the packed offset answer's terms 2^(tj) t mod N take four rows per
+    wavefront; every group's t_g matches the oracle (the group keys are not needed for it)."""
+    rows, cols, n, n_bits, ell = 16390, 24, 3, 1024, 13
+    log(f"packed offset answer, four rows per wavefront: rows {rows}")
+    inst = make_instance(cfg=988, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False)
+    cl = inst.clients[0]
+    N_limbs, ckr, L = client_arrays(cl, n_bits)
+    h = L // 2
+    cko, CKO = _offsets(cl)
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    b = server.answer(inst.D, cl.qu)
+    t_or = protocol.offset_answer(b, E, cko, cl.N)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ckr)
+        srv.hint(cid)
+        srv.set_packing(cid, ell)
+        info = srv.packing_info(cid)
+        G, gamma = info["groups"], 1 << info["log2_gamma"]
+        B = np.zeros((1, rows), np.uint32)
+        srv.answer(cl.qu[None, :], B)
+        Tg = np.zeros((1, G, h), np.uint32)
+        srv.offset_answer_packed([cid], CKO[None], B, Tg)
+    assert limbs_rows_to_ints(Tg[0]) == protocol.offset_answer_packed(t_or, ell, gamma, cl.N)
