@@ -61,6 +61,46 @@ __global__ __launch_bounds__(256) void build_table_kernel(ClientDev cd,
   }
 }
 
+// build_table_kernel with four bases per wavefront (k = 4 kq .. 4 kq + 3, one per 16-lane
+// row, rownum.h) sharing the window w and the segment, so every loop is uniform across the
+// wavefront.  Spare rows past the last base repeat it and store nothing.
+template <int P>
+__global__ __launch_bounds__(256) void build_table_quad_kernel(ClientDev cd,
+                                                               const uint32_t* __restrict__ ck, int n,
+                                                               int windows, int wbits, int segs,
+                                                               uint32_t* __restrict__ table) {
+  constexpr int S = 64 * P;
+  constexpr int Q = 4 * P;
+  const int widx = wave_index();
+  const int nq = (n + 3) / 4;
+  if (widx >= nq * windows * segs) return;
+  const int seg = widx % segs, rest = widx / segs;
+  const int w = rest % windows, kq = rest / windows;
+  const int kmine = 4 * kq + row_index();
+  const int k = min(n - 1, kmine);
+  const int digits = (1 << wbits) - 1;
+  const int v0 = 1 + (int)((long long)digits * seg / segs);
+  const int v1 = (int)((long long)digits * (seg + 1) / segs);  // inclusive
+  RNum<Q> M, RR, x, cur;
+  rn_load(M, cd.N2);
+  rn_load(RR, cd.RR);
+  rn_load_n(x, ck + (size_t)k * cd.L, cd.L);
+  rn_mont_mul(x, x, RR, M, cd.m2prime);  // ck * R mod N^2
+  for (int t = 0; t < wbits * w; ++t) rn_mont_mul(x, x, x, M, cd.m2prime);
+  cur = x;
+  for (int bit = 30 - __builtin_clz((unsigned)v0); bit >= 0; --bit) {
+    rn_mont_mul(cur, cur, cur, M, cd.m2prime);
+    if ((v0 >> bit) & 1) rn_mont_mul(cur, cur, x, M, cd.m2prime);
+  }
+  const bool live = kmine < n;
+  uint32_t* T = table + ((size_t)k * windows + w) * digits * S;
+  if (live) rn_store_n(T + (size_t)(v0 - 1) * S, cur, S);
+  for (int v = v0 + 1; v <= v1; ++v) {
+    rn_mont_mul(cur, cur, x, M, cd.m2prime);
+    if (live) rn_store_n(T + (size_t)(v - 1) * S, cur, S);
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void hint_rows_kernel(ClientDev cd, const uint32_t* __restrict__ H,
                                                         int n, const uint32_t* __restrict__ rowlist,
@@ -289,8 +329,20 @@ void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int wind
                         uint32_t* table, hipStream_t s, int wbits) {
   // wide windows: four segments per (base, window) keep enough wavefronts in flight
   const int segs = wbits > 8 ? 4 : 1;
+  if (n <= 0 || windows <= 0) return;
+  // four bases per wavefront while that still leaves several wavefronts per SIMD
+  const long long quad_waves = (long long)((n + 3) / 4) * windows * segs;
+  if (quad_waves >= 3072) {
+    const int blocks = (int)((quad_waves + 3) / 4);
+    switch (cd.P) {
+      case 1: build_table_quad_kernel<1><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
+      case 2: build_table_quad_kernel<2><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
+      case 3: build_table_quad_kernel<3><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
+      case 4: build_table_quad_kernel<4><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
+    }
+    return;
+  }
   const int waves = n * windows * segs;
-  if (waves <= 0) return;
   const int blocks = (waves + 3) / 4;
   switch (cd.P) {
     case 1: build_table_kernel<1><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;

@@ -402,3 +402,32 @@ def test_empty_and_degenerate_inputs(native):
                            ck=wl.ints_to_limbs(wl.uniform_ciphertexts(934, 0, 4, N), 16)) as cmp:
         X = np.zeros((0, 16), np.uint32)
         cmp.compress_lwe(np.zeros((0, 4), np.uint32), np.zeros(0, np.uint32), X)
+
+
+def test_hint_wide_table_against_narrow(native):
+    # n = 1024 bases: over 16385 rows the hint builds the 11-bit table with four bases per
+    # wavefront and takes four rows per wavefront; in chunks of 4096 rows it takes the 8-bit
+    # table, one base and one row per wavefront.  The two K agree on every row, and sampled rows
+    # match the oracle.
+    rows, cols, n, n_bits = 16385, 16, 1024, 256
+    inst = make_instance(cfg=932, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False, zero_row=7)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, n_bits)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ck)
+        srv.hint(cid)
+        assert srv.hint_window_bits(cid) == 11
+        K11 = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K11)
+        for r0 in range(0, rows, 4096):
+            srv.hint(cid, rows=np.arange(r0, min(rows, r0 + 4096), dtype=np.uint32))
+            assert srv.hint_window_bits(cid) == 8
+        K8 = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K8)
+    assert np.array_equal(K11, K8)
+    sample = [0, 7, 1, 4095, 4096, 8191, 12345, rows - 1]
+    E = server.exponents(server.global_hint(inst.D, inst.A, rows=sample))
+    with Pool(pool_size()) as pool:
+        K_or = oracle_client_hint(cl.ck, E, cl.N, pool=pool)
+    assert [wl.limbs_to_int(K11[j]) for j in sample] == [K_or[i] for i in range(len(sample))]
+    assert K_or[1] == 1
