@@ -45,12 +45,37 @@ def montmul_macs(n_limbs: int) -> int:
 # WRITE_SIZE (calibrated on a plain 1 GiB device copy), keyed by the SHA-256 of the matvec
 # source they were taken on: a changed kernel reports null until the counters are re-taken.
 MATVEC_TRAFFIC = {"3942b980745b36ab": 1083180014}
+# The same for the one-call step's matvec (matvec_part_kernel, in answer.hip).
+STEP_TRAFFIC = {"bb3e08fa73cd3839": 1076962478}
 
 
-def matvec_source_hash() -> str:
+def source_hash(name: str) -> str:
     import hashlib
-    path = os.path.join(ROOT, "paper_2603_09190_amd", "csrc", "matvec.hip")
+    path = os.path.join(ROOT, "paper_2603_09190_amd", "csrc", name)
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def timed_ms(fn, reps: int) -> float:
+    """Milliseconds per call of fn over reps back-to-back calls, synchronized on both sides."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def kernel_avg_ms(srv, fn, reps: int, names) -> dict:
+    """Average launch duration (ms) of each named kernel over reps calls of fn, from the events
+    the library records around its launches (a separate pass: the events delay the launches
+    that follow them, so timed regions run without them)."""
+    srv.profile(True)
+    for _ in range(reps):
+        fn()
+    got = {nm: srv.profile_read(nm) for nm in names}
+    srv.profile(False)
+    return {nm: ms / max(1, cnt) for nm, (ms, cnt) in got.items()}
 
 
 def log(msg: str) -> None:
@@ -172,28 +197,50 @@ def main() -> int:
     B1 = torch.zeros((1, rows), dtype=torch.int32, device=dev)
     C1 = torch.zeros((1, rows, L), dtype=torch.int32, device=dev)
 
+    q1v = q1[0]
+    B2 = torch.zeros(rows, dtype=torch.int32, device=dev)
+    C2 = torch.zeros((rows, L), dtype=torch.int32, device=dev)
+
     def step():
+        # Alg. 5 Response and the Sec. 4.3 Paillier addition in one call, pir_answer_compress:
+        # two launches (the matvec builds the query's byte planes itself and stores per-segment
+        # partial sums; the combine adds them up into b and forms c = K (1 + bN))
+        srv.answer_compress(q1v, cid, B2, C2)
+
+    def step3():
+        # the same results from pir_answer (pack + matvec) and pir_compress: three launches
         srv.answer(q1, B1, native.PATH_MATVEC)
         srv.compress([cid], B1, C1)
 
     for _ in range(args.warmup):
         step()
+        step3()
     torch.cuda.synchronize()
 
-    # timed region: exactly `steps` steps, synchronized on both sides
-    srv.profile(True)
+    # timed region: exactly `steps` steps, synchronized on both sides (no profiling events in
+    # it: an event recorded between two launches delays the second)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    mv_ms, mv_n = srv.profile_read("matvec")
-    cp_ms, cp_n = srv.profile_read("compress")
-    srv.profile(False)
     ms_per_step = elapsed * 1e3 / args.steps
     db_bytes = rows * cols
     value = db_bytes / (elapsed / args.steps) / 1e9
+    # per-launch durations from a separate pass with the library's event timing
+    ka = kernel_avg_ms(srv, step, max(8, args.steps // 4), ["step_matvec", "step_combine"])
+    mv_avg_ms, cp_avg_ms = ka["step_matvec"], ka["step_combine"]
+
+    # the three-launch form
+    step3_ms = timed_ms(step3, args.steps)
+    k3 = kernel_avg_ms(srv, step3, max(8, args.steps // 4), ["matvec", "compress"])
+    torch.cuda.synchronize()
+    same_step = bool(torch.equal(B1[0], B2) and torch.equal(C1[0], C2))
+    three_launch = {"ms_per_step": round(step3_ms, 4), "db_gbs": round(db_bytes / (step3_ms * 1e-3) / 1e9, 3),
+                    "matvec_kernel_avg_us": round(k3["matvec"] * 1e3, 2),
+                    "compress_kernel_avg_us": round(k3["compress"] * 1e3, 2),
+                    "bit_identical_to_one_call": same_step}
 
     # per-step latency distribution (each step synchronized on its own)
     lat = []
@@ -219,15 +266,8 @@ def main() -> int:
     for _ in range(3):
         srv.answer(Qt, Bb, native.PATH_MFMA)
     reps = max(5, args.steps // 4)
-    srv.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        srv.answer(Qt, Bb, native.PATH_MFMA)
-    torch.cuda.synchronize()
-    mfma_ms = (time.perf_counter() - t0) * 1e3 / reps
-    gm_ms, gm_n = srv.profile_read("gemm")
-    srv.profile(False)
+    mfma_ms = timed_ms(lambda: srv.answer(Qt, Bb, native.PATH_MFMA), reps)
+    gm_avg_ms = kernel_avg_ms(srv, lambda: srv.answer(Qt, Bb, native.PATH_MFMA), reps, ["gemm"])["gemm"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(max(2, reps // 4)):
@@ -248,22 +288,17 @@ def main() -> int:
     Cp = torch.zeros((1, G, L), dtype=torch.int32, device=dev)
     for _ in range(3):
         srv.compress_packed([cid], B1, Cp)
-    srv.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    def pk_step():
         srv.answer(q1, B1, native.PATH_MATVEC)
         srv.compress_packed([cid], B1, Cp)
-    torch.cuda.synchronize()
-    pk_step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    pk_ms, pk_n = srv.profile_read("compress")
-    srv.profile(False)
+    pk_step_ms = timed_ms(pk_step, args.steps)
+    pk_avg_ms = kernel_avg_ms(srv, pk_step, max(8, args.steps // 4), ["compress"])["compress"]
     srv.set_packing(cid, 1)
     packed = {"ell": ell, "log2_gamma": pinfo["log2_gamma"], "groups": G,
               "response_bytes": G * L * 4, "unpacked_response_bytes": rows * L * 4,
               "ms_per_step": round(pk_step_ms, 4),
               "db_gbs": round(db_bytes / (pk_step_ms * 1e-3) / 1e9, 3),
-              "compress_kernel_avg_us": round(pk_ms / max(1, pk_n) * 1e3, 2),
+              "compress_kernel_avg_us": round(pk_avg_ms * 1e3, 2),
               "group_key_build_s": round(gk_s, 3)}
 
     # full protocol (Alg. 5): online offset answer t = (b + E.ck_o) mod N after the matvec,
@@ -275,78 +310,55 @@ def main() -> int:
     for _ in range(3):
         srv.answer(q1, B1, native.PATH_MATVEC)
         srv.offset_answer([cid], CKOt, B1, T1)
-    srv.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    def fp_step():
         srv.answer(q1, B1, native.PATH_MATVEC)
         srv.offset_answer([cid], CKOt, B1, T1)
-    torch.cuda.synchronize()
-    fp_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    og_ms, og_n = srv.profile_read("offset_gemm")
-    or_ms, or_n = srv.profile_read("offset")
-    srv.profile(False)
-    srv.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        srv.answer(q1, B1, native.PATH_MATVEC)
-        srv.offset_answer([cid], CKOt, B1, T1)
+
+    def fpc_step():
+        fp_step()
         srv.compress_offset([cid], T1, C1)
-    torch.cuda.synchronize()
-    fpc_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    oc_ms, oc_n = srv.profile_read("compress")
-    srv.profile(False)
+    fp_ms = timed_ms(fp_step, args.steps)
+    fpc_ms = timed_ms(fpc_step, args.steps)
+    ka = kernel_avg_ms(srv, fpc_step, max(8, args.steps // 4), ["offset_gemm", "offset", "compress"])
+    og_avg, or_avg, oc_avg = ka["offset_gemm"], ka["offset"], ka["compress"]
     # with batched compression: one offset answer per group of ell rows
     srv.set_packing(cid, ell)
     Tg = torch.zeros((1, G, h), dtype=torch.int32, device=dev)
     for _ in range(3):
         srv.answer(q1, B1, native.PATH_MATVEC)
         srv.offset_answer_packed([cid], CKOt, B1, Tg)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    def fpp_step():
         srv.answer(q1, B1, native.PATH_MATVEC)
         srv.offset_answer_packed([cid], CKOt, B1, Tg)
-    torch.cuda.synchronize()
-    fpp_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    fpp_ms = timed_ms(fpp_step, args.steps)
     srv.set_packing(cid, 1)
-    og_avg = og_ms / max(1, og_n)
     off_ops = 2.0 * rows * 4 * n * (4 * h + 3)
     full = {"ms_per_step": round(fp_ms, 4), "db_gbs": round(db_bytes / (fp_ms * 1e-3) / 1e9, 3),
             "with_combine_ms_per_step": round(fpc_ms, 4),
             "offset_gemm_kernel_avg_us": round(og_avg * 1e3, 2),
             "offset_gemm_int8_tops": round(off_ops / (og_avg * 1e-3) / 1e12, 1),
             "offset_gemm_frac_of_peak": round(off_ops / (og_avg * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
-            "offset_reduce_kernel_avg_us": round(or_ms / max(1, or_n) * 1e3, 2),
-            "combine_kernel_avg_us": round(oc_ms / max(1, oc_n) * 1e3, 2),
+            "offset_reduce_kernel_avg_us": round(or_avg * 1e3, 2),
+            "combine_kernel_avg_us": round(oc_avg * 1e3, 2),
             "response_bytes": rows * h * 4, "hint_bytes": rows * L * 4,
             "packed": {"ell": ell, "ms_per_step": round(fpp_ms, 4),
                        "db_gbs": round(db_bytes / (fpp_ms * 1e-3) / 1e9, 3),
                        "response_bytes": G * h * 4, "hint_bytes": G * L * 4}}
 
-    # dominant kernel's own duration: 8 queries' matvecs back to back between two events
-    Q8 = Qt[:8].contiguous()
-    B8 = torch.zeros((8, rows), dtype=torch.int32, device=dev)
-    srv.answer(Q8, B8, native.PATH_MATVEC)
-    srv.profile(True)
-    for _ in range(max(2, args.steps // 8)):
-        srv.answer(Q8, B8, native.PATH_MATVEC)
-    mvk_ms, mvk_n = srv.profile_read("matvec")
-    srv.profile(False)
-
-    # roofline of the dominant kernel of the step (the matvec): algorithmic bytes per launch
-    mv_avg_ms = mvk_ms / max(1, mvk_n)
-    cp_avg_ms = cp_ms / max(1, cp_n)
+    # roofline of the dominant kernel of the step (its matvec): algorithmic bytes per launch
+    # over the launch's event-timed duration
     mv_bytes = db_bytes + 4 * cols + 4 * rows
     achieved = mv_bytes / (mv_avg_ms * 1e-3) / 1e9
-    gm_avg_ms = gm_ms / max(1, gm_n)
     mfma_ops = 2.0 * 4 * rows * cols * bsz
-    traffic = MATVEC_TRAFFIC.get(matvec_source_hash()) if (rows, cols) == (32768, 32768) else None
+    traffic = STEP_TRAFFIC.get(source_hash("answer.hip")) if (rows, cols) == (32768, 32768) else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "matvec_seg_kernel<2>", "kernel_avg_us": round(mv_avg_ms * 1e3, 2),
-            "bytes_per_launch": mv_bytes, "step_matvec_event_us": round(mv_ms / max(1, mv_n) * 1e3, 2)}
+            "kernel": "matvec_part_kernel<2>", "kernel_avg_us": round(mv_avg_ms * 1e3, 2),
+            "bytes_per_launch": mv_bytes,
+            "three_launch_matvec": {"kernel": "matvec_seg_kernel<2>",
+                                    "kernel_avg_us": three_launch["matvec_kernel_avg_us"],
+                                    "traffic": MATVEC_TRAFFIC.get(source_hash("matvec.hip"))
+                                    if (rows, cols) == (32768, 32768) else None}}
 
     # the device's streaming-read ceiling: a 1 GiB nontemporal read per launch, timed with
     # events on the same stream
@@ -402,7 +414,8 @@ def main() -> int:
         "p50_ms": round(percentile(lat, 50), 4),
         "p99_ms": round(percentile(lat, 99), 4),
         "answer_only_gbs": round(db_bytes / (ans1_ms * 1e-3) / 1e9, 3),
-        "compress_kernel_avg_us": round(cp_avg_ms * 1e3, 2),
+        "combine_kernel_avg_us": round(cp_avg_ms * 1e3, 2),
+        "three_launch": three_launch,
         "batch32": {"batch": bsz, "ms_per_batch": round(mfma_ms, 4), "ms_per_query": round(mfma_ms / bsz, 5),
                     "per_query_speedup_vs_matvec": round(mv32_ms / mfma_ms, 2),
                     "gemm_kernel_avg_us": round(gm_avg_ms * 1e3, 2),

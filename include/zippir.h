@@ -129,6 +129,18 @@ pir_status pir_compress(pir_server *srv, const uint32_t *client_ids, uint32_t ba
                         const uint32_t *B, uint32_t *C, uint32_t ptr_flags);
 
 /*
+ * One query of one client, answered and combined in one call (Alg. 5 Response, first line,
+ * then the Sec. 4.3 Paillier addition): B = D.Q mod 2^32 and C[j] = K[j] (1 + B[j] N) mod N^2,
+ * the same bits as pir_answer followed by pir_compress.  Q is cols uint32, B rows uint32, C
+ * rows x L uint32.  The device runs two launches instead of three (the query's byte planes are
+ * built inside the matvec, and the per-segment partial sums are added up by the combine).
+ * PIR_EINVAL for an unknown client or a database wider than 262144 columns (use pir_answer and
+ * pir_compress there); PIR_ESTALE as pir_compress.
+ */
+pir_status pir_answer_compress(pir_server *srv, const uint32_t *Q, uint32_t client_id, uint32_t *B,
+                               uint32_t *C, uint32_t ptr_flags);
+
+/*
  * Packed responses: batched compression (Alg. 3, Sec. 3.3; in ZipPIR, Sec. 4.3 "Batched
  * compression for smaller responses").  With packing factor ell, rows g*ell .. g*ell+ell-1
  * share one ciphertext
@@ -279,7 +291,9 @@ pir_status pir_shape(pir_server *srv, uint32_t *rows, uint32_t *cols, uint32_t *
 #define PIR_KERNEL_KEY      5  /* per-row combine key N (K mod N), computed with the hint */
 #define PIR_KERNEL_OFFSET_GEMM 6  /* offset answer: E bytes x offset bytes on int8 MFMA   */
 #define PIR_KERNEL_OFFSET   7  /* offset answer: byte positions -> limbs, + b, mod N     */
-#define PIR_KERNEL_COUNT    8
+#define PIR_KERNEL_STEP_MATVEC  8  /* pir_answer_compress: matvec into segment partials   */
+#define PIR_KERNEL_STEP_COMBINE 9  /* pir_answer_compress: partials -> b, Paillier combine */
+#define PIR_KERNEL_COUNT    10
 pir_status pir_profile(pir_server *srv, int32_t enable);
 pir_status pir_profile_read(pir_server *srv, int32_t kernel, double *total_ms, uint64_t *launches);
 

@@ -61,6 +61,20 @@ void launch_pack_planes_u8(const uint32_t* q, int cols, int pitch, uint8_t* plan
 void launch_matvec(const uint8_t* D, int rows, int pitch, const uint8_t* planes, uint32_t* b,
                    hipStream_t s);
 
+// ---- answer.hip
+// Column segments of the two-launch step (at most 64: one partial per lane of the combine).
+int answer_segments(int pitch);
+// part[j * nseg + s] = row j of D times query q (cols uint32, 16-byte aligned) over column
+// segment s, mod 2^32, for the nseg = answer_segments(pitch) segments; no packing of q and no
+// clearing needed.
+void launch_matvec_part(const uint8_t* D, int rows, int pitch, const uint32_t* q, int cols,
+                        uint32_t* part, hipStream_t s);
+// b_j = sum_s part[j * nseg + s] mod 2^32 (nseg <= 64) and C = K (1 + b N) mod N^2 (rows x L),
+// from K' and M' as launch_compress takes them.
+void launch_combine_parts(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Mp,
+                          const uint32_t* part, int nseg, int rows, uint32_t* b, uint32_t* C,
+                          hipStream_t s);
+
 // ---- gemm_i8.hip
 // Signed byte planes of `ncol` vectors: X element (c, i) is x[c*stride_c + i*stride_i].
 // Xs[(c*4 + b)*pitch + i] = (byte b of X(c,i)) ^ 0x80 for i < cols, 0 beyond.

@@ -114,7 +114,8 @@ struct pir_server {
   };
   std::vector<ProfRecord> prof_ev[PIR_KERNEL_COUNT];
   // growable scratch
-  DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c, s_x, s_xcs, s_w, s_t, s_ys, s_tmp;
+  DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c, s_x, s_xcs, s_w, s_t, s_ys, s_tmp,
+      s_part;
 
   pir_status alloc(void** p, size_t bytes_) {
     *p = nullptr;
@@ -887,6 +888,60 @@ pir_status pir_compress(pir_server* s, const uint32_t* ids, uint32_t batch, cons
   }
   ZP_HIP(hipGetLastError());
   if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(C, dC, cbytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_answer_compress(pir_server* s, const uint32_t* Q, uint32_t id, uint32_t* B,
+                               uint32_t* C, uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !Q || !B || !C) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  ClientState* c = find_client(s, id);
+  if (!c) return fail(PIR_EINVAL, "unknown client id " + std::to_string(id));
+  if (c->stale != 0)
+    return fail(PIR_ESTALE, "client " + std::to_string(id) + " has " + std::to_string(c->stale) +
+                                " stale hint rows");
+  const int nseg = zp::answer_segments((int)s->pitch);
+  if (nseg > 64) return fail(PIR_EINVAL, "database wider than 262144 columns: use pir_answer and pir_compress");
+  ZP_TRY(use_device(s));
+  hipStream_t st = s->stream;
+  const uint32_t L = c->L;
+  const uint32_t* dQ = Q;
+  uint32_t* dB = B;
+  uint32_t* dC = C;
+  const size_t qbytes = (size_t)s->cols * sizeof(uint32_t);
+  const size_t bbytes = (size_t)s->rows * sizeof(uint32_t);
+  const size_t cbytes = (size_t)s->rows * L * sizeof(uint32_t);
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_q, qbytes));
+    ZP_TRY(s->scratch(s->s_b, bbytes));
+    ZP_TRY(s->scratch(s->s_c, cbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_q.p, Q, qbytes, hipMemcpyHostToDevice, st));
+    dQ = (const uint32_t*)s->s_q.p;
+    dB = (uint32_t*)s->s_b.p;
+    dC = (uint32_t*)s->s_c.p;
+  }
+  if (reinterpret_cast<uintptr_t>(dQ) % 16 != 0) {  // the matvec reads the query 16 bytes at a time
+    ZP_TRY(s->scratch(s->s_q, qbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_q.p, dQ, qbytes, hipMemcpyDeviceToDevice, st));
+    dQ = (const uint32_t*)s->s_q.p;
+  }
+  ZP_TRY(s->scratch(s->s_part, (size_t)nseg * s->rows * sizeof(uint32_t)));
+  auto* part = (uint32_t*)s->s_part.p;
+  {
+    ProfScope ps(s, PIR_KERNEL_STEP_MATVEC);
+    zp::launch_matvec_part(s->D, (int)s->rows, (int)s->pitch, dQ, (int)s->cols, part, st);
+  }
+  {
+    ProfScope ps(s, PIR_KERNEL_STEP_COMBINE);
+    zp::launch_combine_parts(c->dev(), c->Kp, c->Mp, part, nseg, (int)s->rows, dB, dC, st);
+  }
+  ZP_HIP(hipGetLastError());
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(B, dB, bbytes, hipMemcpyDeviceToHost, st));
     ZP_HIP(hipMemcpyAsync(C, dC, cbytes, hipMemcpyDeviceToHost, st));
     ZP_HIP(hipStreamSynchronize(st));
   }

@@ -18,7 +18,7 @@ PIR_OK, PIR_EINVAL, PIR_ENOMEM, PIR_EDEVICE, PIR_ESTALE, PIR_EBUSY = 0, -1, -2, 
 PIR_PTR_HOST, PIR_PTR_DEVICE = 0, 1
 PATH_AUTO, PATH_MATVEC, PATH_MFMA = 0, 1, 2
 KERNELS = {"matvec": 0, "gemm": 1, "compress": 2, "hint": 3, "table": 4, "key": 5, "offset_gemm": 6,
-           "offset": 7}
+           "offset": 7, "step_matvec": 8, "step_combine": 9}
 
 
 class ZipPIRError(RuntimeError):
@@ -51,6 +51,8 @@ _sig = {
                                          ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32]),
     "pir_compress": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_answer_compress": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_set_packing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
     "pir_packing_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                           ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
@@ -240,6 +242,11 @@ class Server:
         ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
         _check(_lib.pir_compress(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(B)[0],
                                  _ptr(C)[0], _flags(B, C)), "pir_compress")
+
+    def answer_compress(self, q, cid: int, B, C) -> None:
+        """One query of one client: B = D.q mod 2^32 and C = K (1 + B N) mod N^2 in one call."""
+        _check(_lib.pir_answer_compress(self._h, _ptr(q)[0], cid, _ptr(B)[0], _ptr(C)[0], _flags(q, B, C)),
+               "pir_answer_compress")
 
     # -- packed responses
     def set_packing(self, cid: int, ell: int) -> None:

@@ -431,3 +431,66 @@ def test_hint_wide_table_against_narrow(native):
         K_or = oracle_client_hint(cl.ck, E, cl.N, pool=pool)
     assert [wl.limbs_to_int(K11[j]) for j in sample] == [K_or[i] for i in range(len(sample))]
     assert K_or[1] == 1
+
+
+@pytest.mark.parametrize("rows,cols,n_bits", [(1, 1, 256), (37, 300, 256), (300, 5000, 1024), (257, 8193, 256),
+                                              (130, 70000, 2048)])
+def test_answer_compress_two_launches(native, rows, cols, n_bits):
+    # pir_answer_compress (query planes built in the matvec, per-segment partials added up by
+    # the combine) gives the bits of pir_answer + pir_compress and of the oracle, for one to 18
+    # column segments, ragged rows and columns, and queries at their extremes.
+    log(f"answer_compress rows {rows} cols {cols} N {n_bits}")
+    n = 4
+    inst = make_instance(cfg=940 + rows, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, n_bits)
+    g = np.random.default_rng(941 + rows)
+    queries = [cl.qu, np.full(cols, Q32 - 1, np.uint32), g.integers(0, Q32, size=cols, dtype=np.uint32)]
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ck)
+        srv.hint(cid)
+        K = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K)
+        K_int = limbs_rows_to_ints(K)
+        for q in queries:
+            B1 = np.zeros((1, rows), np.uint32)
+            C1 = np.zeros((1, rows, L), np.uint32)
+            srv.answer(q[None, :], B1)
+            srv.compress([cid], B1, C1)
+            B2 = np.full(rows, 0xDEADBEEF, np.uint32)
+            C2 = np.full((rows, L), 0xDEADBEEF, np.uint32)
+            srv.answer_compress(q, cid, B2, C2)
+            assert np.array_equal(B2, B1[0])
+            assert np.array_equal(C2, C1[0])
+            b_or = server.answer(inst.D, q)
+            assert np.array_equal(B2, b_or)
+            assert limbs_rows_to_ints(C2) == server.compress(K_int, b_or, cl.N)
+        with pytest.raises(native.ZipPIRError) as ei:
+            srv.answer_compress(queries[0], cid + 7, B2, C2)
+        assert ei.value.status == native.PIR_EINVAL
+
+
+def test_answer_compress_device_and_stale(native):
+    import torch
+    rows, cols, n, n_bits = 96, 4200, 4, 256
+    inst = make_instance(cfg=945, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, n_bits)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ck)
+        srv.hint(cid)
+        q = torch.from_numpy(cl.qu.view(np.int32).copy()).cuda()
+        B = torch.zeros(rows, dtype=torch.int32, device="cuda")
+        C = torch.zeros((rows, L), dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            srv.answer_compress(q, cid, B, C)
+        srv.sync()
+        b = B.cpu().numpy().view(np.uint32)
+        assert np.array_equal(b, server.answer(inst.D, cl.qu))
+        K = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K)
+        assert limbs_rows_to_ints(C.cpu().numpy().view(np.uint32)) == server.compress(limbs_rows_to_ints(K), b, cl.N)
+        srv.update_rows([5], np.zeros((1, cols), np.uint8))
+        with pytest.raises(native.ZipPIRError) as ei:
+            srv.answer_compress(q, cid, B, C)
+        assert ei.value.status == native.PIR_ESTALE
