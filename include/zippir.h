@@ -388,7 +388,8 @@ uint32_t pir_engine_plan(const uint32_t *queued_limbs, uint32_t nqueued, uint32_
 /*
  * Streaming-read probe (measurement only): reads the first bytes - bytes mod 16 bytes of the
  * device buffer buf (16-byte aligned) once with nontemporal loads, `blocks` workgroups of 256
- * threads, and writes one word per workgroup to sink (a device array of `blocks` words).
+ * threads, each streaming its own contiguous chunk of about bytes / blocks bytes, and writes
+ * one word per workgroup to sink (a device array of `blocks` words).
  * Enqueued on hip_stream; the time of this launch gives the device's achievable HBM read
  * bandwidth, the practical ceiling of the one-query answer.
  */

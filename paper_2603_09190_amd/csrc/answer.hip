@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "rownum.h"
 #include "wavenum.h"
 
 namespace zp {
@@ -106,9 +107,27 @@ __global__ __launch_bounds__(256) void matvec_part_kernel(const uint8_t* __restr
 }
 
 // b_j = sum_s part[j * nseg + s] mod 2^32, then c_j = (K'_j + b_j M'_j + q N^2) / 2^32 reduced
-// once (the combine of compress.hip).  Each wave takes kCombineRows consecutive rows and loads
-// the next row's K', M' and partials while it reduces the current one.
+// once (the combine of compress.hip).  Each wave takes kCombineRows consecutive rows and requests
+// every row's K', M' and partials before it reduces the first one, so one memory latency covers
+// all of them (a short last wave re-reads its last row instead of branching around loads).
 constexpr int kCombineRows = 8;
+
+// The limbs of a row for a later wn_zero_above: every lane loads, at indices clamped to the row,
+// so no branch separates the loads of consecutive rows (a branch would make the wave wait for
+// each row's loads before requesting the next).
+template <int P>
+__device__ __forceinline__ void wn_load_clamped(WNum<P>& x, const uint32_t* __restrict__ src, int nl) {
+  const int base = P * lane_id();
+#pragma unroll
+  for (int j = 0; j < P; ++j) x.v[j] = src[min(base + j, nl - 1)];
+}
+
+template <int P>
+__device__ __forceinline__ void wn_zero_above(WNum<P>& x, int nl) {
+  const int base = P * lane_id();
+#pragma unroll
+  for (int j = 0; j < P; ++j) x.v[j] = base + j < nl ? x.v[j] : 0u;
+}
 
 template <int P>
 __global__ __launch_bounds__(256) void combine_parts_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
@@ -119,34 +138,120 @@ __global__ __launch_bounds__(256) void combine_parts_kernel(ClientDev cd, const 
   const int wave = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row0 = wave * kCombineRows;
   if (row0 >= rows) return;
-  const int row1 = min(rows, row0 + kCombineRows);
+  const int nr = min(rows - row0, kCombineRows);
   const int lane = lane_id();
-  auto partial = [&](int row) {
-    return lane < nseg ? part[(size_t)row * nseg + lane] : 0u;
-  };
-  WNum<P> M2, t, m, tn, mn;
+  WNum<P> M2;
   wn_load(M2, cd.N2);
-  wn_load_n(t, Kp + (size_t)row0 * cd.L, cd.L);
-  wn_load_n(m, Mp + (size_t)row0 * cd.L, cd.L);
-  uint32_t pj = partial(row0), pn = 0;
-  for (int row = row0; row < row1; ++row) {
-    if (row + 1 < row1) {
-      wn_load_n(tn, Kp + (size_t)(row + 1) * cd.L, cd.L);
-      wn_load_n(mn, Mp + (size_t)(row + 1) * cd.L, cd.L);
-      pn = partial(row + 1);
-    }
-    uint32_t sum = pj;  // lanes at or beyond nseg hold 0: log2(nseg) exchanges leave the total in lane 0
+  WNum<P> t[kCombineRows], m[kCombineRows];
+  uint32_t pj[kCombineRows];
+#pragma unroll
+  for (int i = 0; i < kCombineRows; ++i) {
+    const int row = row0 + min(i, nr - 1);
+    wn_load_clamped(t[i], Kp + (size_t)row * cd.L, cd.L);
+    wn_load_clamped(m[i], Mp + (size_t)row * cd.L, cd.L);
+    pj[i] = part[(size_t)row * nseg + min(lane, nseg - 1)];
+  }
+#pragma unroll
+  for (int i = 0; i < kCombineRows; ++i) {
+    if (i >= nr) break;
+    // lanes at or beyond nseg count nothing: log2(nseg) exchanges leave the total in lane 0
+    uint32_t sum = lane < nseg ? pj[i] : 0u;
+    wn_zero_above(t[i], cd.L);
+    wn_zero_above(m[i], cd.L);
     for (int off = 1; off < nseg; off <<= 1) sum += (uint32_t)__shfl_xor((int)sum, off, 64);
     const uint32_t bj = __builtin_amdgcn_readfirstlane(sum);
-    if (lane == 0) b[row] = bj;
+    if (lane == 0) b[row0 + i] = bj;
     uint64_t c = 0;
-    mont_step(t, c, bj, m, M2, cd.m2prime);
-    const uint64_t ovf = wn_resolve(t, c);
-    wn_cond_sub(t, ovf, M2);
-    wn_store_n(C + (size_t)row * cd.L, t, cd.L);
-    t = tn;
-    m = mn;
-    pj = pn;
+    mont_step(t[i], c, bj, m[i], M2, cd.m2prime);
+    const uint64_t ovf = wn_resolve(t[i], c);
+    wn_cond_sub(t[i], ovf, M2);
+    wn_store_n(C + (size_t)(row0 + i) * cd.L, t[i], cd.L);
+  }
+}
+
+// The same combine with four rows per wavefront, one per 16-lane row (rownum.h): each lane
+// holds Q = 4P consecutive limbs of its row's K', M' and c, so a row's operands are read and
+// written in 16-byte pieces when the row fills all 16 Q limbs (kFull), and the fixed work of
+// the CIOS step, the carry resolution and the final subtraction is shared by four rows.  A
+// lane also reads one segment partial of its row (segments 16 apart for more than 16), and an
+// exchange inside the row adds them up.  A wave takes kCombineRows rows, four per pass, and
+// requests every pass's operands before the first pass computes.
+template <int P, bool kFull>
+__device__ __forceinline__ void rn_load_row(RNum<4 * P>& x, const uint32_t* __restrict__ src, int nl) {
+  constexpr int Q = 4 * P;
+  if (kFull) {
+    const u32x4* p = reinterpret_cast<const u32x4*>(src + Q * row_lane());
+#pragma unroll
+    for (int v = 0; v < Q / 4; ++v) {
+      const u32x4 w = p[v];
+      x.v[4 * v] = w.x; x.v[4 * v + 1] = w.y; x.v[4 * v + 2] = w.z; x.v[4 * v + 3] = w.w;
+    }
+  } else {  // indices clamped to the row; limbs at or beyond nl are zeroed before use
+    const int base = Q * row_lane();
+#pragma unroll
+    for (int j = 0; j < Q; ++j) x.v[j] = src[min(base + j, nl - 1)];
+  }
+}
+
+template <int P, bool kFull>
+__device__ __forceinline__ void rn_zero_above(RNum<4 * P>& x, int nl) {
+  if (kFull) return;
+  const int base = 4 * P * row_lane();
+#pragma unroll
+  for (int j = 0; j < 4 * P; ++j) x.v[j] = base + j < nl ? x.v[j] : 0u;
+}
+
+template <int P, bool kFull>
+__global__ __launch_bounds__(256) void combine_parts_quad_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
+                                                                 const uint32_t* __restrict__ Mp,
+                                                                 const uint32_t* __restrict__ part, int nseg,
+                                                                 int rows, uint32_t* __restrict__ b,
+                                                                 uint32_t* __restrict__ C) {
+  constexpr int Q = 4 * P;
+  constexpr int kPasses = kCombineRows / 4;
+  const int wave = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row0 = wave * kCombineRows;
+  if (row0 >= rows) return;
+  const int rl = row_lane();
+  RNum<Q> t[kPasses], m[kPasses];
+  uint32_t ps[kPasses];
+#pragma unroll
+  for (int i = 0; i < kPasses; ++i) {
+    const int row = min(rows - 1, row0 + 4 * i + row_index());
+    rn_load_row<P, kFull>(t[i], Kp + (size_t)row * cd.L, cd.L);
+    rn_load_row<P, kFull>(m[i], Mp + (size_t)row * cd.L, cd.L);
+    ps[i] = part[(size_t)row * nseg + min(rl, nseg - 1)];
+  }
+  RNum<Q> M2;
+  rn_load(M2, cd.N2);
+#pragma unroll
+  for (int i = 0; i < kPasses; ++i) {
+    if (row0 + 4 * i >= rows) break;
+    const int mine = row0 + 4 * i + row_index();
+    const int row = min(rows - 1, mine);
+    uint32_t sum = rl < nseg ? ps[i] : 0u;
+    for (int s0 = 16; s0 < nseg; s0 += 16)  // more than 16 segments (over 65536 columns)
+      sum += s0 + rl < nseg ? part[(size_t)row * nseg + s0 + rl] : 0u;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) sum += (uint32_t)__shfl_xor((int)sum, off, 64);
+    rn_zero_above<P, kFull>(t[i], cd.L);
+    rn_zero_above<P, kFull>(m[i], cd.L);
+    uint64_t c = 0;
+    rn_mont_step(t[i], c, sum, m[i], M2, cd.m2prime);
+    const uint64_t ovf = rn_resolve(t[i], c);
+    rn_cond_sub(t[i], ovf, M2);
+    if (mine < rows) {
+      if (rl == 0) b[mine] = sum;
+      uint32_t* dst = C + (size_t)mine * cd.L;
+      if (kFull) {
+        u32x4* p = reinterpret_cast<u32x4*>(dst + Q * rl);
+#pragma unroll
+        for (int v = 0; v < Q / 4; ++v)
+          p[v] = u32x4{t[i].v[4 * v], t[i].v[4 * v + 1], t[i].v[4 * v + 2], t[i].v[4 * v + 3]};
+      } else {
+        rn_store_n(dst, t[i], cd.L);
+      }
+    }
   }
 }
 
@@ -162,7 +267,7 @@ void launch_matvec_part(const uint8_t* D, int rows, int pitch, const uint32_t* q
   for (int r0 = 0; r0 < rows; r0 += chunk_rows) {
     const int nr = std::min(chunk_rows, rows - r0);
     dim3 grid((nr + group - 1) / group, nseg);
-    matvec_part_kernel<2><<<grid, 256, 0, s>>>(D + (size_t)r0 * pitch, nr, pitch, q, cols,
+    matvec_part_kernel<4><<<grid, 256, 0, s>>>(D + (size_t)r0 * pitch, nr, pitch, q, cols,
                                                part + (size_t)r0 * nseg, nseg);
   }
 }
@@ -173,6 +278,22 @@ void launch_combine_parts(const ClientDev& cd, const uint32_t* Kp, const uint32_
   if (rows <= 0) return;
   const int waves = (rows + kCombineRows - 1) / kCombineRows;
   const int blocks = (waves + 3) / 4;
+  if (rows >= kQuadItems) {  // four rows per wavefront once that still leaves several per SIMD
+    // 16-byte pieces need rows that fill the lanes and 16-byte aligned arrays
+    const bool full = cd.L == 64 * cd.P && ((reinterpret_cast<uintptr_t>(Kp) | reinterpret_cast<uintptr_t>(Mp) |
+                                              reinterpret_cast<uintptr_t>(C)) & 15) == 0;
+#define ZP_COMBINE_QUAD(PP)                                                                        \
+  (full ? combine_parts_quad_kernel<PP, true><<<blocks, 256, 0, s>>>(cd, Kp, Mp, part, nseg, rows, b, C) \
+        : combine_parts_quad_kernel<PP, false><<<blocks, 256, 0, s>>>(cd, Kp, Mp, part, nseg, rows, b, C))
+    switch (cd.P) {
+      case 1: ZP_COMBINE_QUAD(1); break;
+      case 2: ZP_COMBINE_QUAD(2); break;
+      case 3: ZP_COMBINE_QUAD(3); break;
+      case 4: ZP_COMBINE_QUAD(4); break;
+    }
+#undef ZP_COMBINE_QUAD
+    return;
+  }
   switch (cd.P) {
     case 1: combine_parts_kernel<1><<<blocks, 256, 0, s>>>(cd, Kp, Mp, part, nseg, rows, b, C); break;
     case 2: combine_parts_kernel<2><<<blocks, 256, 0, s>>>(cd, Kp, Mp, part, nseg, rows, b, C); break;

@@ -334,6 +334,14 @@ def test_read_probe(native):
     torch.cuda.synchronize()
     want = int(np.bitwise_xor.reduce(src.cpu().numpy().view(np.uint32)))
     assert int(np.bitwise_xor.reduce(sink.cpu().numpy().view(np.uint32))) == want
+    # ragged: 262139 words are 65534 whole 16-byte units plus 12 bytes that are not read, over
+    # 7 workgroups whose chunks do not divide the units evenly
+    part = src[:262139]
+    sink7 = torch.zeros(7, dtype=torch.int32, device=dev)
+    native.read_probe(part, sink7, 7)
+    torch.cuda.synchronize()
+    want7 = int(np.bitwise_xor.reduce(src.cpu().numpy().view(np.uint32)[:65534 * 4]))
+    assert int(np.bitwise_xor.reduce(sink7.cpu().numpy().view(np.uint32))) == want7
     st = native.lib().pir_read_probe(src.data_ptr() + 4, 1024, sink.data_ptr(), 64, None)
     assert st == native.PIR_EINVAL
 
@@ -468,6 +476,48 @@ def test_answer_compress_two_launches(native, rows, cols, n_bits):
         with pytest.raises(native.ZipPIRError) as ei:
             srv.answer_compress(queries[0], cid + 7, B2, C2)
         assert ei.value.status == native.PIR_EINVAL
+
+
+@pytest.mark.parametrize("rows,cols,n_bits,misalign", [(16387, 300, 256, False), (16390, 520, 2048, False),
+                                                       (16390, 520, 2048, True), (16385, 70000, 256, False)])
+def test_answer_compress_four_rows_per_wave(native, rows, cols, n_bits, misalign):
+    # from 16384 rows the combine takes four rows per wavefront: rows that fill all 16 lanes'
+    # limbs (N 2048-bit) move in 16-byte pieces unless an array is not 16-byte aligned (a
+    # response buffer 4 bytes off), shorter rows (N 256-bit) take clamped loads, and 70000
+    # columns give 18 segment partials per row (more than one per lane of a row).  Ragged row
+    # counts leave part of the last wavefront empty.
+    import torch
+    log(f"answer_compress four rows per wave: rows {rows} cols {cols} N {n_bits} misaligned {misalign}")
+    n = 4
+    inst = make_instance(cfg=950 + cols, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, n_bits)
+    g = np.random.default_rng(951 + rows)
+    q = g.integers(0, Q32, size=cols, dtype=np.uint32)
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ck)
+        srv.hint(cid)
+        B1 = np.zeros((1, rows), np.uint32)
+        C1 = np.zeros((1, rows, L), np.uint32)
+        srv.answer(q[None, :], B1)
+        srv.compress([cid], B1, C1)
+        qd = torch.from_numpy(q.view(np.int32).copy()).cuda()
+        B2 = torch.full((rows,), -1, dtype=torch.int32, device="cuda")
+        Cbig = torch.full((rows * L + 4,), -1, dtype=torch.int32, device="cuda")
+        C2 = Cbig[1:1 + rows * L].view(rows, L) if misalign else Cbig[:rows * L].view(rows, L)
+        assert (C2.data_ptr() % 16 != 0) == misalign
+        srv.answer_compress(qd, cid, B2, C2)
+        srv.sync()
+        b = B2.cpu().numpy().view(np.uint32)
+        c = C2.cpu().numpy().view(np.uint32)
+        assert np.array_equal(b, B1[0])
+        assert np.array_equal(c, C1[0])
+        K = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K)
+    sample = np.unique(np.concatenate([np.arange(8), np.arange(rows - 8, rows), g.integers(0, rows, 24)]))
+    assert np.array_equal(b[sample], server.answer_rows(inst.D, q, sample))
+    K_int = limbs_rows_to_ints(K[sample])
+    assert limbs_rows_to_ints(c[sample]) == server.compress(K_int, b[sample], cl.N)
 
 
 def test_answer_compress_device_and_stale(native):
