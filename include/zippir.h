@@ -93,8 +93,8 @@ pir_status pir_remove_client(pir_server *srv, uint32_t client_id);
  * Hint (Alg. 5): bring H up to date for every stale row, then compute
  * K_j = prod_k ck_k^{(-H_jk) mod 2^32} mod N^2 for the listed rows of this client
  * (rows == NULL or nrows == 0: all rows).  The result stays in device memory.  The
- * exponentiation uses a fixed-base table of ck powers (Alg. 4 with 8-bit windows), built
- * for the call and freed after it.  Row indices must be < rows (PIR_EINVAL otherwise).
+ * exponentiation uses a fixed-base table of ck powers (Alg. 4 taken to 8- or 11-bit windows,
+ * see pir_hint_window_bits), built for the call and freed after it.  Row indices must be < rows (PIR_EINVAL otherwise).
  * Synchronizes the stream.
  */
 pir_status pir_hint(pir_server *srv, uint32_t client_id, const uint32_t *rows, uint32_t nrows);
@@ -106,6 +106,21 @@ pir_status pir_hint(pir_server *srv, uint32_t client_id, const uint32_t *rows, u
  */
 pir_status pir_update_rows(pir_server *srv, const uint32_t *rows, uint32_t nrows,
                            const uint8_t *new_rows, uint32_t ptr_flags);
+
+/*
+ * Memory layout of D for the batched contraction (the Alg. 5 response over many queries, and
+ * H = D.A of the hint).  The server keeps D row-major (rows x pitch, pitch = cols rounded up to
+ * 256) and, by default, a second copy in 16-row x 64-byte tiles: byte (j, i) at
+ * (j/16) 16 pitch + (i/64) 1024 + (j mod 16) 64 + i mod 64, so that each group of 16 rows is
+ * one contiguous run over its whole width.  The contraction reads the tiled copy when there
+ * is one, and D otherwise; both give identical bits.  The copy costs as much HBM as D.
+ * pir_setup makes it when the allocation succeeds; pir_update_rows keeps it current.
+ *   pir_set_tiled_copy: enable != 0 makes it (PIR_ENOMEM if it does not fit), 0 frees it.
+ *     Synchronizes the server's stream.
+ *   pir_tiled_copy: 1 if the server has it, else 0 (also for NULL).
+ */
+pir_status pir_set_tiled_copy(pir_server *srv, int32_t enable);
+int32_t pir_tiled_copy(const pir_server *srv);
 
 /*
  * Response, first line (Alg. 5): B[c] = D.Q[c] mod 2^32 for c < batch.

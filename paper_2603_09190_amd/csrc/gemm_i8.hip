@@ -126,7 +126,10 @@ constexpr int x_ahead(int waves, int depth, int mr, int kb, int pl) {
   return depth >= 2 ? 3 : 2;
 }
 
-template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide>
+// kTiled: D is the tiled copy (see tile_rows_kernel): 16-row x 64-byte pieces, each 16-row
+// group's whole K range contiguous, so a wave's load of 16 rows x 64 bytes is one contiguous
+// kilobyte and a block streams long contiguous runs instead of 256-byte pieces of many rows.
+template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide, bool kTiled>
 __device__ __forceinline__ void gemm_planes_body(
     const uint8_t* __restrict__ D, int rows, int cols, int pitch, const int8_t* __restrict__ Xs,
     const int32_t* __restrict__ colsum, int ncol, const int32_t* __restrict__ rowsum,
@@ -155,7 +158,8 @@ __device__ __forceinline__ void gemm_planes_body(
 #pragma unroll
   for (int mr = 0; mr < kMR; ++mr) {
     const int row = min(rowblk + 16 * kMR * wave + 16 * mr + r, rows - 1);
-    dp[mr] = D + (size_t)row * pitch + (size_t)kstep0 * kKB + 16 * g;
+    dp[mr] = kTiled ? D + (size_t)(row >> 4) * 16 * pitch + (size_t)kstep0 * (kKB / 64) * 1024 + (row & 15) * 64 + 16 * g
+                    : D + (size_t)row * pitch + (size_t)kstep0 * kKB + 16 * g;
   }
   constexpr int kPieces = kPl * kBC * (kKB / 16) / (64 * kW);
   static_assert(kPieces >= 1 && kPieces * 64 * kW == kPl * kBC * (kKB / 16), "X tile split");
@@ -199,7 +203,8 @@ __device__ __forceinline__ void gemm_planes_body(
 #pragma unroll
       for (int s = 0; s < kSl; ++s)
         ring[slot_][mr][s] = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x4*>(dp[mr] + (size_t)st * kKB + 64 * s));
+            reinterpret_cast<const u32x4*>(kTiled ? dp[mr] + (size_t)st * kKB * 16 + 1024 * s
+                                                  : dp[mr] + (size_t)st * kKB + 64 * s));
   };
   auto load_x = [&](int xb, int st) {
 #pragma unroll
@@ -342,16 +347,41 @@ __device__ __forceinline__ void gemm_planes_body(
 #define ZP_GEMM_PASS D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, \
                      ksteps_per_block, nrb, ncb, nkz
 
-template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide>
+template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide, bool kTiled = false>
 __global__ __launch_bounds__(64 * kW) void gemm_planes_kernel(ZP_GEMM_ARGS) {
-  gemm_planes_body<kW, kDepth, kMR, kKB, kPl, kWide>(ZP_GEMM_PASS);
+  gemm_planes_body<kW, kDepth, kMR, kKB, kPl, kWide, kTiled>(ZP_GEMM_PASS);
 }
 
 // Four row tiles per wave need more than half the register file: at most two waves per SIMD.
-template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide>
+template <int kW, int kDepth, int kMR, int kKB, int kPl, bool kWide, bool kTiled = false>
 __global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void gemm_planes_kernel_wide_regs(ZP_GEMM_ARGS) {
-  gemm_planes_body<kW, kDepth, kMR, kKB, kPl, kWide>(ZP_GEMM_PASS);
+  gemm_planes_body<kW, kDepth, kMR, kKB, kPl, kWide, kTiled>(ZP_GEMM_PASS);
+}
+
+// Dt[(j / 16) 16 pitch + (i / 64) 1024 + (j mod 16) 64 + i mod 64] = D[j pitch + i] for the listed
+// rows j (rowlist == nullptr: rows 0 .. nrows-1); pitch is a multiple of 64.  One thread per
+// 16 bytes.
+__global__ void tile_rows_kernel(const uint8_t* __restrict__ D, int pitch, const uint32_t* __restrict__ rowlist,
+                                 int nrows, uint8_t* __restrict__ Dt) {
+  const long long per_row = pitch / 16;
+  const long long n = (long long)nrows * per_row;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long li = i / per_row;
+    const long long j = rowlist ? (long long)rowlist[li] : li;
+    const int k = (int)(i - li * per_row) * 16;
+    const u32x4 v = *reinterpret_cast<const u32x4*>(D + j * pitch + k);
+    *reinterpret_cast<u32x4*>(Dt + (j >> 4) * 16LL * pitch + (long long)(k >> 6) * 1024 + (j & 15) * 64 + (k & 63)) = v;
+  }
+}
+
+void launch_tile_rows(const uint8_t* D, int pitch, const uint32_t* rowlist, int nrows, uint8_t* Dt,
+                      hipStream_t s) {
+  if (nrows <= 0) return;
+  const long long n = (long long)nrows * (pitch / 16);
+  const int blocks = (int)std::min<long long>(8192, (n + 255) / 256);
+  tile_rows_kernel<<<blocks, 256, 0, s>>>(D, pitch, rowlist, nrows, Dt);
 }
 
 // Clears the rows x ncol output block: out[j*ncol + c] (row-major) or out[c*ld + j].
@@ -418,7 +448,8 @@ bool gemm_shape_valid(const GemmShape& sh, int pitch, int planes) {
 void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int planes,
                         const int8_t* Xs, const int32_t* colsum, int ncol, const int32_t* rowsum,
                         uint32_t* out, bool out_rowmajor, long long out_ld, const GemmShape& sh_in,
-                        hipStream_t s) {
+                        hipStream_t s, bool tiled) {
+  if (tiled && planes != 4) return;  // the tiled copy serves the four-plane contraction only
   GemmShape sh = sh_in;
   if (!gemm_shape_valid(sh, pitch, planes))
     sh = planes == 4 ? GemmShape{8, 1, 2, 256, 2, 4} : GemmShape{8, 1, 2, 256, 1, 3};
@@ -432,16 +463,22 @@ void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int pla
   const int ncb = (ncol + cols_per_block - 1) / cols_per_block;
   const long long nblocks = (long long)((nrb + 7) / 8 * 8) * ncb * nkz;
   const dim3 grid((unsigned)nblocks);
-#define ZP_LAUNCH(W, DP, MR, KB, PL, WIDE)                                                          \
+#define ZP_LAUNCHT(W, DP, MR, KB, PL, WIDE, TL)                                                     \
   if constexpr (MR >= 4)                                                                            \
-    gemm_planes_kernel_wide_regs<W, DP, MR, KB, PL, WIDE><<<grid, 64 * W, 0, s>>>(                   \
+    gemm_planes_kernel_wide_regs<W, DP, MR, KB, PL, WIDE, TL><<<grid, 64 * W, 0, s>>>(               \
         D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per, nrb, ncb, nkz); \
   else                                                                                              \
-    gemm_planes_kernel<W, DP, MR, KB, PL, WIDE><<<grid, 64 * W, 0, s>>>(                             \
+    gemm_planes_kernel<W, DP, MR, KB, PL, WIDE, TL><<<grid, 64 * W, 0, s>>>(                         \
         D, rows, cols, pitch, Xs, colsum, ncol, rowsum, out, out_rowmajor, out_ld, per, nrb, ncb, nkz)
+#define ZP_LAUNCH(W, DP, MR, KB, PL, WIDE) ZP_LAUNCHT(W, DP, MR, KB, PL, WIDE, false)
+#define ZP_LAUNCH4(W, DP, MR, KB)                                                                   \
+  do {                                                                                              \
+    if (tiled) ZP_LAUNCHT(W, DP, MR, KB, 4, false, true);                                           \
+    else ZP_LAUNCHT(W, DP, MR, KB, 4, false, false);                                                \
+  } while (0)
 #define ZP_G(W, DP, MR, KB)                                                                         \
   if (sh.waves == W && sh.depth == DP && sh.mr == MR && sh.kb == KB) {                              \
-    if (planes == 4) ZP_LAUNCH(W, DP, MR, KB, 4, false);                                            \
+    if (planes == 4) ZP_LAUNCH4(W, DP, MR, KB);                                                     \
     else if (sh.cg == 2) ZP_LAUNCH(W, DP, MR, KB, 2, true);                                         \
     else if (sh.cg == 3) ZP_LAUNCH(W, DP, MR, KB, 3, true);                                         \
     else ZP_LAUNCH(W, DP, MR, KB, 4, true);                                                         \
@@ -473,10 +510,12 @@ void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int pla
   ZP_G(8, 2, 4, 256) ZP_G(4, 2, 4, 256)
 #undef ZP_G
   if (sh.waves == 2 && sh.depth == 2 && sh.mr == 2 && sh.kb == 256 && planes == 4) {
-    ZP_LAUNCH(2, 2, 2, 256, 4, false);
+    ZP_LAUNCH4(2, 2, 2, 256);
     return;
   }
+#undef ZP_LAUNCH4
 #undef ZP_LAUNCH
+#undef ZP_LAUNCHT
 }
 
 }  // namespace zp

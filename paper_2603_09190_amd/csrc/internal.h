@@ -98,10 +98,15 @@ bool gemm_shape_valid(const GemmShape& sh, int pitch, int planes);
 // out = D . X mod 2^32.  planes = 1: X holds uint8 vectors as one plane,
 // Xs[c*pitch + i] = X(c,i) ^ 0x80 (0 beyond cols), colsum[c] = sum_{i<cols} Xs[c*pitch + i],
 // and out = D . X, exact while cols * 255^2 < 2^32.
+// tiled: D is the tiled copy of a row range starting at a multiple of 16 rows (four planes only)
 void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int planes,
                         const int8_t* Xs, const int32_t* colsum, int ncol, const int32_t* rowsum,
                         uint32_t* out, bool out_rowmajor, long long out_ld, const GemmShape& sh,
-                        hipStream_t s);
+                        hipStream_t s, bool tiled = false);
+// Tiled copy for the contraction: Dt[(j/16) 16 pitch + (i/64) 1024 + (j%16) 64 + i%64] = D[j pitch + i]
+// for the listed rows (device list; nullptr: rows 0 .. nrows-1).
+void launch_tile_rows(const uint8_t* D, int pitch, const uint32_t* rowlist, int nrows, uint8_t* Dt,
+                      hipStream_t s);
 
 // Tuning cross-check: with compare false, ref (rows x ncol, column c at ref + c*rows) receives
 // a copy of the output block; with compare true, *mism is increased by the number of

@@ -90,6 +90,9 @@ struct pir_server {
   hipStream_t stream = nullptr;
   uint32_t rows = 0, cols = 0, n = 0, pitch = 0;
   uint8_t* D = nullptr;         // rows x pitch, zero beyond cols
+  // D again in 16-row x 64-byte tiles (launch_tile_rows), read by the four-plane contraction;
+  // nullptr when switched off or when HBM had no room for it (the contraction then reads D)
+  uint8_t* Dt = nullptr;
   uint32_t* A = nullptr;        // cols x n
   int8_t* Ap = nullptr;         // n x 4 x pitch signed planes of A's columns
   int32_t* Acolsum = nullptr;   // n x 4
@@ -207,8 +210,8 @@ void prof_clear(pir_server* s) {
 // reported as PIR_EDEVICE), times three more launches with events on the server's stream and
 // keeps the fastest.  ZIPPIR_AUTOTUNE=0 disables tuning (default shape);
 // ZIPPIR_TUNE_CACHE=<file> persists choices as lines
-// "rows pitch ncol rowmajor planes waves depth mr kb ksplit cg".
-using TuneKey = std::tuple<int, int, int, int, int>;
+// "rows pitch ncol rowmajor planes tiled waves depth mr kb ksplit cg".
+using TuneKey = std::tuple<int, int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, zp::GemmShape> g_tune;
 bool g_tune_loaded = false;
@@ -237,10 +240,10 @@ void tune_load_locked() {
   const char* path = tune_cache_path();
   if (!path) return;
   std::ifstream f(path);
-  int r, p, n, m, pl, w, d, mr, kb, k, cg;
-  while (f >> r >> p >> n >> m >> pl >> w >> d >> mr >> kb >> k >> cg) {
+  int r, p, n, m, pl, tl, w, d, mr, kb, k, cg;
+  while (f >> r >> p >> n >> m >> pl >> tl >> w >> d >> mr >> kb >> k >> cg) {
     const zp::GemmShape sh{w, d, mr, kb, k, cg};
-    if (zp::gemm_shape_valid(sh, p, pl)) g_tune[TuneKey(r, p, n, m, pl)] = sh;
+    if (zp::gemm_shape_valid(sh, p, pl)) g_tune[TuneKey(r, p, n, m, pl, tl)] = sh;
   }
 }
 
@@ -250,7 +253,8 @@ void tune_store_locked() {
   std::ofstream f(path, std::ios::trunc);
   for (auto& kv : g_tune)
     f << std::get<0>(kv.first) << " " << std::get<1>(kv.first) << " " << std::get<2>(kv.first) << " "
-      << std::get<3>(kv.first) << " " << std::get<4>(kv.first) << " " << kv.second.waves << " "
+      << std::get<3>(kv.first) << " " << std::get<4>(kv.first) << " " << std::get<5>(kv.first) << " "
+      << kv.second.waves << " "
       << kv.second.depth << " "
       << kv.second.mr << " " << kv.second.kb << " " << kv.second.ksplit << " " << kv.second.cg << "\n";
 }
@@ -260,12 +264,14 @@ bool autotune_enabled() {
   return !(e && std::strcmp(e, "0") == 0);
 }
 
-// out = D . X (mod 2^32 for four planes) with the tuned launch shape.
+// out = D . X (mod 2^32 for four planes) with the tuned launch shape; tiled: D is the tiled
+// copy (four planes, rows from a multiple of 16).
 pir_status run_gemm_x(pir_server* s, const uint8_t* D, int rows, int cols, int pitch, int planes,
                       const int8_t* Xs, const int32_t* colsum, int ncol, const int32_t* rowsum,
-                      uint32_t* out, bool rowmajor, long long ld) {
+                      uint32_t* out, bool rowmajor, long long ld, bool tiled = false) {
   hipStream_t st = s->stream;
-  const TuneKey key((int)rows, pitch, ncol, rowmajor ? 1 : 0, planes);
+  if (tiled && planes != 4) return fail(PIR_EINVAL, "the tiled copy serves the four-plane contraction only");
+  const TuneKey key((int)rows, pitch, ncol, rowmajor ? 1 : 0, planes, tiled ? 1 : 0);
   zp::GemmShape shape = planes == 4 ? kDefaultShape4 : kDefaultShape1;
   bool need_tune = false;
   {
@@ -296,14 +302,14 @@ pir_status run_gemm_x(pir_server* s, const uint8_t* D, int rows, int cols, int p
       if (rc != PIR_OK) break;
       if (!zp::gemm_shape_valid(c, pitch, planes)) continue;
       zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor,
-                             ld, c, st);
+                             ld, c, st, tiled);
       zp::launch_gemm_snapshot(out, rows, ncol, rowmajor, ld, ref, have_ref, mism, st);
       have_ref = true;
       float ms = 1e30f;
       for (int rep = 0; rep < 3 && rc == PIR_OK; ++rep) {
         check(hipEventRecord(e0, st));
         zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor,
-                               ld, c, st);
+                               ld, c, st, tiled);
         check(hipEventRecord(e1, st));
         check(hipEventSynchronize(e1));
         float t = 0;
@@ -331,26 +337,28 @@ pir_status run_gemm_x(pir_server* s, const uint8_t* D, int rows, int cols, int p
   }
   ProfScope ps(s, planes == 4 ? PIR_KERNEL_GEMM : PIR_KERNEL_OFFSET_GEMM);
   zp::launch_gemm_planes(D, rows, cols, pitch, planes, Xs, colsum, ncol, rowsum, out, rowmajor, ld,
-                         shape, st);
+                         shape, st, tiled);
   return PIR_OK;
 }
 
-// The database contraction: out = D . X mod 2^32 over the rows of D starting at D.
+// The database contraction: out = D . X mod 2^32 over the rows of D starting at D (row-major,
+// or the tiled copy from a multiple of 16 rows when tiled).
 pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
                     const int32_t* colsum, int ncol, const int32_t* rowsum, uint32_t* out,
-                    bool rowmajor, long long ld) {
+                    bool rowmajor, long long ld, bool tiled = false) {
   return run_gemm_x(s, D, rows, (int)s->cols, (int)s->pitch, 4, Xs, colsum, ncol, rowsum, out,
-                    rowmajor, ld);
+                    rowmajor, ld, tiled);
 }
 
 // Batched answers stream D in row chunks of at most kLaunchBytes (see launch_matvec).
 pir_status run_gemm_chunked(pir_server* s, const int8_t* Xs, const int32_t* colsum, int ncol,
                             uint32_t* out, long long ld) {
   const long long per = std::max<long long>(256, zp::kLaunchBytes / s->pitch / 256 * 256);
+  const uint8_t* base = s->Dt ? s->Dt : s->D;  // chunks start at multiples of 256 rows
   for (long long r0 = 0; r0 < s->rows; r0 += per) {
     const int nr = (int)std::min<long long>(per, s->rows - r0);
-    ZP_TRY(run_gemm(s, s->D + (size_t)r0 * s->pitch, nr, Xs, colsum, ncol, s->rowsum + r0,
-                    out + r0, false, ld));
+    ZP_TRY(run_gemm(s, base + (size_t)r0 * s->pitch, nr, Xs, colsum, ncol, s->rowsum + r0,
+                    out + r0, false, ld, s->Dt != nullptr));
   }
   return PIR_OK;
 }
@@ -360,12 +368,24 @@ pir_status use_device(pir_server* s) {
   return PIR_OK;
 }
 
+// Allocate and fill the contraction's tiled copy of D (rows rounded up to 16; the rows past
+// the last are never read).  PIR_ENOMEM leaves the server without one.
+pir_status build_tiled(pir_server* s) {
+  if (s->Dt) return PIR_OK;
+  const size_t rows16 = ((size_t)s->rows + 15) / 16 * 16;
+  ZP_TRY(s->alloc((void**)&s->Dt, rows16 * s->pitch));
+  zp::launch_tile_rows(s->D, (int)s->pitch, nullptr, (int)s->rows, s->Dt, s->stream);
+  ZP_HIP(hipGetLastError());
+  return PIR_OK;
+}
+
 // Recompute H for the given rows (all rows if the list covers most of them).
 pir_status refresh_H(pir_server* s, const std::vector<uint32_t>& rows_in) {
   if (rows_in.empty()) return PIR_OK;
   hipStream_t st = s->stream;
   if (rows_in.size() * 4 >= s->rows) {
-    ZP_TRY(run_gemm(s, s->D, (int)s->rows, s->Ap, s->Acolsum, (int)s->n, s->rowsum, s->H, true, 0));
+    ZP_TRY(run_gemm(s, s->Dt ? s->Dt : s->D, (int)s->rows, s->Ap, s->Acolsum, (int)s->n, s->rowsum, s->H,
+                    true, 0, s->Dt != nullptr));
   } else {
     const size_t m = rows_in.size();
     ZP_TRY(s->scratch(s->s_rows, m * sizeof(uint32_t)));
@@ -518,6 +538,8 @@ pir_status pir_setup(pir_server** out, int device, void* hip_stream, const uint8
   ZP_TRY(s->alloc((void**)&s->H, (size_t)rows * n * sizeof(uint32_t)));
   s->H_valid.assign(rows, 0);
   s->H_stale = rows;
+  // the contraction's tiled copy, when HBM has room for it (otherwise it reads D)
+  if (build_tiled(s.get()) != PIR_OK) g_last_error.clear();
   ZP_HIP(hipGetLastError());
   ZP_HIP(hipStreamSynchronize(st));
   *out = s.release();
@@ -533,6 +555,23 @@ void pir_destroy(pir_server* s) {
   s->allocs.clear();
   delete s;
 }
+
+pir_status pir_set_tiled_copy(pir_server* s, int32_t enable) {
+  g_last_error.clear();
+  if (!s) return fail(PIR_EINVAL, "NULL server");
+  ZP_TRY(use_device(s));
+  if (enable) {
+    ZP_TRY(build_tiled(s));
+  } else if (s->Dt) {
+    ZP_HIP(hipStreamSynchronize(s->stream));  // no launch may still read it
+    s->release(s->Dt);
+    s->Dt = nullptr;
+  }
+  ZP_HIP(hipStreamSynchronize(s->stream));
+  return PIR_OK;
+}
+
+int32_t pir_tiled_copy(const pir_server* s) { return s && s->Dt ? 1 : 0; }
 
 pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, const uint32_t* ck,
                           uint32_t ptr_flags, uint32_t* client_id) {
@@ -761,6 +800,7 @@ pir_status pir_update_rows(pir_server* s, const uint32_t* rows, uint32_t nrows,
   ZP_HIP(hipMemcpyAsync(s->s_gath.p, new_rows, (size_t)nrows * s->cols, kind_to_dev(ptr_flags), st));
   zp::launch_scatter_rows_u8((const uint8_t*)s->s_gath.p, (int)s->cols, (int)s->cols, drows,
                              (int)nrows, s->D, (int)s->pitch, st);
+  if (s->Dt) zp::launch_tile_rows(s->D, (int)s->pitch, drows, (int)nrows, s->Dt, st);
   // row sums: recompute the changed rows through a gathered copy
   ZP_TRY(s->scratch(s->s_c, (size_t)nrows * s->pitch));
   ZP_TRY(s->scratch(s->s_gsum, (size_t)nrows * sizeof(int32_t)));

@@ -75,6 +75,8 @@ _sig = {
     "pir_client_limbs": (ctypes.c_uint32, [ctypes.c_void_p, ctypes.c_uint32]),
     "pir_stale_rows": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_uint32]),
     "pir_hint_window_bits": (ctypes.c_uint32, [ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_set_tiled_copy": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "pir_tiled_copy": (ctypes.c_int32, [ctypes.c_void_p]),
     "pir_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
                                    ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                                    ctypes.POINTER(ctypes.c_uint64)]),
@@ -219,6 +221,13 @@ class Server:
 
     def stale_rows(self, cid: int | None = None) -> int:
         return _lib.pir_stale_rows(self._h, 0xFFFFFFFF if cid is None else cid)
+
+    def set_tiled_copy(self, enable: bool) -> None:
+        """Make (True) or free (False) the contraction's tiled copy of D (see pir_set_tiled_copy)."""
+        _check(_lib.pir_set_tiled_copy(self._h, 1 if enable else 0), "pir_set_tiled_copy")
+
+    def tiled_copy(self) -> bool:
+        return bool(_lib.pir_tiled_copy(self._h))
 
     def hint_window_bits(self, cid: int) -> int:
         """Window width of the fixed-base table the client's last hint used (8 or 11)."""

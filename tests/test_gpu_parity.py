@@ -315,12 +315,54 @@ def test_autotuned_shape_is_persisted(native, tmp_path, monkeypatch):
     A = _rand(71, (cols, 4), Q32, np.uint32)
     Qm = _rand(72, (batch, cols), Q32, np.uint32)
     with native.Server(D, A) as srv:
+        assert srv.tiled_copy()
         B = np.zeros((batch, rows), np.uint32)
+        srv.answer(Qm, B, native.PATH_MFMA)
+        assert np.array_equal(B, server.answer_batch(D, Qm))
+        srv.set_tiled_copy(False)  # the row-major layout is tuned under its own key
+        B[:] = 0
         srv.answer(Qm, B, native.PATH_MFMA)
         assert np.array_equal(B, server.answer_batch(D, Qm))
     lines = [l.split() for l in cache.read_text().splitlines()]
     mine = [l for l in lines if l[:5] == [str(rows), str(cols + (-cols) % 256), str(batch), "0", "4"]]
-    assert len(mine) == 1 and len(mine[0]) == 11
+    assert sorted(l[5] for l in mine) == ["0", "1"] and all(len(l) == 12 for l in mine)
+
+
+@pytest.mark.parametrize("rows,cols", [(1000, 3000), (16, 256), (4099, 700)])
+def test_tiled_copy_layouts(native, rows, cols):
+    # The contraction reads the tiled copy of D by default (so do the hint tests' H = D.A):
+    # batched answers equal the oracle for row counts that are not multiples of 16, after row
+    # updates (which rewrite the tiled rows too), with the copy freed (row-major D) and after it
+    # is made again.
+    log(f"tiled copy rows {rows} cols {cols}")
+    batch = 5
+    D = _rand(80 + rows, (rows, cols), 256, np.uint8)
+    A = _rand(81, (cols, 4), Q32, np.uint32)
+    Qm = _rand(82, (batch, cols), Q32, np.uint32)
+    upd = np.array(sorted({0, rows // 2, rows - 1}), np.uint32)
+    new = _rand(83, (len(upd), cols), 256, np.uint8)
+    with native.Server(D, A) as srv:
+        assert srv.tiled_copy()
+        B = np.zeros((batch, rows), np.uint32)
+        srv.answer(Qm, B, native.PATH_MFMA)
+        assert np.array_equal(B, server.answer_batch(D, Qm))
+        srv.update_rows(upd, new)
+        D2 = D.copy()
+        D2[upd] = new
+        want = server.answer_batch(D2, Qm)
+        B[:] = 0
+        srv.answer(Qm, B, native.PATH_MFMA)
+        assert np.array_equal(B, want)
+        srv.set_tiled_copy(False)
+        assert not srv.tiled_copy()
+        B[:] = 0
+        srv.answer(Qm, B, native.PATH_MFMA)
+        assert np.array_equal(B, want)
+        srv.set_tiled_copy(True)
+        assert srv.tiled_copy()
+        B[:] = 0
+        srv.answer(Qm, B, native.PATH_MFMA)
+        assert np.array_equal(B, want)
 
 
 def test_read_probe(native):
