@@ -177,31 +177,6 @@ __global__ __launch_bounds__(256) void combine_parts_kernel(ClientDev cd, const 
 // exchange inside the row adds them up.  A wave takes kCombineRows rows, four per pass, and
 // requests every pass's operands before the first pass computes.
 template <int P, bool kFull>
-__device__ __forceinline__ void rn_load_row(RNum<4 * P>& x, const uint32_t* __restrict__ src, int nl) {
-  constexpr int Q = 4 * P;
-  if (kFull) {
-    const u32x4* p = reinterpret_cast<const u32x4*>(src + Q * row_lane());
-#pragma unroll
-    for (int v = 0; v < Q / 4; ++v) {
-      const u32x4 w = p[v];
-      x.v[4 * v] = w.x; x.v[4 * v + 1] = w.y; x.v[4 * v + 2] = w.z; x.v[4 * v + 3] = w.w;
-    }
-  } else {  // indices clamped to the row; limbs at or beyond nl are zeroed before use
-    const int base = Q * row_lane();
-#pragma unroll
-    for (int j = 0; j < Q; ++j) x.v[j] = src[min(base + j, nl - 1)];
-  }
-}
-
-template <int P, bool kFull>
-__device__ __forceinline__ void rn_zero_above(RNum<4 * P>& x, int nl) {
-  if (kFull) return;
-  const int base = 4 * P * row_lane();
-#pragma unroll
-  for (int j = 0; j < 4 * P; ++j) x.v[j] = base + j < nl ? x.v[j] : 0u;
-}
-
-template <int P, bool kFull>
 __global__ __launch_bounds__(256) void combine_parts_quad_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
                                                                  const uint32_t* __restrict__ Mp,
                                                                  const uint32_t* __restrict__ part, int nseg,
@@ -242,15 +217,7 @@ __global__ __launch_bounds__(256) void combine_parts_quad_kernel(ClientDev cd, c
     rn_cond_sub(t[i], ovf, M2);
     if (mine < rows) {
       if (rl == 0) b[mine] = sum;
-      uint32_t* dst = C + (size_t)mine * cd.L;
-      if (kFull) {
-        u32x4* p = reinterpret_cast<u32x4*>(dst + Q * rl);
-#pragma unroll
-        for (int v = 0; v < Q / 4; ++v)
-          p[v] = u32x4{t[i].v[4 * v], t[i].v[4 * v + 1], t[i].v[4 * v + 2], t[i].v[4 * v + 3]};
-      } else {
-        rn_store_n(dst, t[i], cd.L);
-      }
+      rn_store_row<P, kFull>(C + (size_t)mine * cd.L, t[i], cd.L);
     }
   }
 }

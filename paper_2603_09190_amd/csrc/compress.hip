@@ -50,11 +50,65 @@ __global__ __launch_bounds__(256) void compress_kernel(ClientDev cd, const uint3
   }
 }
 
+// compress_kernel with four rows per wavefront, one per 16-lane row (rownum.h): Q = 4P limbs
+// per lane, 16-byte row pieces when the rows fill the lanes (kFull), and every row's K', M'
+// and b requested before the first row is reduced.
+template <int P, bool kFull>
+__global__ __launch_bounds__(256) void compress_quad_kernel(ClientDev cd, const uint32_t* __restrict__ Kp,
+                                                            const uint32_t* __restrict__ Mp,
+                                                            const uint32_t* __restrict__ b, int rows,
+                                                            uint32_t* __restrict__ C) {
+  constexpr int Q = 4 * P;
+  constexpr int kPasses = kRowsPerWave / 4;
+  const int wave = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row0 = wave * kRowsPerWave;
+  if (row0 >= rows) return;
+  RNum<Q> t[kPasses], m[kPasses];
+  uint32_t bj[kPasses];
+#pragma unroll
+  for (int i = 0; i < kPasses; ++i) {
+    const int row = min(rows - 1, row0 + 4 * i + row_index());
+    rn_load_row<P, kFull>(t[i], Kp + (size_t)row * cd.L, cd.L);
+    rn_load_row<P, kFull>(m[i], Mp + (size_t)row * cd.L, cd.L);
+    bj[i] = b[row];
+  }
+  RNum<Q> M2;
+  rn_load(M2, cd.N2);
+#pragma unroll
+  for (int i = 0; i < kPasses; ++i) {
+    if (row0 + 4 * i >= rows) break;
+    const int mine = row0 + 4 * i + row_index();
+    rn_zero_above<P, kFull>(t[i], cd.L);
+    rn_zero_above<P, kFull>(m[i], cd.L);
+    uint64_t c = 0;
+    rn_mont_step(t[i], c, bj[i], m[i], M2, cd.m2prime);
+    const uint64_t ovf = rn_resolve(t[i], c);
+    rn_cond_sub(t[i], ovf, M2);
+    if (mine < rows) rn_store_row<P, kFull>(C + (size_t)mine * cd.L, t[i], cd.L);
+  }
+}
+
 void launch_compress(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Mp,
                      const uint32_t* b, int rows, uint32_t* C, hipStream_t s) {
   if (rows <= 0) return;
   const int waves = (rows + kRowsPerWave - 1) / kRowsPerWave;
   const int blocks = (waves + 3) / 4;
+  if (rows >= kQuadItems) {  // four rows per wavefront once that still leaves several per SIMD
+    // 16-byte pieces need rows that fill the lanes and 16-byte aligned arrays
+    const bool full = cd.L == 64 * cd.P && ((reinterpret_cast<uintptr_t>(Kp) | reinterpret_cast<uintptr_t>(Mp) |
+                                              reinterpret_cast<uintptr_t>(C)) & 15) == 0;
+#define ZP_COMPRESS_QUAD(PP)                                                                        \
+  (full ? compress_quad_kernel<PP, true><<<blocks, 256, 0, s>>>(cd, Kp, Mp, b, rows, C)               \
+        : compress_quad_kernel<PP, false><<<blocks, 256, 0, s>>>(cd, Kp, Mp, b, rows, C))
+    switch (cd.P) {
+      case 1: ZP_COMPRESS_QUAD(1); break;
+      case 2: ZP_COMPRESS_QUAD(2); break;
+      case 3: ZP_COMPRESS_QUAD(3); break;
+      case 4: ZP_COMPRESS_QUAD(4); break;
+    }
+#undef ZP_COMPRESS_QUAD
+    return;
+  }
   switch (cd.P) {
     case 1: compress_kernel<1><<<blocks, 256, 0, s>>>(cd, Kp, Mp, b, rows, C); break;
     case 2: compress_kernel<2><<<blocks, 256, 0, s>>>(cd, Kp, Mp, b, rows, C); break;

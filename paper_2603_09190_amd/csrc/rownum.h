@@ -20,6 +20,8 @@
 
 namespace zp {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // as in internal.h
+
 // DPP row controls: row_shl:1 gives lane i of a row the value of lane i+1, row_shr:1 that of
 // lane i-1 (a lane without a source in its row keeps `old`, here 0); row_newbcast:k gives
 // every lane of a row the value of that row's lane k.
@@ -87,6 +89,49 @@ __device__ __forceinline__ void rn_store_n(uint32_t* __restrict__ dst, const RNu
 #pragma unroll
   for (int j = 0; j < P; ++j)
     if (base + j < nl) dst[base + j] = x.v[j];
+}
+
+// A row of 4P limbs per lane (Q = 4P) from a row array of nl limbs, for kernels that request
+// several rows' operands before using the first: with kFull (nl == 16 Q, 16-byte aligned
+// rows) each lane reads its limbs as 16-byte pieces; otherwise every lane loads at indices
+// clamped to the row, with no branch between the loads, and rn_zero_above clears the limbs at
+// or beyond nl before use.
+template <int P, bool kFull>
+__device__ __forceinline__ void rn_load_row(RNum<4 * P>& x, const uint32_t* __restrict__ src, int nl) {
+  constexpr int Q = 4 * P;
+  if (kFull) {
+    const u32x4* p = reinterpret_cast<const u32x4*>(src + Q * row_lane());
+#pragma unroll
+    for (int v = 0; v < Q / 4; ++v) {
+      const u32x4 w = p[v];
+      x.v[4 * v] = w.x; x.v[4 * v + 1] = w.y; x.v[4 * v + 2] = w.z; x.v[4 * v + 3] = w.w;
+    }
+  } else {
+    const int base = Q * row_lane();
+#pragma unroll
+    for (int j = 0; j < Q; ++j) x.v[j] = src[min(base + j, nl - 1)];
+  }
+}
+
+template <int P, bool kFull>
+__device__ __forceinline__ void rn_zero_above(RNum<4 * P>& x, int nl) {
+  if (kFull) return;
+  const int base = 4 * P * row_lane();
+#pragma unroll
+  for (int j = 0; j < 4 * P; ++j) x.v[j] = base + j < nl ? x.v[j] : 0u;
+}
+
+// The counterpart of rn_load_row for stores (kFull: 16-byte pieces).
+template <int P, bool kFull>
+__device__ __forceinline__ void rn_store_row(uint32_t* __restrict__ dst, const RNum<4 * P>& x, int nl) {
+  constexpr int Q = 4 * P;
+  if (kFull) {
+    u32x4* p = reinterpret_cast<u32x4*>(dst + Q * row_lane());
+#pragma unroll
+    for (int v = 0; v < Q / 4; ++v) p[v] = u32x4{x.v[4 * v], x.v[4 * v + 1], x.v[4 * v + 2], x.v[4 * v + 3]};
+  } else {
+    rn_store_n(dst, x, nl);
+  }
 }
 
 // Resolve pending per-lane carries; returns each row's carry out of its top limb.
