@@ -19,12 +19,6 @@ namespace zp {
 constexpr int kPartSegCols = 4096;   // columns per segment: 64 per lane, 4 x 16-byte pieces
 constexpr int kPartRowsPerWave = 32;
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
-  return v;
-}
-
 // The 16 query entries from column c0 as four byte planes: word t of plane b holds byte b of
 // entries c0 + 4t .. c0 + 4t + 3.  Entries at or beyond cols are zero.
 __device__ __forceinline__ void query_planes16(const uint32_t* __restrict__ q, int cols, int c0,
@@ -100,7 +94,7 @@ __global__ __launch_bounds__(256) void matvec_part_kernel(const uint8_t* __restr
           a[b] = __builtin_amdgcn_udot4(d[r][k].z, qp[k][b].z, a[b], false);
           a[b] = __builtin_amdgcn_udot4(d[r][k].w, qp[k][b].w, a[b], false);
         }
-      const uint32_t v = wave_sum_u32(a[0] + (a[1] << 8) + (a[2] << 16) + (a[3] << 24));
+      const uint32_t v = wave_sum64(a[0] + (a[1] << 8) + (a[2] << 16) + (a[3] << 24));
       if (lane == 0 && row + r < row_end) part[(size_t)(row + r) * nseg + seg] = v;
     }
   }
@@ -207,8 +201,7 @@ __global__ __launch_bounds__(256) void combine_parts_quad_kernel(ClientDev cd, c
     uint32_t sum = rl < nseg ? ps[i] : 0u;
     for (int s0 = 16; s0 < nseg; s0 += 16)  // more than 16 segments (over 65536 columns)
       sum += s0 + rl < nseg ? part[(size_t)row * nseg + s0 + rl] : 0u;
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) sum += (uint32_t)__shfl_xor((int)sum, off, 64);
+    sum = row_sum16(sum);
     rn_zero_above<P, kFull>(t[i], cd.L);
     rn_zero_above<P, kFull>(m[i], cd.L);
     uint64_t c = 0;

@@ -8,6 +8,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "wavenum.h"
 
 namespace zp {
 
@@ -35,12 +36,6 @@ void launch_pack_planes_u8(const uint32_t* q, int cols, int pitch, uint8_t* plan
                            int rows, hipStream_t s) {
   const int n4 = pitch / 4;
   pack_planes_u8_kernel<<<(n4 + 255) / 256, 256, 0, s>>>(q, cols, pitch, planes, b, rows);
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
-  return v;
 }
 
 // A wave owns 4096 columns of the query (64 per lane, as four
@@ -98,7 +93,7 @@ __global__ __launch_bounds__(256) void matvec_seg_kernel(const uint8_t* __restri
           a[b] = __builtin_amdgcn_udot4(d[r][k].w, q[k][b].w, a[b], false);
         }
       uint32_t v = a[0] + (a[1] << 8) + (a[2] << 16) + (a[3] << 24);
-      v = wave_sum(v);
+      v = wave_sum64(v);
       if (lane == 0 && row + r < row_end) atomicAdd(out + row + r, v);
     }
   }

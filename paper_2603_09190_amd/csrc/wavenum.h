@@ -43,6 +43,31 @@ __device__ __forceinline__ uint64_t from_prev_lane64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Sums by DPP quad permutes and row mirrors, VALU operand modifiers with no LDS round trip:
+// quad_perm [1,0,3,2] and [2,3,0,1] give every lane its quad's sum; row_half_mirror (lane i of
+// an 8-lane half takes lane 7-i) and row_mirror (lane i of a 16-lane row takes lane 15-i) then
+// pair each lane with the other quad and the other half.
+constexpr int kDppQuadXor1 = 0xB1;
+constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
+// Wrapping sum over the 16 lanes of each row, in every lane of that row.
+__device__ __forceinline__ uint32_t row_sum16(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppQuadXor1, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppQuadXor2, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowHalfMirror, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowMirror, 0xF, 0xF, false);
+  return v;
+}
+
+// Wrapping sum over all 64 lanes, wave-uniform: the four row sums read from lanes 0, 16, 32, 48.
+__device__ __forceinline__ uint32_t wave_sum64(uint32_t v) {
+  v = row_sum16(v);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+         (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
 __device__ __forceinline__ uint32_t bcast(uint32_t x, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
 }
