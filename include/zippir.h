@@ -114,7 +114,8 @@ pir_status pir_update_rows(pir_server *srv, const uint32_t *rows, uint32_t nrows
  * (j/16) 16 pitch + (i/64) 1024 + (j mod 16) 64 + i mod 64, so that each group of 16 rows is
  * one contiguous run over its whole width.  The contraction reads the tiled copy when there
  * is one, and D otherwise; both give identical bits.  The copy costs as much HBM as D.
- * pir_setup makes it when the allocation succeeds; pir_update_rows keeps it current.
+ * pir_setup makes it when at least an eighth of the device's memory (and 4 GiB) stays free
+ * after it; pir_update_rows keeps it current.
  *   pir_set_tiled_copy: enable != 0 makes it (PIR_ENOMEM if it does not fit), 0 frees it.
  *     Synchronizes the server's stream.
  *   pir_tiled_copy: 1 if the server has it, else 0 (also for NULL).

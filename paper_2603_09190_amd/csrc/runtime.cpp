@@ -369,11 +369,20 @@ pir_status use_device(pir_server* s) {
 }
 
 // Allocate and fill the contraction's tiled copy of D (rows rounded up to 16; the rows past
-// the last are never read).  PIR_ENOMEM leaves the server without one.
-pir_status build_tiled(pir_server* s) {
+// the last are never read).  PIR_ENOMEM leaves the server without one.  With headroom, the
+// copy is only made if at least an eighth of the device's memory (and 4 GiB) stays free for
+// hints, tables and batches after it.
+pir_status build_tiled(pir_server* s, bool headroom) {
   if (s->Dt) return PIR_OK;
   const size_t rows16 = ((size_t)s->rows + 15) / 16 * 16;
-  ZP_TRY(s->alloc((void**)&s->Dt, rows16 * s->pitch));
+  const size_t need = rows16 * s->pitch;
+  if (headroom) {
+    size_t free_b = 0, total_b = 0;
+    ZP_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t keep = std::max<size_t>(size_t(4) << 30, total_b / 8);
+    if (free_b < need + keep) return fail(PIR_ENOMEM, "no room for the tiled copy of D");
+  }
+  ZP_TRY(s->alloc((void**)&s->Dt, need));
   zp::launch_tile_rows(s->D, (int)s->pitch, nullptr, (int)s->rows, s->Dt, s->stream);
   ZP_HIP(hipGetLastError());
   return PIR_OK;
@@ -539,7 +548,7 @@ pir_status pir_setup(pir_server** out, int device, void* hip_stream, const uint8
   s->H_valid.assign(rows, 0);
   s->H_stale = rows;
   // the contraction's tiled copy, when HBM has room for it (otherwise it reads D)
-  if (build_tiled(s.get()) != PIR_OK) g_last_error.clear();
+  if (build_tiled(s.get(), true) != PIR_OK) g_last_error.clear();
   ZP_HIP(hipGetLastError());
   ZP_HIP(hipStreamSynchronize(st));
   *out = s.release();
@@ -561,7 +570,7 @@ pir_status pir_set_tiled_copy(pir_server* s, int32_t enable) {
   if (!s) return fail(PIR_EINVAL, "NULL server");
   ZP_TRY(use_device(s));
   if (enable) {
-    ZP_TRY(build_tiled(s));
+    ZP_TRY(build_tiled(s, false));
   } else if (s->Dt) {
     ZP_HIP(hipStreamSynchronize(s->stream));  // no launch may still read it
     s->release(s->Dt);
