@@ -240,8 +240,12 @@ void tune_load_locked() {
   const char* path = tune_cache_path();
   if (!path) return;
   std::ifstream f(path);
-  int r, p, n, m, pl, tl, w, d, mr, kb, k, cg;
-  while (f >> r >> p >> n >> m >> pl >> tl >> w >> d >> mr >> kb >> k >> cg) {
+  std::string line;
+  while (std::getline(f, line)) {  // lines of any other layout (an older cache) are skipped
+    std::istringstream in(line);
+    int r, p, n, m, pl, tl, w, d, mr, kb, k, cg, extra;
+    if (!(in >> r >> p >> n >> m >> pl >> tl >> w >> d >> mr >> kb >> k >> cg) || (in >> extra)) continue;
+    if ((tl != 0 && tl != 1) || (tl == 1 && pl != 4)) continue;
     const zp::GemmShape sh{w, d, mr, kb, k, cg};
     if (zp::gemm_shape_valid(sh, p, pl)) g_tune[TuneKey(r, p, n, m, pl, tl)] = sh;
   }
