@@ -119,10 +119,11 @@ void launch_compress(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Mp
 
 // Packed response (Alg. 3, online part, gamma = 2^t): for group g of ell rows,
 //   c_g = K_g (1 + beta_g N) mod N^2 = K_g + beta_g M_g mod N^2,  beta_g = sum_j b_{g ell + j} 2^(t j),
-// with M_g = N (K_g mod N) < N^2 kept in Montgomery form (Mr = M_g R mod N^2), so one
-// Montgomery product by the h-limb beta_g gives beta_g M_g mod N^2.  Since t >= 32 the answers
-// occupy disjoint bit ranges of beta_g: each limb takes at most two of them.  One wavefront
-// per group.
+// with M_g = N (K_g mod N) < N^2 kept as Mr = M_g 2^(32h) mod N^2.  beta_g < gamma^ell < N has
+// at most h limbs, so a Montgomery product truncated after those h steps (each dividing by
+// 2^32) gives beta_g M_g mod N^2: half the serial steps of a full product with R = 2^(32 S).
+// Since t >= 32 the answers occupy disjoint bit ranges of beta_g: each limb takes at most two
+// of them.  One wavefront per group.
 template <int P>
 __global__ __launch_bounds__(256) void compress_packed_kernel(
     ClientDev cd, const uint32_t* __restrict__ Kg, const uint32_t* __restrict__ Mr,
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void compress_packed_kernel(
   }
   wn_load_n(mr, Mr + (size_t)g * cd.L, cd.L);
   wn_load(M2, cd.N2);
-  mont_mul_short(acc, beta, cd.h, mr, M2, cd.m2prime);  // beta_g M_g mod N^2
+  mont_mul_trunc(acc, beta, cd.h, mr, M2, cd.m2prime);  // beta_g M_g mod N^2
   WNum<P> k;
   wn_load_n(k, Kg + (size_t)g * cd.L, cd.L);
   uint32_t carry = 0;

@@ -287,9 +287,12 @@ __global__ __launch_bounds__(256) void group_keys_kernel(ClientDev cd, const uin
   wn_store_n(Kg + (size_t)g * cd.L, acc, cd.L);
 }
 
+// x <- x 2^(32 limbs) mod N^2: one Montgomery product by R^2 mod N^2 (x R), then one by the
+// plain number 2^(32 limbs) (< N^2), which divides the R out again.
 template <int P>
-__global__ __launch_bounds__(256) void to_mont_kernel(ClientDev cd, uint32_t* __restrict__ x,
-                                                      const uint32_t* __restrict__ rowlist, int nrows) {
+__global__ __launch_bounds__(256) void mul_pow2_limbs_kernel(ClientDev cd, uint32_t* __restrict__ x,
+                                                             const uint32_t* __restrict__ rowlist, int nrows,
+                                                             int limbs) {
   const int widx = wave_index();
   if (widx >= nrows) return;
   const int row = rowlist ? (int)rowlist[widx] : widx;
@@ -298,6 +301,10 @@ __global__ __launch_bounds__(256) void to_mont_kernel(ClientDev cd, uint32_t* __
   wn_load(RR, cd.RR);
   wn_load_n(v, x + (size_t)row * cd.L, cd.L);
   mont_mul(v, v, RR, M, cd.m2prime);
+  WNum<P> e;
+#pragma unroll
+  for (int j = 0; j < P; ++j) e.v[j] = P * lane_id() + j == limbs ? 1u : 0u;
+  mont_mul(v, v, e, M, cd.m2prime);
   wn_store_n(x + (size_t)row * cd.L, v, cd.L);
 }
 
@@ -313,15 +320,15 @@ void launch_group_keys(const ClientDev& cd, const uint32_t* Kp, int rows, int el
   }
 }
 
-void launch_to_mont(const ClientDev& cd, uint32_t* x, const uint32_t* rowlist, int nrows,
-                    hipStream_t s) {
+void launch_mul_pow2_limbs(const ClientDev& cd, uint32_t* x, const uint32_t* rowlist, int nrows,
+                           int limbs, hipStream_t s) {
   if (nrows <= 0) return;
   const int blocks = (nrows + 3) / 4;
   switch (cd.P) {
-    case 1: to_mont_kernel<1><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows); break;
-    case 2: to_mont_kernel<2><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows); break;
-    case 3: to_mont_kernel<3><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows); break;
-    case 4: to_mont_kernel<4><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows); break;
+    case 1: mul_pow2_limbs_kernel<1><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows, limbs); break;
+    case 2: mul_pow2_limbs_kernel<2><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows, limbs); break;
+    case 3: mul_pow2_limbs_kernel<3><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows, limbs); break;
+    case 4: mul_pow2_limbs_kernel<4><<<blocks, 256, 0, s>>>(cd, x, rowlist, nrows, limbs); break;
   }
 }
 

@@ -147,10 +147,10 @@ void launch_unscale(const ClientDev& cd, const uint32_t* Kp, int row0, int nrows
 // Kg[g] = prod_{j} K_{g ell + j}^{2^(t j)} mod N^2 (canonical) for the listed groups, from K'.
 void launch_group_keys(const ClientDev& cd, const uint32_t* Kp, int rows, int ell, int t,
                        const uint32_t* glist, int ngroups, uint32_t* Kg, hipStream_t s);
-// x[i] <- x[i] R mod N^2 for the listed rows of an L-limb array (Montgomery form).
-void launch_to_mont(const ClientDev& cd, uint32_t* x, const uint32_t* rowlist, int nrows,
-                    hipStream_t s);
-// C[g] = K_g + beta_g M_g mod N^2 with beta_g = sum_j b[g ell + j] 2^(t j); Mr holds M_g R.
+// x[i] <- x[i] 2^(32 limbs) mod N^2 for the listed rows of an L-limb array (2^(32 limbs) < N^2).
+void launch_mul_pow2_limbs(const ClientDev& cd, uint32_t* x, const uint32_t* rowlist, int nrows,
+                           int limbs, hipStream_t s);
+// C[g] = K_g + beta_g M_g mod N^2 with beta_g = sum_j b[g ell + j] 2^(t j); Mr holds M_g 2^(32h).
 void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint32_t* Mr,
                             const uint32_t* b, int rows, int ell, int t, uint32_t* C, hipStream_t s);
 

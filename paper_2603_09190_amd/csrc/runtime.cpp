@@ -74,7 +74,7 @@ struct ClientState {
   // packed responses (batched compression): ell rows per ciphertext, gamma = 2^t
   uint32_t ell = 1, t = 0, ell_max = 1;
   uint32_t* Kg = nullptr;      // groups x L: group keys K_g
-  uint32_t* Mr = nullptr;      // groups x L: N (K_g mod N) R mod N^2
+  uint32_t* Mr = nullptr;      // groups x L: N (K_g mod N) 2^(32h) mod N^2
   uint32_t* Yg = nullptr;      // groups x h: (K_g mod N) R_N mod N, the packed offset-combine key
   uint32_t* PJ = nullptr;      // ell_max x SN: 2^(t j) R_N mod N, the packed offset-answer weights
   std::vector<uint8_t> gvalid; // per group
@@ -477,7 +477,8 @@ pir_status refresh_groups(pir_server* s, ClientState* c, std::vector<uint32_t> g
   }
   zp::launch_group_keys(cd, c->Kp, (int)s->rows, (int)c->ell, (int)c->t, dg, ng, c->Kg, st);
   zp::launch_combine_key(cd, c->Kg, dg, ng, c->Mr, c->Yg, st, false);
-  zp::launch_to_mont(cd, c->Mr, dg, ng, st);
+  // M_g 2^(32h): the packed combine's Montgomery product then takes only beta_g's h limbs
+  zp::launch_mul_pow2_limbs(cd, c->Mr, dg, ng, (int)cd.h, st);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (dg) s->release(dg);

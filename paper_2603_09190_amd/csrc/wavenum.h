@@ -238,6 +238,21 @@ __device__ __forceinline__ void mont_mul(WNum<P>& out, const WNum<P>& a, const W
   out = t;
 }
 
+// a b 2^(-32 na) mod m, canonical, for a < 2^(32 na) given by its first na limbs and b < m:
+// the first na CIOS steps only (each divides by 2^32).  The CIOS bound keeps every partial
+// value below 2m, so one conditional subtraction finishes.
+template <int P>
+__device__ __forceinline__ void mont_mul_trunc(WNum<P>& out, const WNum<P>& a, int na,
+                                               const WNum<P>& b, const WNum<P>& m, uint32_t mprime) {
+  WNum<P> t;
+  wn_zero(t);
+  uint64_t c = 0;
+  for (int i = 0; i < na; ++i) mont_step(t, c, wn_limb(a, i), b, m, mprime);
+  const uint64_t ovf = wn_resolve(t, c);
+  wn_cond_sub(t, ovf, m);
+  out = t;
+}
+
 // Montgomery multiplication by a number given only through its first `na` limbs
 // (the remaining limbs are zero): skips the zero limbs of a.
 template <int P>
