@@ -393,6 +393,24 @@ def main() -> int:
         srv.client_hint(cid, 0, cr, Kh)
         K_ints = [wl.limbs_to_int(Kh[j]) for j in range(cr)]
         cpu = cpu_baseline(D, Qh[0], K_ints, N, cr)
+
+    # incremental update (Sec. 6): 1 % of the rows get fresh bytes, then H and K are refreshed
+    # for those rows only.  The first round also tunes the contraction for the gathered rows'
+    # shape; the second is timed.
+    upd = None
+    for rnd in range(2):
+        upd_idx, upd_new = wl.update_rows(5 + rnd, rows, cols, 0.01)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        srv.update_rows(upd_idx, upd_new)
+        t1 = time.perf_counter()
+        srv.hint(cid, upd_idx)
+        t2 = time.perf_counter()
+        upd = {"rows": int(len(upd_idx)), "update_rows_ms": round((t1 - t0) * 1e3, 2),
+               "hint_refresh_ms": round((t2 - t1) * 1e3, 2), "total_ms": round((t2 - t0) * 1e3, 2),
+               "window_bits": srv.hint_window_bits(cid), "stale_rows_after": int(srv.stale_rows(cid)),
+               "note": "update_rows copies the new rows from pageable host memory"}
+    log(f"update of {upd['rows']} rows: {upd['total_ms']} ms")
     srv.close()
 
     out = {
@@ -428,6 +446,7 @@ def main() -> int:
         "offline_hint_s": round(hint_s, 3),
         "hint_kernel_ms": round(hintk_ms, 1),
         "hint": hint_fig,
+        "update": upd,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
