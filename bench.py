@@ -410,7 +410,16 @@ def main() -> int:
                "hint_refresh_ms": round((t2 - t1) * 1e3, 2), "total_ms": round((t2 - t0) * 1e3, 2),
                "window_bits": srv.hint_window_bits(cid), "stale_rows_after": int(srv.stale_rows(cid)),
                "note": "update_rows copies the new rows from pageable host memory"}
-    log(f"update of {upd['rows']} rows: {upd['total_ms']} ms")
+    # where the refresh goes: the same update once more with the library's event timing
+    upd_idx, upd_new = wl.update_rows(7, rows, cols, 0.01)
+    srv.update_rows(upd_idx, upd_new)
+    srv.profile(True)
+    srv.hint(cid, upd_idx)
+    parts = {nm: srv.profile_read(nm)[0] for nm in ("gemm", "table", "hint", "key")}
+    srv.profile(False)
+    upd["kernel_ms"] = {"H_rows": round(parts["gemm"], 3), "table": round(parts["table"], 3),
+                        "K_rows": round(parts["hint"], 3), "combine_key": round(parts["key"], 3)}
+    log(f"update of {upd['rows']} rows: {upd['total_ms']} ms ({upd['kernel_ms']})")
     srv.close()
 
     out = {

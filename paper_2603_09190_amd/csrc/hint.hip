@@ -15,6 +15,8 @@
 // every value stays in Montgomery form (x R mod N^2) until the final conversion, which stores
 // K'_j = K_j 2^32 mod N^2 (the form the online combine consumes; pir_get_client_hint converts
 // back to K_j).
+#include <algorithm>
+
 #include "internal.h"
 #include "rownum.h"
 #include "wavenum.h"
@@ -128,6 +130,67 @@ __global__ __launch_bounds__(256) void hint_rows_kernel(ClientDev cd, const uint
     }
   }
   // leave Montgomery form scaled by 2^32: acc * 2^32 * R^{-1} = K_j * 2^32 mod N^2
+  WNum<P> two32;
+  wn_zero(two32);
+  if (lane_id() == 1 / P) two32.v[1 % P] = 1;
+  mont_mul(acc, acc, two32, M, cd.m2prime);
+  wn_store_n(K + (size_t)row * cd.L, acc, cd.L);
+}
+
+// Few rows: each row's product over its n bases is split into `parts` chains of `span` bases,
+// one wavefront per (row, part), and the parts are multiplied together afterwards.  A wave
+// otherwise has to run all n W products of its row in sequence, each waiting for its table
+// entry, and a few hundred rows cannot fill the chip.  Partial products stay in Montgomery
+// form: partial[(i parts + part) S ..] for row index i < nrows.
+template <int P>
+__global__ __launch_bounds__(256) void hint_parts_kernel(ClientDev cd, const uint32_t* __restrict__ H,
+                                                         int n, const uint32_t* __restrict__ rowlist,
+                                                         int nrows, const uint32_t* __restrict__ table,
+                                                         int wbits, int parts, int span,
+                                                         uint32_t* __restrict__ partial) {
+  constexpr int S = 64 * P;
+  const int item = wave_index();
+  if (item >= nrows * parts) return;
+  const int i = item / parts, part = item - i * parts;
+  const int row = rowlist ? (int)rowlist[i] : i;
+  const int windows = (32 + wbits - 1) / wbits;
+  const uint32_t digits = (1u << wbits) - 1;
+  WNum<P> M, acc, b;
+  wn_load(M, cd.N2);
+  wn_load(acc, cd.R1);  // Montgomery form of 1
+  const uint32_t* hrow = H + (size_t)row * n;
+  const int k1 = min(n, (part + 1) * span);
+  for (int k = part * span; k < k1; ++k) {
+    const uint32_t e = 0u - hrow[k];  // (-H_jk) mod 2^32
+    const uint32_t* tk = table + (size_t)k * windows * digits * S;
+    for (int w = 0; w < windows; ++w) {
+      const uint32_t d = (e >> (wbits * w)) & digits;
+      if (d != 0) {
+        wn_load(b, tk + ((size_t)w * digits + (d - 1)) * S);
+        mont_mul(acc, acc, b, M, cd.m2prime);
+      }
+    }
+  }
+  wn_store(partial + (size_t)item * S, acc);
+}
+
+// K'_j from row i's parts: their Montgomery product, left scaled by 2^32 as in hint_rows_kernel.
+template <int P>
+__global__ __launch_bounds__(256) void hint_join_kernel(ClientDev cd, const uint32_t* __restrict__ partial,
+                                                        int parts, const uint32_t* __restrict__ rowlist,
+                                                        int nrows, uint32_t* __restrict__ K) {
+  constexpr int S = 64 * P;
+  const int i = wave_index();
+  if (i >= nrows) return;
+  const int row = rowlist ? (int)rowlist[i] : i;
+  WNum<P> M, acc, b;
+  wn_load(M, cd.N2);
+  const uint32_t* pr = partial + (size_t)i * parts * S;
+  wn_load(acc, pr);
+  for (int p = 1; p < parts; ++p) {
+    wn_load(b, pr + (size_t)p * S);
+    mont_mul(acc, acc, b, M, cd.m2prime);
+  }
   WNum<P> two32;
   wn_zero(two32);
   if (lane_id() == 1 / P) two32.v[1 % P] = 1;
@@ -334,8 +397,9 @@ void launch_mul_pow2_limbs(const ClientDev& cd, uint32_t* x, const uint32_t* row
 
 void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int windows,
                         uint32_t* table, hipStream_t s, int wbits) {
-  // wide windows: four segments per (base, window) keep enough wavefronts in flight
-  const int segs = wbits > 8 ? 4 : 1;
+  // four segments per (base, window): four times the wavefronts, each with a quarter of the
+  // chain of products
+  const int segs = 4;
   if (n <= 0 || windows <= 0) return;
   // four bases per wavefront while that still leaves several wavefronts per SIMD
   const long long quad_waves = (long long)((n + 3) / 4) * windows * segs;
@@ -357,6 +421,34 @@ void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int wind
     case 3: build_table_kernel<3><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
     case 4: build_table_kernel<4><<<blocks, 256, 0, s>>>(cd, ck, n, windows, wbits, segs, table); break;
   }
+}
+
+int hint_parts(int nrows, int n) {
+  if (nrows >= kSplitRowsBelow || n < 2) return 1;
+  // enough (row, part) items to fill the chip, but at most 64 parts: the join multiplies a
+  // row's parts in sequence, so its chain grows with their number
+  const int want = std::min({n, 64, (int)((kQuadItems + nrows - 1) / nrows)});
+  const int span = (n + want - 1) / want;
+  return (n + span - 1) / span;  // no empty part
+}
+
+void launch_hint_rows_split(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
+                            int nrows, const uint32_t* table, int wbits, int parts, uint32_t* partial,
+                            uint32_t* K, hipStream_t s) {
+  if (nrows <= 0) return;
+  const int span = (n + parts - 1) / parts;
+  const long long items = (long long)nrows * parts;
+  const int blocks = (int)((items + 3) / 4), jblocks = (nrows + 3) / 4;
+#define ZP_SPLIT(PP)                                                                                \
+  hint_parts_kernel<PP><<<blocks, 256, 0, s>>>(cd, H, n, rowlist, nrows, table, wbits, parts, span, partial); \
+  hint_join_kernel<PP><<<jblocks, 256, 0, s>>>(cd, partial, parts, rowlist, nrows, K)
+  switch (cd.P) {
+    case 1: ZP_SPLIT(1); break;
+    case 2: ZP_SPLIT(2); break;
+    case 3: ZP_SPLIT(3); break;
+    case 4: ZP_SPLIT(4); break;
+  }
+#undef ZP_SPLIT
 }
 
 void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,

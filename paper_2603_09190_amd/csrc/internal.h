@@ -134,6 +134,13 @@ void launch_build_table(const ClientDev& cd, const uint32_t* ck, int n, int wind
 // table of ceil(32 / wbits) windows.  Writes K'_j = K_j 2^32 mod N^2 (rows x L limbs).
 void launch_hint_rows(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
                       int nrows, const uint32_t* table, int wbits, uint32_t* Kp, hipStream_t s);
+// The same for few rows (hint_parts(nrows, n) > 1): each row's bases split into that many parts,
+// one wavefront each, then joined; partial holds nrows x parts x 64P limbs.
+constexpr int kSplitRowsBelow = 4096;
+int hint_parts(int nrows, int n);
+void launch_hint_rows_split(const ClientDev& cd, const uint32_t* H, int n, const uint32_t* rowlist,
+                            int nrows, const uint32_t* table, int wbits, int parts, uint32_t* partial,
+                            uint32_t* Kp, hipStream_t s);
 // M'_j = N (K'_j mod N) (rows x L limbs), the combine key.
 // (Y, when not NULL: rows x h, Y[row] = (K mod N) R_N mod N for the offset combine, where
 // K = Kp 2^-32 when `scaled` and K = Kp otherwise.)

@@ -749,9 +749,18 @@ pir_status pir_hint(pir_server* s, uint32_t id, const uint32_t* rows, uint32_t n
     }
     (void)hipMemcpyAsync(drows, sel.data(), sel.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
   }
+  const int parts = zp::hint_parts(m, (int)s->n);
+  uint32_t* partial = nullptr;
+  if (parts > 1 && s->alloc((void**)&partial, (size_t)m * parts * c->S * sizeof(uint32_t)) != PIR_OK) {
+    g_last_error.clear();  // no room for the partial products: one wavefront per row
+    partial = nullptr;
+  }
   {
     ProfScope ps(s, PIR_KERNEL_HINT);
-    zp::launch_hint_rows(cd, s->H, (int)s->n, drows, m, table, wbits, c->Kp, st);
+    if (partial)
+      zp::launch_hint_rows_split(cd, s->H, (int)s->n, drows, m, table, wbits, parts, partial, c->Kp, st);
+    else
+      zp::launch_hint_rows(cd, s->H, (int)s->n, drows, m, table, wbits, c->Kp, st);
   }
   {
     ProfScope ps(s, PIR_KERNEL_KEY);
@@ -760,6 +769,7 @@ pir_status pir_hint(pir_server* s, uint32_t id, const uint32_t* rows, uint32_t n
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   s->release(table);
+  if (partial) s->release(partial);
   if (drows) s->release(drows);
   if (e != hipSuccess) return fail(PIR_EDEVICE, std::string("hint kernels: ") + hipGetErrorString(e));
   if (all) {

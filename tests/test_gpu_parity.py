@@ -415,6 +415,40 @@ def test_hint_four_rows_per_wave_ragged_count(native):
     assert K_or[rows - 1] == 1
 
 
+@pytest.mark.parametrize("rows,n", [(1101, 250), (300, 250), (1, 64)])
+def test_hint_split_rows(native, rows, n):
+    # Under 4096 rows each row's product over its n bases is split into parts, one wavefront
+    # per (row, part), and the parts are joined: 1101 rows x 15 parts of 17 bases (the last
+    # part 12), 300 rows x 50 parts of 5, a single row 64 parts of one base.  K equals the
+    # oracle on every row, and a re-hint of a few rows after an update equals it too.
+    log(f"hint split rows {rows} n {n}")
+    cols, n_bits = 64, 256
+    inst = make_instance(cfg=960 + rows, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False)
+    cl = inst.clients[0]
+    N_limbs, ck, L = client_arrays(cl, n_bits)
+    upd = np.array(sorted({0, rows // 2, rows - 1}), np.uint32)
+    new = _rand(961, (len(upd), cols), 256, np.uint8)
+    D2 = inst.D.copy()
+    D2[upd] = new
+    with native.Server(inst.D, inst.A) as srv:
+        cid = srv.add_client(N_limbs, n_bits, ck)
+        srv.hint(cid)
+        K = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K)
+        srv.update_rows(upd, new)
+        srv.hint(cid, rows=upd)
+        K2 = np.zeros((rows, L), np.uint32)
+        srv.client_hint(cid, 0, rows, K2)
+    with Pool(pool_size()) as pool:
+        K_or = oracle_client_hint(cl.ck, server.exponents(server.global_hint(inst.D, inst.A)), cl.N, pool=pool)
+        K2_or = oracle_client_hint(cl.ck, server.exponents(server.global_hint(D2, inst.A, rows=upd)), cl.N, pool=pool)
+    assert limbs_rows_to_ints(K) == [K_or[j] for j in range(rows)]
+    got2 = limbs_rows_to_ints(K2[upd])
+    assert got2 == [K2_or[j] for j in range(len(upd))]
+    keep = np.setdiff1d(np.arange(rows), upd)
+    assert np.array_equal(K2[keep], K[keep])
+
+
 def test_empty_and_degenerate_inputs(native):
     # empty shapes are rejected; a 1 x 1 database answers and compresses; empty row lists
     # of an update are a no-op; an empty compressor batch does nothing
