@@ -44,9 +44,9 @@ def montmul_macs(n_limbs: int) -> int:
 # HBM bytes per launch of the matvec on the 1 GiB database, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (calibrated on a plain 1 GiB device copy), keyed by the SHA-256 of the matvec
 # source they were taken on: a changed kernel reports null until the counters are re-taken.
-MATVEC_TRAFFIC = {"a3a2ed2492cf10af": 1083165084}
+MATVEC_TRAFFIC = {"0a75c1f39ae39d63": 1083207299}
 # The same for the one-call step's matvec (matvec_part_kernel, in answer.hip).
-STEP_TRAFFIC = {"84ad8428d96d552e": 1076606319}
+STEP_TRAFFIC = {"84ad8428d96d552e": 1076585960}
 
 
 def source_hash(name: str) -> str:
@@ -355,7 +355,7 @@ def main() -> int:
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "matvec_part_kernel<4>", "kernel_avg_us": round(mv_avg_ms * 1e3, 2),
             "bytes_per_launch": mv_bytes,
-            "three_launch_matvec": {"kernel": "matvec_seg_kernel<2>",
+            "three_launch_matvec": {"kernel": "matvec_seg_kernel<4>",
                                     "kernel_avg_us": three_launch["matvec_kernel_avg_us"],
                                     "traffic": MATVEC_TRAFFIC.get(source_hash("matvec.hip"))
                                     if (rows, cols) == (32768, 32768) else None}}

@@ -112,7 +112,7 @@ void launch_matvec(const uint8_t* D, int rows, int pitch, const uint8_t* planes,
   for (int r0 = 0; r0 < rows; r0 += chunk_rows) {
     const int nr = std::min(chunk_rows, rows - r0);
     dim3 grid((nr + 4 * kSegRowsPerWave - 1) / (4 * kSegRowsPerWave), (pitch + kSegCols - 1) / kSegCols);
-    matvec_seg_kernel<2><<<grid, 256, 0, s>>>(D + (size_t)r0 * pitch, nr, pitch, planes, b + r0,
+    matvec_seg_kernel<4><<<grid, 256, 0, s>>>(D + (size_t)r0 * pitch, nr, pitch, planes, b + r0,
                                               kSegRowsPerWave);
   }
 }
