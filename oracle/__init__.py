@@ -12,7 +12,9 @@ the paper (ZipPIR: High-throughput Single-server PIR without Client-side Storage
 * ``protocol`` -- the paper's full protocol (Alg. 5 with random hint keys and the online
                   offset answer t = b + E.ck_o mod N; Sec. 4.3 Paillier addition).
 * ``compress`` -- standalone LWE and RLWE ciphertext compression (Alg. 2, packed keys of
-                  Alg. 9, RLWE coefficients of Alg. 8).
+                  Alg. 6, RLWE coefficients of Alg. 8).
+* ``prg``      -- the seed expansion of the silent offline phase (Sec. 4.3): ChaCha20
+                  (RFC 8439) and the rejection sampler of random hint keys in Z_{N^2}.
 * ``brute``    -- the same quantities by pure-Python loops, for tiny sizes.
 * ``params``   -- the parameter conditions (Theorem 1 of Sec. 3.1, the ZipPIR correctness
                   condition of Sec. 4.2).
@@ -22,4 +24,4 @@ import this package.  It shares no code with the GPU library and never imports i
 Integer arithmetic is exact: numpy uint64 products wrap modulo 2^64, which is exact
 modulo 2^32 after masking; everything modulo N^2 uses Python integers and ``pow``.
 """
-from . import brute, compress, lwe, paillier, params, protocol, server  # noqa: F401
+from . import brute, compress, lwe, paillier, params, prg, protocol, server  # noqa: F401
