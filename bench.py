@@ -89,15 +89,28 @@ def percentile(xs, q):
     return s[k]
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo; "unknown" where it is not readable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(D, qu, K_ints, N, sample_rows):
-    """The CPU oracle on the first `sample_rows` rows: answer + combine, in GB/s of D."""
+    """The CPU oracle on the first `sample_rows` rows: answer + combine, in GB/s of D.  The
+    oracle runs single-threaded (numpy's integer matmul and Python integers use one core)."""
     from oracle import server as osrv
     t0 = time.perf_counter()
     b = osrv.answer(D[:sample_rows], qu)
     osrv.compress(K_ints[:sample_rows], b, N)
     dt = time.perf_counter() - t0
     return {"value": round(sample_rows * D.shape[1] / dt / 1e9, 6), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpu_count": os.cpu_count(),
             "sample": f"rows 0..{sample_rows - 1} of the 1 GiB database ({sample_rows} x {D.shape[1]} bytes): "
                       f"numpy matvec mod 2^32 + Python-int combine K*(N+1)^b mod N^2, single thread, "
                       f"{dt:.1f} s"}

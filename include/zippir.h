@@ -65,8 +65,10 @@ typedef int32_t pir_status;
  *   out      receives the new server handle (NULL on failure).
  *   device   HIP device ordinal; hip_stream is a hipStream_t on that device (NULL = default).
  *   D        rows x cols uint8, row-major.   A  cols x n uint32, row-major.
- * rows, cols, n >= 1.  The global hint H is computed lazily by the first pir_hint.
- * Errors: PIR_EINVAL (zero size, NULL pointer), PIR_ENOMEM, PIR_EDEVICE.
+ * 1 <= rows <= 2^30, 1 <= cols <= 2^24, 1 <= n <= 2^16.  The global hint H is computed
+ * lazily by the first pir_hint.
+ * Errors: PIR_EINVAL (zero or too large a size, NULL pointer; checked before any device
+ * call), PIR_ENOMEM, PIR_EDEVICE.
  */
 pir_status pir_setup(pir_server **out, int device, void *hip_stream,
                      const uint8_t *D, uint32_t rows, uint32_t cols,
@@ -85,6 +87,33 @@ void pir_destroy(pir_server *srv);
  */
 pir_status pir_add_client(pir_server *srv, const uint32_t *N, uint32_t N_bits,
                           const uint32_t *ck, uint32_t ptr_flags, uint32_t *client_id);
+
+/*
+ * Silent offline phase (Sec. 4.3, "Lowering offline communication costs" and "Supporting
+ * multiple queries"): the client sends only N and a 32-byte seed, and the server expands the
+ * seed into the random ciphertexts ck_r of Alg. 5's Setup, one n-vector per query, on the
+ * device.  Registers `count` clients, one per query index first_query .. first_query+count-1,
+ * each with its own key and hint (pir_hint, pir_offset_answer, pir_compress_offset, ...), and
+ * writes their ids to client_ids (a host array of count entries).
+ *   N, N_bits  as for pir_add_client (N read from host or device memory per ptr_flags).
+ *   seed       32 bytes in host memory: the ChaCha20 key (RFC 8439).
+ * Entry k of query q is uniform over [0, N^2): the ChaCha20 keystream under the 96-bit nonce
+ * (q, k, r) (three little-endian words; r the attempt, from 0), read from block 0 on as
+ * little-endian 32-bit words w_i, gives the candidate sum_i w_i 2^(32 i) over
+ * ceil(bits(N^2)/32) words cut to bits(N^2) bits; the first candidate below N^2 is taken.
+ * The client derives the same ck_r from the seed and decrypts it at query time.
+ * count in [1, 4096].  Errors: PIR_EINVAL (as pir_add_client; count), PIR_ENOMEM,
+ * PIR_EDEVICE (also if an entry is rejected 64 times in a row, probability below 2^-64).
+ * On error no client is registered.
+ */
+pir_status pir_add_client_seeded(pir_server *srv, const uint32_t *N, uint32_t N_bits,
+                                 const uint8_t *seed, uint32_t first_query, uint32_t count,
+                                 uint32_t ptr_flags, uint32_t *client_ids);
+
+/* Copy entries [k0, k0+nk) of a client's key ck (nk x L uint32): the uploaded ciphertexts, or
+ * the ones expanded from a seed.  PIR_EINVAL for an unknown id or a range beyond n. */
+pir_status pir_get_client_key(pir_server *srv, uint32_t client_id, uint32_t k0, uint32_t nk,
+                              uint32_t *ck, uint32_t ptr_flags);
 
 /* Drop a client and free its hint.  PIR_EINVAL for an unknown id. */
 pir_status pir_remove_client(pir_server *srv, uint32_t client_id);
@@ -236,10 +265,10 @@ pir_status pir_compress_offset_packed(pir_server *srv, const uint32_t *client_id
  *
  * pir_compressor_create: ck is n x L uint32 (L = 2 ceil(N_bits/32), little-endian, each below
  *   N^2).  stream: a hipStream_t (NULL: the default stream).
- * pir_compressor_create_packed: the key is given packed (Sec. 3.2, Alg. 9): pck holds
+ * pir_compressor_create_packed: the key is given packed (Sec. 3.2, Alg. 6): pck holds
  *   ceil(n/t) ciphertexts of t secret digits each, scaled for unpacking with
  *   delta = 2^delta_log2, and the device unpacks ck[it+j] = pck_i^(delta^(t-1-j)).  The client
- *   then decrypts with Alg. 9's ModifiedLWEDecryptPackedKey.
+ *   then decrypts with Alg. 6's ModifiedLWEDecryptPackedKey.
  * pir_compress_lwe: X[r] = (1 + B[r] N) prod_i ck_i^((q - A[r][i]) mod q) mod N^2 for
  *   r < rows.  A is rows x n entries and B rows entries; an entry is one uint32 when
  *   q <= 2^32, else two (little-endian uint64); entries are reduced mod q.  X is rows x L.

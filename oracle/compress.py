@@ -5,7 +5,7 @@ the appendix), written as plain definitions.  Test infrastructure only.
   Paillier product and k (x) c = c^k; b enters as Enc(b; 1) = (N+1)^b.  With reading
   (q - a_i) mod q every exponent lies in [0, q).
 * Alg. 2, ModifiedLWEDecrypt: mu** = Dec(x) mod q, mu'' = round(mu** / Delta) mod p.
-* Alg. 9 (appendix A, Sec. 3.2): packed compression keys.  t = floor(0.5 log2 m / log2 delta)
+* Alg. 6 (appendix A, Sec. 3.2): packed compression keys.  t = floor(0.5 log2 m / log2 delta)
   secret digits share one ciphertext pck_i = Enc(delta^-(t-1) sum_j s[it+j] delta^j mod m);
   the server unpacks ck[it+j] = delta^(t-1-j) (x) pck_i, and the client decrypts with
   y = delta^(t-1) Dec(x) mod m, mu** = floor(y / delta^(t-1)) mod q.  delta must exceed the
@@ -45,7 +45,7 @@ def lwe_phase_plaintext(a, b: int, s, q: int) -> int:
     return int(b) + sum(((q - int(ai)) % q) * int(si) for ai, si in zip(a, s))
 
 
-# ----------------------------------------------------------------------------- Alg. 9 (packed keys)
+# ----------------------------------------------------------------------------- Alg. 6 (packed keys)
 
 def packed_digits_per_key(m_bits: int, delta: int) -> int:
     """t = floor(0.5 log2 m / log2 delta), log2 m taken as m_bits."""

@@ -1,6 +1,6 @@
 // Host side of the standalone compressor (pir_compressor_* and pir_compress_lwe/rlwe in
 // zippir.h): the compression key and its fixed-base table stay resident; each call compresses
-// a batch of LWE ciphertexts or RLWE coefficients (Alg. 2, Alg. 8; packed keys of Alg. 9).
+// a batch of LWE ciphertexts or RLWE coefficients (Alg. 2, Alg. 8; packed keys of Alg. 6).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

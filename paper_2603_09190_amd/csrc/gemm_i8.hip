@@ -33,8 +33,8 @@ __global__ __launch_bounds__(256) void pack_planes_s8_kernel(const uint32_t* __r
                                                              long long stride_i, int cols,
                                                              int pitch, int8_t* __restrict__ Xs,
                                                              int32_t* __restrict__ colsum) {
-  const int c = blockIdx.y;
-  const int i4 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.x;
+  const int i4 = blockIdx.y * blockDim.x + threadIdx.x;
   int32_t part[4] = {0, 0, 0, 0};
   if (4 * i4 < pitch) {
     uint32_t w[4] = {0, 0, 0, 0};
@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void pack_planes_s8_kernel(const uint32_t* __r
 void launch_pack_planes_s8(const uint32_t* x, long long stride_c, long long stride_i, int ncol,
                            int cols, int pitch, int8_t* Xs, int32_t* colsum, hipStream_t s) {
   (void)hipMemsetAsync(colsum, 0, sizeof(int32_t) * 4 * (size_t)ncol, s);
-  dim3 grid((pitch / 4 + 255) / 256, ncol);
+  // vectors on x (up to 2^31 blocks), 1024-column pieces on y (at most 2^14 for pitch <= 2^24)
+  dim3 grid(ncol, (pitch / 4 + 255) / 256);
   pack_planes_s8_kernel<<<grid, 256, 0, s>>>(x, stride_c, stride_i, cols, pitch, Xs, colsum);
 }
 
@@ -163,6 +164,10 @@ __device__ __forceinline__ void gemm_planes_body(
   }
   constexpr int kPieces = kPl * kBC * (kKB / 16) / (64 * kW);
   static_assert(kPieces >= 1 && kPieces * 64 * kW == kPl * kBC * (kKB / 16), "X tile split");
+  // The X tile's offsets are kept relative to the block's first vector: at most 32 kPl vectors
+  // (one plane each, kWide) or 32 vectors of kPl planes, so below 128 pitch, which fits 32 bits
+  // for every pitch the library accepts (at most 2^24).  Only the block base is 64-bit.
+  const int8_t* __restrict__ xbase = Xs + (size_t)cblk * (kWide ? 1 : kPl) * pitch + (size_t)kstep0 * kKB;
   int xoff[kPieces], lrow[kPieces], lcol[kPieces];
   bool xval[kPieces];
 #pragma unroll
@@ -174,7 +179,8 @@ __device__ __forceinline__ void gemm_planes_body(
     const int c = kWide ? cblk + lrow[t] : cblk + (lrow[t] & 31);
     xval[t] = c < ncol;
     // vectors beyond ncol read vector ncol-1 (a valid address) and are zeroed in the stash
-    xoff[t] = (kWide ? min(c, ncol - 1) : min(c, ncol - 1) * kPl + b) * pitch + kstep0 * kKB + lcol[t];
+    const int cr = min(c, ncol - 1) - cblk;
+    xoff[t] = (kWide ? cr : cr * kPl + b) * pitch + lcol[t];
   }
 
   v4i acc[kMR][2][kPl];
@@ -209,7 +215,7 @@ __device__ __forceinline__ void gemm_planes_body(
   auto load_x = [&](int xb, int st) {
 #pragma unroll
     for (int t = 0; t < kPieces; ++t)
-      xn[xb][t] = *reinterpret_cast<const u32x4*>(Xs + (size_t)xoff[t] + (size_t)st * kKB);
+      xn[xb][t] = *reinterpret_cast<const u32x4*>(xbase + (size_t)xoff[t] + (size_t)st * kKB);
   };
   // Vectors beyond ncol are zeroed here, when the data is consumed: a select right after the
   // load would make the wave wait for it (and, the load counter being in order, for every

@@ -215,8 +215,27 @@ void launch_reduce_parts(const ClientDev& cd, const LweBatch& lb, const uint32_t
 void launch_unpack_keys(const ClientDev& cd, const uint32_t* pck, int n, int t, int dbits,
                         uint32_t* ck, hipStream_t s);
 
-// ---- runtime.cpp accessors used by the serving engine
+// ---- prg.hip (random hint keys of the silent offline phase)
+// The 32-byte seed as eight little-endian words: the ChaCha20 key (RFC 8439).
+struct SeedKey {
+  uint32_t w[8];
+};
+// out[(i n + k) L ...] = ck_r[k] of query first_query + i (i < count, k < n): the first
+// ChaCha20 candidate below N^2 (N2: W words, the low bits(N^2) bits kept by top_mask on word
+// W-1), zero-padded to L limbs.  Entries rejected kMaxAttempts times add one to *failures.
+void launch_expand_key(const SeedKey& key, uint32_t first_query, int n, int count, const uint32_t* N2, int W,
+                       uint32_t top_mask, int L, uint32_t* out, unsigned* failures, hipStream_t s);
+
+// ---- runtime.cpp accessors used by the serving engine and the no-alloc entry point
 hipStream_t server_stream(pir_server* s);
+void server_shape(pir_server* s, uint32_t* rows, uint32_t* cols);
+// pir_answer_compress's checks (client known and current, at most 64 column segments; nseg
+// receives their number; the server's device made current) and its two launches on device
+// arrays (dQ 16-byte aligned, part nseg x rows words), with no device allocation; `events`
+// false skips the pir_profile events (whose creation allocates).
+pir_status answer_compress_check(pir_server* s, uint32_t id, int* nseg);
+pir_status answer_compress_launch(pir_server* s, uint32_t id, const uint32_t* dQ, uint32_t* dB, uint32_t* dC,
+                                  uint32_t* part, bool events = true);
 void set_error(const char* msg);  // sets the calling thread's pir_last_error() text
 int server_device(pir_server* s);
 

@@ -13,7 +13,7 @@
 // together in a tree of fan-in `fan`; with many ciphertexts one wavefront per ciphertext is
 // enough to fill the GPU.
 //
-// Packed compression keys (Alg. 9, delta = 2^dbits): ck[it+j] = pck_i^(delta^(t-1-j)), i.e.
+// Packed compression keys (Alg. 6, delta = 2^dbits): ck[it+j] = pck_i^(delta^(t-1-j)), i.e.
 // dbits (t-1-j) Montgomery squarings of pck_i.
 #include "internal.h"
 #include "rownum.h"

@@ -44,9 +44,9 @@ __global__ __launch_bounds__(256) void pack_offset_kernel(const uint32_t* __rest
                                                           int h, int cpc, int epitch,
                                                           int8_t* __restrict__ X,
                                                           int32_t* __restrict__ colsum) {
-  const int col = blockIdx.y;
+  const int col = blockIdx.x;
   const int client = col / cpc, pos = col - client * cpc;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;  // one K quadruple (4k .. 4k+3)
+  const int k = blockIdx.y * blockDim.x + threadIdx.x;  // one K quadruple (4k .. 4k+3)
   int32_t part = 0;
   if (4 * k < epitch) {
     uint32_t w = 0;
@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void pack_offset_kernel(const uint32_t* __rest
 void launch_pack_offset(const uint32_t* cko, int batch, int n, int h, int cpc, int epitch,
                         int8_t* X, int32_t* colsum, hipStream_t s) {
   (void)hipMemsetAsync(colsum, 0, sizeof(int32_t) * (size_t)batch * cpc, s);
-  dim3 grid((epitch / 4 + 255) / 256, batch * cpc);
+  // columns on x (batch cpc reaches 66048 at batch 128 and 4096-bit N), K on y (at most 64)
+  dim3 grid(batch * cpc, (epitch / 4 + 255) / 256);
   pack_offset_kernel<<<grid, 256, 0, s>>>(cko, n, h, cpc, epitch, X, colsum);
 }
 

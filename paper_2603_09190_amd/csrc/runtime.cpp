@@ -496,6 +496,46 @@ pir_status refresh_groups(pir_server* s, ClientState* c, std::vector<uint32_t> g
   return PIR_OK;
 }
 
+// The one-call step's checks and launches, shared by pir_answer_compress and its no-alloc
+// variant.  answer_compress_check: the client exists with a complete hint and the database
+// has at most 64 column segments (nseg receives their number); makes the server's device
+// current.  answer_compress_launch: the two launches on device arrays, the query 16-byte
+// aligned, part holding nseg x rows words.
+pir_status zp::answer_compress_check(pir_server* s, uint32_t id, int* nseg) {
+  ClientState* c = find_client(s, id);
+  if (!c) return fail(PIR_EINVAL, "unknown client id " + std::to_string(id));
+  if (c->stale != 0)
+    return fail(PIR_ESTALE, "client " + std::to_string(id) + " has " + std::to_string(c->stale) +
+                                " stale hint rows");
+  *nseg = zp::answer_segments((int)s->pitch);
+  if (*nseg > 64) return fail(PIR_EINVAL, "database wider than 262144 columns: use pir_answer and pir_compress");
+  return use_device(s);
+}
+
+pir_status zp::answer_compress_launch(pir_server* s, uint32_t id, const uint32_t* dQ, uint32_t* dB, uint32_t* dC,
+                                      uint32_t* part, bool events) {
+  ClientState* c = find_client(s, id);
+  hipStream_t st = s->stream;
+  const int nseg = zp::answer_segments((int)s->pitch);
+  // the profiling events (pir_profile) are created per launch, so the no-alloc caller skips them
+  pir_server* ps_srv = events ? s : nullptr;
+  {
+    std::unique_ptr<ProfScope> ps(ps_srv ? new ProfScope(ps_srv, PIR_KERNEL_STEP_MATVEC) : nullptr);
+    zp::launch_matvec_part(s->D, (int)s->rows, (int)s->pitch, dQ, (int)s->cols, part, st);
+  }
+  {
+    std::unique_ptr<ProfScope> ps(ps_srv ? new ProfScope(ps_srv, PIR_KERNEL_STEP_COMBINE) : nullptr);
+    zp::launch_combine_parts(c->dev(), c->Kp, c->Mp, part, nseg, (int)s->rows, dB, dC, st);
+  }
+  ZP_HIP(hipGetLastError());
+  return PIR_OK;
+}
+
+void zp::server_shape(pir_server* s, uint32_t* rows, uint32_t* cols) {
+  *rows = s->rows;
+  *cols = s->cols;
+}
+
 // ============================================================================= C ABI
 
 extern "C" {
@@ -523,8 +563,10 @@ pir_status pir_setup(pir_server** out, int device, void* hip_stream, const uint8
   ZP_TRY(check_flags(ptr_flags));
   if (!D || !A || rows == 0 || cols == 0 || n == 0)
     return fail(PIR_EINVAL, "D and A must be non-NULL and rows, cols, n >= 1");
-  if (cols > (1u << 30) || rows > (1u << 30) || n > (1u << 16))
-    return fail(PIR_EINVAL, "shape too large");
+  // cols <= 2^24 keeps every in-kernel offset within a column block below 2^31 and every
+  // grid dimension below its hardware limit
+  if (cols > (1u << 24) || rows > (1u << 30) || n > (1u << 16))
+    return fail(PIR_EINVAL, "shape too large (cols <= 2^24, rows <= 2^30, n <= 2^16)");
   int ndev = 0;
   ZP_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(PIR_EINVAL, "no such device");
@@ -587,13 +629,19 @@ pir_status pir_set_tiled_copy(pir_server* s, int32_t enable) {
 
 int32_t pir_tiled_copy(const pir_server* s) { return s && s->Dt ? 1 : 0; }
 
-pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, const uint32_t* ck,
-                          uint32_t ptr_flags, uint32_t* client_id) {
-  g_last_error.clear();
-  if (!s || !N || !ck || !client_id) return fail(PIR_EINVAL, "NULL argument");
-  ZP_TRY(check_flags(ptr_flags));
-  if (N_bits < 64 || N_bits > 4096) return fail(PIR_EINVAL, "N_bits must be in [64, 4096]");
-  ZP_TRY(use_device(s));
+}  // extern "C"
+
+// Frees every device buffer of a client (null pointers are skipped).
+static void release_client(pir_server* s, ClientState* c) {
+  for (void* p : {(void*)c->ck, (void*)c->consts, (void*)c->Kp, (void*)c->Mp, (void*)c->Y, (void*)c->PJ,
+                  (void*)c->Kg, (void*)c->Mr, (void*)c->Yg})
+    s->release(p);
+}
+
+// A new client of modulus N (h host limbs) without its key: checks N against Theorem 1,
+// derives the Montgomery constants and packing weights, and allocates the key (n x L limbs,
+// filled by the caller), K', M' and Y.  On failure nothing stays allocated.
+static pir_status new_client(pir_server* s, const Big& Nin, uint32_t N_bits, std::unique_ptr<ClientState>& out) {
   auto c = std::make_unique<ClientState>();
   c->n_bits = N_bits;
   c->h = (N_bits + 31) / 32;
@@ -602,11 +650,7 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
   c->PN = (c->h + 63) / 64;
   c->S = 64 * c->P;
   c->SN = 64 * c->PN;
-  c->N.assign(c->h, 0u);
-  if (ptr_flags == PIR_PTR_DEVICE)
-    ZP_HIP(hipMemcpy(c->N.data(), N, c->h * sizeof(uint32_t), hipMemcpyDeviceToHost));
-  else
-    std::memcpy(c->N.data(), N, c->h * sizeof(uint32_t));
+  c->N = Nin;
   if (bit_length(c->N) != N_bits) return fail(PIR_EINVAL, "N does not have exactly N_bits bits");
   if ((c->N[0] & 1u) == 0) return fail(PIR_EINVAL, "N must be odd");
   // Theorem 1: N > q + n q^2 with q = 2^32, i.e. N > 2^32 + n * 2^64
@@ -628,53 +672,148 @@ pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, con
   c->m2prime = c->mc.m2prime;
   c->nprime = c->mc.nprime;
   const std::vector<uint32_t>& host = c->mc.host;
-  const Big N2 = big_mul(c->N, c->N);
-
-  hipStream_t st = s->stream;
-  {
-    std::vector<uint32_t> pj((size_t)c->ell_max * c->SN, 0u);
-    for (uint32_t j = 0; j < c->ell_max; ++j) {
-      const Big v = big_pow2_mod((uint64_t)c->t * j + 32ull * c->SN, c->N);
-      std::copy(v.begin(), v.begin() + std::min<size_t>(v.size(), c->SN), pj.begin() + (size_t)j * c->SN);
-    }
-    ZP_TRY(s->alloc((void**)&c->PJ, pj.size() * sizeof(uint32_t)));
-    ZP_HIP(hipMemcpy(c->PJ, pj.data(), pj.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  std::vector<uint32_t> pj((size_t)c->ell_max * c->SN, 0u);
+  for (uint32_t j = 0; j < c->ell_max; ++j) {
+    const Big v = big_pow2_mod((uint64_t)c->t * j + 32ull * c->SN, c->N);
+    std::copy(v.begin(), v.begin() + std::min<size_t>(v.size(), c->SN), pj.begin() + (size_t)j * c->SN);
   }
-  ZP_TRY(s->alloc((void**)&c->consts, host.size() * sizeof(uint32_t)));
-  ZP_HIP(hipMemcpyAsync(c->consts, host.data(), host.size() * sizeof(uint32_t),
-                        hipMemcpyHostToDevice, st));
-  const size_t ckbytes = (size_t)s->n * c->L * sizeof(uint32_t);
-  ZP_TRY(s->alloc((void**)&c->ck, ckbytes));
-  ZP_HIP(hipMemcpyAsync(c->ck, ck, ckbytes, kind_to_dev(ptr_flags), st));
-  // every ciphertext must be a residue mod N^2
-  {
-    std::vector<uint32_t> hck((size_t)s->n * c->L);
-    ZP_HIP(hipMemcpyAsync(hck.data(), c->ck, ckbytes, hipMemcpyDeviceToHost, st));
-    ZP_HIP(hipStreamSynchronize(st));
-    const Big N2L = big_resize(N2, c->L);
-    for (uint32_t k = 0; k < s->n; ++k) {
-      Big v(hck.begin() + (size_t)k * c->L, hck.begin() + (size_t)(k + 1) * c->L);
-      if (big_cmp(v, N2L) >= 0) {
-        s->release(c->ck);
-        s->release(c->consts);
-        s->release(c->PJ);
-        return fail(PIR_EINVAL, "ck[" + std::to_string(k) + "] is not below N^2");
-      }
-    }
-  }
-  pir_status a = s->alloc((void**)&c->Kp, (size_t)s->rows * c->L * sizeof(uint32_t));
+  pir_status a = s->alloc((void**)&c->PJ, pj.size() * sizeof(uint32_t));
+  if (a == PIR_OK) a = s->alloc((void**)&c->consts, host.size() * sizeof(uint32_t));
+  if (a == PIR_OK) a = s->alloc((void**)&c->ck, (size_t)s->n * c->L * sizeof(uint32_t));
+  if (a == PIR_OK) a = s->alloc((void**)&c->Kp, (size_t)s->rows * c->L * sizeof(uint32_t));
   if (a == PIR_OK) a = s->alloc((void**)&c->Mp, (size_t)s->rows * c->L * sizeof(uint32_t));
   if (a == PIR_OK) a = s->alloc((void**)&c->Y, (size_t)s->rows * c->h * sizeof(uint32_t));
+  hipError_t e = hipSuccess;
+  if (a == PIR_OK) e = hipMemcpy(c->PJ, pj.data(), pj.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (a == PIR_OK && e == hipSuccess)
+    e = hipMemcpyAsync(c->consts, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream);
+  if (a == PIR_OK && e != hipSuccess) a = fail(PIR_EDEVICE, std::string("client constants: ") + hipGetErrorString(e));
   if (a != PIR_OK) {
-    for (void* p : {(void*)c->ck, (void*)c->consts, (void*)c->Kp, (void*)c->Mp, (void*)c->Y, (void*)c->PJ})
-      s->release(p);
+    release_client(s, c.get());
     return a;
   }
   c->valid.assign(s->rows, 0);
   c->stale = s->rows;
+  out = std::move(c);
+  return PIR_OK;
+}
+
+static pir_status read_modulus(const uint32_t* N, uint32_t N_bits, uint32_t ptr_flags, Big& out) {
+  if (N_bits < 64 || N_bits > 4096) return fail(PIR_EINVAL, "N_bits must be in [64, 4096]");
+  const uint32_t h = (N_bits + 31) / 32;
+  out.assign(h, 0u);
+  if (ptr_flags == PIR_PTR_DEVICE)
+    ZP_HIP(hipMemcpy(out.data(), N, h * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(out.data(), N, h * sizeof(uint32_t));
+  return PIR_OK;
+}
+
+extern "C" {
+
+pir_status pir_add_client(pir_server* s, const uint32_t* N, uint32_t N_bits, const uint32_t* ck,
+                          uint32_t ptr_flags, uint32_t* client_id) {
+  g_last_error.clear();
+  if (!s || !N || !ck || !client_id) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  ZP_TRY(use_device(s));
+  Big Nh;
+  ZP_TRY(read_modulus(N, N_bits, ptr_flags, Nh));
+  std::unique_ptr<ClientState> c;
+  ZP_TRY(new_client(s, Nh, N_bits, c));
+  hipStream_t st = s->stream;
+  const size_t ckbytes = (size_t)s->n * c->L * sizeof(uint32_t);
+  // every ciphertext must be a residue mod N^2
+  std::vector<uint32_t> hck((size_t)s->n * c->L);
+  hipError_t e = hipMemcpyAsync(c->ck, ck, ckbytes, kind_to_dev(ptr_flags), st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hck.data(), c->ck, ckbytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    release_client(s, c.get());
+    return fail(PIR_EDEVICE, std::string("copying ck: ") + hipGetErrorString(e));
+  }
+  const Big N2L = big_resize(big_mul(c->N, c->N), c->L);
+  for (uint32_t k = 0; k < s->n; ++k) {
+    Big v(hck.begin() + (size_t)k * c->L, hck.begin() + (size_t)(k + 1) * c->L);
+    if (big_cmp(v, N2L) >= 0) {
+      release_client(s, c.get());
+      return fail(PIR_EINVAL, "ck[" + std::to_string(k) + "] is not below N^2");
+    }
+  }
   c->id = s->next_id++;
   *client_id = c->id;
   s->clients[c->id] = std::move(c);
+  return PIR_OK;
+}
+
+pir_status pir_add_client_seeded(pir_server* s, const uint32_t* N, uint32_t N_bits, const uint8_t* seed,
+                                 uint32_t first_query, uint32_t count, uint32_t ptr_flags,
+                                 uint32_t* client_ids) {
+  g_last_error.clear();
+  if (!s || !N || !seed || !client_ids) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  if (count < 1 || count > 4096) return fail(PIR_EINVAL, "count must be in [1, 4096]");
+  if ((uint64_t)first_query + count > (1ull << 32)) return fail(PIR_EINVAL, "query indices beyond 2^32");
+  ZP_TRY(use_device(s));
+  Big Nh;
+  ZP_TRY(read_modulus(N, N_bits, ptr_flags, Nh));
+  zp::SeedKey key;
+  for (int i = 0; i < 8; ++i)
+    key.w[i] = (uint32_t)seed[4 * i] | ((uint32_t)seed[4 * i + 1] << 8) | ((uint32_t)seed[4 * i + 2] << 16) |
+               ((uint32_t)seed[4 * i + 3] << 24);
+  const Big N2 = big_mul(Nh, Nh);
+  const uint32_t nbits2 = bit_length(N2);
+  const int W = (int)((nbits2 + 31) / 32);
+  const uint32_t top_mask = (nbits2 % 32) ? ((1u << (nbits2 % 32)) - 1u) : 0xFFFFFFFFu;
+  unsigned* fails = nullptr;
+  ZP_TRY(s->alloc((void**)&fails, sizeof(unsigned)));
+  hipStream_t st = s->stream;
+  std::vector<std::unique_ptr<ClientState>> made;
+  pir_status rc = PIR_OK;
+  hipError_t e = hipMemsetAsync(fails, 0, sizeof(unsigned), st);
+  if (e != hipSuccess) rc = fail(PIR_EDEVICE, std::string("seeded keys: ") + hipGetErrorString(e));
+  for (uint32_t i = 0; i < count && rc == PIR_OK; ++i) {
+    std::unique_ptr<ClientState> c;
+    rc = new_client(s, Nh, N_bits, c);
+    if (rc != PIR_OK) break;
+    const zp::ClientDev cd = c->dev();
+    zp::launch_expand_key(key, first_query + i, (int)s->n, 1, cd.N2, W, top_mask, (int)c->L, c->ck, fails, st);
+    made.push_back(std::move(c));
+  }
+  unsigned bad = 0;
+  if (rc == PIR_OK) {
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, fails, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(PIR_EDEVICE, std::string("seeded keys: ") + hipGetErrorString(e));
+    else if (bad != 0) rc = fail(PIR_EDEVICE, "seeded keys: an entry was rejected 64 times in a row");
+  }
+  (void)hipStreamSynchronize(st);
+  s->release(fails);
+  if (rc != PIR_OK) {
+    for (auto& c : made) release_client(s, c.get());
+    return rc;
+  }
+  for (uint32_t i = 0; i < count; ++i) {
+    made[i]->id = s->next_id++;
+    client_ids[i] = made[i]->id;
+    s->clients[made[i]->id] = std::move(made[i]);
+  }
+  return PIR_OK;
+}
+
+pir_status pir_get_client_key(pir_server* s, uint32_t id, uint32_t k0, uint32_t nk, uint32_t* ck,
+                              uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !ck) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  ClientState* c = find_client(s, id);
+  if (!c) return fail(PIR_EINVAL, "unknown client id");
+  if ((uint64_t)k0 + nk > s->n) return fail(PIR_EINVAL, "key range out of bounds");
+  ZP_TRY(use_device(s));
+  ZP_HIP(hipMemcpyAsync(ck, c->ck + (size_t)k0 * c->L, (size_t)nk * c->L * sizeof(uint32_t),
+                        kind_from_dev(ptr_flags), s->stream));
+  if (ptr_flags == PIR_PTR_HOST) ZP_HIP(hipStreamSynchronize(s->stream));
   return PIR_OK;
 }
 
@@ -685,15 +824,7 @@ pir_status pir_remove_client(pir_server* s, uint32_t id) {
   if (!c) return fail(PIR_EINVAL, "unknown client id");
   ZP_TRY(use_device(s));
   ZP_HIP(hipStreamSynchronize(s->stream));
-  s->release(c->ck);
-  s->release(c->consts);
-  s->release(c->Kp);
-  s->release(c->Mp);
-  s->release(c->Y);
-  s->release(c->Kg);
-  s->release(c->Mr);
-  s->release(c->Yg);
-  s->release(c->PJ);
+  release_client(s, c);
   s->clients.erase(id);
   return PIR_OK;
 }
@@ -963,14 +1094,9 @@ pir_status pir_answer_compress(pir_server* s, const uint32_t* Q, uint32_t id, ui
   g_last_error.clear();
   if (!s || !Q || !B || !C) return fail(PIR_EINVAL, "NULL argument");
   ZP_TRY(check_flags(ptr_flags));
+  int nseg = 0;
+  ZP_TRY(zp::answer_compress_check(s, id, &nseg));
   ClientState* c = find_client(s, id);
-  if (!c) return fail(PIR_EINVAL, "unknown client id " + std::to_string(id));
-  if (c->stale != 0)
-    return fail(PIR_ESTALE, "client " + std::to_string(id) + " has " + std::to_string(c->stale) +
-                                " stale hint rows");
-  const int nseg = zp::answer_segments((int)s->pitch);
-  if (nseg > 64) return fail(PIR_EINVAL, "database wider than 262144 columns: use pir_answer and pir_compress");
-  ZP_TRY(use_device(s));
   hipStream_t st = s->stream;
   const uint32_t L = c->L;
   const uint32_t* dQ = Q;
@@ -994,16 +1120,7 @@ pir_status pir_answer_compress(pir_server* s, const uint32_t* Q, uint32_t id, ui
     dQ = (const uint32_t*)s->s_q.p;
   }
   ZP_TRY(s->scratch(s->s_part, (size_t)nseg * s->rows * sizeof(uint32_t)));
-  auto* part = (uint32_t*)s->s_part.p;
-  {
-    ProfScope ps(s, PIR_KERNEL_STEP_MATVEC);
-    zp::launch_matvec_part(s->D, (int)s->rows, (int)s->pitch, dQ, (int)s->cols, part, st);
-  }
-  {
-    ProfScope ps(s, PIR_KERNEL_STEP_COMBINE);
-    zp::launch_combine_parts(c->dev(), c->Kp, c->Mp, part, nseg, (int)s->rows, dB, dC, st);
-  }
-  ZP_HIP(hipGetLastError());
+  ZP_TRY(zp::answer_compress_launch(s, id, dQ, dB, dC, (uint32_t*)s->s_part.p));
   if (ptr_flags == PIR_PTR_HOST) {
     ZP_HIP(hipMemcpyAsync(B, dB, bbytes, hipMemcpyDeviceToHost, st));
     ZP_HIP(hipMemcpyAsync(C, dC, cbytes, hipMemcpyDeviceToHost, st));

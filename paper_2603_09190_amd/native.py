@@ -41,6 +41,11 @@ _sig = {
     "pir_add_client": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                         ctypes.c_void_p, ctypes.c_uint32,
                                         ctypes.POINTER(ctypes.c_uint32)]),
+    "pir_add_client_seeded": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                               ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                               ctypes.c_uint32, ctypes.c_void_p]),
+    "pir_get_client_key": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_void_p, ctypes.c_uint32]),
     "pir_remove_client": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32]),
     "pir_hint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_update_rows": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
@@ -212,6 +217,21 @@ class Server:
         _check(_lib.pir_add_client(self._h, _ptr(N_limbs)[0], N_bits, _ptr(ck)[0], _flags(N_limbs, ck),
                                    ctypes.byref(cid)), "pir_add_client")
         return cid.value
+
+    def add_client_seeded(self, N_limbs, N_bits: int, seed: bytes, first_query: int, count: int) -> list:
+        """Clients for queries first_query .. first_query+count-1 whose keys the device expands
+        from the 32-byte seed (pir_add_client_seeded); returns their ids."""
+        if len(seed) != 32:
+            raise ValueError("seed must be 32 bytes")
+        sb = ctypes.create_string_buffer(bytes(seed), 32)
+        ids = np.zeros(count, np.uint32)
+        _check(_lib.pir_add_client_seeded(self._h, _ptr(N_limbs)[0], N_bits, ctypes.cast(sb, ctypes.c_void_p),
+                                          first_query, count, _flags(N_limbs), ctypes.c_void_p(ids.ctypes.data)),
+               "pir_add_client_seeded")
+        return [int(x) for x in ids]
+
+    def client_key(self, cid: int, k0: int, nk: int, out) -> None:
+        _check(_lib.pir_get_client_key(self._h, cid, k0, nk, _ptr(out)[0], _flags(out)), "pir_get_client_key")
 
     def remove_client(self, cid: int) -> None:
         _check(_lib.pir_remove_client(self._h, cid), "pir_remove_client")

@@ -69,3 +69,18 @@ def test_engine_policy_plan():
     assert native.engine_plan([128], 32) == 1
     assert native.engine_plan([], 32) == 0
     assert native.engine_plan([64, 64], 0) == 0
+
+
+@pytest.mark.parametrize("rows,cols,n", [(4, (1 << 24) + 1, 4), ((1 << 30) + 1, 4, 4), (4, 4, (1 << 16) + 1)])
+def test_setup_rejects_oversized_shapes_without_touching_the_gpu(lib, rows, cols, n):
+    # Shapes beyond the documented limits (cols <= 2^24 keeps in-kernel offsets and grid
+    # dimensions in range) fail with PIR_EINVAL before any device call; the pointers are
+    # never read.
+    lib.pir_setup.restype = ctypes.c_int32
+    lib.pir_last_error.restype = ctypes.c_char_p
+    dummy = ctypes.create_string_buffer(16)
+    h = ctypes.c_void_p()
+    st = lib.pir_setup(ctypes.byref(h), 0, None, dummy, ctypes.c_uint32(rows), ctypes.c_uint32(cols), dummy,
+                       ctypes.c_uint32(n), 0)
+    assert st == -1 and h.value is None
+    assert b"shape too large" in lib.pir_last_error()

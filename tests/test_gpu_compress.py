@@ -1,5 +1,5 @@
 """GPU parity of standalone compression (Sec. 3): LWE ciphertexts (Alg. 2) at the Table 2
-moduli, RLWE coefficients (Alg. 8) and packed compression keys (Alg. 9).
+moduli, RLWE coefficients (Alg. 8) and packed compression keys (Alg. 6).
 
 Every compressed ciphertext is compared bit for bit with ``oracle.compress`` on the same seeded
 inputs, and the client's decryption recovers the encrypted message (Theorem 1 and its RLWE
@@ -183,7 +183,7 @@ def test_rlwe_coefficients_match_oracle(native):
 
 
 def test_packed_key(native):
-    # Alg. 9 with delta = 2^bitlen(q + n q^2): the device unpacks the key like the oracle, and
+    # Alg. 6 with delta = 2^bitlen(q + n q^2): the device unpacks the key like the oracle, and
     # compression with it decrypts through the packed-key decryption.
     q, p, n, N_bits = 1 << 32, 16, 20, 1024
     sk = _key(995, N_bits)

@@ -20,7 +20,7 @@ import pytest
 import workload as wl
 from oracle import lwe, paillier, server
 from tests.gpu_util import client_arrays, limbs_rows_to_ints, log, pool_size
-from tests.instances import make_client, oracle_client_hint
+from tests.instances import _hint_row_job, make_client, oracle_client_hint
 
 pytestmark = pytest.mark.gpu
 
@@ -94,23 +94,29 @@ def test_c2_one_query_full(native, big):
         log("fullsize c2: oracle answer (all rows)")
         b_or = server.answer(D, cl.qu)
         assert np.array_equal(b_gpu, b_or)
-        log(f"fullsize c2: oracle hint on {len(rows)} rows")
-        H = server.global_hint(D, A, rows=rows)
-        E = server.exponents(H)
-        K_or = oracle_client_hint(cl.ck, E, cl.N, rows=None, pool=pool)
-    for i, j in enumerate(rows):
-        assert wl.limbs_to_int(K_gpu[j]) == K_or[i], f"K row {j}"
-        c_or = server.compress_row(K_or[i], int(b_or[j]), cl.N)
+        # the sampled rows, and every row of the three checked packed groups (first, the zero
+        # row's, the short last one): K from the oracle for all of them
+        pgroups = (0, ZERO_ROW // ell, G - 1)
+        grows = [j for g in pgroups for j in range(g * ell, min(SIDE, g * ell + ell))]
+        krows = sorted(set(rows) | set(grows))
+        log(f"fullsize c2: oracle hint on {len(krows)} rows")
+        E = server.exponents(server.global_hint(D, A, rows=krows))
+        K_list = oracle_client_hint(cl.ck, E, cl.N, rows=None, pool=pool)
+        K_or = {j: K_list[i] for i, j in enumerate(krows)}
+    for j in krows:
+        assert wl.limbs_to_int(K_gpu[j]) == K_or[j], f"K row {j}"
+    for j in rows:
+        c_or = server.compress_row(K_or[j], int(b_or[j]), cl.N)
         assert wl.limbs_to_int(C_gpu[j]) == c_or, f"c row {j}"
         mu = paillier.decrypt(cl.sk, c_or)
         assert lwe.pir_extract_value(mu) == int(D[j, cl.col]), f"round trip row {j}"
-    assert wl.limbs_to_int(K_gpu[ZERO_ROW]) == 1
-    # packed groups: first, the zero row's, last (17 rows); every row's digit decrypts to D
+    assert K_or[ZERO_ROW] == 1
+    # packed groups from the oracle's K: every row's digit decrypts to D
     log("fullsize c2: packed groups vs oracle")
     gamma = 1 << t
-    for g in (0, ZERO_ROW // ell, G - 1):
+    for g in pgroups:
         r0, r1 = g * ell, min(SIDE, g * ell + ell)
-        Kg = [wl.limbs_to_int(K_gpu[j]) for j in range(r0, r1)]
+        Kg = [K_or[j] for j in range(r0, r1)]
         want = server.compress_packed(Kg, b_or[r0:r1], cl.N, ell, gamma)[0]
         assert wl.limbs_to_int(Cp_gpu[g]) == want, f"packed group {g}"
         digits = server.packed_digits(paillier.decrypt(cl.sk, want), r1 - r0, gamma)
@@ -153,26 +159,23 @@ def test_c3_batch32_full(native, big):
             for i, j in enumerate(rows):
                 srv.client_hint(cid, j, 1, Ks[ci, i:i + 1])
     log("fullsize c3: oracle on sampled rows")
-    Dr = D[rows].astype(np.uint64)
-    B_or = ((Dr @ Q.astype(np.uint64).T) & np.uint64(0xFFFFFFFF)).astype(np.uint32).T
+    B_or = np.stack([server.answer_rows(D, Q[c], rows) for c in range(batch)])
     assert np.array_equal(B[:, rows], B_or)
     H = server.global_hint(D, A, rows=rows)
     E = server.exponents(H)
     jobs = []
     for ci, c in enumerate(clients[:4]):  # Paillier rows of four clients (the others share the kernels)
         jobs.append((ci, c))
+    # every sampled row of four clients, and two sampled rows (the first and one more) of each
+    # other client: K and c from the oracle, all (client, row) pairs in one pool
+    pairs = [(ci, i) for ci, _ in jobs for i in range(len(rows))]
+    pairs += [(ci, i) for ci in range(4, batch) for i in (0, 1 + (ci * 7) % (len(rows) - 1))]
     with Pool(pool_size()) as pool:
-        for ci, c in jobs:
-            K_or = oracle_client_hint(c.ck, E, c.N, pool=pool)
-            for i, j in enumerate(rows):
-                assert wl.limbs_to_int(Ks[ci, i]) == K_or[i], f"client {ci} K row {j}"
-                assert wl.limbs_to_int(Cs[ci, i]) == server.compress_row(K_or[i], int(B[ci, j]), c.N)
-    # for every client: the combine matches the closed form on the GPU's own K
-    for ci, c in enumerate(clients):
-        N2 = c.N * c.N
-        for i, j in enumerate(rows):
-            k = wl.limbs_to_int(Ks[ci, i])
-            assert wl.limbs_to_int(Cs[ci, i]) == k * (1 + int(B[ci, j]) * c.N) % N2
+        K_pairs = pool.map(_hint_row_job, [(clients[ci].ck, E[i], clients[ci].N) for ci, i in pairs])
+    for (ci, i), k in zip(pairs, K_pairs):
+        c = clients[ci]
+        assert wl.limbs_to_int(Ks[ci, i]) == k, f"client {ci} K row {rows[i]}"
+        assert wl.limbs_to_int(Cs[ci, i]) == server.compress_row(k, int(B_or[ci, i]), c.N)
 
 
 def test_c5_hint_and_update(native, big):
@@ -249,6 +252,5 @@ def test_database_above_one_launch(native):
         assert torch.equal(Bm, Bv)
         B = Bv.cpu().numpy().view(np.uint32)
     sample = [0, 1, 32766, 32767, 32768, 32769, 39998, 39999] + list(range(1000, 40000, 4111))
-    Dr = D[sample].astype(np.uint64)
-    ref = ((Dr @ Q.astype(np.uint64).T) & np.uint64(0xFFFFFFFF)).astype(np.uint32).T
+    ref = np.stack([server.answer_rows(D, Q[c], sample) for c in range(3)])
     assert np.array_equal(B[:, sample], ref)

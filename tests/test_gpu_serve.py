@@ -200,8 +200,8 @@ def test_engine_errors(native, setup):
 
 def test_packed_clients_in_the_mix(native):
     """A database with one packed client (ell = 5) and one plain client: requests of the two
-    kinds never share a batch, and every response equals the library's own packed or plain
-    combine of that request's answer, which the packed GPU tests check against the oracle."""
+    kinds never share a batch, every response equals the library's own packed or plain
+    combine of that request's answer, and one request of each kind equals the oracle."""
     import torch
     rows, cols, nb = 203, 320, 512
     inst = make_instance(cfg=940, rows=rows, cols=cols, n=N_LWE, n_bits=nb, nclients=2, encrypt_secret=False)
@@ -241,3 +241,14 @@ def test_packed_clients_in_the_mix(native):
                 srv.compress([ids[1]], B, C)
             assert np.array_equal(out, C[0]), f"request {i}"
             assert by_id[i]["batch"] >= 1
+    # the first packed and the first plain request against the oracle, every group and row
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    t = 64 + N_LWE.bit_length()
+    for kind in (0, 1):
+        i = next(i for i, (k, _) in enumerate(reqs) if k == kind)
+        q = reqs[i][1]
+        cl = inst.clients[kind]
+        K = server.client_hint(cl.ck, E, cl.N)
+        b = server.answer(inst.D, q)
+        want = server.compress_packed(K, b, cl.N, 5, 1 << t) if kind == 0 else server.compress(K, b, cl.N)
+        assert limbs_rows_to_ints(got[i]) == want, f"request {i + 1} vs the oracle"

@@ -137,6 +137,26 @@ def test_answer_batch_is_columnwise():
         assert B[c].tolist() == brute.matvec(D.tolist(), Qm[c].tolist())
 
 
+def test_answer_rows_vs_brute_and_full_answer():
+    # answer_rows (the sampled-row form of b = D.qu that the full-size tests use) against a
+    # pure-Python loop per listed row, and against the full answer, for rows listed out of
+    # order, repeated, and at both ends; extreme values where every product wraps 2^32.
+    g = np.random.default_rng(41)
+    rows, cols = 23, 47
+    D = g.integers(0, 256, (rows, cols), dtype=np.uint8)
+    D[5] = 255
+    qu = g.integers(0, Q, cols, dtype=np.uint32)
+    qu[:7] = Q - 1
+    sel = [22, 0, 5, 5, 13, 0, 22, 1]
+    got = server.answer_rows(D, qu, sel)
+    assert got.dtype == np.uint32 and got.shape == (len(sel),)
+    assert got.tolist() == [brute.matvec([D[j].tolist()], qu.tolist())[0] for j in sel]
+    assert np.array_equal(got, server.answer(D, qu)[sel])
+    # a single row and the empty selection
+    assert server.answer_rows(D, qu, [7]).tolist() == brute.matvec([D[7].tolist()], qu.tolist())
+    assert server.answer_rows(D, qu, []).shape == (0,)
+
+
 # ----------------------------------------------------------------------------- H and E
 
 def test_global_hint_vs_brute_rectangular():
@@ -564,7 +584,7 @@ def test_lwe_compress_binary_key_corollary():
 
 
 def test_packed_key_round_trip():
-    # Alg. 9: unpacked keys scale the phase by delta^(t-1); the packed-key decryption recovers
+    # Alg. 6: unpacked keys scale the phase by delta^(t-1); the packed-key decryption recovers
     # the plaintext when delta is a power of two above q + n q^2 (so q divides it) and
     # t = floor(0.5 log2 m / log2 delta).
     q, p, n = 1 << 32, 16, 20
