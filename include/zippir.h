@@ -186,6 +186,24 @@ pir_status pir_answer_compress(pir_server *srv, const uint32_t *Q, uint32_t clie
                                uint32_t *C, uint32_t ptr_flags);
 
 /*
+ * pir_answer_compress for callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same two
+ * launches and the same bits, with no hipMalloc, hipFree or allocating library call.  The
+ * matvec's per-(row, column segment) partial sums go to a static array of the library on each
+ * GPU (16 MiB, held until the process ends) instead of server-owned scratch.
+ *   Q  cols uint32, device memory, 16-byte aligned.   B  rows uint32.   C  rows x L uint32.
+ *   All three are device pointers on the server's device; there is no ptr_flags argument.
+ * Limit: rows x ceil(pitch / 4096) <= 4194304 partial words (pitch = cols rounded up to 256),
+ * e.g. 131072 rows at up to 131072 columns.  Beyond it, or for a misaligned Q: PIR_EINVAL.
+ * Otherwise the errors of pir_answer_compress.  Returns once the work is enqueued.
+ * Every call on one GPU shares that GPU's array and fully overwrites the part it uses, so
+ * calls whose work overlaps on the device (different streams or servers on the same GPU, or
+ * threads) race on it: serialize them.
+ */
+pir_status pir_answer_compress_noalloc(pir_server *srv, const uint32_t *Q, uint32_t client_id,
+                                       uint32_t *B, uint32_t *C);
+
+/*
  * Packed responses: batched compression (Alg. 3, Sec. 3.3; in ZipPIR, Sec. 4.3 "Batched
  * compression for smaller responses").  With packing factor ell, rows g*ell .. g*ell+ell-1
  * share one ciphertext

@@ -239,6 +239,12 @@ pir_status answer_compress_launch(pir_server* s, uint32_t id, const uint32_t* dQ
 void set_error(const char* msg);  // sets the calling thread's pir_last_error() text
 int server_device(pir_server* s);
 
+// ---- noalloc.hip: the static scratch array of pir_answer_compress_noalloc
+// With `device` current: looks up that device's address of the array once (hipGetSymbolAddress)
+// and returns it in *out (out may be NULL).
+pir_status scratch_init(int device, uint32_t** out);
+size_t scratch_words();
+
 // ---- compress.hip
 void launch_compress(const ClientDev& cd, const uint32_t* Kp, const uint32_t* Mp,
                      const uint32_t* b, int rows, uint32_t* C, hipStream_t s);

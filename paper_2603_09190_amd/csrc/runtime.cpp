@@ -578,6 +578,8 @@ pir_status pir_setup(pir_server** out, int device, void* hip_stream, const uint8
   s->n = n;
   s->pitch = (cols + 255u) & ~255u;
   ZP_TRY(use_device(s.get()));
+  // the device address of pir_answer_compress_noalloc's static scratch, looked up once per device
+  ZP_TRY(zp::scratch_init(device, nullptr));
   hipStream_t st = s->stream;
   const size_t dbytes = (size_t)rows * s->pitch;
   ZP_TRY(s->alloc((void**)&s->D, dbytes));

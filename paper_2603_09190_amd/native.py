@@ -58,6 +58,8 @@ _sig = {
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_answer_compress": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_answer_compress_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                                     ctypes.c_void_p, ctypes.c_void_p]),
     "pir_set_packing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
     "pir_packing_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                           ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
@@ -276,6 +278,15 @@ class Server:
         """One query of one client: B = D.q mod 2^32 and C = K (1 + B N) mod N^2 in one call."""
         _check(_lib.pir_answer_compress(self._h, _ptr(q)[0], cid, _ptr(B)[0], _ptr(C)[0], _flags(q, B, C)),
                "pir_answer_compress")
+
+    def answer_compress_noalloc(self, q, cid: int, B, C) -> None:
+        """pir_answer_compress on device arrays with no device allocation: the matvec's segment
+        partials go to the library's static per-device scratch array."""
+        for x in (q, B, C):
+            if _ptr(x)[1] is not True:
+                raise ValueError("pir_answer_compress_noalloc takes device arrays only")
+        _check(_lib.pir_answer_compress_noalloc(self._h, _ptr(q)[0], cid, _ptr(B)[0], _ptr(C)[0]),
+               "pir_answer_compress_noalloc")
 
     # -- packed responses
     def set_packing(self, cid: int, ell: int) -> None:
