@@ -332,6 +332,14 @@ def main() -> int:
         srv.compress_offset([cid], T1, C1)
     fp_ms = timed_ms(fp_step, args.steps)
     fpc_ms = timed_ms(fpc_step, args.steps)
+
+    # the same step as one call: the offset contraction on the server's second stream beside the
+    # matvec (pir_answer_offset), then the fold of b
+    def fp1_step():
+        srv.answer_offset([cid], q1, CKOt, B1, T1)
+    for _ in range(3):
+        fp1_step()
+    fp1_ms = timed_ms(fp1_step, args.steps)
     ka = kernel_avg_ms(srv, fpc_step, max(8, args.steps // 4), ["offset_gemm", "offset", "compress"])
     og_avg, or_avg, oc_avg = ka["offset_gemm"], ka["offset"], ka["compress"]
     # with batched compression: one offset answer per group of ell rows
@@ -347,6 +355,8 @@ def main() -> int:
     srv.set_packing(cid, 1)
     off_ops = 2.0 * rows * 4 * n * (4 * h + 3)
     full = {"ms_per_step": round(fp_ms, 4), "db_gbs": round(db_bytes / (fp_ms * 1e-3) / 1e9, 3),
+            "one_call_ms_per_step": round(fp1_ms, 4),
+            "one_call_db_gbs": round(db_bytes / (fp1_ms * 1e-3) / 1e9, 3),
             "with_combine_ms_per_step": round(fpc_ms, 4),
             "offset_gemm_kernel_avg_us": round(og_avg * 1e3, 2),
             "offset_gemm_int8_tops": round(off_ops / (og_avg * 1e-3) / 1e12, 1),

@@ -250,6 +250,21 @@ pir_status pir_compress_packed(pir_server *srv, const uint32_t *client_ids, uint
 pir_status pir_offset_answer(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
                              const uint32_t *CKO, const uint32_t *B, uint32_t *T,
                              uint32_t ptr_flags);
+
+/*
+ * The full protocol's online step for one query per client in one call (Alg. 5, Response, both
+ * lines): B[c] = D.Q[c] mod 2^32 (as pir_answer) and T[c] = (B[c] + E.CKO[c]) mod N_c (as
+ * pir_offset_answer), the same bits as those two calls.  The offset contraction E.CKO does not
+ * depend on B, so it runs on a second stream of the server (default priority) while the answer
+ * runs on the server's stream; the fold of B into T waits for both.
+ *   client_ids  host array of batch ids (batch in [1, 128], one shared limb count h).
+ *   Q   batch x cols uint32.  CKO  batch x n x h uint32.  B  batch x rows uint32 (output).
+ *   T   batch x rows x h uint32 (output, canonical residues mod N_c).
+ * Errors as pir_offset_answer and pir_answer.  Device outputs: returns once enqueued on the
+ * server's stream (which then orders after the second stream's work).
+ */
+pir_status pir_answer_offset(pir_server *srv, const uint32_t *client_ids, uint32_t batch, const uint32_t *Q,
+                             const uint32_t *CKO, uint32_t *B, uint32_t *T, uint32_t ptr_flags);
 pir_status pir_compress_offset(pir_server *srv, const uint32_t *client_ids, uint32_t batch,
                                const uint32_t *T, uint32_t *C, uint32_t ptr_flags);
 

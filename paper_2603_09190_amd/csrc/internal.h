@@ -103,6 +103,31 @@ void launch_gemm_planes(const uint8_t* D, int rows, int cols, int pitch, int pla
                         const int8_t* Xs, const int32_t* colsum, int ncol, const int32_t* rowsum,
                         uint32_t* out, bool out_rowmajor, long long out_ld, const GemmShape& sh,
                         hipStream_t s, bool tiled = false);
+// ---- hgemm.hip: H = D.A mod 2^32 (rows x n, row-major) on int8 MFMA
+// A's signed byte planes in fragment order (layout in hgemm.hip): Apt holds 4 x hgemm_npad(n) x
+// pitch bytes.  Acolsum[k 4 + b] = sum_{i<cols} (byte b of A[i][k]) - 128.
+int hgemm_npad(int n);
+void launch_a_planes(const uint32_t* A, int cols, int n, int pitch, uint8_t* Apt, hipStream_t s);
+void launch_a_colsum(const uint32_t* A, int cols, int n, int32_t* Acolsum, hipStream_t s);
+// D is the tiled copy (tiled) or row-major rows x pitch; rowsum as launch_rowsum.
+// `variant` < hgemm_variants() picks the launch shape (identical bits for every one).
+int hgemm_variants();
+void launch_hgemm(const uint8_t* D, bool tiled, int rows, int cols, int pitch, const uint8_t* Apt, int n,
+                  const int32_t* Acolsum, const int32_t* rowsum, uint32_t* H, int variant, hipStream_t s);
+
+// ---- batch.hip: the fused, persistent batched answer on the tiled copy Dt
+// B[c ldb + j] = D.Q[c] mod 2^32 for c < batch (Q batch x cols uint32, query c at Q + c cols),
+// j < rows; rowsum as launch_rowsum.  Shapes: mr 16-row tiles per wavefront (1 or 2), depth
+// K steps of D in flight (2..4), ksplit K ranges per row block (0: enough to fill num_cus),
+// blocks_per_cu persistent workgroups per CU.  Every shape gives identical bits.
+struct BatchShape {
+  int mr, depth, ksplit, blocks_per_cu;
+};
+bool batch_answer_supported(int rows, int pitch);
+void launch_batch_answer(const uint8_t* Dt, int rows, int cols, int pitch, const uint32_t* Q, int batch,
+                         const int32_t* rowsum, uint32_t* B, long long ldb, const BatchShape& sh,
+                         int num_cus, hipStream_t s);
+
 // Tiled copy for the contraction: Dt[(j/16) 16 pitch + (i/64) 1024 + (j%16) 64 + i%64] = D[j pitch + i]
 // for the listed rows (device list; nullptr: rows 0 .. nrows-1).
 void launch_tile_rows(const uint8_t* D, int pitch, const uint32_t* rowlist, int nrows, uint8_t* Dt,
@@ -162,17 +187,29 @@ void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint3
                             const uint32_t* b, int rows, int ell, int t, uint32_t* C, hipStream_t s);
 
 // ---- offset answer of the full protocol (offset.hip)
-// Eb row j (epitch bytes) = the 4n little-endian bytes of E row j = -H row j mod 2^32, zero
-// beyond 4n; epitch is a multiple of 256.
-void launch_e_bytes(const uint32_t* H, int rows, int n, int epitch, uint8_t* Eb, hipStream_t s);
+// E planes of the contraction (layout in offset.hip): Ep holds rows_pad x 4 x 64 S bytes with
+// S = offset_slices(n), rows_pad a multiple of 64; Ers (4 x rows_pad) receives the plane sums
+// sum_{k<n} (byte a of E_jk) - 128 for rows below `rows` (the caller zeroes the rest once).
+int offset_slices(int n);
+void launch_e_planes(const uint32_t* H, int rows, int n, int rows_pad, uint8_t* Ep, int32_t* Ers,
+                     hipStream_t s);
+// Column tiles of 16 for the 4h offset bytes (4, 8, 16, 24 or 32).
+int offset_tiles(int h);
 // out[k] = cko[k] 2^96 mod N (canonical) for the n offset entries of one client (h limbs each).
 void launch_scale_offsets(const ClientDev& cd, const uint32_t* cko, int n, uint32_t* out,
                           hipStream_t s);
-// One-plane operand for `batch` offset vectors cko (batch x n x h limbs): column
-// i*cpc + pos, K index 4k + a holds byte (pos - a) of cko[i][k] (XOR 0x80, 0 beyond 4n);
-// also zeroes and fills colsum (batch*cpc).  cpc >= 4h + 3.
-void launch_pack_offset(const uint32_t* cko, int batch, int n, int h, int cpc, int epitch,
-                        int8_t* X, int32_t* colsum, hipStream_t s);
+// The offset bytes of `batch` scaled offset vectors ys (batch x n x h limbs) in the
+// contraction's fragment order: Yf holds batch x S x offset_tiles(h) KiB; colsum (batch x 16
+// offset_tiles(h)) receives sum_{k<n} (byte c of ys[i][k]) - 128.
+void launch_pack_y(const uint32_t* ys, int batch, int n, int h, uint8_t* Yf, int32_t* colsum,
+                   hipStream_t s);
+// W[j ldw + i cpc + pos] = sum_k sum_a (byte a of E_jk) (byte pos - a of ys[i][k]) for j < rows,
+// pos < 4h + 3 and every client i < batch (exact: below 4 n 255^2 < 2^32).
+// `variant` < offset_gemm_variants(h) picks the launch shape (identical bits for every one).
+int offset_gemm_variants(int h);
+void launch_offset_gemm(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
+                        const uint8_t* Yf, const int32_t* colsum, int batch, int h, uint32_t* W,
+                        long long ldw, int cpc, int variant, hipStream_t s);
 // T[j] (h limbs) = (b[j] 2^96 + sum_pos W[j*ldw + pos] 2^(8 pos)) 2^-96 mod N, pos < 4h + 3,
 // where W was computed from offsets scaled by 2^96 (launch_scale_offsets).
 void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,

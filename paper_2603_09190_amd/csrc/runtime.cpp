@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -87,6 +88,11 @@ struct ClientState {
 
 struct pir_server {
   int device = 0;
+  int num_cus = 256;            // compute units of the device (sizes persistent grids)
+  // a second stream (default priority) and two events for pir_answer_offset, which runs the
+  // offset contraction beside the answer
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipStream_t stream = nullptr;
   uint32_t rows = 0, cols = 0, n = 0, pitch = 0;
   uint8_t* D = nullptr;         // rows x pitch, zero beyond cols
@@ -94,16 +100,17 @@ struct pir_server {
   // nullptr when switched off or when HBM had no room for it (the contraction then reads D)
   uint8_t* Dt = nullptr;
   uint32_t* A = nullptr;        // cols x n
-  int8_t* Ap = nullptr;         // n x 4 x pitch signed planes of A's columns
+  uint8_t* Apt = nullptr;       // A's signed byte planes in fragment order (launch_a_planes)
   int32_t* Acolsum = nullptr;   // n x 4
   int32_t* rowsum = nullptr;    // rows: sum_i (D[j][i] - 128)
   uint32_t* H = nullptr;        // rows x n
   std::vector<uint8_t> H_valid;
   int64_t H_stale = 0;
-  // E = -H mod 2^32 as bytes for the offset answer, built on first use after H changes
-  uint8_t* Eb = nullptr;        // rows x epitch
-  int32_t* Erowsum = nullptr;   // rows: sum_{i<4n} (Eb[j][i] - 128)
-  uint32_t epitch = 0;
+  // E = -H mod 2^32 as four signed byte planes in MFMA fragment order (launch_e_planes) for the
+  // offset answer, built on first use after H changes
+  uint8_t* Ep = nullptr;        // rows_pad x 4 x 64 S bytes
+  int32_t* Ers = nullptr;       // 4 x rows_pad: per plane and row, sum_{k<n} (byte - 128)
+  uint32_t rows_pad = 0;        // rows rounded up to 64
   bool E_ready = false;
   std::map<uint32_t, std::unique_ptr<ClientState>> clients;
   uint32_t next_id = 1;
@@ -118,7 +125,7 @@ struct pir_server {
   std::vector<ProfRecord> prof_ev[PIR_KERNEL_COUNT];
   // growable scratch
   DevAlloc s_planes, s_colsum, s_q, s_b, s_rows, s_gath, s_gsum, s_h, s_c, s_x, s_xcs, s_w, s_t, s_ys, s_tmp,
-      s_part;
+      s_part, s_aq, s_ak, s_ab;
 
   pir_status alloc(void** p, size_t bytes_) {
     *p = nullptr;
@@ -178,17 +185,19 @@ struct ProfScope {
   int k;
   int launches;
   hipEvent_t b = nullptr, e = nullptr;
-  ProfScope(pir_server* s_, int k_, int launches_ = 1) : s(s_), k(k_), launches(launches_) {
+  hipStream_t on;
+  ProfScope(pir_server* s_, int k_, int launches_ = 1, hipStream_t on_ = nullptr)
+      : s(s_), k(k_), launches(launches_), on(on_ ? on_ : s_->stream) {
     if (!s->prof) return;
     if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&e) != hipSuccess) {
       b = e = nullptr;
       return;
     }
-    (void)hipEventRecord(b, s->stream);
+    (void)hipEventRecord(b, on);
   }
   ~ProfScope() {
     if (!b) return;
-    (void)hipEventRecord(e, s->stream);
+    (void)hipEventRecord(e, on);
     s->prof_ev[k].push_back(pir_server::ProfRecord{b, e, launches});
   }
 };
@@ -234,6 +243,14 @@ const char* tune_cache_path() {
   return (p && *p) ? p : nullptr;
 }
 
+using BatchKey = std::tuple<int, int, int>;
+bool batch_shape_valid(const zp::BatchShape& b) {
+  if (b.mr == 0) return (b.depth == 1 || b.depth == 2) && (b.ksplit == 2 || b.ksplit == 4);
+  return (b.mr == 1 || b.mr == 2) && b.depth >= 2 && b.depth <= 4 && b.ksplit >= 0 && b.ksplit <= 64 &&
+         b.blocks_per_cu >= 1 && b.blocks_per_cu <= 4;
+}
+std::map<BatchKey, zp::BatchShape> g_btune;
+
 void tune_load_locked() {
   if (g_tune_loaded) return;
   g_tune_loaded = true;
@@ -243,6 +260,15 @@ void tune_load_locked() {
   std::string line;
   while (std::getline(f, line)) {  // lines of any other layout (an older cache) are skipped
     std::istringstream in(line);
+    if (line.compare(0, 6, "batch ") == 0) {
+      std::string tag;
+      int br, bp, ncg, mr, d, k, bpc, bextra;
+      in >> tag;
+      if (!(in >> br >> bp >> ncg >> mr >> d >> k >> bpc) || (in >> bextra)) continue;
+      const zp::BatchShape bs{mr, d, k, bpc};
+      if (batch_shape_valid(bs)) g_btune[BatchKey(br, bp, ncg)] = bs;
+      continue;
+    }
     int r, p, n, m, pl, tl, w, d, mr, kb, k, cg, extra;
     if (!(in >> r >> p >> n >> m >> pl >> tl >> w >> d >> mr >> kb >> k >> cg) || (in >> extra)) continue;
     if ((tl != 0 && tl != 1) || (tl == 1 && pl != 4)) continue;
@@ -251,6 +277,8 @@ void tune_load_locked() {
   }
 }
 
+// Rewrites the cache file with both tables: the contraction's lines, then the fused batched
+// answer's ("batch ..." lines).
 void tune_store_locked() {
   const char* path = tune_cache_path();
   if (!path) return;
@@ -261,6 +289,9 @@ void tune_store_locked() {
       << kv.second.waves << " "
       << kv.second.depth << " "
       << kv.second.mr << " " << kv.second.kb << " " << kv.second.ksplit << " " << kv.second.cg << "\n";
+  for (auto& kv : g_btune)
+    f << "batch " << std::get<0>(kv.first) << " " << std::get<1>(kv.first) << " " << std::get<2>(kv.first) << " "
+      << kv.second.mr << " " << kv.second.depth << " " << kv.second.ksplit << " " << kv.second.blocks_per_cu << "\n";
 }
 
 bool autotune_enabled() {
@@ -354,6 +385,154 @@ pir_status run_gemm(pir_server* s, const uint8_t* D, int rows, const int8_t* Xs,
                     rowmajor, ld, tiled);
 }
 
+// ----------------------------------------------------------------------------- batch tuner
+// Launch shape of the fused batched answer per (rows, pitch, column groups of 32 queries), chosen
+// like the contraction's: every candidate runs once and must give the first one's bits
+// (PIR_EDEVICE otherwise), then the fastest of three timed launches wins.  Batches of 2..32
+// queries share one key, so a database is tuned once for them.  Persisted in the same cache
+// file as lines "batch rows pitch ncg mr depth ksplit blocks_per_cu".
+constexpr zp::BatchShape kDefaultBatch{2, 4, 0, 1};
+// mr 0: the split form (pack launch + byte-plane contraction with depth and ksplit as given)
+const std::vector<zp::BatchShape> kBatchCandidates = {
+    {2, 4, 0, 1}, {2, 2, 0, 1}, {2, 4, 2, 1}, {1, 4, 0, 2}, {1, 2, 2, 2},
+    {0, 1, 2, 0}, {0, 2, 2, 0}, {0, 1, 4, 0}};
+
+
+// Times `ncand` launch variants of one problem and returns the fastest in *best: every variant
+// runs once and must leave the first one's bits in the rows x ncol output block (out with
+// leading dimension ld, row-major or column-major; PIR_EDEVICE otherwise), then the fastest of
+// three event-timed launches wins.
+pir_status tune_variants(pir_server* s, const char* what, int ncand, const std::function<void(int)>& launch,
+                         const uint32_t* out, int rows, int ncol, bool rowmajor, long long ld, int* best) {
+  hipStream_t st = s->stream;
+  const size_t nout = (size_t)rows * (size_t)ncol;
+  const size_t refbytes = (nout * sizeof(uint32_t) + 255) / 256 * 256;
+  void* tmp = nullptr;
+  ZP_TRY(s->alloc(&tmp, refbytes + 256));
+  auto* ref = static_cast<uint32_t*>(tmp);
+  auto* mism = reinterpret_cast<unsigned*>(static_cast<char*>(tmp) + refbytes);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  pir_status rc = PIR_OK;
+  auto check = [&](hipError_t e) {
+    if (e != hipSuccess && rc == PIR_OK) rc = fail(PIR_EDEVICE, std::string(what) + " autotune: " + hipGetErrorString(e));
+  };
+  check(hipEventCreate(&e0));
+  check(hipEventCreate(&e1));
+  check(hipMemsetAsync(mism, 0, sizeof(unsigned), st));
+  float best_ms = 1e30f;
+  *best = 0;
+  for (int c = 0; c < ncand && rc == PIR_OK; ++c) {
+    launch(c);
+    zp::launch_gemm_snapshot(out, rows, ncol, rowmajor, ld, ref, c > 0, mism, st);
+    float ms = 1e30f;
+    for (int rep = 0; rep < 3 && rc == PIR_OK; ++rep) {
+      check(hipEventRecord(e0, st));
+      launch(c);
+      check(hipEventRecord(e1, st));
+      check(hipEventSynchronize(e1));
+      float t = 0;
+      check(hipEventElapsedTime(&t, e0, e1));
+      ms = std::min(ms, t);
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      *best = c;
+    }
+  }
+  unsigned bad = 0;
+  check(hipMemcpyAsync(&bad, mism, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  check(hipStreamSynchronize(st));
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  s->release(tmp);
+  ZP_TRY(rc);
+  if (bad != 0)
+    return fail(PIR_EDEVICE, std::string(what) + " autotune: launch shapes disagree on " + std::to_string(bad) +
+                                 " output elements");
+  return PIR_OK;
+}
+
+// Offset contraction variant per (rows, n, h, batch), tuned on first use (in memory only).
+using OffsetKey = std::tuple<int, int, int, int>;
+std::map<OffsetKey, int> g_otune;
+
+// H = D.A for `rows` rows (tiled copy or row-major rows), the launch shape tuned once per
+// (rows bucket, tiled, n): row counts are bucketed by powers of two so that updates of different
+// sizes share a choice.
+using HKey = std::tuple<int, int, int>;
+std::map<HKey, int> g_htune;
+
+pir_status run_hgemm(pir_server* s, const uint8_t* D, bool tiled, int rows, const int32_t* rowsum, uint32_t* H) {
+  hipStream_t st = s->stream;
+  auto launch = [&](int variant) {
+    zp::launch_hgemm(D, tiled, rows, (int)s->cols, (int)s->pitch, s->Apt, (int)s->n, s->Acolsum, rowsum, H, variant, st);
+  };
+  int bucket = 1;
+  while (bucket < rows) bucket <<= 1;
+  const HKey key(bucket, tiled ? 1 : 0, (int)s->n);
+  int variant = 0;
+  bool need_tune = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_htune.find(key);
+    if (it != g_htune.end()) variant = it->second;
+    else need_tune = autotune_enabled();
+  }
+  if (need_tune) {
+    ZP_TRY(tune_variants(s, "hint contraction", zp::hgemm_variants(), launch, H, rows, (int)s->n, true, s->n, &variant));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_htune[key] = variant;
+  }
+  ProfScope ps(s, PIR_KERNEL_GEMM);
+  launch(variant);
+  return PIR_OK;
+}
+
+// B = D.Q for `rows` rows of the tiled copy from a multiple of 256 rows (B column-major, ld).
+pir_status run_batch(pir_server* s, const uint8_t* Dt, int rows, const uint32_t* Q, int batch,
+                     const int32_t* rowsum, uint32_t* out, long long ld) {
+  hipStream_t st = s->stream;
+  const int ncg = (batch + 31) / 32;
+  const BatchKey key(rows, (int)s->pitch, ncg);
+  zp::BatchShape shape = kDefaultBatch;
+  bool need_tune = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_btune.find(key);
+    if (it != g_btune.end()) shape = it->second;
+    else need_tune = autotune_enabled();
+  }
+  // The split form: planes packed by their own launch, then the byte-plane contraction with
+  // split-K atomics (shape.mr == 0 marks it; depth and ksplit pick its launch shape).
+  const size_t pbytes = (size_t)batch * 4 * s->pitch, cbytes = (size_t)batch * 4 * sizeof(int32_t);
+  auto launch = [&](const zp::BatchShape& c) {
+    if (c.mr != 0) {
+      zp::launch_batch_answer(Dt, rows, (int)s->cols, (int)s->pitch, Q, batch, rowsum, out, ld, c, s->num_cus, st);
+      return;
+    }
+    zp::launch_pack_planes_s8(Q, s->cols, 1, batch, (int)s->cols, (int)s->pitch, (int8_t*)s->s_planes.p,
+                              (int32_t*)s->s_colsum.p, st);
+    const zp::GemmShape gs{8, c.depth, 2, 256, c.ksplit, 4};
+    zp::launch_gemm_planes(Dt, rows, (int)s->cols, (int)s->pitch, 4, (const int8_t*)s->s_planes.p,
+                           (const int32_t*)s->s_colsum.p, batch, rowsum, out, false, ld, gs, st, true);
+  };
+  ZP_TRY(s->scratch(s->s_planes, pbytes));
+  ZP_TRY(s->scratch(s->s_colsum, cbytes));
+  if (need_tune) {
+    int best = 0;
+    ZP_TRY(tune_variants(s, "batch", (int)kBatchCandidates.size(), [&](int c) { launch(kBatchCandidates[c]); }, out,
+                         rows, batch, false, ld, &best));
+    shape = kBatchCandidates[best];
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_btune[key] = shape;
+    tune_store_locked();
+  }
+  ProfScope ps(s, PIR_KERNEL_GEMM);
+  launch(shape);
+  return PIR_OK;
+}
+
 // Batched answers stream D in row chunks of at most kLaunchBytes (see launch_matvec).
 pir_status run_gemm_chunked(pir_server* s, const int8_t* Xs, const int32_t* colsum, int ncol,
                             uint32_t* out, long long ld) {
@@ -397,8 +576,7 @@ pir_status refresh_H(pir_server* s, const std::vector<uint32_t>& rows_in) {
   if (rows_in.empty()) return PIR_OK;
   hipStream_t st = s->stream;
   if (rows_in.size() * 4 >= s->rows) {
-    ZP_TRY(run_gemm(s, s->Dt ? s->Dt : s->D, (int)s->rows, s->Ap, s->Acolsum, (int)s->n, s->rowsum, s->H,
-                    true, 0, s->Dt != nullptr));
+    ZP_TRY(run_hgemm(s, s->Dt ? s->Dt : s->D, s->Dt != nullptr, (int)s->rows, s->rowsum, s->H));
   } else {
     const size_t m = rows_in.size();
     ZP_TRY(s->scratch(s->s_rows, m * sizeof(uint32_t)));
@@ -409,8 +587,8 @@ pir_status refresh_H(pir_server* s, const std::vector<uint32_t>& rows_in) {
     ZP_HIP(hipMemcpyAsync(drows, rows_in.data(), m * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     zp::launch_gather_rows_u8(s->D, (int)s->pitch, drows, (int)m, (uint8_t*)s->s_gath.p, st);
     zp::launch_gather_rowsum(s->rowsum, drows, (int)m, (int32_t*)s->s_gsum.p, st);
-    ZP_TRY(run_gemm(s, (const uint8_t*)s->s_gath.p, (int)m, s->Ap, s->Acolsum, (int)s->n,
-                    (const int32_t*)s->s_gsum.p, (uint32_t*)s->s_h.p, true, 0));
+    ZP_TRY(run_hgemm(s, (const uint8_t*)s->s_gath.p, false, (int)m, (const int32_t*)s->s_gsum.p,
+                     (uint32_t*)s->s_h.p));
     zp::launch_scatter_rows_u32((const uint32_t*)s->s_h.p, (int)s->n, drows, (int)m, s->H, st);
     // the scratch is reused by later calls: finish before returning
     ZP_HIP(hipStreamSynchronize(st));
@@ -449,13 +627,15 @@ void zp::set_error(const char* msg) { g_last_error = msg; }
 pir_status ensure_E(pir_server* s) {
   if (s->E_ready) return PIR_OK;
   hipStream_t st = s->stream;
-  if (!s->Eb) {
-    s->epitch = (4 * s->n + 255) / 256 * 256;
-    ZP_TRY(s->alloc((void**)&s->Eb, (size_t)s->rows * s->epitch));
-    ZP_TRY(s->alloc((void**)&s->Erowsum, (size_t)s->rows * sizeof(int32_t)));
+  if (!s->Ep) {
+    s->rows_pad = (s->rows + 63u) / 64u * 64u;
+    const size_t bytes = (size_t)s->rows_pad * 4 * 64 * zp::offset_slices((int)s->n);
+    ZP_TRY(s->alloc((void**)&s->Ep, bytes));
+    ZP_TRY(s->alloc((void**)&s->Ers, (size_t)4 * s->rows_pad * sizeof(int32_t)));
+    // rows past the last stay zero (every plane sum is read for whole 16-row tiles)
+    ZP_HIP(hipMemsetAsync(s->Ers, 0, (size_t)4 * s->rows_pad * sizeof(int32_t), st));
   }
-  zp::launch_e_bytes(s->H, (int)s->rows, (int)s->n, (int)s->epitch, s->Eb, st);
-  zp::launch_rowsum(s->Eb, (int)s->rows, 4 * (int)s->n, (int)s->epitch, s->Erowsum, st);
+  zp::launch_e_planes(s->H, (int)s->rows, (int)s->n, (int)s->rows_pad, s->Ep, s->Ers, st);
   ZP_HIP(hipGetLastError());
   s->E_ready = true;
   return PIR_OK;
@@ -580,6 +760,14 @@ pir_status pir_setup(pir_server** out, int device, void* hip_stream, const uint8
   ZP_TRY(use_device(s.get()));
   // the device address of pir_answer_compress_noalloc's static scratch, looked up once per device
   ZP_TRY(zp::scratch_init(device, nullptr));
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+      s->num_cus = cus;
+  }
+  ZP_HIP(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+  ZP_HIP(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+  ZP_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
   hipStream_t st = s->stream;
   const size_t dbytes = (size_t)rows * s->pitch;
   ZP_TRY(s->alloc((void**)&s->D, dbytes));
@@ -589,10 +777,10 @@ pir_status pir_setup(pir_server** out, int device, void* hip_stream, const uint8
   ZP_HIP(hipMemcpyAsync(s->A, A, (size_t)cols * n * sizeof(uint32_t), kind_to_dev(ptr_flags), st));
   ZP_TRY(s->alloc((void**)&s->rowsum, (size_t)rows * sizeof(int32_t)));
   zp::launch_rowsum(s->D, (int)rows, (int)cols, (int)s->pitch, s->rowsum, st);
-  ZP_TRY(s->alloc((void**)&s->Ap, (size_t)n * 4 * s->pitch));
+  ZP_TRY(s->alloc((void**)&s->Apt, (size_t)4 * zp::hgemm_npad((int)n) * s->pitch));
   ZP_TRY(s->alloc((void**)&s->Acolsum, (size_t)n * 4 * sizeof(int32_t)));
-  // column k of A is the vector (A[i][k])_i: stride 1 between vectors, n between entries
-  zp::launch_pack_planes_s8(s->A, 1, n, (int)n, (int)cols, (int)s->pitch, s->Ap, s->Acolsum, st);
+  zp::launch_a_planes(s->A, (int)cols, (int)n, (int)s->pitch, s->Apt, st);
+  zp::launch_a_colsum(s->A, (int)cols, (int)n, s->Acolsum, st);
   ZP_TRY(s->alloc((void**)&s->H, (size_t)rows * n * sizeof(uint32_t)));
   s->H_valid.assign(rows, 0);
   s->H_stale = rows;
@@ -609,6 +797,12 @@ void pir_destroy(pir_server* s) {
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
   prof_clear(s);
+  if (s->side) {
+    (void)hipStreamSynchronize(s->side);
+    (void)hipStreamDestroy(s->side);
+  }
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   for (auto& kv : s->allocs) (void)hipFree(kv.first);
   s->allocs.clear();
   delete s;
@@ -1016,6 +1210,14 @@ static pir_status answer_impl(pir_server* s, const uint32_t* Q, uint32_t batch, 
     for (uint32_t c = 0; c < batch; ++c)
       zp::launch_matvec(s->D, (int)s->rows, (int)s->pitch, planes + (size_t)c * 4 * s->pitch,
                         dB + (size_t)c * s->rows, st);
+  } else if (path == PIR_PATH_MFMA && s->Dt && zp::batch_answer_supported((int)s->rows, (int)s->pitch)) {
+    // the fused, persistent contraction on the tiled copy, in row chunks of at most kLaunchBytes
+    const long long per = std::max<long long>(256, zp::kLaunchBytes / s->pitch / 256 * 256);
+    for (long long r0 = 0; r0 < s->rows; r0 += per) {
+      const int nr = (int)std::min<long long>(per, s->rows - r0);
+      ZP_TRY(run_batch(s, s->Dt + (size_t)r0 * s->pitch, nr, dQ, (int)batch, s->rowsum + r0, dB + r0,
+                       (long long)s->rows));
+    }
   } else if (path == PIR_PATH_MFMA) {
     ZP_TRY(s->scratch(s->s_planes, (size_t)batch * 4 * s->pitch));
     ZP_TRY(s->scratch(s->s_colsum, (size_t)batch * 4 * sizeof(int32_t)));
@@ -1231,41 +1433,88 @@ static pir_status offset_clients(pir_server* s, const uint32_t* ids, uint32_t ba
   return PIR_OK;
 }
 
-static pir_status offset_answer_dev(pir_server* s, const std::vector<ClientState*>& cs,
-                                    const uint32_t* dK, const uint32_t* dB, uint32_t* dT) {
+// The offset contraction of the full protocol's online step: W (rows x batch (4h + 4) words in
+// s_w) from the clients' offsets dK, launched on stream cst (the launch shape is tuned on the
+// server's stream first, on the first call of a shape).
+static pir_status offset_contract(pir_server* s, const std::vector<ClientState*>& cs, const uint32_t* dK,
+                                  hipStream_t cst) {
   const uint32_t batch = (uint32_t)cs.size();
   ZP_TRY(refresh_all_stale_H(s));
   ZP_TRY(ensure_E(s));
-  hipStream_t st = s->stream;
   const uint32_t h = cs[0]->h;
   const int cpc = (int)(4 * h + 4);
   const long long ncol = (long long)batch * cpc;
   const size_t kbytes = (size_t)batch * s->n * h * sizeof(uint32_t);
-  ZP_TRY(s->scratch(s->s_x, (size_t)ncol * s->epitch));
-  ZP_TRY(s->scratch(s->s_xcs, (size_t)ncol * sizeof(int32_t)));
+  const int NT = zp::offset_tiles((int)h);
+  ZP_TRY(s->scratch(s->s_x, (size_t)batch * zp::offset_slices((int)s->n) * NT * 1024));
+  ZP_TRY(s->scratch(s->s_xcs, (size_t)batch * 16 * NT * sizeof(int32_t)));
   ZP_TRY(s->scratch(s->s_w, (size_t)s->rows * ncol * sizeof(uint32_t)));
-  auto* X = (int8_t*)s->s_x.p;
+  ZP_TRY(s->scratch(s->s_ys, kbytes));
+  auto* X = (uint8_t*)s->s_x.p;
   auto* xcs = (int32_t*)s->s_xcs.p;
   auto* W = (uint32_t*)s->s_w.p;
-  ZP_TRY(s->scratch(s->s_ys, kbytes));
   auto* ys = (uint32_t*)s->s_ys.p;
-  {
-    ProfScope ps(s, PIR_KERNEL_OFFSET, (int)batch);
+  auto prepare = [&](hipStream_t on) {
+    ProfScope ps(s, PIR_KERNEL_OFFSET, (int)batch, on);
     for (uint32_t i = 0; i < batch; ++i)
-      zp::launch_scale_offsets(cs[i]->dev(), dK + (size_t)i * s->n * h, (int)s->n,
-                               ys + (size_t)i * s->n * h, st);
+      zp::launch_scale_offsets(cs[i]->dev(), dK + (size_t)i * s->n * h, (int)s->n, ys + (size_t)i * s->n * h, on);
+    zp::launch_pack_y(ys, (int)batch, (int)s->n, (int)h, X, xcs, on);
+  };
+  auto launch = [&](int variant, hipStream_t on) {
+    zp::launch_offset_gemm(s->Ep, s->Ers, (int)s->rows_pad, (int)s->rows, (int)s->n, X, xcs, (int)batch, (int)h,
+                           W, ncol, cpc, variant, on);
+  };
+  const OffsetKey key((int)s->rows, (int)s->n, (int)h, (int)batch);
+  int variant = 0;
+  bool need_tune = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_otune.find(key);
+    if (it != g_otune.end()) variant = it->second;
+    else need_tune = autotune_enabled();
   }
-  zp::launch_pack_offset(ys, (int)batch, (int)s->n, (int)h, cpc, (int)s->epitch, X, xcs, st);
-  ZP_TRY(run_gemm_x(s, s->Eb, (int)s->rows, 4 * (int)s->n, (int)s->epitch, 1, X, xcs, (int)ncol,
-                    s->Erowsum, W, true, 0));
+  if (need_tune) {
+    prepare(s->stream);
+    ZP_TRY(tune_variants(s, "offset", zp::offset_gemm_variants((int)h), [&](int v) { launch(v, s->stream); }, W,
+                         (int)s->rows, (int)ncol, true, ncol, &variant));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_otune[key] = variant;
+  }
+  if (cst != s->stream) {  // everything above (H, E, tuning) is ordered before the other stream's work
+    ZP_HIP(hipEventRecord(s->ev_fork, s->stream));
+    ZP_HIP(hipStreamWaitEvent(cst, s->ev_fork, 0));
+  }
+  prepare(cst);
   {
-    ProfScope ps(s, PIR_KERNEL_OFFSET, (int)batch);
-    for (uint32_t i = 0; i < batch; ++i)
-      zp::launch_offset_reduce(cs[i]->dev(), W + (size_t)i * cpc, ncol, dB + (size_t)i * s->rows,
-                               (int)s->rows, dT + (size_t)i * s->rows * h, st);
+    ProfScope ps(s, PIR_KERNEL_OFFSET_GEMM, 1, cst);
+    launch(variant, cst);
   }
   ZP_HIP(hipGetLastError());
   return PIR_OK;
+}
+
+// T[i] = (B[i] + W_i folded into limbs) mod N_i for the contraction in s_w, on the server's stream.
+static pir_status offset_reduce_all(pir_server* s, const std::vector<ClientState*>& cs, const uint32_t* dB,
+                                    uint32_t* dT) {
+  const uint32_t batch = (uint32_t)cs.size();
+  const uint32_t h = cs[0]->h;
+  const int cpc = (int)(4 * h + 4);
+  const long long ncol = (long long)batch * cpc;
+  const auto* W = (const uint32_t*)s->s_w.p;
+  {
+    ProfScope ps(s, PIR_KERNEL_OFFSET, (int)batch);
+    for (uint32_t i = 0; i < batch; ++i)
+      zp::launch_offset_reduce(cs[i]->dev(), W + (size_t)i * cpc, ncol, dB + (size_t)i * s->rows, (int)s->rows,
+                               dT + (size_t)i * s->rows * h, s->stream);
+  }
+  ZP_HIP(hipGetLastError());
+  return PIR_OK;
+}
+
+static pir_status offset_answer_dev(pir_server* s, const std::vector<ClientState*>& cs,
+                                    const uint32_t* dK, const uint32_t* dB, uint32_t* dT) {
+  ZP_TRY(offset_contract(s, cs, dK, s->stream));
+  return offset_reduce_all(s, cs, dB, dT);
 }
 
 static pir_status offset_answer_common(pir_server* s, const uint32_t* ids, uint32_t batch,
@@ -1328,6 +1577,51 @@ static pir_status offset_answer_common(pir_server* s, const uint32_t* ids, uint3
 pir_status pir_offset_answer(pir_server* s, const uint32_t* ids, uint32_t batch, const uint32_t* CKO,
                              const uint32_t* B, uint32_t* T, uint32_t ptr_flags) {
   return offset_answer_common(s, ids, batch, CKO, B, T, ptr_flags, false);
+}
+
+pir_status pir_answer_offset(pir_server* s, const uint32_t* ids, uint32_t batch, const uint32_t* Q,
+                             const uint32_t* CKO, uint32_t* B, uint32_t* T, uint32_t ptr_flags) {
+  g_last_error.clear();
+  if (!s || !ids || !Q || !CKO || !B || !T) return fail(PIR_EINVAL, "NULL argument");
+  ZP_TRY(check_flags(ptr_flags));
+  std::vector<ClientState*> cs;
+  ZP_TRY(offset_clients(s, ids, batch, false, cs));
+  ZP_TRY(use_device(s));
+  hipStream_t st = s->stream;
+  const uint32_t h = cs[0]->h;
+  const size_t qbytes = (size_t)batch * s->cols * sizeof(uint32_t);
+  const size_t kbytes = (size_t)batch * s->n * h * sizeof(uint32_t);
+  const size_t bbytes = (size_t)batch * s->rows * sizeof(uint32_t);
+  const size_t tbytes = (size_t)batch * s->rows * h * sizeof(uint32_t);
+  const uint32_t* dQ = Q;
+  const uint32_t* dK = CKO;
+  uint32_t* dB = B;
+  uint32_t* dT = T;
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_TRY(s->scratch(s->s_aq, qbytes));
+    ZP_TRY(s->scratch(s->s_ak, kbytes));
+    ZP_TRY(s->scratch(s->s_ab, bbytes));
+    ZP_TRY(s->scratch(s->s_t, tbytes));
+    ZP_HIP(hipMemcpyAsync(s->s_aq.p, Q, qbytes, hipMemcpyHostToDevice, st));
+    ZP_HIP(hipMemcpyAsync(s->s_ak.p, CKO, kbytes, hipMemcpyHostToDevice, st));
+    dQ = (const uint32_t*)s->s_aq.p;
+    dK = (const uint32_t*)s->s_ak.p;
+    dB = (uint32_t*)s->s_ab.p;
+    dT = (uint32_t*)s->s_t.p;
+  }
+  // the offset contraction (independent of B) on the second stream, the answer meanwhile on the
+  // server's stream; the reduction needs both
+  ZP_TRY(offset_contract(s, cs, dK, s->side));
+  ZP_HIP(hipEventRecord(s->ev_join, s->side));
+  ZP_TRY(answer_impl(s, dQ, batch, dB, PIR_PTR_DEVICE, PIR_PATH_AUTO));
+  ZP_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+  ZP_TRY(offset_reduce_all(s, cs, dB, dT));
+  if (ptr_flags == PIR_PTR_HOST) {
+    ZP_HIP(hipMemcpyAsync(B, dB, bbytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipMemcpyAsync(T, dT, tbytes, hipMemcpyDeviceToHost, st));
+    ZP_HIP(hipStreamSynchronize(st));
+  }
+  return PIR_OK;
 }
 
 pir_status pir_offset_answer_packed(pir_server* s, const uint32_t* ids, uint32_t batch,

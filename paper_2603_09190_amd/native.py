@@ -68,6 +68,8 @@ _sig = {
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_offset_answer": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_answer_offset": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_compress_offset": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_offset_answer_packed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
@@ -307,6 +309,13 @@ class Server:
         ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
         _check(_lib.pir_offset_answer(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(CKO)[0],
                                       _ptr(B)[0], _ptr(T)[0], _flags(CKO, B, T)), "pir_offset_answer")
+
+    def answer_offset(self, ids, Q, CKO, B, T) -> None:
+        """B = D.Q and T = (B + E.CKO) mod N in one call (the contraction beside the answer)."""
+        ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        _check(_lib.pir_answer_offset(self._h, ctypes.c_void_p(ids_a.ctypes.data), len(ids_a), _ptr(Q)[0],
+                                      _ptr(CKO)[0], _ptr(B)[0], _ptr(T)[0], _flags(Q, CKO, B, T)),
+               "pir_answer_offset")
 
     def compress_offset(self, ids, T, C) -> None:
         ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))

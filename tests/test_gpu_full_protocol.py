@@ -291,3 +291,50 @@ def test_packed_offset_answer_many_rows(native):
         Tg = np.zeros((1, G, h), np.uint32)
         srv.offset_answer_packed([cid], CKO[None], B, Tg)
     assert limbs_rows_to_ints(Tg[0]) == protocol.offset_answer_packed(t_or, ell, gamma, cl.N)
+
+
+@pytest.mark.parametrize("nclients,n_bits,on_device", [(1, 2048, False), (3, 1024, True), (2, 256, False)])
+def test_answer_offset_one_call(native, nclients, n_bits, on_device):
+    """pir_answer_offset: the answer and the offset answer in one call, the contraction on the
+    server's second stream beside the answer; B and T equal the oracle on every row (and a row
+    update between calls is seen by both)."""
+    rows, cols, n = 150, 300, 12
+    log(f"answer_offset: {nclients} clients, N {n_bits}, device {on_device}")
+    inst = make_instance(cfg=990 + nclients, rows=rows, cols=cols, n=n, n_bits=n_bits, nclients=nclients,
+                         encrypt_secret=False, zero_row=7)
+    offs = [_offsets(cl) for cl in inst.clients]
+    h = (n_bits + 31) // 32
+    CKO = np.ascontiguousarray(np.stack([o[1] for o in offs]))
+    Q = np.ascontiguousarray(np.stack([cl.qu for cl in inst.clients]))
+    upd = np.array([0, rows - 1], np.uint32)
+    new = np.random.default_rng(991).integers(0, 256, size=(2, cols), dtype=np.uint8)
+    with native.Server(inst.D, inst.A) as srv:
+        ids = []
+        for cl in inst.clients:
+            N_limbs, ckr, _ = client_arrays(cl, n_bits)
+            ids.append(srv.add_client(N_limbs, n_bits, ckr))
+        for rnd, D in enumerate((inst.D, None)):
+            if rnd == 1:
+                srv.update_rows(upd, new)
+                D = inst.D.copy()
+                D[upd] = new
+            if on_device:
+                import torch
+                dev = torch.device("cuda:0")
+                Bt = torch.zeros((nclients, rows), dtype=torch.int32, device=dev)
+                Tt = torch.zeros((nclients, rows, h), dtype=torch.int32, device=dev)
+                srv.answer_offset(ids, torch.from_numpy(Q.view(np.int32)).to(dev),
+                                  torch.from_numpy(CKO.view(np.int32)).to(dev), Bt, Tt)
+                srv.sync()
+                B = Bt.cpu().numpy().view(np.uint32)
+                T = Tt.cpu().numpy().view(np.uint32)
+            else:
+                B = np.zeros((nclients, rows), np.uint32)
+                T = np.zeros((nclients, rows, h), np.uint32)
+                srv.answer_offset(ids, Q, CKO, B, T)
+            E = server.exponents(server.global_hint(D, inst.A))
+            for i, cl in enumerate(inst.clients):
+                b = server.answer(D, cl.qu)
+                assert np.array_equal(B[i], b), f"answer of client {i}, round {rnd}"
+                assert limbs_rows_to_ints(T[i]) == protocol.offset_answer(b, E, offs[i][0], cl.N), \
+                    f"offset answer of client {i}, round {rnd}"

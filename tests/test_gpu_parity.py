@@ -307,7 +307,9 @@ def test_hint_and_combine_other_moduli(native, n_bits):
 
 def test_autotuned_shape_is_persisted(native, tmp_path, monkeypatch):
     # The first batched contraction of a new shape times the candidate launch shapes and
-    # records the winner; every candidate computes the same bits.
+    # records the winner; every candidate computes the same bits.  On the tiled copy the fused
+    # batched kernel is tuned (a "batch" line keyed by rows, pitch and 32-query groups); on
+    # row-major D the byte-plane contraction (its own line layout, tiled flag 0).
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("ZIPPIR_TUNE_CACHE", str(cache))
     rows, cols, batch = 77, 1280, 3
@@ -324,8 +326,11 @@ def test_autotuned_shape_is_persisted(native, tmp_path, monkeypatch):
         srv.answer(Qm, B, native.PATH_MFMA)
         assert np.array_equal(B, server.answer_batch(D, Qm))
     lines = [l.split() for l in cache.read_text().splitlines()]
-    mine = [l for l in lines if l[:5] == [str(rows), str(cols + (-cols) % 256), str(batch), "0", "4"]]
-    assert sorted(l[5] for l in mine) == ["0", "1"] and all(len(l) == 12 for l in mine)
+    pitch = str(cols + (-cols) % 256)
+    mine = [l for l in lines if l[:5] == [str(rows), pitch, str(batch), "0", "4"]]
+    assert [l[5] for l in mine] == ["0"] and all(len(l) == 12 for l in mine)
+    fused = [l for l in lines if l[:4] == ["batch", str(rows), pitch, "1"]]
+    assert len(fused) == 1 and len(fused[0]) == 8
 
 
 @pytest.mark.parametrize("rows,cols", [(1000, 3000), (16, 256), (4099, 700)])
