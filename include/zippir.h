@@ -326,6 +326,10 @@ pir_status pir_compressor_key(pir_compressor *cmp, uint32_t k0, uint32_t nk, uin
                               uint32_t ptr_flags);
 pir_status pir_compressor_info(pir_compressor *cmp, uint32_t *L, uint32_t *windows,
                                uint64_t *device_bytes);
+/* Device time of the compressor's setup, from events on its stream: the unpacking of a packed
+ * key (Alg. 6; 0 for an unpacked key) and the fixed-base table build, in milliseconds (either
+ * pointer may be NULL).  Table 3 reports the unpacking time. */
+pir_status pir_compressor_setup_ms(const pir_compressor *cmp, float *unpack_ms, float *table_ms);
 pir_status pir_compress_lwe(pir_compressor *cmp, const uint32_t *A, const uint32_t *B,
                             uint32_t rows, uint32_t *X, uint32_t ptr_flags);
 pir_status pir_compress_rlwe(pir_compressor *cmp, const uint32_t *A, const uint32_t *B,

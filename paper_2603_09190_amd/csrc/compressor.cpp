@@ -25,6 +25,8 @@ struct pir_compressor {
   uint32_t* table = nullptr;  // n x windows x 255 x S
   std::map<void*, size_t> allocs;
   uint64_t bytes = 0;
+  // device time of the setup steps, from events on the compressor's stream
+  float unpack_ms = 0.0f, table_ms = 0.0f;
   // growable scratch
   void* s_in = nullptr;
   size_t s_in_bytes = 0;
@@ -149,10 +151,27 @@ pir_status setup_common(pir_compressor* c, int device, void* stream, uint32_t n,
   return PIR_OK;
 }
 
+// Device milliseconds of the work `fn` enqueues on the compressor's stream (0 if events fail).
+template <typename F>
+float time_on_stream(pir_compressor* c, F fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  const bool ev = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+  if (ev) (void)hipEventRecord(a, c->stream);
+  fn();
+  float ms = 0.0f;
+  if (ev) {
+    (void)hipEventRecord(b, c->stream);
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 0.0f;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return ms;
+}
+
 pir_status build_table(pir_compressor* c) {
   const size_t tb = (size_t)c->n * c->windows * zp::kDigits * c->mc.S * sizeof(uint32_t);
   ZC_TRY(c->alloc((void**)&c->table, tb));
-  zp::launch_build_table(c->dev(), c->ck, (int)c->n, c->windows, c->table, c->stream);
+  c->table_ms = time_on_stream(c, [&] { zp::launch_build_table(c->dev(), c->ck, (int)c->n, c->windows, c->table, c->stream); });
   ZC_HIP(hipGetLastError());
   ZC_HIP(hipStreamSynchronize(c->stream));
   return PIR_OK;
@@ -281,7 +300,7 @@ pir_status pir_compressor_create_packed(pir_compressor** out, int device, void* 
       st = cfail(PIR_EDEVICE, "copying the packed key");
   }
   if (st == PIR_OK) {
-    zp::launch_unpack_keys(c->dev(), dp, (int)n, (int)t, (int)delta_log2, c->ck, c->stream);
+    c->unpack_ms = time_on_stream(c, [&] { zp::launch_unpack_keys(c->dev(), dp, (int)n, (int)t, (int)delta_log2, c->ck, c->stream); });
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
       st = cfail(PIR_EDEVICE, "unpacking the compression key");
   }
@@ -293,6 +312,13 @@ pir_status pir_compressor_create_packed(pir_compressor** out, int device, void* 
     return st;
   }
   *out = c;
+  return PIR_OK;
+}
+
+pir_status pir_compressor_setup_ms(const pir_compressor* c, float* unpack_ms, float* table_ms) {
+  if (!c) return cfail(PIR_EINVAL, "NULL compressor");
+  if (unpack_ms) *unpack_ms = c->unpack_ms;
+  if (table_ms) *table_ms = c->table_ms;
   return PIR_OK;
 }
 

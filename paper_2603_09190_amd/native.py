@@ -70,6 +70,8 @@ _sig = {
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_answer_offset": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "pir_compressor_setup_ms": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.POINTER(ctypes.c_float)]),
     "pir_compress_offset": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "pir_offset_answer_packed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
@@ -407,6 +409,12 @@ class Compressor:
         _check(_lib.pir_compressor_info(self._h, ctypes.byref(L), ctypes.byref(w), ctypes.byref(b)),
                "pir_compressor_info")
         self.L, self.windows = L.value, w.value
+
+    def setup_ms(self) -> dict:
+        """Device milliseconds of the setup: key unpacking (packed keys) and table build."""
+        u, t = ctypes.c_float(), ctypes.c_float()
+        _check(_lib.pir_compressor_setup_ms(self._h, ctypes.byref(u), ctypes.byref(t)), "pir_compressor_setup_ms")
+        return {"unpack_ms": u.value, "table_ms": t.value}
 
     def info(self) -> dict:
         L, w, b = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()

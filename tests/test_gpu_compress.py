@@ -207,6 +207,86 @@ def test_packed_key(native):
     assert [compress.modified_decrypt_packed_key(sk, x, delta, t, q, p) for x in got] == mu.tolist()
 
 
+def _rlwe_job(args):
+    ck, A, B, k, q, N = args
+    return compress.rlwe_compress_coefficient(ck, A, B, k, q, N)
+
+
+def test_rlwe_paper_size(native):
+    """RLWE(1024, 27) of Table 2 with a 3072-bit modulus: coefficients 0, 1, N_r - 1 and a random
+    one, bit-exact, and each decrypts to its message (Alg. 8 then the modified decryption)."""
+    q, p, Nr, N_bits = Q27, 16, 1024, 3072
+    log("rlwe paper size: N_r 1024, q 2^27, N 3072 bits")
+    sk = _key(1024, N_bits)
+    N, N2 = sk.pk.N, sk.pk.N2
+    g = np.random.default_rng(1024)
+    S = [int(x) for x in g.integers(0, q, size=Nr)]
+    A = [int(x) for x in g.integers(0, q, size=Nr)]
+    E = [int(x) for x in np.rint(6.4 * g.standard_normal(Nr))]
+    mu = [int(x) for x in g.integers(0, p, size=Nr)]
+    B = compress.rlwe_encrypt(S, mu, A, E, q, p)
+    # Enc(S_i; r) for one r: (1 + S_i N) r^N mod N^2, so r^N is computed once
+    r = wl.paillier_randomness(1024, 0, 1, N)[0]
+    rN = pow(r, N, N2)
+    ck = [(1 + s_i * N) * rN % N2 for s_i in S]
+    assert ck[5] == paillier.encrypt(sk.pk, S[5], r)
+    ks = [0, 1, Nr - 1, int(g.integers(2, Nr - 1))]
+    N_limbs, L = _limbs(sk, N_bits)
+    with native.Compressor(Nr, q, N_limbs, N_bits, ck=wl.ints_to_limbs(ck, L)) as cmp:
+        X = np.zeros((len(ks), L), np.uint32)
+        cmp.compress_rlwe(np.array(A, np.uint32), np.array(B, np.uint32), ks, X)
+    got = limbs_rows_to_ints(X)
+    with Pool(pool_size()) as pool:
+        want = pool.map(_rlwe_job, [(ck, A, B, k, q, N) for k in ks])
+    assert got == want
+    assert [compress.modified_lwe_decrypt(sk, x, q, p) for x in got] == [mu[k] for k in ks]
+
+
+def _packed_job(args):
+    pk, digits, delta, t, r = args
+    return compress.generate_packed_key(pk, digits, delta, t, [r])[0]
+
+
+def _unpack_job(args):
+    # the key entries of packed ciphertext i alone
+    pck_i, delta, t, count, N = args
+    return compress.unpack_compression_key([pck_i], delta, t, count, N)
+
+
+@pytest.mark.parametrize("binary", [False, True])
+def test_packed_key_table3_size(native, binary):
+    """Alg. 6 at Table 3's (630, 2^64) with a 3072-bit modulus: the device's unpacked key equals
+    the oracle's entry by entry, and two compressed ciphertexts match the oracle and decrypt
+    (binary keys take delta above q + n q, others above q + n q^2)."""
+    q, p, n, N_bits = 1 << 64, 16, 630, 3072
+    log(f"packed key, table 3 size: n {n} q 2^64 N 3072 bits binary {binary}")
+    sk = _key(1630, N_bits)
+    N = sk.pk.N
+    dbits = (q + n * q * (1 if binary else q)).bit_length()
+    delta = 1 << dbits
+    t = compress.packed_digits_per_key(N_bits, delta)
+    keys = -(-n // t)
+    g = np.random.default_rng(1630 + binary)
+    s = [int(x) for x in g.integers(0, 2 if binary else q, size=n, dtype=np.uint64)]
+    rs = wl.paillier_randomness(1630, int(binary), keys, N)
+    N_limbs, L = _limbs(sk, N_bits)
+    A, B, mu = _lwe_batch(g, s, q, p, 2)
+    with Pool(pool_size()) as pool:
+        pck = pool.map(_packed_job, [(sk.pk, s[i * t:(i + 1) * t], delta, t, rs[i]) for i in range(keys)])
+        with native.Compressor(n, q, N_limbs, N_bits, packed=wl.ints_to_limbs(pck, L), t=t,
+                               delta_log2=dbits) as cmp:
+            assert cmp.setup_ms()["unpack_ms"] > 0
+            dev_ck = limbs_rows_to_ints(cmp.key())
+            X = np.zeros((2, L), np.uint32)
+            cmp.compress_lwe(A, B, X)
+        ck = sum(pool.map(_unpack_job, [(pck[i], delta, t, min(t, n - i * t), N) for i in range(keys)]), [])
+        assert len(ck) == n and dev_ck == ck
+        got = limbs_rows_to_ints(X)
+        want = pool.map(_compress_job, [(ck, [int(x) for x in A[r]], int(B[r]), q, N) for r in range(2)])
+    assert got == want
+    assert [compress.modified_decrypt_packed_key(sk, x, delta, t, q, p) for x in got] == mu.tolist()
+
+
 def test_compressor_errors(native):
     q, n = 1 << 64, 8
     sk = _key(996, 128)                         # 128 bits < q + n q^2
