@@ -491,6 +491,8 @@ def main() -> int:
 TABLE2 = [("lwe", 630, 64), ("lwe", 742, 64), ("lwe", 870, 64), ("lwe", 1305, 11),
           ("rlwe", 1024, 27), ("rlwe", 2048, 54), ("rlwe", 4096, 36), ("rlwe", 8192, 43)]
 TABLE2_PAPER_MS = [9.7, 11.0, 12.9, 16.6, 7.2, 23.8, 33.8, 83.3]
+# Table 3: (n, log2 q), then the paper's unpacking time (ms, CPU) for non-binary and binary keys
+TABLE3 = [((630, 64), 14, 13), ((742, 64), 25, 12), ((870, 64), 74, 13), ((1305, 11), 15, 15)]
 
 
 def _prime_below(bits: int) -> int:
@@ -591,6 +593,27 @@ def compress_bench(args) -> int:
         log(f"  single {results[-1]['single_ms_p50']} ms, batch {batch} in {batch_ms:.2f} ms")
         del A, B, X
         torch.cuda.empty_cache()
+    unpack = []
+    for (n, qbits), paper_nb, paper_b in TABLE3:
+        q = 1 << qbits
+        for binary, paper_ms in ((False, paper_nb), (True, paper_b)):
+            # delta: a power of two above the largest phase, q + n q^2 (any key) or q + n q (binary)
+            dbits = (q + n * q * (1 if binary else q)).bit_length()
+            t = int((0.5 * nbits) // dbits)
+            keys = -(-n // t)
+            pck = wl.ints_to_limbs(wl.uniform_ciphertexts(78, n, keys, N), L)
+            runs = []
+            for _ in range(3):
+                with native.Compressor(n, q, N_limbs, nbits, packed=pck, t=t, delta_log2=dbits) as cmp:
+                    runs.append(cmp.setup_ms())
+            best = min(runs, key=lambda r: r["unpack_ms"])
+            unpack.append({"n": n, "log2_q": qbits, "binary": binary, "delta_log2": dbits, "t": t,
+                           "packed_keys": keys, "packed_kb": round(keys * L * 4 / 1024, 1),
+                           "unpacked_kb": round(n * L * 4 / 1024, 1),
+                           "unpack_ms": round(best["unpack_ms"], 3), "table_ms": round(best["table_ms"], 3),
+                           "paper_cpu_unpack_ms": paper_ms})
+            log(f"  unpack n={n} log2 q={qbits} binary={binary}: t {t}, {keys} keys, "
+                f"{best['unpack_ms']:.3f} ms (paper CPU {paper_ms} ms)")
     out = {
         "metric": "standalone ciphertext compression time, Table 2 parameters (single ciphertext)",
         "value": results[0]["single_ms_p50"], "unit": "ms", "n_gpus": 1, "steps": 20, "warmup": 1,
@@ -599,6 +622,7 @@ def compress_bench(args) -> int:
         "config": {"workload": "LWE/RLWE ciphertext compression into 3072-bit Paillier (Table 2 parameter sets); "
                                "value = one (630, 2^64) LWE ciphertext", "N_bits": nbits},
         "sets": results,
+        "table3_unpacking": unpack,
     }
     print(json.dumps(out), flush=True)
     return 0
