@@ -696,6 +696,22 @@ def serve(args) -> int:
         for c in eng.poll(1024, timeout_ms):
             comps[c["request_id"]] = c
 
+    # a seeded sample of requests (the first of each database, then random ones) whose served
+    # responses are kept and checked afterwards against a lone library call
+    first_of = {}
+    for k in range(nreq):
+        first_of.setdefault(int(which[k]), k)
+    sample = set(first_of.values()) | {int(x) for x in g.choice(nreq, size=min(8, nreq), replace=False)}
+    kept = {}
+    req_of_rid = {}
+
+    def keep(rid):
+        k = req_of_rid.get(rid)
+        if k in sample and k not in kept:
+            i, slot = int(which[k]), slot_of[k]
+            kept[k] = rings[i][slot].array.copy()
+
+    slot_of = {}
     rid_of = []
     for k in range(nreq):
         i = int(which[k])
@@ -704,9 +720,13 @@ def serve(args) -> int:
         prev = slot_owner[i][slot]
         while prev is not None and prev not in comps:
             collect(50)
+        if prev is not None:
+            keep(prev)
+        slot_of[k] = slot
         cid = clients[i][k % len(clients[i])]
         rid = eng.submit(i, cid, queries[i][k % 8], rings[i][slot].array, arrival_ms=t_start + 1000.0 * arr[k])
         slot_owner[i][slot] = rid
+        req_of_rid[rid] = k
         rid_of.append((rid, i))
         if k % 500 == 0:
             log(f"  submitted {k}/{nreq}")
@@ -714,6 +734,19 @@ def serve(args) -> int:
     collect(0)
     st = eng.stats()
     eng.close()
+    for rid, _ in rid_of:
+        keep(rid)
+    # the sampled responses against a lone pir_answer + pir_compress of the same query
+    sample_ok = True
+    for k in sorted(sample):
+        i = int(which[k])
+        srv, cid = servers[i], clients[i][k % len(clients[i])]
+        B1 = np.zeros((1, sides[i]), np.uint32)
+        C1 = np.zeros((out_rows[i], L), np.uint32)
+        srv.answer(queries[i][k % 8][None, :], B1)
+        (srv.compress_packed if args.pack else srv.compress)([cid], B1, C1)
+        sample_ok &= bool(np.array_equal(C1, kept[k]))
+    log(f"serve: {len(sample)} sampled responses {'equal' if sample_ok else 'DIFFER FROM'} a lone library call")
     lat = np.array([comps[r]["done_ms"] - comps[r]["arrival_ms"] for r, _ in rid_of])
     dbi = np.array([i for _, i in rid_of])
     ok = all(comps[r]["status"] == 0 for r, _ in rid_of)
@@ -733,7 +766,7 @@ def serve(args) -> int:
     for srv in servers:
         srv.close()
     out = {
-        "metric": "online answer DB GB/s (1 GB DB, batch 1 vs 32) + p50/p99 latency",
+        "metric": "serving mix: database bytes answered per second under Poisson arrivals (p50/p99 latency)",
         "value": round(db_bytes / wall_s / 1e9, 3),
         "unit": "GB/s",
         "n_gpus": 1,
@@ -755,6 +788,8 @@ def serve(args) -> int:
         "p50_ms": round(percentile(lat, 50), 3),
         "p99_ms": round(percentile(lat, 99), 3),
         "all_ok": ok,
+        "sampled_equal_lone_call": sample_ok,
+        "sampled_requests": len(sample),
         "per_db": per_db,
         "requests_per_s": round(nreq / wall_s, 2),
         "mean_batch": round(st["mean_batch"], 3),

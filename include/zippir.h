@@ -398,10 +398,15 @@ const char *pir_last_error(void);
  * takes up to max_batch queued requests whose clients share a limb count, runs
  * pir_answer (batch 1: matvec; larger: one int8-MFMA contraction) and pir_compress on the
  * database's stream, and copies each compressed response into the caller's buffer.
- * Batches of different databases run on different streams and overlap on the device.
+ * Batches of different databases run on different streams and overlap on the device.  A
+ * batch is enqueued in steps (the answer in row ranges of at most step_bytes of D, each
+ * response's download in pieces of at most copy_bytes); with more than one database
+ * registered, at most two steps of a batch are queued on the device at a time, so a small
+ * database's request waits for at most a couple of a large database's steps.
  * Device buffers for in-flight batches are admitted against a byte budget: a batch that
- * does not fit waits until earlier batches complete.  Results do not depend on how
- * requests were batched.
+ * does not fit waits until earlier batches complete.  Buffers are reused through a pool and
+ * freed only when the budget cannot otherwise admit a batch.  Results do not depend on how
+ * requests were batched or stepped.
  * ==========================================================================*/
 typedef struct pir_engine pir_engine;
 
@@ -428,8 +433,17 @@ typedef struct pir_engine_stats {
  * batches (0: the device's free memory at creation minus 1 GiB). */
 pir_status pir_engine_create(pir_engine **out, uint32_t max_batch, uint64_t hbm_budget_bytes);
 
+/* Step sizes of a batch: bytes of D per answer step (rounded down to a multiple of 256 rows,
+ * at least 256 rows; default 256 MiB) and response bytes per download step (default 8 MiB).
+ * Only before the first pir_engine_add_db (PIR_EINVAL after it, or for 0). */
+pir_status pir_engine_set_steps(pir_engine *eng, uint64_t step_bytes, uint64_t copy_bytes);
+
 /* Register a database.  The server must have been set up with its own stream (not NULL); from
- * now until pir_engine_destroy only the engine may use it. */
+ * now until pir_engine_destroy only the engine may use it.  The call runs the batched answer
+ * once for each column-group shape up to max_batch (on zero queries, in the engine's row
+ * steps) so that those contraction shapes are tuned and their scratch sized now; while the
+ * server is registered, a shape not tuned yet runs with the default launch shape instead of
+ * being tuned in place. */
 pir_status pir_engine_add_db(pir_engine *eng, pir_server *srv, uint32_t *db_index);
 
 /* Queue one request.  query: host array of the database's cols uint32 (copied before the call

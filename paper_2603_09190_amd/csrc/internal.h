@@ -193,14 +193,16 @@ void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint3
 int offset_slices(int n);
 void launch_e_planes(const uint32_t* H, int rows, int n, int rows_pad, uint8_t* Ep, int32_t* Ers,
                      hipStream_t s);
-// Column tiles of 16 for the 4h offset bytes (4, 8, 16, 24 or 32).
+// Column tiles of 16 of the contraction: the 4h + 3 output positions, padded to whole column
+// groups (offset.hip).
 int offset_tiles(int h);
 // out[k] = cko[k] 2^96 mod N (canonical) for the n offset entries of one client (h limbs each).
 void launch_scale_offsets(const ClientDev& cd, const uint32_t* cko, int n, uint32_t* out,
                           hipStream_t s);
-// The offset bytes of `batch` scaled offset vectors ys (batch x n x h limbs) in the
-// contraction's fragment order: Yf holds batch x S x offset_tiles(h) KiB; colsum (batch x 16
-// offset_tiles(h)) receives sum_{k<n} (byte c of ys[i][k]) - 128.
+// The offset bytes of `batch` scaled offset vectors ys (batch x n x h limbs), shifted by one
+// position per E plane, in the contraction's fragment order: Yf holds batch x 4 S x
+// offset_tiles(h) KiB; colsum (batch x 16 offset_tiles(h)) receives
+// sum_{k<n} (byte c of ys[i][k]) - 128 for c < 4h.
 void launch_pack_y(const uint32_t* ys, int batch, int n, int h, uint8_t* Yf, int32_t* colsum,
                    hipStream_t s);
 // W[j ldw + i cpc + pos] = sum_k sum_a (byte a of E_jk) (byte pos - a of ys[i][k]) for j < rows,
@@ -275,6 +277,16 @@ pir_status answer_compress_launch(pir_server* s, uint32_t id, const uint32_t* dQ
                                   uint32_t* part, bool events = true);
 void set_error(const char* msg);  // sets the calling thread's pir_last_error() text
 int server_device(pir_server* s);
+// pir_answer on device arrays in steps, for a caller that interleaves other streams' work
+// between them (the serving engine): answer_begin picks the path (*path PIR_PATH_AUTO on entry)
+// and enqueues the query packing; answer_rows enqueues rows [r0, r0 + nr) of B (r0 a multiple
+// of 256).  Both on the server's stream, which must be current.
+pir_status answer_begin(pir_server* s, const uint32_t* dQ, uint32_t batch, uint32_t* dB, int32_t* path);
+pir_status answer_rows(pir_server* s, const uint32_t* dQ, uint32_t batch, uint32_t* dB, int32_t path, uint32_t r0,
+                       uint32_t nr);
+// Attach the server to a serving engine (tunes and sizes the batched shapes for batches up to
+// max_batch answered in steps of step_rows rows, then stops in-place tuning) or detach it.
+pir_status server_serving(pir_server* s, bool on, uint32_t max_batch, uint32_t step_rows);
 
 // ---- noalloc.hip: the static scratch array of pir_answer_compress_noalloc
 // With `device` current: looks up that device's address of the array once (hipGetSymbolAddress)

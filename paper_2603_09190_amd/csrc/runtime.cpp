@@ -116,6 +116,9 @@ struct pir_server {
   uint32_t next_id = 1;
   std::map<void*, size_t> allocs;
   uint64_t bytes = 0;
+  // attached to a serving engine: shapes not yet tuned run with the default launch shape
+  // instead of being tuned in place (the engine tunes its shapes when the database is added)
+  bool serving = false;
   // per-kernel event timing (pir_profile)
   bool prof = false;
   struct ProfRecord {
@@ -294,7 +297,8 @@ void tune_store_locked() {
       << kv.second.mr << " " << kv.second.depth << " " << kv.second.ksplit << " " << kv.second.blocks_per_cu << "\n";
 }
 
-bool autotune_enabled() {
+bool autotune_enabled(const pir_server* s) {
+  if (s->serving) return false;
   const char* e = std::getenv("ZIPPIR_AUTOTUNE");
   return !(e && std::strcmp(e, "0") == 0);
 }
@@ -314,7 +318,7 @@ pir_status run_gemm_x(pir_server* s, const uint8_t* D, int rows, int cols, int p
     tune_load_locked();
     auto it = g_tune.find(key);
     if (it != g_tune.end()) shape = it->second;
-    else need_tune = autotune_enabled();
+    else need_tune = autotune_enabled(s);
   }
   if (need_tune) {
     const size_t nout = (size_t)rows * (size_t)ncol;
@@ -476,7 +480,7 @@ pir_status run_hgemm(pir_server* s, const uint8_t* D, bool tiled, int rows, cons
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_htune.find(key);
     if (it != g_htune.end()) variant = it->second;
-    else need_tune = autotune_enabled();
+    else need_tune = autotune_enabled(s);
   }
   if (need_tune) {
     ZP_TRY(tune_variants(s, "hint contraction", zp::hgemm_variants(), launch, H, rows, (int)s->n, true, s->n, &variant));
@@ -501,7 +505,7 @@ pir_status run_batch(pir_server* s, const uint8_t* Dt, int rows, const uint32_t*
     tune_load_locked();
     auto it = g_btune.find(key);
     if (it != g_btune.end()) shape = it->second;
-    else need_tune = autotune_enabled();
+    else need_tune = autotune_enabled(s);
   }
   // The split form: planes packed by their own launch, then the byte-plane contraction with
   // split-K atomics (shape.mr == 0 marks it; depth and ksplit pick its launch shape).
@@ -530,19 +534,6 @@ pir_status run_batch(pir_server* s, const uint8_t* Dt, int rows, const uint32_t*
   }
   ProfScope ps(s, PIR_KERNEL_GEMM);
   launch(shape);
-  return PIR_OK;
-}
-
-// Batched answers stream D in row chunks of at most kLaunchBytes (see launch_matvec).
-pir_status run_gemm_chunked(pir_server* s, const int8_t* Xs, const int32_t* colsum, int ncol,
-                            uint32_t* out, long long ld) {
-  const long long per = std::max<long long>(256, zp::kLaunchBytes / s->pitch / 256 * 256);
-  const uint8_t* base = s->Dt ? s->Dt : s->D;  // chunks start at multiples of 256 rows
-  for (long long r0 = 0; r0 < s->rows; r0 += per) {
-    const int nr = (int)std::min<long long>(per, s->rows - r0);
-    ZP_TRY(run_gemm(s, base + (size_t)r0 * s->pitch, nr, Xs, colsum, ncol, s->rowsum + r0,
-                    out + r0, false, ld, s->Dt != nullptr));
-  }
   return PIR_OK;
 }
 
@@ -1183,6 +1174,58 @@ pir_status pir_update_rows(pir_server* s, const uint32_t* rows, uint32_t nrows,
   return PIR_OK;
 }
 
+// The answer's first step on device queries: picks the path (PIR_PATH_AUTO: the matvec for one
+// query, the contraction otherwise) and sizes the scratch the row ranges use.  Nothing is
+// enqueued: every row range packs what it reads itself, so the ranges of batches interleaved on
+// one stream (the serving engine's two slots per database) never share packed operands.
+static pir_status answer_begin_impl(pir_server* s, const uint32_t* dQ, uint32_t batch, uint32_t* dB, int32_t* path) {
+  (void)dQ;
+  (void)dB;
+  if (*path == PIR_PATH_AUTO) *path = batch == 1 ? PIR_PATH_MATVEC : PIR_PATH_MFMA;
+  if (*path != PIR_PATH_MATVEC && *path != PIR_PATH_MFMA) return fail(PIR_EINVAL, "unknown answer path");
+  ZP_TRY(s->scratch(s->s_planes, (size_t)batch * 4 * s->pitch));
+  ZP_TRY(s->scratch(s->s_colsum, (size_t)batch * 4 * sizeof(int32_t)));
+  return PIR_OK;
+}
+
+// Rows [r0, r0 + nr) of the answer (r0 a multiple of 256), after answer_begin_impl: the query
+// planes packed (and, for the matvec, B's rows of the range cleared), then the range's launches.
+static pir_status answer_rows_impl(pir_server* s, const uint32_t* dQ, uint32_t batch, uint32_t* dB, int32_t path,
+                                   uint32_t r0, uint32_t nr) {
+  hipStream_t st = s->stream;
+  if (r0 % 256 != 0 || r0 > s->rows || nr > s->rows - r0) return fail(PIR_EINVAL, "bad answer row range");
+  if (nr == 0) return PIR_OK;
+  uint8_t* planes = (uint8_t*)s->s_planes.p;
+  if (path == PIR_PATH_MATVEC) {
+    for (uint32_t c = 0; c < batch; ++c)
+      zp::launch_pack_planes_u8(dQ + (size_t)c * s->cols, (int)s->cols, (int)s->pitch,
+                                planes + (size_t)c * 4 * s->pitch, dB + (size_t)c * s->rows + r0, (int)nr, st);
+    ProfScope ps(s, PIR_KERNEL_MATVEC, (int)batch);
+    for (uint32_t c = 0; c < batch; ++c)
+      zp::launch_matvec(s->D + (size_t)r0 * s->pitch, (int)nr, (int)s->pitch, planes + (size_t)c * 4 * s->pitch,
+                        dB + (size_t)c * s->rows + r0, st);
+  } else if (s->Dt && zp::batch_answer_supported((int)s->rows, (int)s->pitch)) {
+    // the contraction on the tiled copy packs the planes itself (run_batch)
+    ZP_TRY(run_batch(s, s->Dt + (size_t)r0 * s->pitch, (int)nr, dQ, (int)batch, s->rowsum + r0, dB + r0,
+                     (long long)s->rows));
+  } else {
+    zp::launch_pack_planes_s8(dQ, s->cols, 1, (int)batch, (int)s->cols, (int)s->pitch, (int8_t*)planes,
+                              (int32_t*)s->s_colsum.p, st);
+    const uint8_t* base = s->Dt ? s->Dt : s->D;
+    ZP_TRY(run_gemm(s, base + (size_t)r0 * s->pitch, (int)nr, (const int8_t*)planes, (const int32_t*)s->s_colsum.p,
+                    (int)batch, s->rowsum + r0, dB + r0, false, (long long)s->rows, s->Dt != nullptr));
+  }
+  ZP_HIP(hipGetLastError());
+  return PIR_OK;
+}
+
+// Rows of D per launch when a whole answer is enqueued at once: at most kLaunchBytes of D, a
+// multiple of 256 rows.
+static uint32_t rows_per_launch(const pir_server* s, long long bytes) {
+  const long long per = std::max<long long>(256, bytes / s->pitch / 256 * 256);
+  return (uint32_t)std::min<long long>(per, 1LL << 30);
+}
+
 static pir_status answer_impl(pir_server* s, const uint32_t* Q, uint32_t batch, uint32_t* B,
                               uint32_t ptr_flags, int32_t path) {
   hipStream_t st = s->stream;
@@ -1197,44 +1240,66 @@ static pir_status answer_impl(pir_server* s, const uint32_t* Q, uint32_t batch, 
     dQ = (const uint32_t*)s->s_q.p;
     dB = (uint32_t*)s->s_b.p;
   }
-  if (path == PIR_PATH_AUTO) path = batch == 1 ? PIR_PATH_MATVEC : PIR_PATH_MFMA;
-  if (path == PIR_PATH_MATVEC) {
-    // pack every query first so the matvecs run back to back
-    ZP_TRY(s->scratch(s->s_planes, (size_t)batch * 4 * s->pitch));
-    uint8_t* planes = (uint8_t*)s->s_planes.p;
-    for (uint32_t c = 0; c < batch; ++c)
-      zp::launch_pack_planes_u8(dQ + (size_t)c * s->cols, (int)s->cols, (int)s->pitch,
-                                planes + (size_t)c * 4 * s->pitch, dB + (size_t)c * s->rows,
-                                (int)s->rows, st);
-    ProfScope ps(s, PIR_KERNEL_MATVEC, (int)batch);
-    for (uint32_t c = 0; c < batch; ++c)
-      zp::launch_matvec(s->D, (int)s->rows, (int)s->pitch, planes + (size_t)c * 4 * s->pitch,
-                        dB + (size_t)c * s->rows, st);
-  } else if (path == PIR_PATH_MFMA && s->Dt && zp::batch_answer_supported((int)s->rows, (int)s->pitch)) {
-    // the fused, persistent contraction on the tiled copy, in row chunks of at most kLaunchBytes
-    const long long per = std::max<long long>(256, zp::kLaunchBytes / s->pitch / 256 * 256);
-    for (long long r0 = 0; r0 < s->rows; r0 += per) {
-      const int nr = (int)std::min<long long>(per, s->rows - r0);
-      ZP_TRY(run_batch(s, s->Dt + (size_t)r0 * s->pitch, nr, dQ, (int)batch, s->rowsum + r0, dB + r0,
-                       (long long)s->rows));
-    }
-  } else if (path == PIR_PATH_MFMA) {
-    ZP_TRY(s->scratch(s->s_planes, (size_t)batch * 4 * s->pitch));
-    ZP_TRY(s->scratch(s->s_colsum, (size_t)batch * 4 * sizeof(int32_t)));
-    zp::launch_pack_planes_s8(dQ, s->cols, 1, (int)batch, (int)s->cols, (int)s->pitch,
-                              (int8_t*)s->s_planes.p, (int32_t*)s->s_colsum.p, st);
-    ZP_TRY(run_gemm_chunked(s, (const int8_t*)s->s_planes.p, (const int32_t*)s->s_colsum.p,
-                            (int)batch, dB, (long long)s->rows));
-  } else {
-    return fail(PIR_EINVAL, "unknown answer path");
-  }
-  ZP_HIP(hipGetLastError());
+  ZP_TRY(answer_begin_impl(s, dQ, batch, dB, &path));
+  // D is streamed in row ranges of at most kLaunchBytes per launch, so that work queued on
+  // other streams is dispatched between them
+  const uint32_t per = rows_per_launch(s, zp::kLaunchBytes);
+  for (uint32_t r0 = 0; r0 < s->rows; r0 += per)
+    ZP_TRY(answer_rows_impl(s, dQ, batch, dB, path, r0, std::min(per, s->rows - r0)));
   if (ptr_flags == PIR_PTR_HOST) {
     ZP_HIP(hipMemcpyAsync(B, dB, bbytes, hipMemcpyDeviceToHost, st));
     ZP_HIP(hipStreamSynchronize(st));
   }
   return PIR_OK;
 }
+
+}  // extern "C"
+
+pir_status zp::answer_begin(pir_server* s, const uint32_t* dQ, uint32_t batch, uint32_t* dB, int32_t* path) {
+  return answer_begin_impl(s, dQ, batch, dB, path);
+}
+
+pir_status zp::answer_rows(pir_server* s, const uint32_t* dQ, uint32_t batch, uint32_t* dB, int32_t path,
+                           uint32_t r0, uint32_t nr) {
+  return answer_rows_impl(s, dQ, batch, dB, path, r0, nr);
+}
+
+// Attach to (on) or detach from (off) a serving engine.  Attaching first runs the engine's
+// batched answer shapes once on zero queries -- every batch size from 2 to max_batch falls in
+// one of ceil(max_batch / 32) column-group shapes, answered in row ranges of `step_rows` rows
+// as the engine does -- so that each contraction shape is tuned (and its scratch sized) before
+// serving; afterwards shapes are no longer tuned in place.
+pir_status zp::server_serving(pir_server* s, bool on, uint32_t max_batch, uint32_t step_rows) {
+  ZP_TRY(use_device(s));
+  if (!on) {
+    s->serving = false;
+    return PIR_OK;
+  }
+  if (max_batch >= 2) {
+    if (step_rows == 0 || step_rows % 256 != 0) return fail(PIR_EINVAL, "step rows must be a multiple of 256");
+    void* q = nullptr;
+    void* b = nullptr;
+    ZP_TRY(s->alloc(&q, (size_t)max_batch * s->cols * sizeof(uint32_t)));
+    pir_status rc = s->alloc(&b, (size_t)max_batch * s->rows * sizeof(uint32_t));
+    if (rc == PIR_OK && hipMemsetAsync(q, 0, (size_t)max_batch * s->cols * sizeof(uint32_t), s->stream) != hipSuccess)
+      rc = fail(PIR_EDEVICE, "hipMemsetAsync failed");
+    for (uint32_t g = 1; rc == PIR_OK && 32 * (g - 1) + 2 <= max_batch; ++g) {
+      const uint32_t batch = std::min(max_batch, 32 * g);
+      int32_t path = PIR_PATH_AUTO;
+      rc = answer_begin_impl(s, (const uint32_t*)q, batch, (uint32_t*)b, &path);
+      for (uint32_t r0 = 0; rc == PIR_OK && r0 < s->rows; r0 += step_rows)
+        rc = answer_rows_impl(s, (const uint32_t*)q, batch, (uint32_t*)b, path, r0, std::min(step_rows, s->rows - r0));
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess && rc == PIR_OK) rc = fail(PIR_EDEVICE, "hipStreamSynchronize failed");
+    s->release(q);
+    s->release(b);
+    ZP_TRY(rc);
+  }
+  s->serving = true;
+  return PIR_OK;
+}
+
+extern "C" {
 
 pir_status pir_answer_path(pir_server* s, const uint32_t* Q, uint32_t batch, uint32_t* B,
                            uint32_t ptr_flags, int32_t path) {
@@ -1446,7 +1511,7 @@ static pir_status offset_contract(pir_server* s, const std::vector<ClientState*>
   const long long ncol = (long long)batch * cpc;
   const size_t kbytes = (size_t)batch * s->n * h * sizeof(uint32_t);
   const int NT = zp::offset_tiles((int)h);
-  ZP_TRY(s->scratch(s->s_x, (size_t)batch * zp::offset_slices((int)s->n) * NT * 1024));
+  ZP_TRY(s->scratch(s->s_x, (size_t)batch * 4 * zp::offset_slices((int)s->n) * NT * 1024));
   ZP_TRY(s->scratch(s->s_xcs, (size_t)batch * 16 * NT * sizeof(int32_t)));
   ZP_TRY(s->scratch(s->s_w, (size_t)s->rows * ncol * sizeof(uint32_t)));
   ZP_TRY(s->scratch(s->s_ys, kbytes));
@@ -1471,7 +1536,7 @@ static pir_status offset_contract(pir_server* s, const std::vector<ClientState*>
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_otune.find(key);
     if (it != g_otune.end()) variant = it->second;
-    else need_tune = autotune_enabled();
+    else need_tune = autotune_enabled(s);
   }
   if (need_tune) {
     prepare(s->stream);

@@ -5,12 +5,21 @@
 // keeps one FIFO queue per database.  Each database has two batch slots (device buffers for
 // the queries, the answers and the compressed responses of one batch); whenever a slot is
 // free and arrived requests are waiting, it takes up to max_batch of them whose clients
-// share a limb count and a packing factor, and enqueues on the database's stream: query
-// uploads, pir_answer (matvec for one request, one int8-MFMA contraction otherwise),
-// pir_compress (or pir_compress_packed for clients with packed responses), and one download
-// per response.  An event marks the batch's end; the scheduler polls events and
-// hands completions to pir_engine_poll.  Databases use different streams, so their batches
-// overlap on the device, and a database with a batch in flight forms its next one meanwhile.
+// share a limb count and a packing factor.  A batch is a list of steps enqueued on the
+// database's stream: query uploads and packing, the answer in row ranges of at most
+// step_bytes of D (matvec for one request, one int8-MFMA contraction otherwise),
+// pir_compress (or pir_compress_packed for clients with packed responses), and the
+// downloads in pieces of at most copy_bytes.  With more than one database registered, a
+// batch keeps at most kDepth steps queued on its stream and the scheduler enqueues the next
+// one as an earlier one completes, so a large database's answer never stands more than a
+// couple of steps ahead of a small database's request on the device.  The scheduler polls
+// the step events and hands completions to pir_engine_poll.  Databases use different
+// streams, so their batches overlap on the device, and a database with a batch in flight
+// forms its next one meanwhile.
+//
+// Device buffers of batches come from a pool: a slot that needs a larger buffer hands its
+// old one back, and buffers are only freed (hipFree synchronises the device) when the budget
+// cannot otherwise admit a batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +42,12 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// D bytes per answer step and response bytes per download step (defaults; pir_engine_set_steps).
+constexpr uint64_t kStepBytes = 256ull << 20;
+constexpr uint64_t kCopyBytes = 8ull << 20;
+// Steps of one batch queued ahead on its stream when several databases share the device.
+constexpr size_t kDepth = 2;
+
 struct Request {
   uint64_t id = 0;
   uint32_t db = 0, client = 0, L = 0;
@@ -42,14 +57,32 @@ struct Request {
   uint32_t* result = nullptr;
 };
 
+enum StepKind : uint8_t { kBegin, kRows, kCompress, kCopy };
+
+struct Step {
+  StepKind kind;
+  uint32_t a = 0, b = 0;  // kRows: first row, rows; kCopy: request, byte offset / kCopyBytes
+};
+
 struct Slot {
-  uint32_t* dev = nullptr;  // queries | answers | responses, capacity `cap` requests of `L_cap`
+  uint32_t* dev = nullptr;  // queries | answers | responses of the batch
   uint64_t bytes = 0;
   bool busy = false;
-  hipEvent_t ev = nullptr;
   std::vector<Request> reqs;
+  uint32_t L = 0, ell = 1;
+  int32_t path = PIR_PATH_AUTO;
+  std::vector<Step> steps;
+  size_t next = 0;                  // first step not yet enqueued
+  std::deque<hipEvent_t> pending;   // events after enqueued steps, oldest first
+  std::vector<hipEvent_t> spare;    // recorded-and-passed events for reuse
   double start_ms = 0;
   int32_t status = PIR_OK;
+};
+
+struct PoolBuf {
+  uint32_t* dev;
+  uint64_t bytes;
+  int device;
 };
 
 struct Db {
@@ -57,6 +90,7 @@ struct Db {
   hipStream_t stream = nullptr;
   int device = 0;
   uint32_t rows = 0, cols = 0;
+  uint32_t step_rows = 0;        // rows of D per answer step (a multiple of 256)
   std::deque<Request> queue;
   Slot slots[2];
   std::vector<uint32_t*> qpool;  // free pinned query buffers (cols words each)
@@ -77,7 +111,10 @@ uint32_t batch_key(const Request& r) { return r.L | (r.ell << 16); }
 struct pir_engine {
   Clock::time_point t0 = Clock::now();
   uint32_t max_batch = 32;
-  uint64_t budget = 0, in_use = 0, peak = 0;
+  uint64_t step_bytes = kStepBytes, copy_bytes = kCopyBytes;
+  uint64_t budget = 0, in_use = 0, peak = 0;  // in_use counts slot and pool buffers
+  std::vector<PoolBuf> pool;                   // idle device buffers
+  uint64_t pooled = 0;
   std::vector<std::unique_ptr<Db>> dbs;
   std::mutex mu;
   std::condition_variable cv_sched, cv_done;
@@ -94,8 +131,11 @@ struct pir_engine {
   }
   void run();
   bool launch(Db& d, Slot& slot, uint32_t n);
+  bool advance(Db& d, Slot& slot);
+  int32_t run_step(Db& d, Slot& slot, const Step& st);
   void complete(Db& d, Slot& slot);
-  bool reserve(Db& d, Slot& slot, uint64_t need);
+  bool reserve(Db& d, Slot& slot, uint64_t need, uint64_t full);
+  void free_pool(int device, uint64_t target);
 };
 
 namespace {
@@ -120,71 +160,176 @@ extern "C" uint32_t pir_engine_plan(const uint32_t* queued_limbs, uint32_t nqueu
   return n;
 }
 
-// Make sure `slot` holds at least `need` bytes of device memory within the budget.  Idle
-// slots of every database are released if the budget is short.  Called with mu held.
-bool pir_engine::reserve(Db& d, Slot& slot, uint64_t need) {
-  if (slot.bytes >= need) return true;
-  auto release = [&](Slot& s) {
-    if (s.dev) {
-      (void)hipFree(s.dev);
-      in_use -= s.bytes;
-      s.dev = nullptr;
-      s.bytes = 0;
-    }
-  };
-  release(slot);
-  if (in_use + need > budget) {
-    for (auto& other : dbs)
-      for (Slot& s : other->slots)
-        if (!s.busy && &s != &slot) release(s);
+// Free pooled buffers (largest first) until in_use + target fits the budget or the pool is
+// empty.  Called with mu held, only when the budget is short.
+void pir_engine::free_pool(int device, uint64_t target) {
+  std::sort(pool.begin(), pool.end(), [](const PoolBuf& x, const PoolBuf& y) { return x.bytes < y.bytes; });
+  while (in_use + target > budget && !pool.empty()) {
+    PoolBuf pb = pool.back();
+    pool.pop_back();
+    (void)hipSetDevice(pb.device);
+    (void)hipFree(pb.dev);
+    in_use -= pb.bytes;
+    pooled -= pb.bytes;
   }
-  if (in_use + need > budget) return false;
+  (void)hipSetDevice(device);
+}
+
+// Make sure `slot` holds at least `need` bytes of device memory within the budget: its own
+// buffer, else the smallest pooled buffer that is large enough, else a new one of `full`
+// bytes (a max_batch batch of the same kind) when the budget has room for that, else of
+// `need` bytes.  Called with mu held.
+bool pir_engine::reserve(Db& d, Slot& slot, uint64_t need, uint64_t full) {
+  if (slot.bytes >= need) return true;
+  if (slot.dev) {
+    pool.push_back(PoolBuf{slot.dev, slot.bytes, d.device});
+    pooled += slot.bytes;
+    slot.dev = nullptr;
+    slot.bytes = 0;
+  }
+  int best = -1;
+  for (size_t i = 0; i < pool.size(); ++i)
+    if (pool[i].device == d.device && pool[i].bytes >= need && (best < 0 || pool[i].bytes < pool[(size_t)best].bytes))
+      best = (int)i;
+  if (best >= 0) {
+    slot.dev = pool[(size_t)best].dev;
+    slot.bytes = pool[(size_t)best].bytes;
+    pooled -= slot.bytes;
+    pool.erase(pool.begin() + best);
+    return true;
+  }
+  uint64_t want = std::max(need, full);
+  if (in_use + want > budget) want = need;
+  if (in_use + want > budget) free_pool(d.device, want);
+  if (in_use + want > budget) {
+    // idle slots elsewhere give their buffers up too
+    for (auto& other : dbs)
+      for (Slot& o : other->slots)
+        if (!o.busy && &o != &slot && o.dev) {
+          pool.push_back(PoolBuf{o.dev, o.bytes, other->device});
+          pooled += o.bytes;
+          o.dev = nullptr;
+          o.bytes = 0;
+        }
+    free_pool(d.device, want);
+  }
+  if (in_use + want > budget) return false;
   (void)hipSetDevice(d.device);
-  if (hipMalloc((void**)&slot.dev, need) != hipSuccess) {
+  if (hipMalloc((void**)&slot.dev, want) != hipSuccess) {
     (void)hipGetLastError();
     slot.dev = nullptr;
     return false;
   }
-  slot.bytes = need;
-  in_use += need;
+  slot.bytes = want;
+  in_use += want;
   peak = std::max(peak, in_use);
   return true;
 }
 
+// Form the batch of the first n queued requests in `slot` and enqueue its first steps.
 bool pir_engine::launch(Db& d, Slot& slot, uint32_t n) {
   const uint32_t L = d.queue.front().L, ell = d.queue.front().ell;
-  const uint64_t orows = response_rows(d, ell);
-  const uint64_t need = bytes_per_request(d, L, ell) * n;
-  if (!reserve(d, slot, need)) return false;
+  const uint64_t per = bytes_per_request(d, L, ell);
+  if (!reserve(d, slot, per * n, per * max_batch)) return false;
   slot.reqs.assign(d.queue.begin(), d.queue.begin() + n);
   d.queue.erase(d.queue.begin(), d.queue.begin() + n);
-  uint32_t* dQ = slot.dev;
-  uint32_t* dB = dQ + (size_t)n * d.cols;
-  uint32_t* dC = dB + (size_t)n * d.rows;
-  (void)hipSetDevice(d.device);
-  int32_t st = PIR_OK;
-  for (uint32_t i = 0; i < n && st == PIR_OK; ++i)
-    if (hipMemcpyAsync(dQ + (size_t)i * d.cols, slot.reqs[i].host_q, 4ull * d.cols,
-                       hipMemcpyHostToDevice, d.stream) != hipSuccess)
-      st = PIR_EDEVICE;
-  std::vector<uint32_t> ids(n);
-  for (uint32_t i = 0; i < n; ++i) ids[i] = slot.reqs[i].client;
-  if (st == PIR_OK) st = pir_answer(d.srv, dQ, n, dB, PIR_PTR_DEVICE);
-  if (st == PIR_OK)
-    st = ell > 1 ? pir_compress_packed(d.srv, ids.data(), n, dB, dC, PIR_PTR_DEVICE)
-                 : pir_compress(d.srv, ids.data(), n, dB, dC, PIR_PTR_DEVICE);
-  for (uint32_t i = 0; i < n && st == PIR_OK; ++i)
-    if (hipMemcpyAsync(slot.reqs[i].result, dC + (size_t)i * orows * L, 4ull * orows * L,
-                       hipMemcpyDefault, d.stream) != hipSuccess)
-      st = PIR_EDEVICE;
-  if (!slot.ev) (void)hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming);
-  (void)hipEventRecord(slot.ev, d.stream);
-  slot.status = st;
+  slot.L = L;
+  slot.ell = ell;
+  slot.path = PIR_PATH_AUTO;
+  slot.steps.clear();
+  slot.steps.push_back(Step{kBegin});
+  for (uint32_t r0 = 0; r0 < d.rows; r0 += d.step_rows)
+    slot.steps.push_back(Step{kRows, r0, std::min(d.step_rows, d.rows - r0)});
+  slot.steps.push_back(Step{kCompress});
+  const uint64_t rbytes = 4ull * response_rows(d, ell) * L;
+  for (uint32_t i = 0; i < n; ++i)
+    for (uint64_t off = 0; off < rbytes; off += copy_bytes) slot.steps.push_back(Step{kCopy, i, (uint32_t)(off / copy_bytes)});
+  slot.next = 0;
+  slot.status = PIR_OK;
   slot.start_ms = now();
   slot.busy = true;
   ++batches;
   batched_reqs += n;
+  advance(d, slot);
   return true;
+}
+
+int32_t pir_engine::run_step(Db& d, Slot& slot, const Step& st) {
+  const uint32_t n = (uint32_t)slot.reqs.size();
+  uint32_t* dQ = slot.dev;
+  uint32_t* dB = dQ + (size_t)n * d.cols;
+  uint32_t* dC = dB + (size_t)n * d.rows;
+  (void)hipSetDevice(d.device);
+  switch (st.kind) {
+    case kBegin:
+      for (uint32_t i = 0; i < n; ++i)
+        if (hipMemcpyAsync(dQ + (size_t)i * d.cols, slot.reqs[i].host_q, 4ull * d.cols, hipMemcpyHostToDevice,
+                           d.stream) != hipSuccess)
+          return PIR_EDEVICE;
+      return zp::answer_begin(d.srv, dQ, n, dB, &slot.path);
+    case kRows:
+      return zp::answer_rows(d.srv, dQ, n, dB, slot.path, st.a, st.b);
+    case kCompress: {
+      std::vector<uint32_t> ids(n);
+      for (uint32_t i = 0; i < n; ++i) ids[i] = slot.reqs[i].client;
+      return slot.ell > 1 ? pir_compress_packed(d.srv, ids.data(), n, dB, dC, PIR_PTR_DEVICE)
+                          : pir_compress(d.srv, ids.data(), n, dB, dC, PIR_PTR_DEVICE);
+    }
+    case kCopy: {
+      const uint64_t rbytes = 4ull * response_rows(d, slot.ell) * slot.L;
+      const uint64_t off = (uint64_t)st.b * copy_bytes;
+      const uint64_t len = std::min(copy_bytes, rbytes - off);
+      const char* src = reinterpret_cast<const char*>(dC) + (uint64_t)st.a * rbytes + off;
+      char* dst = reinterpret_cast<char*>(slot.reqs[st.a].result) + off;
+      return hipMemcpyAsync(dst, src, len, hipMemcpyDefault, d.stream) == hipSuccess ? PIR_OK : PIR_EDEVICE;
+    }
+  }
+  return PIR_EINVAL;
+}
+
+// Retire the slot's passed step events and enqueue further steps while fewer than kDepth are
+// outstanding (every step at once when only one database is registered).  A step that fails
+// marks the batch failed and the rest are skipped.  Returns true if anything changed.
+bool pir_engine::advance(Db& d, Slot& slot) {
+  bool changed = false;
+  while (!slot.pending.empty()) {
+    const hipError_t q = hipEventQuery(slot.pending.front());
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) {
+      (void)hipGetLastError();
+      slot.status = PIR_EDEVICE;
+    }
+    slot.spare.push_back(slot.pending.front());
+    slot.pending.pop_front();
+    changed = true;
+  }
+  const bool paced = dbs.size() > 1;
+  while (slot.next < slot.steps.size() && (!paced || slot.pending.size() < kDepth)) {
+    if (slot.status == PIR_OK) slot.status = run_step(d, slot, slot.steps[slot.next]);
+    ++slot.next;
+    changed = true;
+    if (!paced && slot.next < slot.steps.size()) continue;
+    hipEvent_t ev = nullptr;
+    if (!slot.spare.empty()) {
+      ev = slot.spare.back();
+      slot.spare.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      ev = nullptr;
+    }
+    if (ev && hipEventRecord(ev, d.stream) == hipSuccess) {
+      slot.pending.push_back(ev);
+    } else {
+      // no event to poll: wait for the stream here instead
+      (void)hipGetLastError();
+      if (ev) slot.spare.push_back(ev);
+      if (hipStreamSynchronize(d.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        slot.status = PIR_EDEVICE;
+      }
+    }
+  }
+  return changed;
 }
 
 void pir_engine::complete(Db& d, Slot& slot) {
@@ -229,16 +374,12 @@ void pir_engine::run() {
       Db& d = *dp;
       for (Slot& s : d.slots)
         if (s.busy) {
-          const hipError_t q = hipEventQuery(s.ev);
-          if (q == hipErrorNotReady) {
-            inflight = true;
-          } else {
-            if (q != hipSuccess) {
-              (void)hipGetLastError();
-              s.status = PIR_EDEVICE;
-            }
+          if (advance(d, s)) progress = true;
+          if (s.next == s.steps.size() && s.pending.empty()) {
             complete(d, s);
             progress = true;
+          } else {
+            inflight = true;
           }
         }
       for (Slot& s : d.slots) {
@@ -254,7 +395,7 @@ void pir_engine::run() {
         }
         if (limbs.empty()) continue;
         const uint64_t per = bytes_per_request(d, d.queue.front().L, d.queue.front().ell);
-        uint64_t avail = budget - std::min(budget, in_use) + s.bytes;
+        uint64_t avail = budget - std::min(budget, in_use) + s.bytes + pooled;
         uint32_t cap = pir_engine_capacity(avail, per, max_batch);
         if (cap == 0) {
           // idle slots elsewhere can be released to make room
@@ -329,6 +470,16 @@ pir_status pir_engine_create(pir_engine** out, uint32_t max_batch, uint64_t hbm_
   return PIR_OK;
 }
 
+pir_status pir_engine_set_steps(pir_engine* e, uint64_t step_bytes, uint64_t copy_bytes) {
+  if (!e) return efail(PIR_EINVAL, "NULL engine");
+  if (step_bytes == 0 || copy_bytes == 0) return efail(PIR_EINVAL, "step sizes must be positive");
+  std::lock_guard<std::mutex> lk(e->mu);
+  if (!e->dbs.empty()) return efail(PIR_EINVAL, "step sizes must be set before the first database is added");
+  e->step_bytes = step_bytes;
+  e->copy_bytes = copy_bytes;
+  return PIR_OK;
+}
+
 pir_status pir_engine_add_db(pir_engine* e, pir_server* srv, uint32_t* db_index) {
   if (!e || !srv || !db_index) return efail(PIR_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(e->mu);
@@ -343,6 +494,11 @@ pir_status pir_engine_add_db(pir_engine* e, pir_server* srv, uint32_t* db_index)
   if (pir_shape(srv, &rows, &cols, &n, &b) != PIR_OK) return efail(PIR_EINVAL, "bad server");
   d->rows = rows;
   d->cols = cols;
+  const uint64_t pitch = ((uint64_t)cols + 255) / 256 * 256;
+  d->step_rows = (uint32_t)std::min<uint64_t>(1u << 30, std::max<uint64_t>(256, e->step_bytes / pitch / 256 * 256));
+  // tune and size the batched answer's shapes now, not while serving
+  const pir_status st = zp::server_serving(srv, true, e->max_batch, d->step_rows);
+  if (st != PIR_OK) return st;
   *db_index = (uint32_t)e->dbs.size();
   e->dbs.push_back(std::move(d));
   return PIR_OK;
@@ -468,12 +624,18 @@ void pir_engine_destroy(pir_engine* e) {
     (void)hipStreamSynchronize(d->stream);
     for (Slot& s : d->slots) {
       if (s.dev) (void)hipFree(s.dev);
-      if (s.ev) (void)hipEventDestroy(s.ev);
+      for (hipEvent_t ev : s.pending) (void)hipEventDestroy(ev);
+      for (hipEvent_t ev : s.spare) (void)hipEventDestroy(ev);
     }
+    (void)zp::server_serving(d->srv, false, 0, 0);
     for (uint32_t* q : d->qpool) (void)hipHostFree(q);
     for (Request& r : d->queue) (void)hipHostFree(r.host_q);
   }
   for (Request& r : e->incoming) (void)hipHostFree(r.host_q);
+  for (const PoolBuf& pb : e->pool) {
+    (void)hipSetDevice(pb.device);
+    (void)hipFree(pb.dev);
+  }
   delete e;
 }
 

@@ -96,6 +96,7 @@ _sig = {
                                           ctypes.POINTER(ctypes.c_uint64)]),
     "pir_sync": (ctypes.c_int32, [ctypes.c_void_p]),
     "pir_engine_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.c_uint64]),
+    "pir_engine_set_steps": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]),
     "pir_engine_add_db": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "pir_engine_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
@@ -499,6 +500,10 @@ class Engine:
         _check(_lib.pir_engine_create(ctypes.byref(h), max_batch, hbm_budget), "pir_engine_create")
         self._h = h
         self._servers = []
+
+    def set_steps(self, step_bytes: int, copy_bytes: int) -> None:
+        """Bytes of D per answer step and response bytes per download step (before add_db)."""
+        _check(_lib.pir_engine_set_steps(self._h, step_bytes, copy_bytes), "pir_engine_set_steps")
 
     def add_db(self, server: Server) -> int:
         idx = ctypes.c_uint32()

@@ -84,3 +84,23 @@ def test_setup_rejects_oversized_shapes_without_touching_the_gpu(lib, rows, cols
                        ctypes.c_uint32(n), 0)
     assert st == -1 and h.value is None
     assert b"shape too large" in lib.pir_last_error()
+
+
+def test_engine_step_sizes_without_touching_the_gpu(lib):
+    # An engine with an explicit budget is created without device calls; its step sizes are
+    # accepted before any database is added, and 0 is rejected.
+    lib.pir_engine_create.restype = ctypes.c_int32
+    lib.pir_engine_set_steps.restype = ctypes.c_int32
+    lib.pir_engine_set_steps.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]
+    lib.pir_engine_destroy.argtypes = [ctypes.c_void_p]
+    lib.pir_last_error.restype = ctypes.c_char_p
+    h = ctypes.c_void_p()
+    assert lib.pir_engine_create(ctypes.byref(h), 8, ctypes.c_uint64(1 << 30)) == 0 and h.value
+    try:
+        assert lib.pir_engine_set_steps(h, 1 << 20, 4096) == 0
+        assert lib.pir_engine_set_steps(h, 0, 4096) == -1
+        assert b"positive" in lib.pir_last_error()
+        assert lib.pir_engine_set_steps(h, 1 << 20, 0) == -1
+        assert lib.pir_engine_set_steps(None, 1 << 20, 4096) == -1
+    finally:
+        lib.pir_engine_destroy(h)

@@ -61,9 +61,11 @@ def _requests(infos, count, seed):
     return reqs
 
 
-def _run(native, servers, infos, reqs, max_batch=32, budget=0, together=True):
+def _run(native, servers, infos, reqs, max_batch=32, budget=0, together=True, steps=None):
     outs = []
     with native.Engine(max_batch=max_batch, hbm_budget=budget) as eng:
+        if steps:
+            eng.set_steps(*steps)
         for s in servers:
             eng.add_db(s)
         bufs = []
@@ -109,6 +111,27 @@ def test_alone_equals_mix(native, setup):
         b = server.answer(inst.D, q)
         assert limbs_rows_to_ints(mix[idx]) == server.compress(K, b, cl.N)
     assert stats["p99_ms"] >= stats["p50_ms"] > 0
+
+
+def test_stepped_batches_equal_alone(native, setup):
+    # Small steps: the answer in ranges of 256 rows (pitch 1024 and 768) or 512 rows (pitch
+    # 512), ragged at the end, and each response downloaded in pieces of 10000 bytes; with three
+    # databases registered at most two steps of a batch are queued at a time.  Every response
+    # equals the one-at-a-time run with default steps, and the oracle's on two requests.
+    servers, infos, _ = setup
+    reqs = _requests(infos, 40, seed=4)
+    alone, _, _ = _run(native, servers, infos, reqs, together=False)
+    log("serve: stepped mix")
+    mix, comps, stats = _run(native, servers, infos, reqs, steps=(256 * 1024, 10000))
+    assert all(c["status"] == 0 for c in comps) and stats["mean_batch"] > 1.0
+    for a, m in zip(alone, mix):
+        assert np.array_equal(a, m)
+    for idx in (3, 4):
+        db, ci, q = reqs[idx]
+        inst, clients = infos[db]
+        cid, cl, L = clients[ci]
+        K = server.client_hint(cl.ck, server.exponents(server.global_hint(inst.D, inst.A)), cl.N)
+        assert limbs_rows_to_ints(mix[idx]) == server.compress(K, server.answer(inst.D, q), cl.N)
 
 
 def test_memory_pressure_still_exact(native, setup):
@@ -252,3 +275,74 @@ def test_packed_clients_in_the_mix(native):
         b = server.answer(inst.D, q)
         want = server.compress_packed(K, b, cl.N, 5, 1 << t) if kind == 0 else server.compress(K, b, cl.N)
         assert limbs_rows_to_ints(got[i]) == want, f"request {i + 1} vs the oracle"
+
+
+def _hint_row(args):
+    ck, e_row, N = args
+    return server.client_hint_row(ck, e_row, N)
+
+
+def test_mix_at_serving_scale_sampled(native):
+    """The 256 MiB (16384 x 16384) and 1 GiB (32768 x 32768) databases of the serving mix,
+    n = 1024, 2048-bit N, default steps (the 1 GiB answer in four 256 MiB steps, paced beside
+    the other database): every response of a 24-request mix with staggered arrivals equals
+    the one-at-a-time run, and sampled rows of three 256 MiB responses equal the oracle's."""
+    import torch
+    from multiprocessing import Pool
+    from tests.gpu_util import pool_size
+    from tests.instances import make_client
+    n, nb, sides = 1024, 2048, (16384, 32768)
+    servers, clients, Ds, streams = [], [], [], []
+    for i, side in enumerate(sides):
+        log(f"serve scale: database {side}x{side}")
+        D = wl.database(60 + i, side, side, threads=16)
+        A = wl.lwe_matrix(60 + i, side, n)
+        st = torch.cuda.Stream()
+        srv = native.Server(D, A, stream=st.cuda_stream)
+        cl = make_client(60 + i, 0, A, nb, encrypt_secret=False)
+        N_limbs, ck, L = client_arrays(cl, nb)
+        cid = srv.add_client(N_limbs, nb, ck)
+        srv.hint(cid)
+        servers.append(srv)
+        streams.append(st)
+        clients.append((cid, cl, L, A))
+        Ds.append(D)
+    g = np.random.default_rng(61)
+    which = [int(x) for x in g.integers(0, 2, size=24)]
+    which[:3] = [0, 0, 0]
+    qs = [g.integers(0, 1 << 32, size=sides[w], dtype=np.uint32) for w in which]
+
+    def run(together):
+        with native.Engine(max_batch=32) as eng:
+            for s in servers:
+                eng.add_db(s)
+            bufs = [native.PinnedArray((sides[w], clients[w][2])) for w in which]
+            t0 = eng.now_ms()
+            for k, (w, q, b) in enumerate(zip(which, qs, bufs)):
+                eng.submit(w, clients[w][0], q, b.array, arrival_ms=t0 + 0.3 * k if together else -1.0)
+                if not together:
+                    eng.drain()
+            eng.drain()
+            comps = eng.poll(64)
+            outs = [b.array.copy() for b in bufs]
+            for b in bufs:
+                b.close()
+        return outs, comps
+
+    log("serve scale: one at a time")
+    alone, _ = run(False)
+    log("serve scale: mix")
+    mix, comps = run(True)
+    assert len(comps) == 24 and all(c["status"] == 0 for c in comps)
+    for a, m in zip(alone, mix):
+        assert np.array_equal(a, m)
+    cid, cl, L, A = clients[0]
+    rows = [0, 1, sides[0] - 1] + [int(x) for x in g.integers(2, sides[0] - 1, size=5)]
+    E = server.exponents(server.global_hint(Ds[0], A, rows=rows))
+    with Pool(pool_size()) as pool:
+        K = pool.map(_hint_row, [(cl.ck, E[j], cl.N) for j in range(len(rows))])
+    for k in range(3):
+        b = server.answer(Ds[0][rows], qs[k])
+        assert limbs_rows_to_ints(mix[k][rows]) == server.compress(K, b, cl.N), k
+    for s in servers:
+        s.close()
