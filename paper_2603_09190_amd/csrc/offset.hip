@@ -13,6 +13,8 @@
 // so the contraction is exact in 32-bit accumulators.  The offsets are first replaced by
 // y_k = ck_o,k 2^96 mod N, so that a reduction kernel can fold the byte positions into limbs,
 // add b_j 2^96 and finish modulo N with three Montgomery reduction steps (see below).
+#include <type_traits>
+
 #include "internal.h"
 #include "rownum.h"
 #include "stage.h"
@@ -24,17 +26,22 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ---- operands of the offset contraction
 //
-// The contraction runs on v_mfma_i32_16x16x64_i8 with E split into its four byte planes:
-//   W_a[j][c] = sum_k e_jk[a] y_k[c]   (a < 4, c < 4h),    W[j][pos] = sum_a W_a[j][pos - a].
+// The contraction runs on v_mfma_i32_16x16x64_i8 with E's four byte planes laid end to end
+// along K: K' = 4 kpad entries, slice sigma = a S + s holding plane a, entries 64 s ... 64 s + 63.
+// Shifting the offsets' bytes by one position per plane,
+//   Y4[pos][(a, k)] = byte pos - a of y_k   (0 where pos - a is outside [0, 4h)),
+// turns the four shifted plane products into one:
+//   W[j][pos] = sum_{(a, k)} e_jk[a] Y4[pos][(a, k)],   pos < 4h + 3,
+// so the accumulators hold W itself and nothing is added across planes afterwards.
 // Both operands are stored already in MFMA fragment order, shifted to int8 by XOR 0x80:
 //   Ep (E planes): piece (T, a, s) is 1 KiB, lane l's 16 bytes at 16 l hold
 //     E'_a[16 T + l mod 16][64 s + 16 (l / 16) + u], u < 16,
-//   so the stream of one 16-row tile and one plane is contiguous over its S = kpad / 64 slices;
-//   Yf (offset bytes of one client): piece (s, t) is 1 KiB, lane l's bytes
-//     Y'[16 t + l mod 16][64 s + 16 (l / 16) + u] with Y'[c][k] = byte c of y_k,
-//   so one K slice of every column tile is one contiguous NT KiB run.
-// Entries beyond rows, n or 4h are 0 (the value 128 before the shift), which adds nothing to
-// the signed product; the shift terms below count only the real entries.
+//   so one 16-row tile's whole K' stream (4 S pieces) is contiguous;
+//   Yq (shifted offset bytes of one client): piece (sigma, t) is 1 KiB, lane l's bytes
+//     Y4'[16 t + l mod 16][64 s + 16 (l / 16) + u] of plane a,
+//   so one K' slice of the client's NTq column tiles is one contiguous NTq KiB run.
+// Entries beyond rows, n or the shifted range are 0 (the value 128 before the shift), which adds
+// nothing to the signed product; the shift terms below count only the real entries.
 
 // One thread per (tile, slice, lane): reads 16 entries of H once and writes the four planes.
 __global__ __launch_bounds__(256) void e_planes_kernel(const uint32_t* __restrict__ H, int rows, int n,
@@ -101,9 +108,30 @@ void launch_e_planes(const uint32_t* H, int rows, int n, int rows_pad, uint8_t* 
 // its slices in flight; the padding slices are zero and add nothing)
 int offset_slices(int n) { return ((n + 63) / 64 + 3) / 4 * 4; }
 
+// Column tiles of the contraction: the 4h + 3 output positions in tiles of 16, padded to a
+// whole number of column groups of 2 offset_cw(h) tiles.
+int offset_cw(int h) {
+  const int nt = (4 * h + 3 + 15) / 16;
+  if (nt <= 4) return 2;
+  if (nt <= 6) return 3;
+  if (nt <= 10) return 5;
+  if (nt <= 14) return 7;
+  if (nt <= 18) return 9;
+  // several column groups: the width that pads least
+  int best = 9, pad = 1 << 30;
+  for (int cw : {9, 7, 5}) {
+    const int tiles = (nt + 2 * cw - 1) / (2 * cw) * 2 * cw;
+    if (tiles < pad) {
+      pad = tiles;
+      best = cw;
+    }
+  }
+  return best;
+}
+
 int offset_tiles(int h) {
-  const int c = 4 * h;
-  return c <= 64 ? 4 : c <= 128 ? 8 : c <= 256 ? 16 : c <= 384 ? 24 : 32;
+  const int nt = (4 * h + 3 + 15) / 16, bc = 2 * offset_cw(h);
+  return (nt + bc - 1) / bc * bc;
 }
 
 __global__ void zero_i32_kernel(int32_t* __restrict__ p, int n) {
@@ -111,23 +139,26 @@ __global__ void zero_i32_kernel(int32_t* __restrict__ p, int n) {
   if (i < n) p[i] = 0;
 }
 
-// One thread per 16-byte piece of client blockIdx.y; colsum[i 16 NT + c] = sum_{k<n} Y'[c][k]
-// (zeroed first) by one atomic per column and piece row.
+// One thread per 16-byte piece (sigma, t, l) of client blockIdx.y.  colsum[i 16 NTq + c] (zeroed
+// first) = sum_{k<n} (byte c of y_k) - 128 for c < 4h, from the plane-0 pieces: one atomic per
+// column and piece row.
 __global__ __launch_bounds__(256) void pack_y_kernel(const uint32_t* __restrict__ ys, int n, int h, int S,
-                                                     int NT, u32x4* __restrict__ Yf,
+                                                     int NTq, u32x4* __restrict__ Yq,
                                                      int32_t* __restrict__ colsum) {
   const int i = blockIdx.y;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;  // piece within the client: (s, t, l)
-  const int per = S * NT * 64;
+  const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long per = (long long)4 * S * NTq * 64;
   const bool live = p < per;
-  const int l = p & 63;
-  const int q = p >> 6;
-  const int t = q % NT, s = q / NT;
-  const int c = 16 * t + (l & 15);
+  const int l = (int)(p & 63);
+  const long long q = p >> 6;
+  const int t = (int)(q % NTq);
+  const int sig = (int)(q / NTq);
+  const int a = sig / S, s = sig % S;
+  const int c = 16 * t + (l & 15) - a;  // byte position of y this lane holds
   const int k0 = 64 * s + 16 * (l >> 4);
   uint32_t w[4] = {0u, 0u, 0u, 0u};
   int32_t part = 0;
-  if (live && c < 4 * h) {
+  if (live && c >= 0 && c < 4 * h) {
     const uint32_t* y = ys + (size_t)i * n * h + (c >> 2);
     const int sh = 8 * (c & 3);
 #pragma unroll
@@ -140,211 +171,240 @@ __global__ __launch_bounds__(256) void pack_y_kernel(const uint32_t* __restrict_
       }
     }
   }
-  if (live) Yf[(size_t)i * per + p] = u32x4{w[0], w[1], w[2], w[3]};
+  if (live) Yq[(size_t)i * per + p] = u32x4{w[0], w[1], w[2], w[3]};
   // the four lanes l, l^16, l^32, l^48 hold the same column
   part += __shfl_xor(part, 16, 64);
   part += __shfl_xor(part, 32, 64);
-  if (live && l < 16 && c < 4 * h && part != 0) atomicAdd(colsum + (size_t)i * 16 * NT + c, part);
+  if (live && a == 0 && l < 16 && c < 4 * h && part != 0) atomicAdd(colsum + (size_t)i * 16 * NTq + c, part);
 }
 
-void launch_pack_y(const uint32_t* ys, int batch, int n, int h, uint8_t* Yf, int32_t* colsum,
+void launch_pack_y(const uint32_t* ys, int batch, int n, int h, uint8_t* Yq, int32_t* colsum,
                    hipStream_t s) {
-  const int S = offset_slices(n), NT = offset_tiles(h);
-  const int ncs = batch * 16 * NT;
+  const int S = offset_slices(n), NTq = offset_tiles(h);
+  const int ncs = batch * 16 * NTq;
   zero_i32_kernel<<<(ncs + 255) / 256, 256, 0, s>>>(colsum, ncs);
-  const int per = S * NT * 64;
-  dim3 grid((per + 255) / 256, batch);
-  pack_y_kernel<<<grid, 256, 0, s>>>(ys, n, h, S, NT, reinterpret_cast<u32x4*>(Yf), colsum);
+  const long long per = (long long)4 * S * NTq * 64;
+  dim3 grid((unsigned)((per + 255) / 256), batch);
+  pack_y_kernel<<<grid, 256, 0, s>>>(ys, n, h, S, NTq, reinterpret_cast<u32x4*>(Yq), colsum);
 }
 
 // ---- the contraction
 //
-// A workgroup of four wavefronts takes 16 MR rows and one client; wavefront a computes W_a for
-// all 16 NT columns: MR x NT accumulator tiles.  Both operands pass through LDS in NS stages
-// of one 64-byte K slice each, by direct global-to-LDS loads (stage.h): a stage holds the four
-// planes' MR fragments of the block's rows (4 MR KiB, each one contiguous kilobyte of Ep) and
-// the client's NT fragments of the offset bytes (NT KiB, contiguous in Yf).  No operand passes
-// through VGPRs on its way in, so the only wait per slice is for that slice's own loads, and
-// the NS - 2 later slices stay in flight; one barrier per slice.  Each B fragment read from
-// LDS feeds MR MFMAs, each A fragment NT.  Then the four planes are added with their shifts
-// through LDS, one 16-row tile at a time:
-//   W_a = acc + 128 colsum_c + 128 Ers_a[j] + 16384 n (exact modulo 2^32, and the true value
-//   is below 2^32), and W[j][pos] = sum_a W_a[j][pos - a] for pos < 4h + 3.
-// The grid is XCD-aware: workgroup L runs on XCD L mod 8, and each XCD takes the clients of its
-// row blocks (x, x + 8, ...) one after the other, so a block's E stream comes from HBM once and
-// from that XCD's L2 for the other clients.
-template <int MR, int NT, int NS>
-struct OffsetGeom {
-  static constexpr int kAChunks = 4 * MR;                 // (plane, row tile) fragments per slice
-  static constexpr int kChunks = kAChunks + NT;           // plus the offset-byte fragments
-  static constexpr int kPerWave = kChunks / 4;            // loads per lane per slice
-  static constexpr int kStage = kChunks * 1024;
-  static constexpr int kCW = 16 * NT + 4;                 // words per row of a plane in the epilogue
-  static constexpr int kEpi = 4 * 16 * kCW * 4;
-  static constexpr int kLds = NS * kStage > kEpi ? NS * kStage : kEpi;
-  static_assert(kChunks % 4 == 0, "chunks are dealt to four wavefronts");
-};
-
-template <int MR, int NT, int NS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, MR * NT <= 32 ? 2 : 1)))
+// A workgroup of four wavefronts takes 32 RW rows, 32 CW columns (one column group) and one
+// client; wavefront (wr, wc) computes RW x CW accumulator tiles: rows of half wr, columns of
+// half wc.  Both operands pass through LDS in NS stages of one 64-byte K' slice each, by direct
+// global-to-LDS loads (stage.h): a stage holds the block's 2 RW row-tile fragments of E (each a
+// kilobyte of Ep) and its 2 CW column-tile fragments of Yq (one contiguous run); wavefront w
+// issues the fragments w, w + 4, ...  One barrier per slice.
+//   DB = false: each slice's fragments are read from LDS right before its MFMAs (two
+//     wavefronts per SIMD hide each other's waits);
+//   DB = true: the fragments of slice sigma + 1 are read into a second register set while the
+//     MFMAs of slice sigma run (one wavefront per SIMD), so the stage written by the loads issued
+//     at slice sigma is that of slice sigma - 1 and NS - 3 later slices stay in flight.
+// Then each accumulator becomes a W entry, straight to memory:
+//   W = acc + 128 sum_{a in A(pos)} (colsum[pos - a] + Ers_a[j]) + 16384 n |A(pos)|
+// (exact modulo 2^32, and the true value is below 4 n 255^2 < 2^32 for n <= 16384).
+// The grid is XCD-aware: workgroup L runs on XCD L mod 8, and each XCD takes the (client, column
+// group) items of its row blocks (x, x + 8, ...) one after the other, so a block's E stream comes
+// from HBM once and from that XCD's L2 for the other items.
+template <int RW, int CW, int NS, bool DB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, DB ? 1 : 2)))
 void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restrict__ Ers, int rows_pad, int rows,
-                        int n, int S, const uint8_t* __restrict__ Yf, const int32_t* __restrict__ colsum,
-                        int batch, int nrb, int h, uint32_t* __restrict__ W, long long ldw, int cpc) {
-  using Geo = OffsetGeom<MR, NT, NS>;
-  __shared__ __attribute__((aligned(1024))) uint8_t lds[Geo::kLds];
+                        int n, int S, const uint8_t* __restrict__ Yq, const int32_t* __restrict__ colsum,
+                        int batch, int nrb, int ncg, int NTq, int h, uint32_t* __restrict__ W, long long ldw,
+                        int cpc) {
+  constexpr int BR = 2 * RW, BC = 2 * CW, CH = BR + BC, PW = (CH + 3) / 4, STAGE = CH * 1024;
+  static_assert(!DB || NS >= 4, "the double-buffered loop keeps NS - 3 slices in flight");
+  static_assert(PW >= 2 && 3 * PW < 64, "loads per slice");
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[NS * STAGE];
   const int tid = threadIdx.x, lane = tid & 63;
-  const int a = __builtin_amdgcn_readfirstlane(tid >> 6);  // the plane of this wavefront
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = w >> 1, wc = w & 1;
   const int g = lane >> 4, r = lane & 15;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int rb = (slot / batch) * 8 + xcd;
-  const int ci = slot % batch;
+  const int items = batch * ncg;
+  const int rb = (slot / items) * 8 + xcd;
+  const int item = slot % items;
+  const int ci = item / ncg, cg = item % ncg;
   if (rb >= nrb) return;
-  const int T0 = rb * MR;
+  const int T0 = rb * BR, t0 = cg * BC, KS = 4 * S;
+  const int tiles = rows_pad / 16;
 
-  // this wavefront's share of each slice's loads: chunks a, a + 4, ...
-  const uint8_t* src[Geo::kPerWave];
-  long long sstride[Geo::kPerWave];
+  // this wavefront's fragments of each slice: w, w + 4, ...; where that passes CH the wavefront
+  // loads its previous fragment once more (same bytes, same place), so that every wavefront
+  // issues PW loads per slice.  A row tiles are clamped to the last (whose rows are not stored).
+  const uint8_t* src[PW];
+  long long sstride[PW];
+  int dst[PW];
 #pragma unroll
-  for (int j = 0; j < Geo::kPerWave; ++j) {
-    const int c = a + 4 * j;
-    if (c < Geo::kAChunks) {
-      const int pa = c / MR, i = c % MR;
-      src[j] = Ep + ((size_t)((T0 + i) * 4 + pa) * S) * 1024 + lane * 16;
+  for (int j = 0; j < PW; ++j) {
+    const int c = w + 4 * j < CH ? w + 4 * j : w + 4 * j - 4;
+    dst[j] = c * 1024;
+    if (c < BR) {
+      src[j] = Ep + (size_t)min(T0 + c, tiles - 1) * KS * 1024 + lane * 16;
       sstride[j] = 1024;
     } else {
-      src[j] = Yf + ((size_t)ci * S * NT + (c - Geo::kAChunks)) * 1024 + lane * 16;
-      sstride[j] = (long long)NT * 1024;
+      src[j] = Yq + ((size_t)ci * KS * NTq + t0 + c - BR) * 1024 + lane * 16;
+      sstride[j] = (long long)NTq * 1024;
     }
   }
   auto issue = [&](int sl) {  // slice sl (clamped to the last) into its stage buffer
-    const int sc = min(sl, S - 1);
-    uint8_t* base = lds + (sl % NS) * Geo::kStage;
+    const int sc = min(sl, KS - 1);
+    uint8_t* base = lds + (sl % NS) * STAGE;
 #pragma unroll
-    for (int j = 0; j < Geo::kPerWave; ++j) g2l16(src[j] + (size_t)sc * sstride[j], base + (a + 4 * j) * 1024);
+    for (int j = 0; j < PW; ++j) g2l16(src[j] + (size_t)sc * sstride[j], base + dst[j]);
+  };
+  auto wait_slices = [&](auto in_flight) {  // at most in_flight slices of this wavefront's loads pending
+    wait_vmcnt<decltype(in_flight)::value * PW>();
+  };
+  auto sync = [&] {
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   };
 
-  v4i acc[MR][NT];
+  v4i acc[RW][CW];
 #pragma unroll
-  for (int i = 0; i < MR; ++i)
+  for (int i = 0; i < RW; ++i)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[i][t] = v4i{0, 0, 0, 0};
+    for (int t = 0; t < CW; ++t) acc[i][t] = v4i{0, 0, 0, 0};
+
+  struct Frags {
+    v4i b[CW];
+    v4i a[RW];
+  };
+  auto read = [&](Frags& f, int sl) {
+    const uint8_t* base = lds + (sl % NS) * STAGE + lane * 16;
+#pragma unroll
+    for (int t = 0; t < CW; ++t) f.b[t] = *reinterpret_cast<const v4i*>(base + (BR + wc * CW + t) * 1024);
+#pragma unroll
+    for (int i = 0; i < RW; ++i) f.a[i] = *reinterpret_cast<const v4i*>(base + (wr * RW + i) * 1024);
+  };
+  auto mma = [&](const Frags& f) {
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+      for (int t = 0; t < CW; ++t) acc[i][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(f.a[i], f.b[t], acc[i][t], 0, 0, 0);
+  };
 
 #pragma unroll
   for (int st = 0; st < NS - 1; ++st) issue(st);
-  for (int s = 0; s < S; ++s) {
-    wait_vmcnt<(NS - 2) * Geo::kPerWave>();  // slice s has landed (later slices stay in flight)
-    __builtin_amdgcn_s_barrier();            // ... for every wavefront; slice s - 1 is consumed
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-    issue(s + NS - 1);
-    const uint8_t* base = lds + (s % NS) * Geo::kStage + lane * 16;
-    v4i bf[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) bf[t] = *reinterpret_cast<const v4i*>(base + (Geo::kAChunks + t) * 1024);
-#pragma unroll
-    for (int i = 0; i < MR; ++i) {
-      const v4i af = *reinterpret_cast<const v4i*>(base + (a * MR + i) * 1024);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[i][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[t], acc[i][t], 0, 0, 0);
+  if constexpr (!DB) {
+    for (int sg = 0; sg < KS; ++sg) {
+      wait_slices(std::integral_constant<int, NS - 2>{});  // slice sg has landed
+      sync();                                               // ... for every wavefront; sg - 1 is consumed
+      issue(sg + NS - 1);
+      Frags f;
+      read(f, sg);
+      mma(f);
     }
+  } else {
+    Frags f0, f1;
+    wait_slices(std::integral_constant<int, NS - 2>{});
+    sync();
+    read(f0, 0);
+    // KS is a multiple of 4: the loop runs in pairs of slices, alternating the register sets
+    for (int sg = 0; sg < KS - 2; sg += 2) {
+      wait_slices(std::integral_constant<int, NS - 3>{});  // slice sg + 1 has landed
+      sync();                                               // slice sg - 1 is consumed
+      issue(sg + NS - 1);
+      read(f1, sg + 1);
+      mma(f0);
+      wait_slices(std::integral_constant<int, NS - 3>{});  // slice sg + 2
+      sync();
+      issue(sg + NS);
+      read(f0, sg + 2);
+      mma(f1);
+    }
+    wait_slices(std::integral_constant<int, NS - 3>{});  // the last slice
+    sync();
+    read(f1, KS - 1);
+    mma(f0);
+    mma(f1);
   }
-  wait_vmcnt<0>();  // the surplus loads past the last slice write LDS the epilogue reuses
-  lds_barrier_sync();
+  wait_vmcnt<0>();  // the surplus loads past the last slice
 
-  // epilogue: planes through LDS, one 16-row tile at a time
-  uint32_t* wl = reinterpret_cast<uint32_t*>(lds);
-  constexpr int CW = Geo::kCW;
+  // epilogue: shift terms, then W entries straight from the accumulators
   const uint32_t nterm = 16384u * (uint32_t)n;
-  const int npos = 4 * h + 3;
-  const int32_t* cs = colsum + (size_t)ci * 16 * NT;
+  const int npos = 4 * h + 3, nreal = 4 * h;
+  const int32_t* cs = colsum + (size_t)ci * 16 * NTq;
+  uint32_t cterm[CW];
+  uint32_t amask[CW];  // bit a: pos - a is a real byte position
 #pragma unroll
-  for (int i = 0; i < MR; ++i) {
-    const int rowbase = (T0 + i) * 16;
-    uint32_t rterm[4];
+  for (int t = 0; t < CW; ++t) {
+    const int pos = (t0 + wc * CW + t) * 16 + r;
+    uint32_t c = 0, m = 0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) rterm[e] = 128u * (uint32_t)Ers[(size_t)a * rows_pad + rowbase + 4 * g + e] + nterm;
+    for (int a = 0; a < 4; ++a)
+      if (pos - a >= 0 && pos - a < nreal) {
+        c += 128u * (uint32_t)cs[pos - a];
+        m |= 1u << a;
+      }
+    cterm[t] = c;
+    amask[t] = m;
+  }
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int c = 16 * t + r;
-      const uint32_t ct = 128u * (uint32_t)cs[c];
+  for (int i = 0; i < RW; ++i) {
+    const int rowbase = (T0 + wr * RW + i) * 16 + 4 * g;
+    uint32_t R[4][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) wl[(a * 16 + 4 * g + e) * CW + c] = (uint32_t)acc[i][t][e] + ct + rterm[e];
-    }
-    lds_barrier_sync();
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int rho = 4 * a + rr;
-      const int row = rowbase + rho;
-      if (row < rows) {
-        uint32_t* wrow = W + (size_t)row * ldw + (size_t)ci * cpc;
-        for (int pos = lane; pos < npos; pos += 64) {
-          uint32_t v = 0;
+      for (int a = 0; a < 4; ++a)
+        R[e][a] = rowbase + e < rows ? 128u * (uint32_t)Ers[(size_t)a * rows_pad + rowbase + e] + nterm : 0u;
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int p = pos - b;
-            if (p >= 0 && p < 4 * h) v += wl[(b * 16 + rho) * CW + p];
-          }
-          wrow[pos] = v;
-        }
+    for (int t = 0; t < CW; ++t) {
+      const int pos = (t0 + wc * CW + t) * 16 + r;
+      if (pos >= npos) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = rowbase + e;
+        if (row >= rows) continue;
+        uint32_t v = (uint32_t)acc[i][t][e] + cterm[t];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          if (amask[t] & (1u << a)) v += R[e][a];
+        W[(size_t)row * ldw + (size_t)ci * cpc + pos] = v;
       }
     }
-    lds_barrier_sync();
   }
 }
 
-template <int MR, int NT, int NS>
+template <int RW, int CW, int NS, bool DB>
 static void launch_offset_gemm_t(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
-                                 const uint8_t* Yf, const int32_t* colsum, int batch, int h, uint32_t* W,
+                                 const uint8_t* Yq, const int32_t* colsum, int batch, int h, uint32_t* W,
                                  long long ldw, int cpc, hipStream_t s) {
-  const int S = offset_slices(n);
-  const int nrb = rows_pad / (16 * MR);
-  const long long nblocks = (long long)((nrb + 7) / 8 * 8) * batch;
-  offset_gemm_kernel<MR, NT, NS><<<(unsigned)nblocks, 256, 0, s>>>(Ep, Ers, rows_pad, rows, n, S, Yf, colsum,
-                                                                    batch, nrb, h, W, ldw, cpc);
+  const int S = offset_slices(n), NTq = offset_tiles(h);
+  const int ncg = NTq / (2 * CW);
+  const int nrb = (rows_pad / 16 + 2 * RW - 1) / (2 * RW);
+  const long long nblocks = (long long)((nrb + 7) / 8 * 8) * batch * ncg;
+  offset_gemm_kernel<RW, CW, NS, DB><<<(unsigned)nblocks, 256, 0, s>>>(Ep, Ers, rows_pad, rows, n, S, Yq, colsum,
+                                                                        batch, nrb, ncg, NTq, h, W, ldw, cpc);
 }
 
-// Launch variants (row tiles per wavefront MR, stages in flight NS) per column-tile count; the
-// runtime times them once per problem shape (every variant gives identical bits).
+// Launch variants per column width CW (row tiles per wavefront, stages, double-buffered
+// fragments); the runtime times them once per problem shape (every variant gives identical bits).
 struct OffsetVariant {
-  int mr, ns;
+  int rw, ns;
+  bool db;
 };
-static const OffsetVariant* offset_variant_list(int NT, int* count) {
-  static const OffsetVariant v4[] = {{4, 4}, {4, 3}, {2, 4}};
-  static const OffsetVariant v8[] = {{4, 4}, {4, 3}, {2, 4}};
-  static const OffsetVariant v16[] = {{4, 4}, {4, 3}, {2, 4}, {2, 3}, {1, 4}};
-  static const OffsetVariant v24[] = {{2, 4}, {2, 3}, {1, 4}};
-  static const OffsetVariant v32[] = {{2, 3}, {1, 4}, {1, 3}};
-  switch (NT) {
-    case 4: *count = 3; return v4;
-    case 8: *count = 3; return v8;
-    case 16: *count = 5; return v16;
-    case 24: *count = 3; return v24;
-    default: *count = 3; return v32;
-  }
-}
+static const OffsetVariant kOffsetVariants[] = {{4, 5, true}, {4, 4, true}, {2, 3, false}, {4, 3, false}};
+constexpr int kOffsetVariantCount = 4;
 
-int offset_gemm_variants(int h) {
-  int count = 0;
-  (void)offset_variant_list(offset_tiles(h), &count);
-  return count;
-}
+int offset_gemm_variants(int) { return kOffsetVariantCount; }
 
 void launch_offset_gemm(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
-                        const uint8_t* Yf, const int32_t* colsum, int batch, int h, uint32_t* W,
+                        const uint8_t* Yq, const int32_t* colsum, int batch, int h, uint32_t* W,
                         long long ldw, int cpc, int variant, hipStream_t s) {
-  const int NT = offset_tiles(h);
-  int count = 0;
-  const OffsetVariant* vl = offset_variant_list(NT, &count);
-  const OffsetVariant v = vl[(variant >= 0 && variant < count) ? variant : 0];
-#define ZP_OFF(M, T, N)                                                                                       \
-  if (NT == T && v.mr == M && v.ns == N) {                                                                    \
-    launch_offset_gemm_t<M, T, N>(Ep, Ers, rows_pad, rows, n, Yf, colsum, batch, h, W, ldw, cpc, s);          \
-    return;                                                                                                   \
+  const int CW = offset_cw(h);
+  const OffsetVariant v = kOffsetVariants[(variant >= 0 && variant < kOffsetVariantCount) ? variant : 0];
+#define ZP_OFF(R, C, N, D)                                                                                      \
+  if (CW == C && v.rw == R && v.ns == N && v.db == D) {                                                         \
+    launch_offset_gemm_t<R, C, N, D>(Ep, Ers, rows_pad, rows, n, Yq, colsum, batch, h, W, ldw, cpc, s);          \
+    return;                                                                                                     \
   }
-  ZP_OFF(4, 4, 4) ZP_OFF(4, 4, 3) ZP_OFF(2, 4, 4)
-  ZP_OFF(4, 8, 4) ZP_OFF(4, 8, 3) ZP_OFF(2, 8, 4)
-  ZP_OFF(4, 16, 4) ZP_OFF(4, 16, 3) ZP_OFF(2, 16, 4) ZP_OFF(2, 16, 3) ZP_OFF(1, 16, 4)
-  ZP_OFF(2, 24, 4) ZP_OFF(2, 24, 3) ZP_OFF(1, 24, 4)
-  ZP_OFF(2, 32, 3) ZP_OFF(1, 32, 4) ZP_OFF(1, 32, 3)
+#define ZP_OFF_CW(C) ZP_OFF(4, C, 5, true) ZP_OFF(4, C, 4, true) ZP_OFF(2, C, 3, false) ZP_OFF(4, C, 3, false)
+  ZP_OFF_CW(2) ZP_OFF_CW(3) ZP_OFF_CW(5) ZP_OFF_CW(7) ZP_OFF_CW(9)
+#undef ZP_OFF_CW
 #undef ZP_OFF
 }
 
