@@ -49,6 +49,29 @@ MATVEC_TRAFFIC = {"0a75c1f39ae39d63": 1083207299}
 STEP_TRAFFIC = {"84ad8428d96d552e": 1076585960}
 
 
+# Counter-derived figures of the dominant kernels, from rocprofv3 --pmc runs of this bench (the
+# summaries under profiles/), keyed by the SHA-256 of the source they were taken on (a changed
+# kernel reports null until the counters are re-taken):
+#   mfma_busy_frac = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE / 8), the share of
+#     SIMD cycles with the matrix core busy (the fastest tuner candidate of the run);
+#   valu_insts_per_simd_cycle = SQ_INSTS_VALU / (1024 x GRBM_GUI_ACTIVE / 8), with the shares of
+#     SQ_INSTS_VALU_INT64 and SQ_INSTS_VALU_INT32 in SQ_INSTS_VALU.
+COUNTERS = {
+    "gemm_i8.hip": {"629d2dbca623b53d": {"kernel": "gemm_planes_kernel<8, 2, 2, 256, 4, false, true>",
+                                         "mfma_busy_frac": 0.301}},
+    "hgemm.hip": {"8e56631f39ef1271": {"kernel": "hgemm_kernel<2, 3, true>", "mfma_busy_frac": 0.507}},
+    "offset.hip": {},
+    "hint.hip": {"eaca529d7b991e6c": {"kernel": "hint_rows_quad_kernel<2>", "valu_insts_per_simd_cycle": 0.324,
+                                      "int64_share_of_valu": 0.447, "int32_share_of_valu": 0.017}},
+    "lwec.hip": {"d4a4410b6ccb70fc": {"kernel": "compress_lwe_quad_kernel<3>", "valu_insts_per_simd_cycle": 0.298,
+                                      "int64_share_of_valu": 0.460, "int32_share_of_valu": 0.012}},
+}
+
+
+def counters(name: str):
+    return COUNTERS.get(name, {}).get(source_hash(name))
+
+
 def source_hash(name: str) -> str:
     import hashlib
     path = os.path.join(ROOT, "paper_2603_09190_amd", "csrc", name)
@@ -203,7 +226,9 @@ def main() -> int:
                 "montmuls": int(hint_mm), "montmul_per_s": round(hint_rate, 0),
                 "limbs": S, "word_mac_per_s": round(hint_rate * montmul_macs(S), 0),
                 "alu_peak_mac_per_s": ALU_PEAK_MACS,
-                "frac": round(hint_rate * montmul_macs(S) / ALU_PEAK_MACS, 4)}
+                "frac": round(hint_rate * montmul_macs(S) / ALU_PEAK_MACS, 4),
+                "counters": counters("hint.hip")}
+    h_ops = 8.0 * rows * cols * n   # H = D.A over A's four byte planes
 
     Qt = torch.from_numpy(Qh.view(np.int32)).to(dev)
     q1 = Qt[:1].contiguous()
@@ -354,6 +379,7 @@ def main() -> int:
     fpp_ms = timed_ms(fpp_step, args.steps)
     srv.set_packing(cid, 1)
     off_ops = 2.0 * rows * 4 * n * (4 * h + 3)
+    off_bytes = rows * 4 * n + rows * (4 * h + 3) * 4   # E's four byte planes in, W out
     full = {"ms_per_step": round(fp_ms, 4), "db_gbs": round(db_bytes / (fp_ms * 1e-3) / 1e9, 3),
             "one_call_ms_per_step": round(fp1_ms, 4),
             "one_call_db_gbs": round(db_bytes / (fp1_ms * 1e-3) / 1e9, 3),
@@ -361,6 +387,10 @@ def main() -> int:
             "offset_gemm_kernel_avg_us": round(og_avg * 1e3, 2),
             "offset_gemm_int8_tops": round(off_ops / (og_avg * 1e-3) / 1e12, 1),
             "offset_gemm_frac_of_peak": round(off_ops / (og_avg * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+            # E's planes are read once and W written once: the HBM-side position of the contraction
+            "offset_gemm_hbm_gbs": round(off_bytes / (og_avg * 1e-3) / 1e9, 1),
+            "offset_gemm_hbm_frac": round(off_bytes / (og_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "offset_gemm_counters": counters("offset.hip"),
             "offset_reduce_kernel_avg_us": round(or_avg * 1e3, 2),
             "combine_kernel_avg_us": round(oc_avg * 1e3, 2),
             "response_bytes": rows * h * 4, "hint_bytes": rows * L * 4,
@@ -471,10 +501,14 @@ def main() -> int:
                     "gemm_kernel_avg_us": round(gm_avg_ms * 1e3, 2),
                     "mfma_int8_tops": round(mfma_ops / (gm_avg_ms * 1e-3) / 1e12, 1),
                     "mfma_frac_of_peak": round(mfma_ops / (gm_avg_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+                    "counters": counters("gemm_i8.hip"),
                     "db_gbs": round(db_bytes / (gm_avg_ms * 1e-3) / 1e9, 1),
                     "bit_identical_to_matvec": same},
         "packed": packed,
         "full_protocol": full,
+        "H": {"ms": round(gemm_ms, 3), "int8_tops": round(h_ops / (gemm_ms * 1e-3) / 1e12, 1),
+              "frac_of_peak": round(h_ops / (gemm_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+              "counters": counters("hgemm.hip")},
         "offline_hint_s": round(hint_s, 3),
         "hint_kernel_ms": round(hintk_ms, 1),
         "hint": hint_fig,
@@ -586,6 +620,7 @@ def compress_bench(args) -> int:
         results.append({"kind": kind, "n": n, "log2_q": qbits, "q": q, "single_ms_p50": round(percentile(lat, 50), 4),
                         "batch_montmul_per_s": round(rate, 0),
                         "batch_alu_frac": round(rate * montmul_macs(3 * 64) / ALU_PEAK_MACS, 4),
+                        "counters": counters("lwec.hip"),
                         "batch": batch, "batch_ms": round(batch_ms, 3),
                         "per_ciphertext_us": round(batch_ms * 1e3 / batch, 3),
                         "setup_s": round(setup_s, 3), "table_bytes": info["device_bytes"],

@@ -249,10 +249,142 @@ void hgemm_kernel(const uint8_t* __restrict__ D, int rows, int cols, int pitch, 
   }
 }
 
+// The same contraction with eight wavefronts (two per SIMD): wavefront (wr, wc) = (w mod 4, w / 4)
+// takes four row tiles of the workgroup's 256 rows and the eight column tiles of column half wc
+// (two 16-column groups x four planes), 4 x 8 accumulator tiles that fit the architectural VGPRs.
+// Each slice stages 16 A and 16 B kilobytes as before, four loads per wavefront; the epilogue
+// parks one row tile at a time in the wavefront's 8 KiB of LDS and lanes 32 h + c build column c
+// of the half's 32 for rows h, h + 2, ..., so every store writes 128 contiguous bytes of a row.
+template <int NS, bool kTiled>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void hgemm_w8_kernel(const uint8_t* __restrict__ D, int rows, int cols, int pitch, const uint8_t* __restrict__ Apt,
+                     int n, int npad, const int32_t* __restrict__ Acolsum, const int32_t* __restrict__ rowsum,
+                     uint32_t* __restrict__ H, int nrb, int ncb) {
+  constexpr int kAChunks = 16;                  // row tiles of the workgroup's 256 rows
+  constexpr int kChunks = kAChunks + kHNT;
+  constexpr int kStage = kChunks * 1024;
+  constexpr int kEpi = 8 * 8 * 64 * 16;         // the epilogue's 8 KiB per wavefront
+  constexpr int kLds = NS * kStage > kEpi ? NS * kStage : kEpi;
+  constexpr int kPerWave = kChunks / 8;
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[kLds];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave & 3, wc = wave >> 2;
+  const int g = lane >> 4, r = lane & 15;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int round = slot / (kHSR * kHSC), loc = slot % (kHSR * kHSC);
+  const int st = round * 8 + xcd;
+  const int nsc = (ncb + kHSC - 1) / kHSC;
+  const int rb = (st / nsc) * kHSR + loc / kHSC;
+  const int cb = (st % nsc) * kHSC + loc % kHSC;
+  if (rb >= nrb || cb >= ncb) return;
+  const int S = pitch / 64;
+  const int last_group = (rows - 1) >> 4;
+
+  // loads of this wavefront per slice: pieces wave, wave + 8, wave + 16, wave + 24 (A row tiles,
+  // then B tiles t = 4 cgrp + b)
+  const uint8_t* src[kPerWave];
+  int dst[kPerWave];
+  bool isa[kPerWave];
+  const long long groups = npad / 16;
+#pragma unroll
+  for (int j = 0; j < kPerWave; ++j) {
+    const int c = wave + 8 * j;
+    dst[j] = c * 1024;
+    isa[j] = c < kAChunks;
+    if (c < kAChunks) {
+      const int T = min(rb * kAChunks + c, last_group);
+      if constexpr (kTiled) src[j] = D + (size_t)T * 16 * pitch + lane * 16;
+      else src[j] = D + (size_t)min(16 * T + (lane >> 2), rows - 1) * pitch + (lane & 3) * 16;
+    } else {
+      const int t = c - kAChunks;
+      const long long G = (t & 3) * groups + 4 * cb + (t >> 2);
+      src[j] = Apt + (size_t)G * S * 1024 + lane * 16;
+    }
+  }
+  auto issue = [&](int p) {
+    const int pc = min(p, S - 1);
+    uint8_t* base = lds + (p % NS) * kStage;
+#pragma unroll
+    for (int j = 0; j < kPerWave; ++j) {
+      const size_t adv = isa[j] ? (kTiled ? (size_t)pc * 1024 : (size_t)pc * 64) : (size_t)pc * 1024;
+      g2l16(src[j] + adv, base + dst[j]);
+    }
+  };
+
+  v4i acc[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[i][t] = v4i{0, 0, 0, 0};
+
+#pragma unroll
+  for (int p = 0; p < NS - 1; ++p) issue(p);
+  const int aread = (r * 4 + g) * 16;  // where the MFMA's lane (g, r) finds row r, bytes 16 g
+  for (int p = 0; p < S; ++p) {
+    wait_vmcnt<(NS - 2) * kPerWave>();
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    issue(p + NS - 1);
+    const uint8_t* base = lds + (p % NS) * kStage;
+    v4i bf[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      bf[t] = *reinterpret_cast<const v4i*>(base + (kAChunks + 8 * wc + t) * 1024 + lane * 16);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      u32x4 v = *reinterpret_cast<const u32x4*>(base + (wr * 4 + i) * 1024 + aread);
+      v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
+      const v4i af = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[i][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[t], acc[i][t], 0, 0, 0);
+    }
+  }
+  wait_vmcnt<0>();  // the surplus loads past the last slice write LDS the epilogue reuses
+  lds_barrier_sync();
+
+  // epilogue: H[row][col] = sum_b (acc_b + 128 colsum_b + 128 rowsum + 16384 cols) 2^(8b)
+  uint32_t* wl = reinterpret_cast<uint32_t*>(lds) + wave * (8 * 64 * 4);
+  const uint32_t kterm = 16384u * (uint32_t)cols;
+  const int c = lane & 31, half = lane >> 5;  // column within the half's 32, row parity
+  const int col = kHCols * cb + 32 * wc + c;
+  const int cgrp = c >> 4, cr = c & 15;
+  uint32_t ct[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) ct[b] = col < n ? 128u * (uint32_t)Acolsum[col * 4 + b] : 0u;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) wl[(t * 64 + lane) * 4 + e] = (uint32_t)acc[i][t][e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    const int row0 = (rb * kAChunks + wr * 4 + i) * 16;
+#pragma unroll 4
+    for (int k = 0; k < 8; ++k) {
+      const int rho = 2 * k + half;
+      const int row = row0 + rho;
+      if (row < rows) {
+        const uint32_t rterm = 128u * (uint32_t)rowsum[row] + kterm;
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          v += (wl[((cgrp * 4 + b) * 64 + (rho >> 2) * 16 + cr) * 4 + (rho & 3)] + ct[b] + rterm) << (8 * b);
+        if (col < n) H[(size_t)row * n + col] = v;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+  }
+}
+
 struct HVariant {
-  int mr, ns;
+  int mr, ns;  // mr 0: the eight-wavefront kernel
 };
-static const HVariant kHVariants[] = {{4, 4}, {4, 3}, {2, 4}, {2, 3}};
+static const HVariant kHVariants[] = {{4, 4}, {4, 3}, {2, 4}, {2, 3}, {0, 3}, {0, 4}};
 
 int hgemm_variants() { return (int)(sizeof(kHVariants) / sizeof(kHVariants[0])); }
 
@@ -276,6 +408,22 @@ void launch_hgemm(const uint8_t* D, bool tiled, int rows, int cols, int pitch, c
                   const int32_t* Acolsum, const int32_t* rowsum, uint32_t* H, int variant, hipStream_t s) {
   if (rows <= 0 || n <= 0) return;
   const HVariant v = kHVariants[(variant >= 0 && variant < hgemm_variants()) ? variant : 0];
+  if (v.mr == 0) {
+    const int npad = hgemm_npad(n);
+    const int nrb = (rows + 255) / 256;
+    const int ncb = npad / kHCols;
+    const int nsr = (nrb + kHSR - 1) / kHSR, nsc = (ncb + kHSC - 1) / kHSC;
+    const long long rounds = ((long long)nsr * nsc + 7) / 8;
+    const unsigned nblocks = (unsigned)(rounds * 8 * kHSR * kHSC);
+#define ZP_H8(N, T) hgemm_w8_kernel<N, T><<<nblocks, 512, 0, s>>>(D, rows, cols, pitch, Apt, n, npad, Acolsum, rowsum, H, nrb, ncb)
+    if (v.ns == 3) {
+      if (tiled) ZP_H8(3, true); else ZP_H8(3, false);
+    } else {
+      if (tiled) ZP_H8(4, true); else ZP_H8(4, false);
+    }
+#undef ZP_H8
+    return;
+  }
   if (v.mr == 4 && v.ns == 4) launch_hgemm_t<4, 4>(D, tiled, rows, cols, pitch, Apt, n, Acolsum, rowsum, H, s);
   else if (v.mr == 4) launch_hgemm_t<4, 3>(D, tiled, rows, cols, pitch, Apt, n, Acolsum, rowsum, H, s);
   else if (v.ns == 4) launch_hgemm_t<2, 4>(D, tiled, rows, cols, pitch, Apt, n, Acolsum, rowsum, H, s);

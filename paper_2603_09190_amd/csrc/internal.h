@@ -188,7 +188,7 @@ void launch_compress_packed(const ClientDev& cd, const uint32_t* Kg, const uint3
 
 // ---- offset answer of the full protocol (offset.hip)
 // E planes of the contraction (layout in offset.hip): Ep holds rows_pad x 4 x 64 S bytes with
-// S = offset_slices(n), rows_pad a multiple of 64; Ers (4 x rows_pad) receives the plane sums
+// S = offset_slices(n), rows_pad a multiple of 128; Ers (4 x rows_pad) receives the plane sums
 // sum_{k<n} (byte a of E_jk) - 128 for rows below `rows` (the caller zeroes the rest once).
 int offset_slices(int n);
 void launch_e_planes(const uint32_t* H, int rows, int n, int rows_pad, uint8_t* Ep, int32_t* Ers,
@@ -199,10 +199,10 @@ int offset_tiles(int h);
 // out[k] = cko[k] 2^96 mod N (canonical) for the n offset entries of one client (h limbs each).
 void launch_scale_offsets(const ClientDev& cd, const uint32_t* cko, int n, uint32_t* out,
                           hipStream_t s);
-// The offset bytes of `batch` scaled offset vectors ys (batch x n x h limbs), shifted by one
-// position per E plane, in the contraction's fragment order: Yf holds batch x 4 S x
-// offset_tiles(h) KiB; colsum (batch x 16 offset_tiles(h)) receives
-// sum_{k<n} (byte c of ys[i][k]) - 128 for c < 4h.
+// The offset bytes of `batch` scaled offset vectors ys (batch x n x h limbs) in the
+// contraction's staging order (offset.hip): Yf holds batch x offset_y_bytes(n, h) bytes; colsum
+// (batch x 16 offset_tiles(h)) receives sum_{k<n} (byte c of ys[i][k]) - 128 for c < 4h.
+long long offset_y_bytes(int n, int h);
 void launch_pack_y(const uint32_t* ys, int batch, int n, int h, uint8_t* Yf, int32_t* colsum,
                    hipStream_t s);
 // W[j ldw + i cpc + pos] = sum_k sum_a (byte a of E_jk) (byte pos - a of ys[i][k]) for j < rows,

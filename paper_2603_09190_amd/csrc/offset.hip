@@ -13,6 +13,7 @@
 // so the contraction is exact in 32-bit accumulators.  The offsets are first replaced by
 // y_k = ck_o,k 2^96 mod N, so that a reduction kernel can fold the byte positions into limbs,
 // add b_j 2^96 and finish modulo N with three Montgomery reduction steps (see below).
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -26,22 +27,28 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ---- operands of the offset contraction
 //
-// The contraction runs on v_mfma_i32_16x16x64_i8 with E's four byte planes laid end to end
-// along K: K' = 4 kpad entries, slice sigma = a S + s holding plane a, entries 64 s ... 64 s + 63.
-// Shifting the offsets' bytes by one position per plane,
+// The contraction runs on v_mfma_i32_16x16x64_i8 over K' = 4 kpad entries, E's four byte planes
+// laid end to end along K (plane a, entries k).  With the offsets' bytes shifted by one position
+// per plane,
 //   Y4[pos][(a, k)] = byte pos - a of y_k   (0 where pos - a is outside [0, 4h)),
-// turns the four shifted plane products into one:
+// the four shifted plane products become one:
 //   W[j][pos] = sum_{(a, k)} e_jk[a] Y4[pos][(a, k)],   pos < 4h + 3,
-// so the accumulators hold W itself and nothing is added across planes afterwards.
-// Both operands are stored already in MFMA fragment order, shifted to int8 by XOR 0x80:
+// so the accumulators hold W itself and nothing is added across planes afterwards.  The shifted
+// copies are never stored: the B fragment of plane a is the unshifted one read a columns to the
+// left, so each 64-entry slice of K stages Y once and serves all four planes.
+// Both operands are int8 (XOR 0x80; padding 0) in MFMA fragment order:
 //   Ep (E planes): piece (T, a, s) is 1 KiB, lane l's 16 bytes at 16 l hold
-//     E'_a[16 T + l mod 16][64 s + 16 (l / 16) + u], u < 16,
-//   so one 16-row tile's whole K' stream (4 S pieces) is contiguous;
-//   Yq (shifted offset bytes of one client): piece (sigma, t) is 1 KiB, lane l's bytes
-//     Y4'[16 t + l mod 16][64 s + 16 (l / 16) + u] of plane a,
-//   so one K' slice of the client's NTq column tiles is one contiguous NTq KiB run.
-// Entries beyond rows, n or the shifted range are 0 (the value 128 before the shift), which adds
-// nothing to the signed product; the shift terms below count only the real entries.
+//     E'_a[16 T + l mod 16][64 s + 16 (l / 16) + u], u < 16; the pieces of eight consecutive
+//     row tiles (one row block of the contraction) are ordered by slice, then plane, then tile:
+//     piece (T, a, s) is number ((T / 8) S + s) 32 + 8 a + T mod 8, so a row block streams one
+//     contiguous 32 KiB run per slice;
+//   Yc (one client's offset bytes): per slice s, NTq + 1 pieces of 16 columns, piece u holding
+//     columns c = 16 u - 16 ... 16 u - 1 (piece 0 is the zero padding left of column 0).  In a
+//     piece, column c's 64 bytes Y'[c][64 s ...] sit at 64 (c mod 16), as four 16-byte runs
+//     whose order is swizzled by bits 2-3 of the column: run g at 16 (g ^ ((c / 4) mod 4)).
+//     Reading the 16 columns of a fragment then touches 16 distinct 16-byte bank groups.
+// Entries beyond rows, n or 4h are 0 (the value 128 before the shift), which adds nothing to the
+// signed product; the shift terms below count only the real entries.
 
 // One thread per (tile, slice, lane): reads 16 entries of H once and writes the four planes.
 __global__ __launch_bounds__(256) void e_planes_kernel(const uint32_t* __restrict__ H, int rows, int n,
@@ -71,7 +78,7 @@ __global__ __launch_bounds__(256) void e_planes_kernel(const uint32_t* __restric
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
-    Ep[((T * 4 + a) * S + s) * 64 + l] = u32x4{w[a][0], w[a][1], w[a][2], w[a][3]};
+    Ep[(((T >> 3) * S + s) * 32 + 8 * a + (T & 7)) * 64 + l] = u32x4{w[a][0], w[a][1], w[a][2], w[a][3]};
 }
 
 // Ers[a * rows_pad + j] = sum_{k<n} (byte a of E_jk) - 128: one wavefront per row.
@@ -139,83 +146,85 @@ __global__ void zero_i32_kernel(int32_t* __restrict__ p, int n) {
   if (i < n) p[i] = 0;
 }
 
-// One thread per 16-byte piece (sigma, t, l) of client blockIdx.y.  colsum[i 16 NTq + c] (zeroed
-// first) = sum_{k<n} (byte c of y_k) - 128 for c < 4h, from the plane-0 pieces: one atomic per
-// column and piece row.
+// One thread per 16-byte run (s, u, l) of client blockIdx.y: lane l of piece u holds column
+// c = 16 u + l / 4 - 16, run g = (l mod 4) ^ ((l / 16) mod 4).  colsum[i 16 NTq + c] (zeroed
+// first) = sum_{k<n} (byte c of y_k) - 128 for c < 4h: the four lanes of a column hold the
+// slice's 64 entries, one atomic per column and slice.
 __global__ __launch_bounds__(256) void pack_y_kernel(const uint32_t* __restrict__ ys, int n, int h, int S,
-                                                     int NTq, u32x4* __restrict__ Yq,
+                                                     int NTq, u32x4* __restrict__ Yc,
                                                      int32_t* __restrict__ colsum) {
   const int i = blockIdx.y;
   const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const long long per = (long long)4 * S * NTq * 64;
+  const long long per = (long long)S * (NTq + 1) * 64;
   const bool live = p < per;
   const int l = (int)(p & 63);
   const long long q = p >> 6;
-  const int t = (int)(q % NTq);
-  const int sig = (int)(q / NTq);
-  const int a = sig / S, s = sig % S;
-  const int c = 16 * t + (l & 15) - a;  // byte position of y this lane holds
-  const int k0 = 64 * s + 16 * (l >> 4);
+  const int u = (int)(q % (NTq + 1));
+  const int s = (int)(q / (NTq + 1));
+  const int c = 16 * u + (l >> 2) - 16;
+  const int g = (l & 3) ^ ((l >> 4) & 3);
+  const int k0 = 64 * s + 16 * g;
   uint32_t w[4] = {0u, 0u, 0u, 0u};
   int32_t part = 0;
   if (live && c >= 0 && c < 4 * h) {
     const uint32_t* y = ys + (size_t)i * n * h + (c >> 2);
     const int sh = 8 * (c & 3);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int k = k0 + u;
+    for (int v = 0; v < 16; ++v) {
+      const int k = k0 + v;
       if (k < n) {
         const uint32_t sb = ((y[(size_t)k * h] >> sh) & 0xFFu) ^ 0x80u;
-        w[u >> 2] |= sb << (8 * (u & 3));
+        w[v >> 2] |= sb << (8 * (v & 3));
         part += (int32_t)(int8_t)sb;
       }
     }
   }
-  if (live) Yq[(size_t)i * per + p] = u32x4{w[0], w[1], w[2], w[3]};
-  // the four lanes l, l^16, l^32, l^48 hold the same column
-  part += __shfl_xor(part, 16, 64);
-  part += __shfl_xor(part, 32, 64);
-  if (live && a == 0 && l < 16 && c < 4 * h && part != 0) atomicAdd(colsum + (size_t)i * 16 * NTq + c, part);
+  if (live) Yc[(size_t)i * per + p] = u32x4{w[0], w[1], w[2], w[3]};
+  part += __shfl_xor(part, 1, 64);
+  part += __shfl_xor(part, 2, 64);
+  if (live && (l & 3) == 0 && c >= 0 && c < 4 * h && part != 0) atomicAdd(colsum + (size_t)i * 16 * NTq + c, part);
 }
 
-void launch_pack_y(const uint32_t* ys, int batch, int n, int h, uint8_t* Yq, int32_t* colsum,
+void launch_pack_y(const uint32_t* ys, int batch, int n, int h, uint8_t* Yc, int32_t* colsum,
                    hipStream_t s) {
   const int S = offset_slices(n), NTq = offset_tiles(h);
   const int ncs = batch * 16 * NTq;
   zero_i32_kernel<<<(ncs + 255) / 256, 256, 0, s>>>(colsum, ncs);
-  const long long per = (long long)4 * S * NTq * 64;
+  const long long per = (long long)S * (NTq + 1) * 64;
   dim3 grid((unsigned)((per + 255) / 256), batch);
-  pack_y_kernel<<<grid, 256, 0, s>>>(ys, n, h, S, NTq, reinterpret_cast<u32x4*>(Yq), colsum);
+  pack_y_kernel<<<grid, 256, 0, s>>>(ys, n, h, S, NTq, reinterpret_cast<u32x4*>(Yc), colsum);
 }
+
+long long offset_y_bytes(int n, int h) { return (long long)offset_slices(n) * (offset_tiles(h) + 1) * 1024; }
 
 // ---- the contraction
 //
-// A workgroup of four wavefronts takes 32 RW rows, 32 CW columns (one column group) and one
-// client; wavefront (wr, wc) computes RW x CW accumulator tiles: rows of half wr, columns of
-// half wc.  Both operands pass through LDS in NS stages of one 64-byte K' slice each, by direct
-// global-to-LDS loads (stage.h): a stage holds the block's 2 RW row-tile fragments of E (each a
-// kilobyte of Ep) and its 2 CW column-tile fragments of Yq (one contiguous run); wavefront w
-// issues the fragments w, w + 4, ...  One barrier per slice.
-//   DB = false: each slice's fragments are read from LDS right before its MFMAs (two
-//     wavefronts per SIMD hide each other's waits);
-//   DB = true: the fragments of slice sigma + 1 are read into a second register set while the
-//     MFMAs of slice sigma run (one wavefront per SIMD), so the stage written by the loads issued
-//     at slice sigma is that of slice sigma - 1 and NS - 3 later slices stay in flight.
+// A workgroup of four wavefronts takes 128 rows (eight 16-row tiles), 32 CW columns (one column
+// group) and one client; wavefront (wr, wc) computes 4 x CW accumulator tiles: row tiles of half
+// wr, column tiles of half wc.  Per 64-entry slice s of K, the operands pass through LDS in NS
+// stages by direct global-to-LDS loads (stage.h): a stage holds the block's 32 E fragments
+// (eight row tiles x four planes, each a kilobyte of Ep) and the 2 CW + 1 pieces of Yc its
+// columns need (one contiguous run); wavefront w issues the pieces w, w + 4, ...  One barrier per
+// slice; the four planes then run back to back on the staged slice (4 x 4 x CW MFMAs per
+// wavefront), plane a reading its B fragments a columns to the left.
 // Then each accumulator becomes a W entry, straight to memory:
-//   W = acc + 128 sum_{a in A(pos)} (colsum[pos - a] + Ers_a[j]) + 16384 n |A(pos)|
+//   W = acc + 128 sum_{a in A(pos)} (colsum[pos - a] + Ers_a[j]) + 16384 n |A(pos)|,
+//   A(pos) = {a < 4 : 0 <= pos - a < 4h}
 // (exact modulo 2^32, and the true value is below 4 n 255^2 < 2^32 for n <= 16384).
 // The grid is XCD-aware: workgroup L runs on XCD L mod 8, and each XCD takes the (client, column
 // group) items of its row blocks (x, x + 8, ...) one after the other, so a block's E stream comes
 // from HBM once and from that XCD's L2 for the other items.
-template <int RW, int CW, int NS, bool DB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, DB ? 1 : 2)))
+template <int CW, int NS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restrict__ Ers, int rows_pad, int rows,
-                        int n, int S, const uint8_t* __restrict__ Yq, const int32_t* __restrict__ colsum,
+                        int n, int S, const uint8_t* __restrict__ Yc, const int32_t* __restrict__ colsum,
                         int batch, int nrb, int ncg, int NTq, int h, uint32_t* __restrict__ W, long long ldw,
                         int cpc) {
-  constexpr int BR = 2 * RW, BC = 2 * CW, CH = BR + BC, PW = (CH + 3) / 4, STAGE = CH * 1024;
-  static_assert(!DB || NS >= 4, "the double-buffered loop keeps NS - 3 slices in flight");
-  static_assert(PW >= 2 && 3 * PW < 64, "loads per slice");
+  constexpr int RW = 4, BR = 8, BC = 2 * CW;
+  constexpr int EA = 4 * BR;      // E pieces per stage: piece a BR + i is plane a of row tile i
+  constexpr int YP = BC + 1;      // Yc pieces per stage
+  constexpr int CH = EA + YP, PW = (CH + 3) / 4, STAGE = CH * 1024;
+  static_assert((NS - 2) * PW < 64 && PW >= 2, "loads per slice");
   __shared__ __attribute__((aligned(1024))) uint8_t lds[NS * STAGE];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -227,12 +236,11 @@ void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restric
   const int item = slot % items;
   const int ci = item / ncg, cg = item % ncg;
   if (rb >= nrb) return;
-  const int T0 = rb * BR, t0 = cg * BC, KS = 4 * S;
-  const int tiles = rows_pad / 16;
+  const int T0 = rb * BR, t0 = cg * BC;
 
-  // this wavefront's fragments of each slice: w, w + 4, ...; where that passes CH the wavefront
-  // loads its previous fragment once more (same bytes, same place), so that every wavefront
-  // issues PW loads per slice.  A row tiles are clamped to the last (whose rows are not stored).
+  // this wavefront's pieces of each slice: w, w + 4, ...; where that passes CH the wavefront
+  // loads its previous piece once more (same bytes, same place), so that every wavefront issues
+  // PW loads per slice.
   const uint8_t* src[PW];
   long long sstride[PW];
   int dst[PW];
@@ -240,27 +248,30 @@ void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restric
   for (int j = 0; j < PW; ++j) {
     const int c = w + 4 * j < CH ? w + 4 * j : w + 4 * j - 4;
     dst[j] = c * 1024;
-    if (c < BR) {
-      src[j] = Ep + (size_t)min(T0 + c, tiles - 1) * KS * 1024 + lane * 16;
-      sstride[j] = 1024;
+    if (c < EA) {  // piece c = 8 a + i of the row block's run for the slice
+      src[j] = Ep + ((size_t)rb * S * 32 + c) * 1024 + lane * 16;
+      sstride[j] = 32 * 1024;
     } else {
-      src[j] = Yq + ((size_t)ci * KS * NTq + t0 + c - BR) * 1024 + lane * 16;
-      sstride[j] = (long long)NTq * 1024;
+      src[j] = Yc + ((size_t)ci * S * (NTq + 1) + t0 + (c - EA)) * 1024 + lane * 16;
+      sstride[j] = (long long)(NTq + 1) * 1024;
     }
   }
   auto issue = [&](int sl) {  // slice sl (clamped to the last) into its stage buffer
-    const int sc = min(sl, KS - 1);
+    const int sc = min(sl, S - 1);
     uint8_t* base = lds + (sl % NS) * STAGE;
 #pragma unroll
     for (int j = 0; j < PW; ++j) g2l16(src[j] + (size_t)sc * sstride[j], base + dst[j]);
   };
-  auto wait_slices = [&](auto in_flight) {  // at most in_flight slices of this wavefront's loads pending
-    wait_vmcnt<decltype(in_flight)::value * PW>();
-  };
-  auto sync = [&] {
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-  };
+
+  // where lane (g, r) finds its B bytes for plane a: column 16 t + r - a of the block's window
+  // (window column 16 + the block's first output column), run g swizzled by that column's bits
+  // 2-3 (independent of t, so tile t adds 1024 t)
+  int boff[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int cw = 16 * (wc * CW) + r - a + 16;
+    boff[a] = EA * 1024 + cw * 64 + ((g ^ ((cw >> 2) & 3)) << 4);
+  }
 
   v4i acc[RW][CW];
 #pragma unroll
@@ -268,58 +279,26 @@ void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restric
 #pragma unroll
     for (int t = 0; t < CW; ++t) acc[i][t] = v4i{0, 0, 0, 0};
 
-  struct Frags {
-    v4i b[CW];
-    v4i a[RW];
-  };
-  auto read = [&](Frags& f, int sl) {
-    const uint8_t* base = lds + (sl % NS) * STAGE + lane * 16;
-#pragma unroll
-    for (int t = 0; t < CW; ++t) f.b[t] = *reinterpret_cast<const v4i*>(base + (BR + wc * CW + t) * 1024);
-#pragma unroll
-    for (int i = 0; i < RW; ++i) f.a[i] = *reinterpret_cast<const v4i*>(base + (wr * RW + i) * 1024);
-  };
-  auto mma = [&](const Frags& f) {
-#pragma unroll
-    for (int i = 0; i < RW; ++i)
-#pragma unroll
-      for (int t = 0; t < CW; ++t) acc[i][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(f.a[i], f.b[t], acc[i][t], 0, 0, 0);
-  };
-
 #pragma unroll
   for (int st = 0; st < NS - 1; ++st) issue(st);
-  if constexpr (!DB) {
-    for (int sg = 0; sg < KS; ++sg) {
-      wait_slices(std::integral_constant<int, NS - 2>{});  // slice sg has landed
-      sync();                                               // ... for every wavefront; sg - 1 is consumed
-      issue(sg + NS - 1);
-      Frags f;
-      read(f, sg);
-      mma(f);
+  for (int s = 0; s < S; ++s) {
+    wait_vmcnt<(NS - 2) * PW>();  // slice s has landed (later slices stay in flight)
+    __builtin_amdgcn_s_barrier();  // ... for every wavefront; slice s - 1 is consumed
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    issue(s + NS - 1);
+    const uint8_t* base = lds + (s % NS) * STAGE;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      v4i bf[CW];
+#pragma unroll
+      for (int t = 0; t < CW; ++t) bf[t] = *reinterpret_cast<const v4i*>(base + boff[a] + 1024 * t);
+#pragma unroll
+      for (int i = 0; i < RW; ++i) {
+        const v4i af = *reinterpret_cast<const v4i*>(base + (a * BR + wr * RW + i) * 1024 + lane * 16);
+#pragma unroll
+        for (int t = 0; t < CW; ++t) acc[i][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[t], acc[i][t], 0, 0, 0);
+      }
     }
-  } else {
-    Frags f0, f1;
-    wait_slices(std::integral_constant<int, NS - 2>{});
-    sync();
-    read(f0, 0);
-    // KS is a multiple of 4: the loop runs in pairs of slices, alternating the register sets
-    for (int sg = 0; sg < KS - 2; sg += 2) {
-      wait_slices(std::integral_constant<int, NS - 3>{});  // slice sg + 1 has landed
-      sync();                                               // slice sg - 1 is consumed
-      issue(sg + NS - 1);
-      read(f1, sg + 1);
-      mma(f0);
-      wait_slices(std::integral_constant<int, NS - 3>{});  // slice sg + 2
-      sync();
-      issue(sg + NS);
-      read(f0, sg + 2);
-      mma(f1);
-    }
-    wait_slices(std::integral_constant<int, NS - 3>{});  // the last slice
-    sync();
-    read(f1, KS - 1);
-    mma(f0);
-    mma(f1);
   }
   wait_vmcnt<0>();  // the surplus loads past the last slice
 
@@ -369,42 +348,36 @@ void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restric
   }
 }
 
-template <int RW, int CW, int NS, bool DB>
+template <int CW, int NS>
 static void launch_offset_gemm_t(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
-                                 const uint8_t* Yq, const int32_t* colsum, int batch, int h, uint32_t* W,
+                                 const uint8_t* Yc, const int32_t* colsum, int batch, int h, uint32_t* W,
                                  long long ldw, int cpc, hipStream_t s) {
   const int S = offset_slices(n), NTq = offset_tiles(h);
   const int ncg = NTq / (2 * CW);
-  const int nrb = (rows_pad / 16 + 2 * RW - 1) / (2 * RW);
+  const int nrb = rows_pad / 128;  // rows_pad is a multiple of 128
   const long long nblocks = (long long)((nrb + 7) / 8 * 8) * batch * ncg;
-  offset_gemm_kernel<RW, CW, NS, DB><<<(unsigned)nblocks, 256, 0, s>>>(Ep, Ers, rows_pad, rows, n, S, Yq, colsum,
-                                                                        batch, nrb, ncg, NTq, h, W, ldw, cpc);
+  offset_gemm_kernel<CW, NS><<<(unsigned)nblocks, 256, 0, s>>>(Ep, Ers, rows_pad, rows, n, S, Yc, colsum, batch,
+                                                                nrb, ncg, NTq, h, W, ldw, cpc);
 }
 
-// Launch variants per column width CW (row tiles per wavefront, stages, double-buffered
-// fragments); the runtime times them once per problem shape (every variant gives identical bits).
-struct OffsetVariant {
-  int rw, ns;
-  bool db;
-};
-static const OffsetVariant kOffsetVariants[] = {{4, 5, true}, {4, 4, true}, {2, 3, false}, {4, 3, false}};
-constexpr int kOffsetVariantCount = 4;
+// Launch variants: the stages in flight, as many as LDS holds (every variant gives identical
+// bits; the runtime times them once per problem shape).
+static int offset_stage_limit(int cw) { return 163840 / ((32 + 2 * cw + 1) * 1024); }
 
-int offset_gemm_variants(int) { return kOffsetVariantCount; }
+int offset_gemm_variants(int h) { return std::min(offset_stage_limit(offset_cw(h)), 5) - 2; }
 
 void launch_offset_gemm(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
-                        const uint8_t* Yq, const int32_t* colsum, int batch, int h, uint32_t* W,
+                        const uint8_t* Yc, const int32_t* colsum, int batch, int h, uint32_t* W,
                         long long ldw, int cpc, int variant, hipStream_t s) {
   const int CW = offset_cw(h);
-  const OffsetVariant v = kOffsetVariants[(variant >= 0 && variant < kOffsetVariantCount) ? variant : 0];
-#define ZP_OFF(R, C, N, D)                                                                                      \
-  if (CW == C && v.rw == R && v.ns == N && v.db == D) {                                                         \
-    launch_offset_gemm_t<R, C, N, D>(Ep, Ers, rows_pad, rows, n, Yq, colsum, batch, h, W, ldw, cpc, s);          \
-    return;                                                                                                     \
+  const int count = offset_gemm_variants(h);
+  const int NS = 3 + ((variant >= 0 && variant < count) ? variant : 0);
+#define ZP_OFF(C, N)                                                                                \
+  if (CW == C && NS == N) {                                                                         \
+    launch_offset_gemm_t<C, N>(Ep, Ers, rows_pad, rows, n, Yc, colsum, batch, h, W, ldw, cpc, s);   \
+    return;                                                                                         \
   }
-#define ZP_OFF_CW(C) ZP_OFF(4, C, 5, true) ZP_OFF(4, C, 4, true) ZP_OFF(2, C, 3, false) ZP_OFF(4, C, 3, false)
-  ZP_OFF_CW(2) ZP_OFF_CW(3) ZP_OFF_CW(5) ZP_OFF_CW(7) ZP_OFF_CW(9)
-#undef ZP_OFF_CW
+  ZP_OFF(2, 3) ZP_OFF(2, 4) ZP_OFF(3, 3) ZP_OFF(3, 4) ZP_OFF(5, 3) ZP_OFF(7, 3) ZP_OFF(9, 3)
 #undef ZP_OFF
 }
 

@@ -110,7 +110,7 @@ struct pir_server {
   // offset answer, built on first use after H changes
   uint8_t* Ep = nullptr;        // rows_pad x 4 x 64 S bytes
   int32_t* Ers = nullptr;       // 4 x rows_pad: per plane and row, sum_{k<n} (byte - 128)
-  uint32_t rows_pad = 0;        // rows rounded up to 64
+  uint32_t rows_pad = 0;        // rows rounded up to 128 (the contraction's row blocks)
   bool E_ready = false;
   std::map<uint32_t, std::unique_ptr<ClientState>> clients;
   uint32_t next_id = 1;
@@ -619,7 +619,7 @@ pir_status ensure_E(pir_server* s) {
   if (s->E_ready) return PIR_OK;
   hipStream_t st = s->stream;
   if (!s->Ep) {
-    s->rows_pad = (s->rows + 63u) / 64u * 64u;
+    s->rows_pad = (s->rows + 127u) / 128u * 128u;
     const size_t bytes = (size_t)s->rows_pad * 4 * 64 * zp::offset_slices((int)s->n);
     ZP_TRY(s->alloc((void**)&s->Ep, bytes));
     ZP_TRY(s->alloc((void**)&s->Ers, (size_t)4 * s->rows_pad * sizeof(int32_t)));
@@ -1511,7 +1511,7 @@ static pir_status offset_contract(pir_server* s, const std::vector<ClientState*>
   const long long ncol = (long long)batch * cpc;
   const size_t kbytes = (size_t)batch * s->n * h * sizeof(uint32_t);
   const int NT = zp::offset_tiles((int)h);
-  ZP_TRY(s->scratch(s->s_x, (size_t)batch * 4 * zp::offset_slices((int)s->n) * NT * 1024));
+  ZP_TRY(s->scratch(s->s_x, (size_t)batch * zp::offset_y_bytes((int)s->n, (int)h)));
   ZP_TRY(s->scratch(s->s_xcs, (size_t)batch * 16 * NT * sizeof(int32_t)));
   ZP_TRY(s->scratch(s->s_w, (size_t)s->rows * ncol * sizeof(uint32_t)));
   ZP_TRY(s->scratch(s->s_ys, kbytes));
