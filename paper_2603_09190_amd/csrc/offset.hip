@@ -115,29 +115,24 @@ void launch_e_planes(const uint32_t* H, int rows, int n, int rows_pad, uint8_t* 
 // its slices in flight; the padding slices are zero and add nothing)
 int offset_slices(int n) { return ((n + 63) / 64 + 3) / 4 * 4; }
 
-// Column tiles of the contraction: the 4h + 3 output positions in tiles of 16, padded to a
-// whole number of column groups of 2 offset_cw(h) tiles.
-int offset_cw(int h) {
+// Column tiles of the contraction: the 4h + 3 output positions in tiles of 16, in column groups
+// of offset_group(h) tiles (a multiple of 4, at most 20: the width that pads least, the wider
+// on a tie), padded to whole groups.
+int offset_group(int h) {
   const int nt = (4 * h + 3 + 15) / 16;
-  if (nt <= 4) return 2;
-  if (nt <= 6) return 3;
-  if (nt <= 10) return 5;
-  if (nt <= 14) return 7;
-  if (nt <= 18) return 9;
-  // several column groups: the width that pads least
-  int best = 9, pad = 1 << 30;
-  for (int cw : {9, 7, 5}) {
-    const int tiles = (nt + 2 * cw - 1) / (2 * cw) * 2 * cw;
-    if (tiles < pad) {
+  int best = 4, pad = 1 << 30;
+  for (int bc = 4; bc <= 20; bc += 4) {
+    const int tiles = (nt + bc - 1) / bc * bc;
+    if (tiles <= pad) {
       pad = tiles;
-      best = cw;
+      best = bc;
     }
   }
   return best;
 }
 
 int offset_tiles(int h) {
-  const int nt = (4 * h + 3 + 15) / 16, bc = 2 * offset_cw(h);
+  const int nt = (4 * h + 3 + 15) / 16, bc = offset_group(h);
   return (nt + bc - 1) / bc * bc;
 }
 
@@ -199,13 +194,15 @@ long long offset_y_bytes(int n, int h) { return (long long)offset_slices(n) * (o
 
 // ---- the contraction
 //
-// A workgroup of four wavefronts takes 128 rows (eight 16-row tiles), 32 CW columns (one column
-// group) and one client; wavefront (wr, wc) computes 4 x CW accumulator tiles: row tiles of half
-// wr, column tiles of half wc.  Per 64-entry slice s of K, the operands pass through LDS in NS
-// stages by direct global-to-LDS loads (stage.h): a stage holds the block's 32 E fragments
-// (eight row tiles x four planes, each a kilobyte of Ep) and the 2 CW + 1 pieces of Yc its
-// columns need (one contiguous run); wavefront w issues the pieces w, w + 4, ...  One barrier per
-// slice; the four planes then run back to back on the staged slice (4 x 4 x CW MFMAs per
+// A workgroup of 2 WC wavefronts takes 128 rows (eight 16-row tiles), one column group of
+// BC = WC CWV tiles and one client; wavefront (wr, wc) computes 4 x CWV accumulator tiles: row
+// tiles of half wr, column tiles wc CWV ... of the group.  With WC = 2 each SIMD runs one
+// wavefront with a wide tile; with WC = 4 two narrower ones, which hide each other's waits at
+// the price of more LDS reads per MFMA.  Per 64-entry slice s of K, the operands pass through LDS
+// in NS stages by direct global-to-LDS loads (stage.h): a stage holds the block's 32 E fragments
+// (eight row tiles x four planes, each a kilobyte of Ep) and the BC + 1 pieces of Yc its columns
+// need (one contiguous run); wavefront w issues the pieces w, w + 2 WC, ...  One barrier per
+// slice; the four planes then run back to back on the staged slice (4 x 4 x CWV MFMAs per
 // wavefront), plane a reading its B fragments a columns to the left.
 // Then each accumulator becomes a W entry, straight to memory:
 //   W = acc + 128 sum_{a in A(pos)} (colsum[pos - a] + Ers_a[j]) + 16384 n |A(pos)|,
@@ -214,21 +211,21 @@ long long offset_y_bytes(int n, int h) { return (long long)offset_slices(n) * (o
 // The grid is XCD-aware: workgroup L runs on XCD L mod 8, and each XCD takes the (client, column
 // group) items of its row blocks (x, x + 8, ...) one after the other, so a block's E stream comes
 // from HBM once and from that XCD's L2 for the other items.
-template <int CW, int NS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+template <int CWV, int WC, int NS>
+__global__ __launch_bounds__(128 * WC) __attribute__((amdgpu_waves_per_eu(WC / 2, WC / 2)))
 void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restrict__ Ers, int rows_pad, int rows,
                         int n, int S, const uint8_t* __restrict__ Yc, const int32_t* __restrict__ colsum,
                         int batch, int nrb, int ncg, int NTq, int h, uint32_t* __restrict__ W, long long ldw,
                         int cpc) {
-  constexpr int RW = 4, BR = 8, BC = 2 * CW;
+  constexpr int RW = 4, BR = 8, CW = CWV, BC = WC * CWV, NW = 2 * WC;
   constexpr int EA = 4 * BR;      // E pieces per stage: piece a BR + i is plane a of row tile i
   constexpr int YP = BC + 1;      // Yc pieces per stage
-  constexpr int CH = EA + YP, PW = (CH + 3) / 4, STAGE = CH * 1024;
+  constexpr int CH = EA + YP, PW = (CH + NW - 1) / NW, STAGE = CH * 1024;
   static_assert((NS - 2) * PW < 64 && PW >= 2, "loads per slice");
   __shared__ __attribute__((aligned(1024))) uint8_t lds[NS * STAGE];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = w >> 1, wc = w & 1;
+  const int wr = w / WC, wc = w % WC;
   const int g = lane >> 4, r = lane & 15;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int items = batch * ncg;
@@ -238,7 +235,7 @@ void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restric
   if (rb >= nrb) return;
   const int T0 = rb * BR, t0 = cg * BC;
 
-  // this wavefront's pieces of each slice: w, w + 4, ...; where that passes CH the wavefront
+  // this wavefront's pieces of each slice: w, w + NW, ...; where that passes CH the wavefront
   // loads its previous piece once more (same bytes, same place), so that every wavefront issues
   // PW loads per slice.
   const uint8_t* src[PW];
@@ -246,7 +243,7 @@ void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restric
   int dst[PW];
 #pragma unroll
   for (int j = 0; j < PW; ++j) {
-    const int c = w + 4 * j < CH ? w + 4 * j : w + 4 * j - 4;
+    const int c = w + NW * j < CH ? w + NW * j : w + NW * j - NW;
     dst[j] = c * 1024;
     if (c < EA) {  // piece c = 8 a + i of the row block's run for the slice
       src[j] = Ep + ((size_t)rb * S * 32 + c) * 1024 + lane * 16;
@@ -348,36 +345,40 @@ void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restric
   }
 }
 
-template <int CW, int NS>
+template <int CWV, int WC, int NS>
 static void launch_offset_gemm_t(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
                                  const uint8_t* Yc, const int32_t* colsum, int batch, int h, uint32_t* W,
                                  long long ldw, int cpc, hipStream_t s) {
   const int S = offset_slices(n), NTq = offset_tiles(h);
-  const int ncg = NTq / (2 * CW);
+  const int ncg = NTq / (WC * CWV);
   const int nrb = rows_pad / 128;  // rows_pad is a multiple of 128
   const long long nblocks = (long long)((nrb + 7) / 8 * 8) * batch * ncg;
-  offset_gemm_kernel<CW, NS><<<(unsigned)nblocks, 256, 0, s>>>(Ep, Ers, rows_pad, rows, n, S, Yc, colsum, batch,
-                                                                nrb, ncg, NTq, h, W, ldw, cpc);
+  offset_gemm_kernel<CWV, WC, NS><<<(unsigned)nblocks, 128 * WC, 0, s>>>(Ep, Ers, rows_pad, rows, n, S, Yc, colsum,
+                                                                          batch, nrb, ncg, NTq, h, W, ldw, cpc);
 }
 
-// Launch variants: the stages in flight, as many as LDS holds (every variant gives identical
-// bits; the runtime times them once per problem shape).
-static int offset_stage_limit(int cw) { return 163840 / ((32 + 2 * cw + 1) * 1024); }
+// Launch variants per column group width BC: four wavefronts of BC / 2 columns tiles or eight of
+// BC / 4, each with three stages in flight, and four stages where LDS holds them (every variant
+// gives identical bits; the runtime times them once per problem shape).
+static bool offset_four_stages(int bc) { return 4 * (32 + bc + 1) * 1024 <= 163840; }
 
-int offset_gemm_variants(int h) { return std::min(offset_stage_limit(offset_cw(h)), 5) - 2; }
+int offset_gemm_variants(int h) { return offset_four_stages(offset_group(h)) ? 4 : 2; }
 
 void launch_offset_gemm(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
                         const uint8_t* Yc, const int32_t* colsum, int batch, int h, uint32_t* W,
                         long long ldw, int cpc, int variant, hipStream_t s) {
-  const int CW = offset_cw(h);
-  const int count = offset_gemm_variants(h);
-  const int NS = 3 + ((variant >= 0 && variant < count) ? variant : 0);
-#define ZP_OFF(C, N)                                                                                \
-  if (CW == C && NS == N) {                                                                         \
-    launch_offset_gemm_t<C, N>(Ep, Ers, rows_pad, rows, n, Yc, colsum, batch, h, W, ldw, cpc, s);   \
-    return;                                                                                         \
+  const int BC = offset_group(h);
+  const int v = (variant >= 0 && variant < offset_gemm_variants(h)) ? variant : 0;
+  const int WC = (v & 1) ? 4 : 2, NS = v >= 2 ? 4 : 3;
+#define ZP_OFF(B, C, N)                                                                                     \
+  if (BC == B && WC == C && NS == N) {                                                                      \
+    launch_offset_gemm_t<B / C, C, N>(Ep, Ers, rows_pad, rows, n, Yc, colsum, batch, h, W, ldw, cpc, s);     \
+    return;                                                                                                 \
   }
-  ZP_OFF(2, 3) ZP_OFF(2, 4) ZP_OFF(3, 3) ZP_OFF(3, 4) ZP_OFF(5, 3) ZP_OFF(7, 3) ZP_OFF(9, 3)
+#define ZP_OFF_B(B) ZP_OFF(B, 2, 3) ZP_OFF(B, 4, 3)
+  ZP_OFF_B(4) ZP_OFF_B(8) ZP_OFF_B(12) ZP_OFF_B(16) ZP_OFF_B(20)
+  ZP_OFF(4, 2, 4) ZP_OFF(4, 4, 4)
+#undef ZP_OFF_B
 #undef ZP_OFF
 }
 
