@@ -59,8 +59,8 @@ STEP_TRAFFIC = {"84ad8428d96d552e": 1076585960}
 COUNTERS = {
     "gemm_i8.hip": {"629d2dbca623b53d": {"kernel": "gemm_planes_kernel<8, 2, 2, 256, 4, false, true>",
                                          "mfma_busy_frac": 0.301}},
-    "hgemm.hip": {"8e56631f39ef1271": {"kernel": "hgemm_kernel<2, 3, true>", "mfma_busy_frac": 0.507}},
-    "offset.hip": {},
+    "hgemm.hip": {"5ccb5e2a713d9050": {"kernel": "hgemm_w8_kernel<4, true>", "mfma_busy_frac": 0.555}},
+    "offset.hip": {"7010379a06e6184e": {"kernel": "offset_gemm_kernel<5, 4, 3>", "mfma_busy_frac": 0.290}},
     "hint.hip": {"eaca529d7b991e6c": {"kernel": "hint_rows_quad_kernel<2>", "valu_insts_per_simd_cycle": 0.324,
                                       "int64_share_of_valu": 0.447, "int32_share_of_valu": 0.017}},
     "lwec.hip": {"d4a4410b6ccb70fc": {"kernel": "compress_lwe_quad_kernel<3>", "valu_insts_per_simd_cycle": 0.298,
