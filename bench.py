@@ -63,7 +63,7 @@ COUNTERS = {
     "offset.hip": {"7010379a06e6184e": {"kernel": "offset_gemm_kernel<5, 4, 3>", "mfma_busy_frac": 0.290}},
     "hint.hip": {"eaca529d7b991e6c": {"kernel": "hint_rows_quad_kernel<2>", "valu_insts_per_simd_cycle": 0.324,
                                       "int64_share_of_valu": 0.447, "int32_share_of_valu": 0.017}},
-    "lwec.hip": {"d4a4410b6ccb70fc": {"kernel": "compress_lwe_quad_kernel<3>", "valu_insts_per_simd_cycle": 0.298,
+    "lwec.hip": {"58b66fd162a18100": {"kernel": "compress_lwe_quad_kernel<3>", "valu_insts_per_simd_cycle": 0.298,
                                       "int64_share_of_valu": 0.460, "int32_share_of_valu": 0.012}},
 }
 

@@ -19,7 +19,8 @@ LIB = os.path.join(PKG, "libzippir.so")
 ARCH = os.environ.get("ZIPPIR_ARCH", "gfx950")
 
 SOURCES = ["runtime.cpp", "serve.cpp", "compressor.cpp", "matvec.hip", "gemm_i8.hip", "rows.hip", "hint.hip",
-           "compress.hip", "offset.hip", "lwec.hip", "probe.hip", "answer.hip", "prg.hip", "noalloc.hip", "batch.hip", "hgemm.hip"]
+           "compress.hip", "offset.hip", "lwec.hip", "probe.hip", "answer.hip", "prg.hip", "noalloc.hip", "batch.hip", "hgemm.hip",
+           "unpack.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

@@ -299,12 +299,26 @@ pir_status pir_compressor_create_packed(pir_compressor** out, int device, void* 
     if (hipMemcpyAsync(dp, pck, (size_t)npck * c->mc.L * sizeof(uint32_t), kind, c->stream) != hipSuccess)
       st = cfail(PIR_EDEVICE, "copying the packed key");
   }
+  // -(N^2)^{-1} mod 2^(32 S), the full-width Montgomery constant of the workgroup products
+  uint32_t* ni = nullptr;
   if (st == PIR_OK) {
-    c->unpack_ms = time_on_stream(c, [&] { zp::launch_unpack_keys(c->dev(), dp, (int)n, (int)t, (int)delta_log2, c->ck, c->stream); });
+    const zp::Big N2 = zp::big_mul(c->mc.N, c->mc.N);
+    const zp::Big Ni = zp::big_neg_inv_pow2(N2, c->mc.S);
+    if (Ni.size() != c->mc.S) st = cfail(PIR_EINVAL, "no inverse of N^2 modulo the Montgomery radix");
+    if (st == PIR_OK) st = c->alloc((void**)&ni, Ni.size() * sizeof(uint32_t));
+    if (st == PIR_OK && (hipMemcpyAsync(ni, Ni.data(), Ni.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                        c->stream) != hipSuccess ||
+                         hipStreamSynchronize(c->stream) != hipSuccess))
+      st = cfail(PIR_EDEVICE, "copying the packed key constants");
+  }
+  if (st == PIR_OK) {
+    c->unpack_ms = time_on_stream(
+        c, [&] { zp::launch_unpack_chains(c->dev(), ni, dp, (int)n, (int)t, (int)delta_log2, c->ck, c->stream); });
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
       st = cfail(PIR_EDEVICE, "unpacking the compression key");
   }
   if (dp) c->release(dp);
+  if (ni) c->release(ni);
   if (st == PIR_OK) st = check_key(c);
   if (st == PIR_OK) st = build_table(c);
   if (st != PIR_OK) {

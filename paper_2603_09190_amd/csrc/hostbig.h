@@ -81,6 +81,44 @@ inline uint32_t neg_inv32(uint32_t m0) {  // -m0^{-1} mod 2^32 for odd m0 (Newto
   return 0u - inv;
 }
 
+// -m^{-1} mod 2^(32 words) for odd m, by Newton's iteration x <- x (2 - m x), which doubles the
+// number of correct low bits each step, from the 32-bit inverse; checked by m n' + 1 = 0.
+inline Big big_neg_inv_pow2(const Big& m, size_t words) {
+  const Big mw = big_resize(m, words);
+  Big x(words, 0u);
+  x[0] = 0u - neg_inv32(mw[0]);
+  auto negate = [](Big& v) {  // v <- -v mod 2^(32 |v|)
+    uint64_t carry = 1;
+    for (auto& w : v) {
+      const uint64_t t = (uint64_t)(uint32_t)~w + carry;
+      w = (uint32_t)t;
+      carry = t >> 32;
+    }
+  };
+  for (size_t bits = 32; bits < 32 * words; bits *= 2) {
+    Big e = big_resize(big_mul(mw, x), words);  // m x
+    negate(e);                                  // -m x
+    uint64_t carry = 2;                         // 2 - m x
+    for (size_t i = 0; i < words && carry; ++i) {
+      const uint64_t t = (uint64_t)e[i] + carry;
+      e[i] = (uint32_t)t;
+      carry = t >> 32;
+    }
+    x = big_resize(big_mul(x, e), words);
+  }
+  negate(x);
+  Big chk = big_resize(big_mul(mw, x), words);
+  uint64_t carry = 1;
+  bool zero = true;
+  for (auto& w : chk) {
+    const uint64_t t = (uint64_t)w + carry;
+    zero = zero && (uint32_t)t == 0u;
+    carry = t >> 32;
+  }
+  if (!zero) x.clear();
+  return x;
+}
+
 inline size_t bit_length(const Big& a) {
   for (size_t i = a.size(); i-- > 0;)
     if (a[i]) return 32 * i + (32 - __builtin_clz(a[i]));

@@ -250,9 +250,10 @@ void launch_compress_lwe(const ClientDev& cd, const LweBatch& lb, const uint32_t
 void launch_reduce_parts(const ClientDev& cd, const LweBatch& lb, const uint32_t* Part, int parts,
                          int fan, uint32_t* Out, uint32_t* X, hipStream_t s);
 // ck[k] = pck[k / t]^(2^(dbits (t - 1 - k mod t))) mod N^2 for k < n (unpacking of packed keys
-// with delta = 2^dbits).
-void launch_unpack_keys(const ClientDev& cd, const uint32_t* pck, int n, int t, int dbits,
-                        uint32_t* ck, hipStream_t s);
+// with delta = 2^dbits): one chain of squarings per packed ciphertext, each Montgomery product
+// spread over a workgroup; Ni = -(N^2)^{-1} mod 2^(32 S) (S words, device).
+void launch_unpack_chains(const ClientDev& cd, const uint32_t* Ni, const uint32_t* pck, int n, int t,
+                          int dbits, uint32_t* ck, hipStream_t s);
 
 // ---- prg.hip (random hint keys of the silent offline phase)
 // The 32-byte seed as eight little-endian words: the ChaCha20 key (RFC 8439).

@@ -12,9 +12,7 @@
 // table entries of a contiguous range of bases), and the partial products are multiplied
 // together in a tree of fan-in `fan`; with many ciphertexts one wavefront per ciphertext is
 // enough to fill the GPU.
-//
-// Packed compression keys (Alg. 6, delta = 2^dbits): ck[it+j] = pck_i^(delta^(t-1-j)), i.e.
-// dbits (t-1-j) Montgomery squarings of pck_i.
+
 #include "internal.h"
 #include "rownum.h"
 #include "wavenum.h"
@@ -209,26 +207,6 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(ClientDev cd, LweBatc
   }
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void unpack_keys_kernel(ClientDev cd, const uint32_t* __restrict__ pck,
-                                                          int n, int t, int dbits,
-                                                          uint32_t* __restrict__ ck) {
-  const int k = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (k >= n) return;
-  WNum<P> M, RR, x;
-  wn_load(M, cd.N2);
-  wn_load(RR, cd.RR);
-  wn_load_n(x, pck + (size_t)(k / t) * cd.L, cd.L);
-  mont_mul(x, x, RR, M, cd.m2prime);  // Montgomery form
-  const int sq = dbits * (t - 1 - k % t);
-  for (int i = 0; i < sq; ++i) mont_mul(x, x, x, M, cd.m2prime);
-  WNum<P> one;
-  wn_zero(one);
-  if (lane_id() == 0) one.v[0] = 1;
-  mont_mul(x, x, one, M, cd.m2prime);
-  wn_store_n(ck + (size_t)k * cd.L, x, cd.L);
-}
-
 #define ZP_BY_P(KERNEL, GRID, ...)                                                   \
   switch (cd.P) {                                                                    \
     case 1: KERNEL<1><<<GRID, 256, 0, s>>>(__VA_ARGS__); break;                      \
@@ -257,13 +235,6 @@ void launch_reduce_parts(const ClientDev& cd, const LweBatch& lb, const uint32_t
   if (waves <= 0) return;
   const int blocks = (int)((waves + 3) / 4);
   ZP_BY_P(reduce_parts_kernel, blocks, cd, lb, Part, parts, fan, Out, X)
-}
-
-void launch_unpack_keys(const ClientDev& cd, const uint32_t* pck, int n, int t, int dbits,
-                        uint32_t* ck, hipStream_t s) {
-  if (n <= 0) return;
-  const int blocks = (n + 3) / 4;
-  ZP_BY_P(unpack_keys_kernel, blocks, cd, pck, n, t, dbits, ck)
 }
 
 #undef ZP_BY_P

@@ -300,3 +300,25 @@ def test_compressor_errors(native):
     with pytest.raises(native.ZipPIRError) as ei:
         native.Compressor(n, q, N_limbs, 512, ck=bad)
     assert ei.value.status == native.PIR_EINVAL
+
+
+@pytest.mark.parametrize("N_bits,n,dbits", [(1024, 5, 600), (1024, 130, 9), (2048, 77, 13),
+                                            (3072, 30, 138), (4096, 205, 20)])
+def test_unpack_chains_every_width(native, N_bits, n, dbits):
+    """Alg. 6's unpacking alone, at every limb width of N^2 (64, 128, 192 and 256 words): the
+    device's key equals the oracle's entry by entry for uniform packed elements of Z*_(N^2), with
+    ragged last groups (n not a multiple of t) and one case of t = 1 (no squarings at all)."""
+    sk = _key(2000 + N_bits, N_bits)
+    N = sk.pk.N
+    delta = 1 << dbits
+    t = max(1, compress.packed_digits_per_key(N_bits, delta))
+    keys = -(-n // t)
+    log(f"unpack chains: N {N_bits} bits, n {n}, delta 2^{dbits}, t {t}, {keys} packed")
+    pck = wl.uniform_ciphertexts(2000 + N_bits, dbits, keys, N)
+    N_limbs, L = _limbs(sk, N_bits)
+    with native.Compressor(n, 1 << 32, N_limbs, N_bits, packed=wl.ints_to_limbs(pck, L), t=t,
+                           delta_log2=dbits) as cmp:
+        dev_ck = limbs_rows_to_ints(cmp.key())
+    with Pool(pool_size()) as pool:
+        ck = sum(pool.map(_unpack_job, [(pck[i], delta, t, min(t, n - i * t), N) for i in range(keys)]), [])
+    assert len(ck) == n and dev_ck == ck
