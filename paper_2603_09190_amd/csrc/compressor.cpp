@@ -299,26 +299,34 @@ pir_status pir_compressor_create_packed(pir_compressor** out, int device, void* 
     if (hipMemcpyAsync(dp, pck, (size_t)npck * c->mc.L * sizeof(uint32_t), kind, c->stream) != hipSuccess)
       st = cfail(PIR_EDEVICE, "copying the packed key");
   }
-  // -(N^2)^{-1} mod 2^(32 S), the full-width Montgomery constant of the workgroup products
-  uint32_t* ni = nullptr;
+  // the unpacking's constants as 7-bit digits: N^2, -(N^2)^{-1} mod R and R^2 mod N^2 for
+  // R = 2^(7 DP)
+  uint8_t* cdig = nullptr;
   if (st == PIR_OK) {
-    const zp::Big N2 = zp::big_mul(c->mc.N, c->mc.N);
-    const zp::Big Ni = zp::big_neg_inv_pow2(N2, c->mc.S);
-    if (Ni.size() != c->mc.S) st = cfail(PIR_EINVAL, "no inverse of N^2 modulo the Montgomery radix");
-    if (st == PIR_OK) st = c->alloc((void**)&ni, Ni.size() * sizeof(uint32_t));
-    if (st == PIR_OK && (hipMemcpyAsync(ni, Ni.data(), Ni.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                                        c->stream) != hipSuccess ||
+    const int DP = zp::unpack_digits((int)c->mc.S);
+    const zp::Big N2 = zp::big_resize(zp::big_mul(c->mc.N, c->mc.N), c->mc.L);
+    const zp::Big Ni = zp::big_neg_inv_pow2(N2, (7 * (size_t)DP + 31) / 32);
+    const zp::Big RR = zp::big_pow2_mod(14ull * DP, N2);
+    if (Ni.empty()) st = cfail(PIR_EINVAL, "no inverse of N^2 modulo the Montgomery radix");
+    std::vector<uint8_t> host(3 * (size_t)DP, 0);
+    if (st == PIR_OK) {
+      const zp::Big* parts[3] = {&N2, &Ni, &RR};
+      for (int p = 0; p < 3; ++p)
+        for (int k = 0; k < DP; ++k) host[(size_t)p * DP + k] = zp::big_digit7(*parts[p], k);
+      st = c->alloc((void**)&cdig, host.size());
+    }
+    if (st == PIR_OK && (hipMemcpyAsync(cdig, host.data(), host.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
                          hipStreamSynchronize(c->stream) != hipSuccess))
       st = cfail(PIR_EDEVICE, "copying the packed key constants");
   }
   if (st == PIR_OK) {
     c->unpack_ms = time_on_stream(
-        c, [&] { zp::launch_unpack_chains(c->dev(), ni, dp, (int)n, (int)t, (int)delta_log2, c->ck, c->stream); });
+        c, [&] { zp::launch_unpack_chains(c->dev(), cdig, dp, (int)n, (int)t, (int)delta_log2, c->ck, c->stream); });
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
       st = cfail(PIR_EDEVICE, "unpacking the compression key");
   }
   if (dp) c->release(dp);
-  if (ni) c->release(ni);
+  if (cdig) c->release(cdig);
   if (st == PIR_OK) st = check_key(c);
   if (st == PIR_OK) st = build_table(c);
   if (st != PIR_OK) {

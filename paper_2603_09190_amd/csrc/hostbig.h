@@ -119,6 +119,14 @@ inline Big big_neg_inv_pow2(const Big& m, size_t words) {
   return x;
 }
 
+// Bits 7k .. 7k + 6 of a (the k-th base-128 digit).
+inline uint8_t big_digit7(const Big& a, size_t k) {
+  const size_t bit = 7 * k, wi = bit / 32, sh = bit % 32;
+  uint64_t v = wi < a.size() ? a[wi] : 0u;
+  if (wi + 1 < a.size()) v |= (uint64_t)a[wi + 1] << 32;
+  return (uint8_t)((v >> sh) & 0x7Fu);
+}
+
 inline size_t bit_length(const Big& a) {
   for (size_t i = a.size(); i-- > 0;)
     if (a[i]) return 32 * i + (32 - __builtin_clz(a[i]));

@@ -251,8 +251,11 @@ void launch_reduce_parts(const ClientDev& cd, const LweBatch& lb, const uint32_t
                          int fan, uint32_t* Out, uint32_t* X, hipStream_t s);
 // ck[k] = pck[k / t]^(2^(dbits (t - 1 - k mod t))) mod N^2 for k < n (unpacking of packed keys
 // with delta = 2^dbits): one chain of squarings per packed ciphertext, each Montgomery product
-// spread over a workgroup; Ni = -(N^2)^{-1} mod 2^(32 S) (S words, device).
-void launch_unpack_chains(const ClientDev& cd, const uint32_t* Ni, const uint32_t* pck, int n, int t,
+// spread over a workgroup.  Residues are kept as unpack_digits(S) 7-bit digits, the Montgomery
+// radix is R = 2^(7 unpack_digits(S)) > 4 N^2, and cdig (device) holds three digit arrays of
+// that length: N^2, -(N^2)^{-1} mod R and R^2 mod N^2.
+constexpr int unpack_digits(int S) { return 16 * (((32 * S + 2 + 6) / 7 + 15) / 16); }
+void launch_unpack_chains(const ClientDev& cd, const uint8_t* cdig, const uint32_t* pck, int n, int t,
                           int dbits, uint32_t* ck, hipStream_t s);
 
 // ---- prg.hip (random hint keys of the silent offline phase)

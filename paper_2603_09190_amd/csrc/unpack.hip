@@ -2,240 +2,333 @@
 // pck_i^(delta^(t-1-j)) mod N^2, and with delta = 2^dbits that is pck_i raised to 2^(dbits (t-1-j)):
 // one chain of squarings per packed ciphertext, each key entry a stop along the chain.
 //
-// A chain cannot be split: squaring is the whole work and step k needs step k-1.  So each step
-// (one Montgomery product modulo M = N^2, S = 64 P words, R = 2^(32 S)) is spread over a workgroup
-// of 256 threads, and a chain runs on one workgroup:
-//   1. column sums of a b: thread (bi, bj) of a 16 x 16 grid multiplies the K x K block
-//      a[bi K ...] x b[bj K ...] (K = S / 16) into 2K - 1 column accumulators in registers and adds
-//      them into LDS columns (two 64-bit LDS atomics per column: bits 0-31 and 32-); the columns
-//      become words in two local passes and one carry-lookahead pass;
-//   2. m = (a b mod R) n' mod R with n' = -M^-1 mod R, the same block product restricted to the
-//      low S columns;
-//   3. U = (a b + m M) / R: the block product m M added to a b's words, carried, the high half
-//      taken, and M subtracted once if U >= M (U < 2M).
-// Carry-lookahead: for a chunk of 64 words x_l < 2^33 - 1 (one per lane), G = ballot(x_l > 2^32 - 1)
-// and P = ballot(x_l == 2^32 - 1); the carries into the lanes are the internal carries of the
-// 64-bit addition G + (G | P) + c_in, i.e. (G + (G | P) + c_in) ^ G ^ (G | P), and the addition's
-// own carry-out goes into the next chunk.  Borrows of a subtraction work the same way with
-// "u < m" and "u == m".
+// A chain cannot be split: squaring is the whole work and step k needs step k-1.  So each step,
+// one Montgomery product modulo M = N^2, is spread over a workgroup of 256 threads, and a chain
+// runs on one workgroup.  Its latency is what counts, so the chain stays in one representation:
+//   - a residue is DP = unpack_digits(S) digits of 7 bits (each a non-negative int8), and the
+//     Montgomery radix is R = 128^DP > 4M.  Products are then only reduced lazily: for a, b < 2M,
+//     U = (a b + m M) / R < (4M^2 + R M) / R < 2M, so no final subtraction is needed along the
+//     chain, and a last product with 1 lands below M;
+//   - the three multiprecision products (a b; m = (a b mod R) n' mod R with n' = -M^-1 mod R;
+//     m M) run on the int8 matrix cores.  The digit coefficients c_k = sum_i x_i y_(k-i) are a
+//     matrix product: with k = 16 u + r and i = 16 v + s, c_(16u+r) = sum_w sum_s Y_w[r][s] X[s][u-w],
+//     Y_w[r][s] = y_(16w+r-s) a 16 x 16 Toeplitz block of y and X[s][v] = x_(16v+s) x's v-th
+//     16-digit block.  One v_mfma_i32_16x16x64_i8 covers 16 coefficient rows r, 16 blocks u and
+//     four w's along K: its A operand (lane: row r, one w) is 16 consecutive bytes of y's digits
+//     stored in reverse, read at a byte offset and aligned with v_alignbyte; its B operand (lane:
+//     column u, one w) is one aligned 16-digit block of x.  The (column tile, K step) pairs with
+//     nonzero operands are dealt evenly to the four wavefronts, which add their partial tiles
+//     into LDS;
+//   - coefficients (below 2^25) become digits in one pass: thread l takes a run of RUN digits,
+//     folds each coefficient's four 7-bit pieces into the digits above it (sums below 2^10) and
+//     once more (digits at most 131), so that a carry-lookahead finishes: a run carries out
+//     with c_in = 0 (G) or with c_in = 1 (G | P), the carries into the runs of a wavefront are
+//     the internal carries of the 64-bit addition G + (G | P) + c_in, i.e.
+//     (G + (G | P) + c_in) ^ G ^ (G | P) over ballots, and each wavefront's own carry-outs go
+//     through LDS to the wavefronts above.
 #include "internal.h"
 
 namespace zp {
 
 namespace {
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+
 constexpr int kThreads = 256;
 
-// Products have 2S - 1 columns; one more word (index 2S) takes the top bit of T + m M.
 template <int S>
-struct UnpackLds {
-  static constexpr int kW = 2 * S + 64;
-  uint32_t M[S], Ni[S], X[S], Y[S], m[S];
-  uint32_t T[kW];                              // a b, then a b + m M, as words
-  unsigned long long c0[kW], c1[kW];           // column sums: bits 0-31, bits 32- (as added)
-  unsigned long long x[kW];                    // words before the carry-lookahead
+struct Dig {
+  static constexpr int DP = unpack_digits(S);            // digits of a residue; R = 128^DP
+  static constexpr int NB = DP / 16;                     // 16-digit blocks
+  static constexpr int NT = (2 * NB + 15) / 16;          // 16-block column tiles of a product
+  static constexpr int CF = 256 * NT;                    // coefficient slots (>= 2 DP)
+  // Operand buffers carry zeros around the digits, so that every block an MFMA step can touch
+  // is a valid address and the out-of-range ones read as zero: forward digits start at PX
+  // (blocks v in [-(NB + 3), 16 NT) are readable), reversed digits at PY (64 zero bytes below,
+  // 32 above).
+  static constexpr int PX = 16 * (NB + 4);
+  static constexpr int XB = PX + 256 * NT;
+  static constexpr int PY = 64;
+  static constexpr int RB = PY + DP + 32;
+  static constexpr int RUN = 4 * ((2 * DP + 4 * kThreads - 1) / (4 * kThreads));  // digits per thread
 };
 
-// Carry-lookahead over `words` entries of v (each < 2^33 - 1), written as 32-bit words to out;
-// returns the carry out of the top word.  Wave 0 only.
-__device__ uint32_t carry_chain(const unsigned long long* v, int words, uint32_t* out) {
-  const int lane = threadIdx.x & 63;
-  unsigned long long cin = 0;
-  for (int base = 0; base < words; base += 64) {
-    const unsigned long long xv = base + lane < words ? v[base + lane] : 0ull;
-    const unsigned long long G = __ballot(xv > 0xFFFFFFFFull);
-    const unsigned long long P = __ballot(xv == 0xFFFFFFFFull);
-    const unsigned long long B = G | P;
-    const unsigned long long s1 = G + B;
-    const unsigned long long s2 = s1 + cin;
-    const unsigned long long C = s2 ^ G ^ B;
-    const unsigned long long cout = (s1 < G) | (s2 < s1);
-    if (base + lane < words) out[base + lane] = (uint32_t)(xv + ((C >> lane) & 1ull));
-    cin = cout;
-  }
-  return (uint32_t)cin;
-}
+// Where a normalised product goes.
+enum NormMode { kModeT, kModeM, kModeU, kModeOut };
 
-// Column sums of a x b into L.c0 / L.c1 (cleared by the caller): all columns, or only those
-// below S (low = true).
-template <int S, bool kLow>
-__device__ void block_product(UnpackLds<S>& L, const uint32_t* a, const uint32_t* b) {
-  constexpr int K = S / 16;
-  const int bi = threadIdx.x >> 4, bj = threadIdx.x & 15;
-  const int cb = (bi + bj) * K;
-  if (kLow && cb >= S) return;
-  uint32_t ar[K], br[K];
+template <int S>
+struct UnpackLds {
+  using D = Dig<S>;
+  int cf[2][D::CF];                    // digit coefficients (two buffers: one filled, one cleared)
+  alignas(16) uint8_t xa[D::XB];       // digits of the chain value (B operand of a b), from PX
+  alignas(16) uint8_t xb[D::XB];       // digits of T mod R, then of m (B operands), from PX
+  alignas(16) uint8_t td[2 * D::DP];   // digits of T = a b
+  alignas(16) uint8_t yr[D::RB];       // reversed digits of the chain value (byte PY + DP - 1 - k: digit k)
+  alignas(16) uint8_t nr[D::RB];       // reversed digits of n'
+  alignas(16) uint8_t mr[D::RB];       // reversed digits of M
+  alignas(16) uint8_t rr[D::RB];       // reversed digits of R^2 mod M
+  alignas(16) uint8_t one[D::RB];      // reversed digits of 1
+  uint32_t X[S];                       // packed ciphertext words
+  uint32_t flag[4];                    // wavefront carry-outs
+};
+
+// Digit coefficients of x y into cf (zeroed) for the 16-digit blocks u < ulim: x's digits in xd
+// (blocks), y's reversed in yr.  Every thread; no barrier inside.
+template <int S>
+__device__ void mfma_product(const uint8_t* xd, const uint8_t* yr, int ulim, int* cf) {
+  using D = Dig<S>;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int ntiles = (ulim + 15) >> 4;
+  // column tile nt (blocks u = 16 nt ...) meets w in [16 nt - NB + 1, min(NB, 16 nt + 15, ulim - 1)]
+  auto ks_lo = [&](int nt) { return max(0, 16 * nt - D::NB + 1) >> 2; };
+  auto ks_hi = [&](int nt) { return min(D::NB, min(16 * nt + 15, ulim - 1)) >> 2; };
+  int total = 0;
+  for (int nt = 0; nt < ntiles; ++nt) total += ks_hi(nt) - ks_lo(nt) + 1;
+  const int beg = total * wave / 4, end = total * (wave + 1) / 4;
+  // Lane (g, c) in K step ks: A = y_(16w + c - s), s = 0..15, w = 4 ks + g, i.e. the reversed
+  // bytes from PY + DP - 1 - 16 w - c on; B = x's block v = 16 nt + c - w.  Both move down by
+  // 64 bytes per K step; the A window's misalignment (o & 3) is the lane's for every step.
+  const int oA = D::PY + D::DP - 1 - 16 * g - c;
+  const int aA = oA & ~3, sh = oA & 3;
+  int idx = 0;
+  for (int nt = 0; nt < ntiles; ++nt) {
+    const int lo = ks_lo(nt), cnt = ks_hi(nt) - lo + 1;
+    const int a = max(beg, idx), b = min(end, idx + cnt);
+    if (a < b) {
+      const uint8_t* pb = xd + D::PX + 16 * (16 * nt + c - g);
+      v4i acc = {0, 0, 0, 0};
+      // four K steps per round: all their operand reads are issued before the products
+      for (int q = a; q < b; q += 4) {
+        v4i af[4], bf[4];
 #pragma unroll
-  for (int d = 0; d < K; ++d) {
-    ar[d] = a[bi * K + d];
-    br[d] = b[bj * K + d];
-  }
-  unsigned long long acc[2 * K - 1];
-  uint32_t hi[2 * K - 1];
+        for (int j = 0; j < 4; ++j)
+          if (q + j < b) {
+            const int ks = lo + q + j - idx;
+            const uint32_t* pa = reinterpret_cast<const uint32_t*>(yr + aA - 64 * ks);
+            const uint32_t y0 = pa[0], y1 = pa[1], y2 = pa[2], y3 = pa[3], y4 = pa[4];
+            af[j] = v4i{(int)__builtin_amdgcn_alignbyte(y1, y0, sh), (int)__builtin_amdgcn_alignbyte(y2, y1, sh),
+                        (int)__builtin_amdgcn_alignbyte(y3, y2, sh), (int)__builtin_amdgcn_alignbyte(y4, y3, sh)};
+            bf[j] = *reinterpret_cast<const v4i*>(pb - 64 * ks);
+          }
 #pragma unroll
-  for (int c = 0; c < 2 * K - 1; ++c) {
-    acc[c] = 0ull;
-    hi[c] = 0u;
-  }
-#pragma unroll
-  for (int di = 0; di < K; ++di)
-#pragma unroll
-    for (int dj = 0; dj < K; ++dj) {
-      if (kLow && cb + di + dj >= S) continue;
-      const unsigned long long p = (unsigned long long)ar[di] * br[dj];
-      const unsigned long long s = acc[di + dj] + p;
-      hi[di + dj] += s < p ? 1u : 0u;
-      acc[di + dj] = s;
+        for (int j = 0; j < 4; ++j)
+          if (q + j < b) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[j], bf[j], acc, 0, 0, 0);
+      }
+      // acc[e]: coefficient row 4 g + e of block 16 nt + c
+      int* dst = cf + 16 * (16 * nt + c) + 4 * g;
+      atomicAdd(dst + 0, acc[0]);
+      atomicAdd(dst + 1, acc[1]);
+      atomicAdd(dst + 2, acc[2]);
+      atomicAdd(dst + 3, acc[3]);
     }
+    idx += cnt;
+  }
+}
+
+// Digits of sum_k cf[k] 128^k (+ the digits td for kModeU and kModeOut) for k < K (K = DP for kModeM, else
+// 2 DP; the carry out of digit K - 1 is dropped), written where MODE says:
+//   kModeT: T's digits to td, and T mod R's to xb;   kModeM: m's digits to xb;
+//   kModeU: digits DP .. 2DP - 1 (U = (T + m M) / R) to xa and, reversed, to yr;
+//   kModeOut: the same U to xb.
+// Also clears `spare` (the other coefficient buffer).  Every thread; two barriers inside, the
+// first after the carry-outs are published, the second after the digits are written.
+template <int S, int MODE>
+__device__ void normalize(UnpackLds<S>& L, const int* cf, int* spare) {
+  using D = Dig<S>;
+  constexpr int K = MODE == kModeM ? D::DP : 2 * D::DP;
+  constexpr int RUN = D::RUN;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int k0 = RUN * threadIdx.x;
+  uint32_t f[RUN];
+  uint32_t co0 = 0, co1 = 0;
 #pragma unroll
-  for (int c = 0; c < 2 * K - 1; ++c) {
-    if (kLow && cb + c >= S) continue;
-    atomicAdd(&L.c0[cb + c], acc[c] & 0xFFFFFFFFull);
-    atomicAdd(&L.c1[cb + c], (acc[c] >> 32) + ((unsigned long long)hi[c] << 32));
-  }
-}
-
-// Column sums (c0, c1) over `cols` columns, plus `add` (cols words or nullptr), to words in x
-// (each at most 2^32 + 6): two local passes.  Every thread; barriers inside.
-template <int S>
-__device__ void columns_to_x(UnpackLds<S>& L, int cols, const uint32_t* add) {
-  // value of column c: c0[c] + c1[c] 2^32 with c0 < 2^37 and c1 < 2^42 (at most 32 blocks add
-  // into a column); word c receives lo(c0[c]) + hi(c0[c-1]) + lo(c1[c-1]) + hi(c1[c-2])
-  for (int c = threadIdx.x; c < cols; c += kThreads) {
-    unsigned long long w = L.c0[c] & 0xFFFFFFFFull;
-    if (c >= 1) w += (L.c0[c - 1] >> 32) + (L.c1[c - 1] & 0xFFFFFFFFull);
-    if (c >= 2) w += L.c1[c - 2] >> 32;
-    if (add) w += add[c];
-    L.x[c] = w;  // < 2^35
-  }
-  __syncthreads();
-  unsigned long long v[(2 * S + 1 + kThreads - 1) / kThreads];
-  int k = 0;
-  for (int c = threadIdx.x; c < cols; c += kThreads, ++k)
-    v[k] = (L.x[c] & 0xFFFFFFFFull) + (c >= 1 ? L.x[c - 1] >> 32 : 0ull);
-  __syncthreads();
-  k = 0;
-  for (int c = threadIdx.x; c < cols; c += kThreads, ++k) L.x[c] = v[k];  // <= 2^32 + 6
-  __syncthreads();
-}
-
-template <int S>
-__device__ void clear_columns(UnpackLds<S>& L, int cols) {
-  for (int c = threadIdx.x; c < cols; c += kThreads) {
-    L.c0[c] = 0ull;
-    L.c1[c] = 0ull;
-  }
-}
-
-// out = a b R^-1 mod M (a, b, out in LDS, S words; out may alias a or b).
-template <int S>
-__device__ void mont_mul_wg(UnpackLds<S>& L, const uint32_t* a, const uint32_t* b, uint32_t* out) {
-  const int wave = threadIdx.x >> 6;
-  // 1. T = a b (2S + 1 words, the top one 0)
-  clear_columns(L, 2 * S + 1);
-  __syncthreads();
-  block_product<S, false>(L, a, b);
-  __syncthreads();
-  columns_to_x(L, 2 * S + 1, nullptr);
-  if (wave == 0) (void)carry_chain(L.x, 2 * S + 1, L.T);
-  __syncthreads();
-  // 2. m = T_low n' mod R
-  clear_columns(L, S);
-  __syncthreads();
-  block_product<S, true>(L, L.T, L.Ni);
-  __syncthreads();
-  columns_to_x(L, S, nullptr);
-  if (wave == 0) (void)carry_chain(L.x, S, L.m);
-  __syncthreads();
-  // 3. U = (T + m M) / R, then U mod M
-  clear_columns(L, 2 * S + 1);
-  __syncthreads();
-  block_product<S, false>(L, L.m, L.M);
-  __syncthreads();
-  columns_to_x(L, 2 * S + 1, L.T);
-  if (wave == 0) {
-    const int lane = threadIdx.x & 63;
-    // T + m M < 2 R M: words 0 .. S-1 are zero by construction (their carry reaches word S
-    // through the chain), U is words S .. 2S-1, and word 2S its top bit
-    (void)carry_chain(L.x, 2 * S + 1, L.T);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
-    __builtin_amdgcn_wave_barrier();
-    const uint32_t top = L.T[2 * S];
-    const uint32_t* U = L.T + S;
-    // U >= M ?  (U < 2M): compare from the top
-    bool ge = top != 0;
-    if (!ge) {
-      int decided = 0;
-      for (int base = S - 64; base >= 0 && !decided; base -= 64) {
-        const uint32_t u = U[base + lane], mm = L.M[base + lane];
-        const unsigned long long gt = __ballot(u > mm), lt = __ballot(u < mm);
-        if (gt | lt) {
-          const int hg = gt ? 63 - __builtin_clzll(gt) : -1, hl = lt ? 63 - __builtin_clzll(lt) : -1;
-          ge = hg > hl;
-          decided = 1;
+  for (int i = 0; i < RUN; ++i) f[i] = 0;
+  if (k0 < K) {
+    // c_(k0-4) .. c_(k0+RUN-1), zero outside [0, K)
+    uint32_t cv[RUN + 4];
+#pragma unroll
+    for (int i = 0; i < RUN + 4; i += 4) {
+      const int k = k0 - 4 + i;
+      v4i v = v4i{0, 0, 0, 0};
+      if (k >= 0) v = *reinterpret_cast<const v4i*>(cf + k);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cv[i + j] = k + j < K ? (uint32_t)v[j] : 0u;
+    }
+    // e_k for k = k0 - 1 .. k0 + RUN - 1: the 7-bit pieces of c_k, c_(k-1), c_(k-2), c_(k-3) that
+    // land on digit k (at most 3 127 + 15, plus a digit of T)
+    uint32_t e[RUN + 1];
+#pragma unroll
+    for (int i = 0; i <= RUN; ++i)
+      e[i] = (cv[i + 3] & 127u) + ((cv[i + 2] >> 7) & 127u) + ((cv[i + 1] >> 14) & 127u) + (cv[i] >> 21);
+    if (MODE == kModeU || MODE == kModeOut) {
+#pragma unroll
+      for (int i = 0; i < RUN + 4; i += 4) {
+        const int k = k0 - 4 + i;
+        if (k >= 0 && k < 2 * D::DP) {
+          const uint32_t dw = *reinterpret_cast<const uint32_t*>(L.td + k);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (i + j >= 3) e[i + j - 3] += (dw >> (8 * j)) & 0xFFu;
         }
       }
-      if (!decided) ge = true;  // U == M
     }
-    // out = U - M (if ge) with borrow lookahead, else U
-    unsigned long long bin = 0;
-    for (int base = 0; base < S; base += 64) {
-      const uint32_t u = U[base + lane], mm = ge ? L.M[base + lane] : 0u;
-      const unsigned long long G = __ballot(u < mm), P = __ballot(u == mm);
-      const unsigned long long B = G | P;
-      const unsigned long long s1 = G + B, s2 = s1 + bin;
-      const unsigned long long C = s2 ^ G ^ B;
-      bin = (s1 < G) | (s2 < s1);
-      out[base + lane] = u - mm - (uint32_t)((C >> lane) & 1ull);
+#pragma unroll
+    for (int i = 0; i < RUN; ++i) f[i] = (e[i + 1] & 127u) + (e[i] >> 7);  // <= 131
+    uint32_t c0 = 0, c1 = 1;
+#pragma unroll
+    for (int i = 0; i < RUN; ++i) {
+      c0 = (f[i] + c0) >> 7;
+      c1 = (f[i] + c1) >> 7;
+    }
+    co0 = c0;
+    co1 = c1;
+  }
+  const unsigned long long G = __ballot(co0 != 0u), B = __ballot(co1 != 0u);
+  const unsigned long long s1 = G + B;
+  if (lane == 0) L.flag[wave] = (s1 < G ? 1u : 0u) | (s1 < G || s1 == ~0ull ? 2u : 0u);
+  for (int i = threadIdx.x; i < D::CF / 4; i += kThreads) reinterpret_cast<v4i*>(spare)[i] = v4i{0, 0, 0, 0};
+  __syncthreads();
+  uint32_t cw = 0;
+  for (int j = 0; j < wave; ++j) cw = (L.flag[j] >> cw) & 1u;
+  uint32_t cin = (uint32_t)((((s1 + cw) ^ G ^ B) >> lane) & 1ull);
+  if (k0 < K) {
+#pragma unroll
+    for (int i = 0; i < RUN; i += 4) {
+      uint32_t dw = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t sv = f[i + j] + cin;
+        dw |= (sv & 127u) << (8 * j);
+        cin = sv >> 7;
+      }
+      const int k = k0 + i;
+      if (k >= K) continue;
+      if (MODE == kModeT) {
+        *reinterpret_cast<uint32_t*>(L.td + k) = dw;
+        if (k < D::DP) *reinterpret_cast<uint32_t*>(L.xb + D::PX + k) = dw;
+      } else if (MODE == kModeM) {
+        *reinterpret_cast<uint32_t*>(L.xb + D::PX + k) = dw;
+      } else if (k >= D::DP) {
+        const int j = k - D::DP;
+        if (MODE == kModeU) {
+          *reinterpret_cast<uint32_t*>(L.xa + D::PX + j) = dw;
+          *reinterpret_cast<uint32_t*>(L.yr + D::PY + D::DP - 4 - j) = __builtin_bswap32(dw);
+        } else {
+          *reinterpret_cast<uint32_t*>(L.xb + D::PX + j) = dw;
+        }
+      }
     }
   }
   __syncthreads();
+}
+
+// U = a b R^-1 (mod M, below 2M) for a = the chain value (digits in xa) and b given by its
+// reversed digits br; U goes to xa / yr (kModeU) or xb (kModeOut).  `buf` alternates the
+// coefficient buffers.
+template <int S, int OUT>
+__device__ void mont_mul_wg(UnpackLds<S>& L, const uint8_t* br, int& buf) {
+  using D = Dig<S>;
+  // 1. T = a b
+  mfma_product<S>(L.xa, br, 2 * D::NB, L.cf[buf]);
+  __syncthreads();
+  normalize<S, kModeT>(L, L.cf[buf], L.cf[buf ^ 1]);
+  buf ^= 1;
+  // 2. m = (T mod R) n' mod R
+  mfma_product<S>(L.xb, L.nr, D::NB, L.cf[buf]);
+  __syncthreads();
+  normalize<S, kModeM>(L, L.cf[buf], L.cf[buf ^ 1]);
+  buf ^= 1;
+  // 3. U = (T + m M) / R
+  mfma_product<S>(L.xb, L.mr, 2 * D::NB, L.cf[buf]);
+  __syncthreads();
+  normalize<S, OUT>(L, L.cf[buf], L.cf[buf ^ 1]);
+  buf ^= 1;
+}
+
+// Reversed digits (byte PY + DP - 1 - k holds digit k) from DP forward digits in global memory.
+template <int S>
+__device__ void load_reversed(const uint8_t* dig, uint8_t* rev) {
+  using D = Dig<S>;
+  for (int q = threadIdx.x; q < D::DP / 4; q += kThreads)
+    reinterpret_cast<uint32_t*>(rev + D::PY)[(D::DP - 4 - 4 * q) >> 2] =
+        __builtin_bswap32(reinterpret_cast<const uint32_t*>(dig)[q]);
 }
 
 // One workgroup per packed ciphertext i: keys i t + t - 1, i t + t - 2, ..., i t (those below n),
 // stopping to write each after dbits further squarings.
 template <int S>
-__global__ __launch_bounds__(kThreads) void unpack_chain_kernel(const uint32_t* __restrict__ M,
-                                                                const uint32_t* __restrict__ RR,
-                                                                const uint32_t* __restrict__ Ni,
+__global__ __launch_bounds__(kThreads) void unpack_chain_kernel(const uint8_t* __restrict__ cdig,
                                                                 const uint32_t* __restrict__ pck, int n, int t,
                                                                 int dbits, int L, uint32_t* __restrict__ ck) {
   __shared__ UnpackLds<S> lds;
+  using D = Dig<S>;
   const int i = blockIdx.x;
-  for (int w = threadIdx.x; w < S; w += kThreads) {
-    lds.M[w] = M[w];
-    lds.Ni[w] = Ni[w];
-    lds.Y[w] = RR[w];
-    lds.X[w] = w < L ? pck[(size_t)i * L + w] : 0u;
+  for (int w = threadIdx.x; w < S; w += kThreads) lds.X[w] = w < L ? pck[(size_t)i * L + w] : 0u;
+  for (int w = threadIdx.x; w < D::RB / 4; w += kThreads) {
+    reinterpret_cast<uint32_t*>(lds.yr)[w] = 0u;
+    reinterpret_cast<uint32_t*>(lds.nr)[w] = 0u;
+    reinterpret_cast<uint32_t*>(lds.mr)[w] = 0u;
+    reinterpret_cast<uint32_t*>(lds.rr)[w] = 0u;
+    reinterpret_cast<uint32_t*>(lds.one)[w] = 0u;
+  }
+  for (int w = threadIdx.x; w < 2 * D::CF / 4; w += kThreads) reinterpret_cast<v4i*>(&lds.cf[0][0])[w] = v4i{0, 0, 0, 0};
+  for (int w = threadIdx.x; w < D::XB / 16; w += kThreads) {
+    reinterpret_cast<v4i*>(lds.xa)[w] = v4i{0, 0, 0, 0};
+    reinterpret_cast<v4i*>(lds.xb)[w] = v4i{0, 0, 0, 0};
   }
   __syncthreads();
-  mont_mul_wg(lds, lds.X, lds.Y, lds.X);  // Montgomery form
+  // the packed ciphertext's digits, and the constants reversed
+  for (int q = threadIdx.x; q < D::DP / 4; q += kThreads) {
+    uint32_t dw = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int bit = 7 * (4 * q + j), wi = bit >> 5, sh = bit & 31;
+      uint32_t d = 0;
+      if (wi < S) {
+        d = lds.X[wi] >> sh;
+        if (sh > 25 && wi + 1 < S) d |= lds.X[wi + 1] << (32 - sh);
+      }
+      dw |= (d & 0x7Fu) << (8 * j);
+    }
+    reinterpret_cast<uint32_t*>(lds.xa + D::PX)[q] = dw;
+  }
+  load_reversed<S>(cdig, lds.mr);
+  load_reversed<S>(cdig + D::DP, lds.nr);
+  load_reversed<S>(cdig + 2 * D::DP, lds.rr);
+  if (threadIdx.x == 0) lds.one[D::PY + D::DP - 1] = 1;
+  __syncthreads();
+  int buf = 0;
+  mont_mul_wg<S, kModeU>(lds, lds.rr, buf);  // Montgomery form: pck R mod M (below 2M)
   for (int j = t - 1; j >= 0; --j) {
     const int k = i * t + j;
     if (k < n) {
-      // key k = X R^-1 (out of Montgomery form) via a product with 1
-      for (int w = threadIdx.x; w < S; w += kThreads) lds.Y[w] = w == 0 ? 1u : 0u;
-      __syncthreads();
-      mont_mul_wg(lds, lds.X, lds.Y, lds.Y);
-      for (int w = threadIdx.x; w < L; w += kThreads) ck[(size_t)k * L + w] = lds.Y[w];
+      // key k = X R^-1 mod M (below M) via a product with 1, its digits in xb, then as words
+      mont_mul_wg<S, kModeOut>(lds, lds.one, buf);
+      for (int w = threadIdx.x; w < L; w += kThreads) {
+        const int kb = (32 * w) / 7, ke = min((32 * w + 31) / 7, D::DP - 1);
+        unsigned long long acc = 0;
+        for (int kk = ke; kk >= kb; --kk) acc = (acc << 7) | lds.xb[D::PX + kk];
+        ck[(size_t)k * L + w] = (uint32_t)(acc >> (32 * w - 7 * kb));
+      }
       __syncthreads();
     }
     if (j > 0)
-      for (int sq = 0; sq < dbits; ++sq) mont_mul_wg(lds, lds.X, lds.X, lds.X);
+      for (int sq = 0; sq < dbits; ++sq) mont_mul_wg<S, kModeU>(lds, lds.yr, buf);
   }
 }
 
 }  // namespace
 
-void launch_unpack_chains(const ClientDev& cd, const uint32_t* Ni, const uint32_t* pck, int n, int t, int dbits,
+void launch_unpack_chains(const ClientDev& cd, const uint8_t* cdig, const uint32_t* pck, int n, int t, int dbits,
                           uint32_t* ck, hipStream_t s) {
   if (n <= 0) return;
   const int groups = (n + t - 1) / t;
   switch (cd.P) {
-    case 1: unpack_chain_kernel<64><<<groups, kThreads, 0, s>>>(cd.N2, cd.RR, Ni, pck, n, t, dbits, cd.L, ck); break;
-    case 2: unpack_chain_kernel<128><<<groups, kThreads, 0, s>>>(cd.N2, cd.RR, Ni, pck, n, t, dbits, cd.L, ck); break;
-    case 3: unpack_chain_kernel<192><<<groups, kThreads, 0, s>>>(cd.N2, cd.RR, Ni, pck, n, t, dbits, cd.L, ck); break;
-    case 4: unpack_chain_kernel<256><<<groups, kThreads, 0, s>>>(cd.N2, cd.RR, Ni, pck, n, t, dbits, cd.L, ck); break;
+    case 1: unpack_chain_kernel<64><<<groups, kThreads, 0, s>>>(cdig, pck, n, t, dbits, cd.L, ck); break;
+    case 2: unpack_chain_kernel<128><<<groups, kThreads, 0, s>>>(cdig, pck, n, t, dbits, cd.L, ck); break;
+    case 3: unpack_chain_kernel<192><<<groups, kThreads, 0, s>>>(cdig, pck, n, t, dbits, cd.L, ck); break;
+    case 4: unpack_chain_kernel<256><<<groups, kThreads, 0, s>>>(cdig, pck, n, t, dbits, cd.L, ck); break;
   }
 }
 
