@@ -33,7 +33,8 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # instead of in AGPRs, which keeps the register allocator from rotating them through copies
 # between the MFMAs of the main loop.
 MFMA_VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
-PER_FILE_FLAGS = {"offset.hip": MFMA_VGPR_FORM, "hgemm.hip": MFMA_VGPR_FORM, "batch.hip": MFMA_VGPR_FORM}
+PER_FILE_FLAGS = {"offset.hip": MFMA_VGPR_FORM, "hgemm.hip": MFMA_VGPR_FORM, "batch.hip": MFMA_VGPR_FORM,
+                  "unpack.hip": MFMA_VGPR_FORM}
 
 
 def _compile(src: str) -> str:

@@ -16,9 +16,10 @@
 //     16-digit block.  One v_mfma_i32_16x16x64_i8 covers 16 coefficient rows r, 16 blocks u and
 //     four w's along K: its A operand (lane: row r, one w) is 16 consecutive bytes of y's digits
 //     stored in reverse, read at a byte offset and aligned with v_alignbyte; its B operand (lane:
-//     column u, one w) is one aligned 16-digit block of x.  The (column tile, K step) pairs with
-//     nonzero operands are dealt evenly to the four wavefronts, which add their partial tiles
-//     into LDS;
+//     column u, one w) is one aligned 16-digit block of x.  The K steps are split evenly among
+//     the four wavefronts, each runs every column tile in its K steps (pairs with zero operands
+//     read zero padding, which costs less than branching around them), so a wavefront reads
+//     each A operand once for all column tiles, and each writes its partial coefficients to LDS;
 //   - coefficients (below 2^25) become digits in one pass: thread l takes a run of RUN digits,
 //     folds each coefficient's four 7-bit pieces into the digits above it (sums below 2^10) and
 //     once more (digits at most 131), so that a carry-lookahead finishes: a run carries out
@@ -59,7 +60,7 @@ enum NormMode { kModeT, kModeM, kModeU, kModeOut };
 template <int S>
 struct UnpackLds {
   using D = Dig<S>;
-  int cf[2][D::CF];                    // digit coefficients (two buffers: one filled, one cleared)
+  int cf[4][D::CF];                    // digit coefficients of a product, one partial per wavefront
   alignas(16) uint8_t xa[D::XB];       // digits of the chain value (B operand of a b), from PX
   alignas(16) uint8_t xb[D::XB];       // digits of T mod R, then of m (B operands), from PX
   alignas(16) uint8_t td[2 * D::DP];   // digits of T = a b
@@ -69,61 +70,60 @@ struct UnpackLds {
   alignas(16) uint8_t rr[D::RB];       // reversed digits of R^2 mod M
   alignas(16) uint8_t one[D::RB];      // reversed digits of 1
   uint32_t X[S];                       // packed ciphertext words
-  uint32_t flag[4];                    // wavefront carry-outs
+  alignas(16) uint32_t flag[4];        // wavefront carry-outs
 };
 
-// Digit coefficients of x y into cf (zeroed) for the 16-digit blocks u < ulim: x's digits in xd
-// (blocks), y's reversed in yr.  Every thread; no barrier inside.
-template <int S>
-__device__ void mfma_product(const uint8_t* xd, const uint8_t* yr, int ulim, int* cf) {
+// Digit coefficients of x y for the 16-digit blocks u < ulim (NTL = ceil(ulim / 16) column
+// tiles): x's digits in xd (blocks), y's reversed in yr.  The K steps (ks = 0 .. (min(NB, ulim -
+// 1)) / 4) are split evenly among the wavefronts, and a wavefront runs every column tile in
+// each of its K steps: one A operand serves all the tiles of a K step, consecutive products go
+// to different accumulators, and there is no branch.  Pairs whose operands are zero read the
+// zero padding (and, for the low product, the extra terms only reach blocks u >= ulim).
+// Wavefront w writes its partial coefficients (zero past the NTL tiles) to cf[w].  Every
+// thread; no barrier inside.
+template <int S, int NTL>
+__device__ void mfma_product(const uint8_t* xd, const uint8_t* yr, int ulim, int (*cf)[Dig<S>::CF]) {
   using D = Dig<S>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-  const int ntiles = (ulim + 15) >> 4;
-  // column tile nt (blocks u = 16 nt ...) meets w in [16 nt - NB + 1, min(NB, 16 nt + 15, ulim - 1)]
-  auto ks_lo = [&](int nt) { return max(0, 16 * nt - D::NB + 1) >> 2; };
-  auto ks_hi = [&](int nt) { return min(D::NB, min(16 * nt + 15, ulim - 1)) >> 2; };
-  int total = 0;
-  for (int nt = 0; nt < ntiles; ++nt) total += ks_hi(nt) - ks_lo(nt) + 1;
-  const int beg = total * wave / 4, end = total * (wave + 1) / 4;
+  const int kn = (min(D::NB, ulim - 1) >> 2) + 1;
+  const int ka = kn * wave / 4, kb = kn * (wave + 1) / 4;
   // Lane (g, c) in K step ks: A = y_(16w + c - s), s = 0..15, w = 4 ks + g, i.e. the reversed
   // bytes from PY + DP - 1 - 16 w - c on; B = x's block v = 16 nt + c - w.  Both move down by
   // 64 bytes per K step; the A window's misalignment (o & 3) is the lane's for every step.
   const int oA = D::PY + D::DP - 1 - 16 * g - c;
   const int aA = oA & ~3, sh = oA & 3;
-  int idx = 0;
-  for (int nt = 0; nt < ntiles; ++nt) {
-    const int lo = ks_lo(nt), cnt = ks_hi(nt) - lo + 1;
-    const int a = max(beg, idx), b = min(end, idx + cnt);
-    if (a < b) {
-      const uint8_t* pb = xd + D::PX + 16 * (16 * nt + c - g);
-      v4i acc = {0, 0, 0, 0};
-      // four K steps per round: all their operand reads are issued before the products
-      for (int q = a; q < b; q += 4) {
-        v4i af[4], bf[4];
+  const uint8_t* pb = xd + D::PX + 16 * (c - g);
+  v4i acc[NTL];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (q + j < b) {
-            const int ks = lo + q + j - idx;
-            const uint32_t* pa = reinterpret_cast<const uint32_t*>(yr + aA - 64 * ks);
-            const uint32_t y0 = pa[0], y1 = pa[1], y2 = pa[2], y3 = pa[3], y4 = pa[4];
-            af[j] = v4i{(int)__builtin_amdgcn_alignbyte(y1, y0, sh), (int)__builtin_amdgcn_alignbyte(y2, y1, sh),
-                        (int)__builtin_amdgcn_alignbyte(y3, y2, sh), (int)__builtin_amdgcn_alignbyte(y4, y3, sh)};
-            bf[j] = *reinterpret_cast<const v4i*>(pb - 64 * ks);
-          }
+  for (int nt = 0; nt < NTL; ++nt) acc[nt] = v4i{0, 0, 0, 0};
+  // operands of K step ks: the five words under the A window, and the NTL B blocks
+  auto load = [&](int ks, uint32_t (&y)[5], v4i (&bf)[NTL]) {
+    const uint32_t* pa = reinterpret_cast<const uint32_t*>(yr + aA - 64 * ks);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (q + j < b) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[j], bf[j], acc, 0, 0, 0);
-      }
-      // acc[e]: coefficient row 4 g + e of block 16 nt + c
-      int* dst = cf + 16 * (16 * nt + c) + 4 * g;
-      atomicAdd(dst + 0, acc[0]);
-      atomicAdd(dst + 1, acc[1]);
-      atomicAdd(dst + 2, acc[2]);
-      atomicAdd(dst + 3, acc[3]);
-    }
-    idx += cnt;
+    for (int i = 0; i < 5; ++i) y[i] = pa[i];
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) bf[nt] = *reinterpret_cast<const v4i*>(pb + 256 * nt - 64 * ks);
+  };
+  // the next K step's reads are in flight during this one's products
+  uint32_t y[5], yn[5];
+  v4i bf[NTL], bn[NTL];
+  if (ka < kb) load(ka, y, bf);
+  for (int ks = ka; ks < kb; ++ks) {
+    if (ks + 1 < kb) load(ks + 1, yn, bn);
+    const v4i af = v4i{(int)__builtin_amdgcn_alignbyte(y[1], y[0], sh), (int)__builtin_amdgcn_alignbyte(y[2], y[1], sh),
+                       (int)__builtin_amdgcn_alignbyte(y[3], y[2], sh), (int)__builtin_amdgcn_alignbyte(y[4], y[3], sh)};
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[nt], acc[nt], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) y[i] = yn[i];
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) bf[nt] = bn[nt];
   }
+  // acc[nt][e]: coefficient row 4 g + e of block 16 nt + c
+  int* dst = cf[wave] + 16 * c + 4 * g;
+#pragma unroll
+  for (int nt = 0; nt < D::NT; ++nt) *reinterpret_cast<v4i*>(dst + 256 * nt) = nt < NTL ? acc[nt < NTL ? nt : 0] : v4i{0, 0, 0, 0};
 }
 
 // Digits of sum_k cf[k] 128^k (+ the digits td for kModeU and kModeOut) for k < K (K = DP for kModeM, else
@@ -131,10 +131,11 @@ __device__ void mfma_product(const uint8_t* xd, const uint8_t* yr, int ulim, int
 //   kModeT: T's digits to td, and T mod R's to xb;   kModeM: m's digits to xb;
 //   kModeU: digits DP .. 2DP - 1 (U = (T + m M) / R) to xa and, reversed, to yr;
 //   kModeOut: the same U to xb.
-// Also clears `spare` (the other coefficient buffer).  Every thread; two barriers inside, the
-// first after the carry-outs are published, the second after the digits are written.
+// The coefficients are the sums of the four partials in L.cf.  Every thread; two barriers
+// inside, the first after the carry-outs are published, the second after the digits are
+// written.
 template <int S, int MODE>
-__device__ void normalize(UnpackLds<S>& L, const int* cf, int* spare) {
+__device__ void normalize(UnpackLds<S>& L) {
   using D = Dig<S>;
   constexpr int K = MODE == kModeM ? D::DP : 2 * D::DP;
   constexpr int RUN = D::RUN;
@@ -151,7 +152,9 @@ __device__ void normalize(UnpackLds<S>& L, const int* cf, int* spare) {
     for (int i = 0; i < RUN + 4; i += 4) {
       const int k = k0 - 4 + i;
       v4i v = v4i{0, 0, 0, 0};
-      if (k >= 0) v = *reinterpret_cast<const v4i*>(cf + k);
+      if (k >= 0)
+        v = *reinterpret_cast<const v4i*>(&L.cf[0][k]) + *reinterpret_cast<const v4i*>(&L.cf[1][k]) +
+            *reinterpret_cast<const v4i*>(&L.cf[2][k]) + *reinterpret_cast<const v4i*>(&L.cf[3][k]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) cv[i + j] = k + j < K ? (uint32_t)v[j] : 0u;
     }
@@ -187,10 +190,12 @@ __device__ void normalize(UnpackLds<S>& L, const int* cf, int* spare) {
   const unsigned long long G = __ballot(co0 != 0u), B = __ballot(co1 != 0u);
   const unsigned long long s1 = G + B;
   if (lane == 0) L.flag[wave] = (s1 < G ? 1u : 0u) | (s1 < G || s1 == ~0ull ? 2u : 0u);
-  for (int i = threadIdx.x; i < D::CF / 4; i += kThreads) reinterpret_cast<v4i*>(spare)[i] = v4i{0, 0, 0, 0};
   __syncthreads();
+  const v4i fl = *reinterpret_cast<const v4i*>(L.flag);
   uint32_t cw = 0;
-  for (int j = 0; j < wave; ++j) cw = (L.flag[j] >> cw) & 1u;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (j < wave) cw = ((uint32_t)fl[j] >> cw) & 1u;
   uint32_t cin = (uint32_t)((((s1 + cw) ^ G ^ B) >> lane) & 1ull);
   if (k0 < K) {
 #pragma unroll
@@ -224,26 +229,23 @@ __device__ void normalize(UnpackLds<S>& L, const int* cf, int* spare) {
 }
 
 // U = a b R^-1 (mod M, below 2M) for a = the chain value (digits in xa) and b given by its
-// reversed digits br; U goes to xa / yr (kModeU) or xb (kModeOut).  `buf` alternates the
-// coefficient buffers.
+// reversed digits br; U goes to xa / yr (kModeU) or xb (kModeOut).
 template <int S, int OUT>
-__device__ void mont_mul_wg(UnpackLds<S>& L, const uint8_t* br, int& buf) {
+__device__ void mont_mul_wg(UnpackLds<S>& L, const uint8_t* br) {
   using D = Dig<S>;
+  constexpr int kLowTiles = (D::NB + 15) / 16;
   // 1. T = a b
-  mfma_product<S>(L.xa, br, 2 * D::NB, L.cf[buf]);
+  mfma_product<S, D::NT>(L.xa, br, 2 * D::NB, L.cf);
   __syncthreads();
-  normalize<S, kModeT>(L, L.cf[buf], L.cf[buf ^ 1]);
-  buf ^= 1;
+  normalize<S, kModeT>(L);
   // 2. m = (T mod R) n' mod R
-  mfma_product<S>(L.xb, L.nr, D::NB, L.cf[buf]);
+  mfma_product<S, kLowTiles>(L.xb, L.nr, D::NB, L.cf);
   __syncthreads();
-  normalize<S, kModeM>(L, L.cf[buf], L.cf[buf ^ 1]);
-  buf ^= 1;
+  normalize<S, kModeM>(L);
   // 3. U = (T + m M) / R
-  mfma_product<S>(L.xb, L.mr, 2 * D::NB, L.cf[buf]);
+  mfma_product<S, D::NT>(L.xb, L.mr, 2 * D::NB, L.cf);
   __syncthreads();
-  normalize<S, OUT>(L, L.cf[buf], L.cf[buf ^ 1]);
-  buf ^= 1;
+  normalize<S, OUT>(L);
 }
 
 // Reversed digits (byte PY + DP - 1 - k holds digit k) from DP forward digits in global memory.
@@ -272,7 +274,6 @@ __global__ __launch_bounds__(kThreads) void unpack_chain_kernel(const uint8_t* _
     reinterpret_cast<uint32_t*>(lds.rr)[w] = 0u;
     reinterpret_cast<uint32_t*>(lds.one)[w] = 0u;
   }
-  for (int w = threadIdx.x; w < 2 * D::CF / 4; w += kThreads) reinterpret_cast<v4i*>(&lds.cf[0][0])[w] = v4i{0, 0, 0, 0};
   for (int w = threadIdx.x; w < D::XB / 16; w += kThreads) {
     reinterpret_cast<v4i*>(lds.xa)[w] = v4i{0, 0, 0, 0};
     reinterpret_cast<v4i*>(lds.xb)[w] = v4i{0, 0, 0, 0};
@@ -298,13 +299,12 @@ __global__ __launch_bounds__(kThreads) void unpack_chain_kernel(const uint8_t* _
   load_reversed<S>(cdig + 2 * D::DP, lds.rr);
   if (threadIdx.x == 0) lds.one[D::PY + D::DP - 1] = 1;
   __syncthreads();
-  int buf = 0;
-  mont_mul_wg<S, kModeU>(lds, lds.rr, buf);  // Montgomery form: pck R mod M (below 2M)
+  mont_mul_wg<S, kModeU>(lds, lds.rr);  // Montgomery form: pck R mod M (below 2M)
   for (int j = t - 1; j >= 0; --j) {
     const int k = i * t + j;
     if (k < n) {
       // key k = X R^-1 mod M (below M) via a product with 1, its digits in xb, then as words
-      mont_mul_wg<S, kModeOut>(lds, lds.one, buf);
+      mont_mul_wg<S, kModeOut>(lds, lds.one);
       for (int w = threadIdx.x; w < L; w += kThreads) {
         const int kb = (32 * w) / 7, ke = min((32 * w + 31) / 7, D::DP - 1);
         unsigned long long acc = 0;
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kThreads) void unpack_chain_kernel(const uint8_t* _
       __syncthreads();
     }
     if (j > 0)
-      for (int sq = 0; sq < dbits; ++sq) mont_mul_wg<S, kModeU>(lds, lds.yr, buf);
+      for (int sq = 0; sq < dbits; ++sq) mont_mul_wg<S, kModeU>(lds, lds.yr);
   }
 }
 
