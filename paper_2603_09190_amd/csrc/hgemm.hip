@@ -255,7 +255,9 @@ void hgemm_kernel(const uint8_t* __restrict__ D, int rows, int cols, int pitch, 
 // Each slice stages 16 A and 16 B kilobytes as before, four loads per wavefront; the epilogue
 // parks one row tile at a time in the wavefront's 8 KiB of LDS and lanes 32 h + c build column c
 // of the half's 32 for rows h, h + 2, ..., so every store writes 128 contiguous bytes of a row.
-template <int NS, bool kTiled>
+// kPair: the slice loop software-pipelined over two register sets (NS = 4), described at the
+// loop.
+template <int NS, bool kTiled, bool kPair = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void hgemm_w8_kernel(const uint8_t* __restrict__ D, int rows, int cols, int pitch, const uint8_t* __restrict__ Apt,
                      int n, int npad, const int32_t* __restrict__ Acolsum, const int32_t* __restrict__ rowsum,
@@ -318,14 +320,8 @@ void hgemm_w8_kernel(const uint8_t* __restrict__ D, int rows, int cols, int pitc
 #pragma unroll
     for (int t = 0; t < 8; ++t) acc[i][t] = v4i{0, 0, 0, 0};
 
-#pragma unroll
-  for (int p = 0; p < NS - 1; ++p) issue(p);
   const int aread = (r * 4 + g) * 16;  // where the MFMA's lane (g, r) finds row r, bytes 16 g
-  for (int p = 0; p < S; ++p) {
-    wait_vmcnt<(NS - 2) * kPerWave>();
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-    issue(p + NS - 1);
+  auto compute = [&](int p) {
     const uint8_t* base = lds + (p % NS) * kStage;
     v4i bf[8];
 #pragma unroll
@@ -338,6 +334,66 @@ void hgemm_w8_kernel(const uint8_t* __restrict__ D, int rows, int cols, int pitc
       const v4i af = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
 #pragma unroll
       for (int t = 0; t < 8; ++t) acc[i][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[t], acc[i][t], 0, 0, 0);
+    }
+  };
+  if constexpr (kPair) {
+    // Operands of slice p + 1 are read from LDS into a second register set while the MFMAs of
+    // slice p run, so that a wavefront's LDS reads overlap its own products; the barrier of a
+    // slice therefore comes one slice earlier (slice p + 1 must have landed before its reads),
+    // and four buffers keep the one being overwritten (slice p - 1) consumed.
+    static_assert(NS == 4, "the pipelined loop uses four buffers");
+    v4i b0[8], b1[8];
+    u32x4 a0[4], a1[4];
+    auto load_regs = [&](int p, v4i (&bf)[8], u32x4 (&af)[4]) {
+      const uint8_t* base = lds + (p % NS) * kStage;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        bf[t] = *reinterpret_cast<const v4i*>(base + (kAChunks + 8 * wc + t) * 1024 + lane * 16);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const u32x4*>(base + (wr * 4 + i) * 1024 + aread);
+    };
+    auto mfma_regs = [&](const v4i (&bf)[8], const u32x4 (&af)[4]) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const u32x4 v = af[i] ^ 0x80808080u;
+        const v4i a = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[i][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bf[t], acc[i][t], 0, 0, 0);
+      }
+    };
+    auto sync_slice = [&]() {
+      wait_vmcnt<kPerWave>();
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    };
+    issue(0);
+    issue(1);
+    issue(2);
+    wait_vmcnt<2 * kPerWave>();
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    load_regs(0, b0, a0);
+    for (int p = 0; p < S; p += 2) {
+      sync_slice();  // slice p + 1 landed; slice p - 1's buffer consumed by every wavefront
+      issue(p + 3);
+      load_regs(p + 1, b1, a1);
+      mfma_regs(b0, a0);
+      if (p + 1 < S) {
+        sync_slice();
+        issue(p + 4);
+        load_regs(p + 2, b0, a0);
+        mfma_regs(b1, a1);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < NS - 1; ++p) issue(p);
+    for (int p = 0; p < S; ++p) {
+      wait_vmcnt<(NS - 2) * kPerWave>();
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+      issue(p + NS - 1);
+      compute(p);
     }
   }
   wait_vmcnt<0>();  // the surplus loads past the last slice write LDS the epilogue reuses
@@ -382,9 +438,9 @@ void hgemm_w8_kernel(const uint8_t* __restrict__ D, int rows, int cols, int pitc
 }
 
 struct HVariant {
-  int mr, ns;  // mr 0: the eight-wavefront kernel
+  int mr, ns;  // mr 0: the eight-wavefront kernel; mr 1: the same with its LDS reads pipelined
 };
-static const HVariant kHVariants[] = {{4, 4}, {4, 3}, {2, 4}, {2, 3}, {0, 3}, {0, 4}};
+static const HVariant kHVariants[] = {{4, 4}, {4, 3}, {2, 4}, {2, 3}, {0, 3}, {0, 4}, {1, 4}};
 
 int hgemm_variants() { return (int)(sizeof(kHVariants) / sizeof(kHVariants[0])); }
 
@@ -408,7 +464,7 @@ void launch_hgemm(const uint8_t* D, bool tiled, int rows, int cols, int pitch, c
                   const int32_t* Acolsum, const int32_t* rowsum, uint32_t* H, int variant, hipStream_t s) {
   if (rows <= 0 || n <= 0) return;
   const HVariant v = kHVariants[(variant >= 0 && variant < hgemm_variants()) ? variant : 0];
-  if (v.mr == 0) {
+  if (v.mr == 0 || v.mr == 1) {
     const int npad = hgemm_npad(n);
     const int nrb = (rows + 255) / 256;
     const int ncb = npad / kHCols;
@@ -416,7 +472,12 @@ void launch_hgemm(const uint8_t* D, bool tiled, int rows, int cols, int pitch, c
     const long long rounds = ((long long)nsr * nsc + 7) / 8;
     const unsigned nblocks = (unsigned)(rounds * 8 * kHSR * kHSC);
 #define ZP_H8(N, T) hgemm_w8_kernel<N, T><<<nblocks, 512, 0, s>>>(D, rows, cols, pitch, Apt, n, npad, Acolsum, rowsum, H, nrb, ncb)
-    if (v.ns == 3) {
+    if (v.mr == 1) {
+      if (tiled)
+        hgemm_w8_kernel<4, true, true><<<nblocks, 512, 0, s>>>(D, rows, cols, pitch, Apt, n, npad, Acolsum, rowsum, H, nrb, ncb);
+      else
+        hgemm_w8_kernel<4, false, true><<<nblocks, 512, 0, s>>>(D, rows, cols, pitch, Apt, n, npad, Acolsum, rowsum, H, nrb, ncb);
+    } else if (v.ns == 3) {
       if (tiled) ZP_H8(3, true); else ZP_H8(3, false);
     } else {
       if (tiled) ZP_H8(4, true); else ZP_H8(4, false);
