@@ -191,9 +191,10 @@ __device__ __forceinline__ void rn_redc_step(RNum<P>& t, uint64_t& c, const RNum
   uint32_t carry = 0;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const uint64_t x = (uint64_t)q * m.v[j] + t.v[j] + carry;
-    t.v[j] = (uint32_t)x;
-    carry = (uint32_t)(x >> 32);
+    const uint64_t x = (uint64_t)q * m.v[j] + t.v[j];
+    unsigned int c1;
+    t.v[j] = __builtin_addc((uint32_t)x, carry, 0u, &c1);
+    carry = (uint32_t)(x >> 32) + c1;
   }
   c += carry;
   const uint32_t up = row_from_next(t.v[0]);
@@ -210,9 +211,10 @@ __device__ __forceinline__ void rn_mont_step(RNum<P>& t, uint64_t& c, uint32_t a
   uint32_t carry = 0;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const uint64_t x = (uint64_t)ai * b.v[j] + t.v[j] + carry;
-    t.v[j] = (uint32_t)x;
-    carry = (uint32_t)(x >> 32);
+    const uint64_t x = (uint64_t)ai * b.v[j] + t.v[j];
+    unsigned int c1;
+    t.v[j] = __builtin_addc((uint32_t)x, carry, 0u, &c1);
+    carry = (uint32_t)(x >> 32) + c1;
   }
   c += carry;
   rn_redc_step(t, c, m, mprime);
