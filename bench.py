@@ -58,24 +58,30 @@ STEP_TRAFFIC = {"84ad8428d96d552e": 1076585960}
 #     SQ_INSTS_VALU_INT64 and SQ_INSTS_VALU_INT32 in SQ_INSTS_VALU.
 COUNTERS = {
     "gemm_i8.hip": {"629d2dbca623b53d": {"kernel": "gemm_planes_kernel<8, 2, 2, 256, 4, false, true>",
-                                         "mfma_busy_frac": 0.301}},
-    "hgemm.hip": {"5ccb5e2a713d9050": {"kernel": "hgemm_w8_kernel<4, true>", "mfma_busy_frac": 0.555}},
-    "offset.hip": {"7010379a06e6184e": {"kernel": "offset_gemm_kernel<5, 4, 3>", "mfma_busy_frac": 0.290}},
-    "hint.hip": {"eaca529d7b991e6c": {"kernel": "hint_rows_quad_kernel<2>", "valu_insts_per_simd_cycle": 0.324,
-                                      "int64_share_of_valu": 0.447, "int32_share_of_valu": 0.017}},
-    "lwec.hip": {"58b66fd162a18100": {"kernel": "compress_lwe_quad_kernel<3>", "valu_insts_per_simd_cycle": 0.298,
-                                      "int64_share_of_valu": 0.460, "int32_share_of_valu": 0.012}},
+                                         "mfma_busy_frac": 0.300}},
+    "hgemm.hip": {"dbb3df29fd3d6f3c": {"kernel": "hgemm_w8_kernel<4, true, true>", "mfma_busy_frac": 0.681}},
+    "offset.hip": {"7010379a06e6184e": {"kernel": "offset_gemm_kernel<5, 4, 3>", "mfma_busy_frac": 0.291}},
+    "hint.hip": {"228424c8ab17600b": {"kernel": "hint_rows_quad_kernel<2>", "valu_insts_per_simd_cycle": 0.323,
+                                      "int64_share_of_valu": 0.267, "int32_share_of_valu": 0.407}},
+    "lwec.hip": {"48d5a64197984e83": {"kernel": "compress_lwe_quad_kernel<3>", "valu_insts_per_simd_cycle": 0.294,
+                                      "int64_share_of_valu": 0.261, "int32_share_of_valu": 0.435}},
 }
 
 
+# Headers whose code the counted kernels of a source compile in: their text joins the key.
+COUNTER_DEPS = {"hint.hip": ("rownum.h", "wavenum.h"), "lwec.hip": ("rownum.h", "wavenum.h")}
+
+
 def counters(name: str):
-    return COUNTERS.get(name, {}).get(source_hash(name))
+    return COUNTERS.get(name, {}).get(source_hash(name, *COUNTER_DEPS.get(name, ())))
 
 
-def source_hash(name: str) -> str:
+def source_hash(name: str, *deps: str) -> str:
     import hashlib
-    path = os.path.join(ROOT, "paper_2603_09190_amd", "csrc", name)
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in (name, *deps):
+        h.update(open(os.path.join(ROOT, "paper_2603_09190_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def timed_ms(fn, reps: int) -> float:

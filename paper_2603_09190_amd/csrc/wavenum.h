@@ -189,9 +189,10 @@ __device__ __forceinline__ void redc_step(WNum<P>& t, uint64_t& c, const WNum<P>
   uint32_t carry = 0;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    uint64_t x = (uint64_t)q * m.v[j] + t.v[j] + carry;
-    t.v[j] = (uint32_t)x;
-    carry = (uint32_t)(x >> 32);
+    const uint64_t x = (uint64_t)q * m.v[j] + t.v[j];
+    unsigned int c1;
+    t.v[j] = __builtin_addc((uint32_t)x, carry, 0u, &c1);
+    carry = (uint32_t)(x >> 32) + c1;
   }
   c += carry;
   // lane 0's limb 0 is now zero: shift the whole number down one limb
@@ -211,9 +212,10 @@ __device__ __forceinline__ void mont_step(WNum<P>& t, uint64_t& c, uint32_t ai, 
   uint32_t carry = 0;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    uint64_t x = (uint64_t)ai * b.v[j] + t.v[j] + carry;
-    t.v[j] = (uint32_t)x;
-    carry = (uint32_t)(x >> 32);
+    const uint64_t x = (uint64_t)ai * b.v[j] + t.v[j];
+    unsigned int c1;
+    t.v[j] = __builtin_addc((uint32_t)x, carry, 0u, &c1);
+    carry = (uint32_t)(x >> 32) + c1;
   }
   c += carry;
   redc_step(t, c, m, mprime);
