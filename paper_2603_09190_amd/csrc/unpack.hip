@@ -5,28 +5,28 @@
 // A chain cannot be split: squaring is the whole work and step k needs step k-1.  So each step,
 // one Montgomery product modulo M = N^2, is spread over a workgroup of 256 threads, and a chain
 // runs on one workgroup.  Its latency is what counts, so the chain stays in one representation:
-//   - a residue is DP = unpack_digits(S) digits of 7 bits (each a non-negative int8), and the
-//     Montgomery radix is R = 128^DP > 4M.  Products are then only reduced lazily: for a, b < 2M,
-//     U = (a b + m M) / R < (4M^2 + R M) / R < 2M, so no final subtraction is needed along the
-//     chain, and a last product with 1 lands below M;
-//   - the three multiprecision products (a b; m = (a b mod R) n' mod R with n' = -M^-1 mod R;
-//     m M) run on the int8 matrix cores.  The digit coefficients c_k = sum_i x_i y_(k-i) are a
-//     matrix product: with k = 16 u + r and i = 16 v + s, c_(16u+r) = sum_w sum_s Y_w[r][s] X[s][u-w],
-//     Y_w[r][s] = y_(16w+r-s) a 16 x 16 Toeplitz block of y and X[s][v] = x_(16v+s) x's v-th
-//     16-digit block.  One v_mfma_i32_16x16x64_i8 covers 16 coefficient rows r, 16 blocks u and
-//     four w's along K: its A operand (lane: row r, one w) is 16 consecutive bytes of y's digits
-//     stored in reverse, read at a byte offset and aligned with v_alignbyte; its B operand (lane:
-//     column u, one w) is one aligned 16-digit block of x.  The K steps are split evenly among
-//     the four wavefronts, each runs every column tile in its K steps (pairs with zero operands
-//     read zero padding, which costs less than branching around them), so a wavefront reads
-//     each A operand once for all column tiles, and each writes its partial coefficients to LDS;
-//   - coefficients (below 2^25) become digits in one pass: thread l takes a run of RUN digits,
-//     folds each coefficient's four 7-bit pieces into the digits above it (sums below 2^10) and
-//     once more (digits at most 131), so that a carry-lookahead finishes: a run carries out
-//     with c_in = 0 (G) or with c_in = 1 (G | P), the carries into the runs of a wavefront are
-//     the internal carries of the 64-bit addition G + (G | P) + c_in, i.e.
-//     (G + (G | P) + c_in) ^ G ^ (G | P) over ballots, and each wavefront's own carry-outs go
-//     through LDS to the wavefronts above.
+//   - a residue is DP = unpack_digits(S) balanced 7-bit digits d_k in [-64, 64] (int8), value
+//     sum d_k 128^k, possibly negative, and the Montgomery radix is R = 128^DP > 4M.  With
+//     |a|, |b| < M, T = a b, m = (T mod R) n' taken as the balanced low DP digits of T n'
+//     (|m| < 0.51 R, m = -T M^-1 mod R) and n' = -M^-1 mod R, the value T + m M is a multiple of R
+//     whose low DP balanced digits have a value below R / 2 in magnitude, so they sum to exactly
+//     zero and U = (T + m M) / R is the high DP digits, with |U| < M^2 / R + 0.51 M < M.  The chain
+//     needs no carry propagation and no subtraction; only a key written out is made canonical
+//     (its words, plus M when negative);
+//   - the three multiprecision products (a b; T n'; m M) run on the int8 matrix cores.  The
+//     digit coefficients c_k = sum_i x_i y_(k-i) are a matrix product: with k = 16 u + r and
+//     i = 16 v + s, c_(16u+r) = sum_w sum_s Y_w[r][s] X[s][u-w], Y_w[r][s] = y_(16w+r-s) a 16 x 16
+//     Toeplitz block of y and X[s][v] = x_(16v+s) x's v-th 16-digit block.  One
+//     v_mfma_i32_16x16x64_i8 covers 16 coefficient rows r, 16 blocks u and four w's along K: its
+//     A operand (lane: row r, one w) is 16 consecutive bytes of y's digits stored in reverse,
+//     read at a byte offset and aligned with v_alignbyte; its B operand (lane: column u, one w)
+//     is one aligned 16-digit block of x.  The K steps are split evenly among the four
+//     wavefronts, each runs every column tile in its K steps (pairs with zero operands read zero
+//     padding, which costs less than branching around them), so a wavefront reads each A operand
+//     once for all column tiles, and each writes its partial coefficients to LDS;
+//   - coefficients (magnitude below 2^25) become balanced digits locally: each digit depends on
+//     the coefficients at most five places below it, so each thread turns its own run of
+//     digits around with no exchange (see normalize).
 #include "internal.h"
 
 namespace zp {
@@ -70,7 +70,8 @@ struct UnpackLds {
   alignas(16) uint8_t rr[D::RB];       // reversed digits of R^2 mod M
   alignas(16) uint8_t one[D::RB];      // reversed digits of 1
   uint32_t X[S];                       // packed ciphertext words
-  alignas(16) uint32_t flag[4];        // wavefront carry-outs
+  uint32_t Mw[S];                      // M's words
+  uint32_t ow[S + 2];                  // a key entry's words
 };
 
 // Digit coefficients of x y for the 16-digit blocks u < ulim (NTL = ceil(ulim / 16) column
@@ -126,110 +127,92 @@ __device__ void mfma_product(const uint8_t* xd, const uint8_t* yr, int ulim, int
   for (int nt = 0; nt < D::NT; ++nt) *reinterpret_cast<v4i*>(dst + 256 * nt) = nt < NTL ? acc[nt < NTL ? nt : 0] : v4i{0, 0, 0, 0};
 }
 
-// Digits of sum_k cf[k] 128^k (+ the digits td for kModeU and kModeOut) for k < K (K = DP for kModeM, else
-// 2 DP; the carry out of digit K - 1 is dropped), written where MODE says:
+// Balanced digits of sum_k c_k 128^k (c_k the sum of the four partials in L.cf, plus the digits
+// td for kModeU and kModeOut) for k < K (K = DP for kModeM, else 2 DP; what lies above is
+// dropped), written where MODE says:
 //   kModeT: T's digits to td, and T mod R's to xb;   kModeM: m's digits to xb;
 //   kModeU: digits DP .. 2DP - 1 (U = (T + m M) / R) to xa and, reversed, to yr;
 //   kModeOut: the same U to xb.
-// The coefficients are the sums of the four partials in L.cf.  Every thread; two barriers
-// inside, the first after the carry-outs are published, the second after the digits are
-// written.
+// Each digit is found from the coefficients at most five places below it, so every thread
+// works alone on its run: e_k takes the 7-bit pieces of c_k, c_(k-1), c_(k-2) and c_(k-3) that
+// land on digit k (with c_k below 2^25 in magnitude, e_k is in [-73, 454]); f_k = (e_k mod 128)
+// + floor(e_(k-1) / 128) is in [-1, 130] and sum f_k 128^k equals the value; and
+// d_k = f_k - 128 g_k + g_(k-1) with g_k = [f_k >= 64] is in [-64, 64].  Every thread; no barrier
+// inside.
 template <int S, int MODE>
 __device__ void normalize(UnpackLds<S>& L) {
   using D = Dig<S>;
   constexpr int K = MODE == kModeM ? D::DP : 2 * D::DP;
   constexpr int RUN = D::RUN;
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int k0 = RUN * threadIdx.x;
-  uint32_t f[RUN];
-  uint32_t co0 = 0, co1 = 0;
+  if (k0 >= K) return;
+  // c_(k0-8) .. c_(k0+RUN-1); below 0 there is nothing
+  int cv[RUN + 8];
 #pragma unroll
-  for (int i = 0; i < RUN; ++i) f[i] = 0;
-  if (k0 < K) {
-    // c_(k0-4) .. c_(k0+RUN-1), zero outside [0, K)
-    uint32_t cv[RUN + 4];
+  for (int i = 0; i < RUN + 8; i += 4) {
+    const int k = k0 - 8 + i;
+    v4i v = v4i{0, 0, 0, 0};
+    if (k >= 0)
+      v = *reinterpret_cast<const v4i*>(&L.cf[0][k]) + *reinterpret_cast<const v4i*>(&L.cf[1][k]) +
+          *reinterpret_cast<const v4i*>(&L.cf[2][k]) + *reinterpret_cast<const v4i*>(&L.cf[3][k]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cv[i + j] = v[j];
+  }
+  // e_k for k = k0 - 2 .. k0 + RUN - 1 (index k - k0 + 2); c_k is cv[k - k0 + 8]
+  int e[RUN + 2];
+#pragma unroll
+  for (int i = 0; i < RUN + 2; ++i) {
+    const int b = i + 6;  // c_(k0 - 2 + i)
+    e[i] = (cv[b] & 127) + ((cv[b - 1] >> 7) & 127) + ((cv[b - 2] >> 14) & 127) + (cv[b - 3] >> 21);
+  }
+  if (MODE == kModeU || MODE == kModeOut) {
+    // T's digits k0 - 4 .. k0 + RUN - 1 (signed bytes), added to e for k >= k0 - 2
 #pragma unroll
     for (int i = 0; i < RUN + 4; i += 4) {
       const int k = k0 - 4 + i;
-      v4i v = v4i{0, 0, 0, 0};
-      if (k >= 0)
-        v = *reinterpret_cast<const v4i*>(&L.cf[0][k]) + *reinterpret_cast<const v4i*>(&L.cf[1][k]) +
-            *reinterpret_cast<const v4i*>(&L.cf[2][k]) + *reinterpret_cast<const v4i*>(&L.cf[3][k]);
+      if (k >= 0 && k < 2 * D::DP) {
+        const uint32_t dw = *reinterpret_cast<const uint32_t*>(L.td + k);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) cv[i + j] = k + j < K ? (uint32_t)v[j] : 0u;
-    }
-    // e_k for k = k0 - 1 .. k0 + RUN - 1: the 7-bit pieces of c_k, c_(k-1), c_(k-2), c_(k-3) that
-    // land on digit k (at most 3 127 + 15, plus a digit of T)
-    uint32_t e[RUN + 1];
-#pragma unroll
-    for (int i = 0; i <= RUN; ++i)
-      e[i] = (cv[i + 3] & 127u) + ((cv[i + 2] >> 7) & 127u) + ((cv[i + 1] >> 14) & 127u) + (cv[i] >> 21);
-    if (MODE == kModeU || MODE == kModeOut) {
-#pragma unroll
-      for (int i = 0; i < RUN + 4; i += 4) {
-        const int k = k0 - 4 + i;
-        if (k >= 0 && k < 2 * D::DP) {
-          const uint32_t dw = *reinterpret_cast<const uint32_t*>(L.td + k);
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (i + j >= 3) e[i + j - 3] += (dw >> (8 * j)) & 0xFFu;
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < RUN; ++i) f[i] = (e[i + 1] & 127u) + (e[i] >> 7);  // <= 131
-    uint32_t c0 = 0, c1 = 1;
-#pragma unroll
-    for (int i = 0; i < RUN; ++i) {
-      c0 = (f[i] + c0) >> 7;
-      c1 = (f[i] + c1) >> 7;
-    }
-    co0 = c0;
-    co1 = c1;
-  }
-  const unsigned long long G = __ballot(co0 != 0u), B = __ballot(co1 != 0u);
-  const unsigned long long s1 = G + B;
-  if (lane == 0) L.flag[wave] = (s1 < G ? 1u : 0u) | (s1 < G || s1 == ~0ull ? 2u : 0u);
-  __syncthreads();
-  const v4i fl = *reinterpret_cast<const v4i*>(L.flag);
-  uint32_t cw = 0;
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-    if (j < wave) cw = ((uint32_t)fl[j] >> cw) & 1u;
-  uint32_t cin = (uint32_t)((((s1 + cw) ^ G ^ B) >> lane) & 1ull);
-  if (k0 < K) {
-#pragma unroll
-    for (int i = 0; i < RUN; i += 4) {
-      uint32_t dw = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t sv = f[i + j] + cin;
-        dw |= (sv & 127u) << (8 * j);
-        cin = sv >> 7;
-      }
-      const int k = k0 + i;
-      if (k >= K) continue;
-      if (MODE == kModeT) {
-        *reinterpret_cast<uint32_t*>(L.td + k) = dw;
-        if (k < D::DP) *reinterpret_cast<uint32_t*>(L.xb + D::PX + k) = dw;
-      } else if (MODE == kModeM) {
-        *reinterpret_cast<uint32_t*>(L.xb + D::PX + k) = dw;
-      } else if (k >= D::DP) {
-        const int j = k - D::DP;
-        if (MODE == kModeU) {
-          *reinterpret_cast<uint32_t*>(L.xa + D::PX + j) = dw;
-          *reinterpret_cast<uint32_t*>(L.yr + D::PY + D::DP - 4 - j) = __builtin_bswap32(dw);
-        } else {
-          *reinterpret_cast<uint32_t*>(L.xb + D::PX + j) = dw;
-        }
+        for (int j = 0; j < 4; ++j)
+          if (i + j >= 2) e[i + j - 2] += (int)(int8_t)(uint8_t)(dw >> (8 * j));
       }
     }
   }
-  __syncthreads();
+  // f_k for k = k0 - 1 .. k0 + RUN - 1 (index k - k0 + 1), then the balanced digits
+  int f[RUN + 1];
+#pragma unroll
+  for (int i = 0; i < RUN + 1; ++i) f[i] = (e[i + 1] & 127) + (e[i] >> 7);
+  if (k0 == 0) f[0] = 0;  // no digit below 0
+#pragma unroll
+  for (int i = 0; i < RUN; i += 4) {
+    uint32_t dw = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int fk = f[i + j + 1], fp = f[i + j];
+      const int d = fk - (fk >= 64 ? 128 : 0) + (fp >= 64 ? 1 : 0);
+      dw |= (uint32_t)(uint8_t)(int8_t)d << (8 * j);
+    }
+    const int k = k0 + i;
+    if (k >= K) continue;
+    if (MODE == kModeT) {
+      *reinterpret_cast<uint32_t*>(L.td + k) = dw;
+      if (k < D::DP) *reinterpret_cast<uint32_t*>(L.xb + D::PX + k) = dw;
+    } else if (MODE == kModeM) {
+      *reinterpret_cast<uint32_t*>(L.xb + D::PX + k) = dw;
+    } else if (k >= D::DP) {
+      const int j = k - D::DP;
+      if (MODE == kModeU) {
+        *reinterpret_cast<uint32_t*>(L.xa + D::PX + j) = dw;
+        *reinterpret_cast<uint32_t*>(L.yr + D::PY + D::DP - 4 - j) = __builtin_bswap32(dw);
+      } else {
+        *reinterpret_cast<uint32_t*>(L.xb + D::PX + j) = dw;
+      }
+    }
+  }
 }
 
-// U = a b R^-1 (mod M, below 2M) for a = the chain value (digits in xa) and b given by its
-// reversed digits br; U goes to xa / yr (kModeU) or xb (kModeOut).
+// U = a b R^-1 (mod M) for a = the chain value (digits in xa) and b given by its reversed digits
+// br, with |U| < M when |a|, |b| < M; U goes to xa / yr (kModeU) or xb (kModeOut).
 template <int S, int OUT>
 __device__ void mont_mul_wg(UnpackLds<S>& L, const uint8_t* br) {
   using D = Dig<S>;
@@ -238,14 +221,18 @@ __device__ void mont_mul_wg(UnpackLds<S>& L, const uint8_t* br) {
   mfma_product<S, D::NT>(L.xa, br, 2 * D::NB, L.cf);
   __syncthreads();
   normalize<S, kModeT>(L);
-  // 2. m = (T mod R) n' mod R
+  __syncthreads();
+  // 2. m = (T mod R) n' mod R, up to a multiple of R (|m| < 0.51 R)
   mfma_product<S, kLowTiles>(L.xb, L.nr, D::NB, L.cf);
   __syncthreads();
   normalize<S, kModeM>(L);
-  // 3. U = (T + m M) / R
+  __syncthreads();
+  // 3. U = (T + m M) / R: in balanced digits the low DP digits of T + m M sum to exactly zero
+  //    (their value is a multiple of R below R / 2 in magnitude), so U is the high half
   mfma_product<S, D::NT>(L.xb, L.mr, 2 * D::NB, L.cf);
   __syncthreads();
   normalize<S, OUT>(L);
+  __syncthreads();
 }
 
 // Reversed digits (byte PY + DP - 1 - k holds digit k) from DP forward digits in global memory.
@@ -260,13 +247,17 @@ __device__ void load_reversed(const uint8_t* dig, uint8_t* rev) {
 // One workgroup per packed ciphertext i: keys i t + t - 1, i t + t - 2, ..., i t (those below n),
 // stopping to write each after dbits further squarings.
 template <int S>
-__global__ __launch_bounds__(kThreads) void unpack_chain_kernel(const uint8_t* __restrict__ cdig,
+__global__ __launch_bounds__(kThreads) void unpack_chain_kernel(const uint32_t* __restrict__ M,
+                                                                const uint8_t* __restrict__ cdig,
                                                                 const uint32_t* __restrict__ pck, int n, int t,
                                                                 int dbits, int L, uint32_t* __restrict__ ck) {
   __shared__ UnpackLds<S> lds;
   using D = Dig<S>;
   const int i = blockIdx.x;
-  for (int w = threadIdx.x; w < S; w += kThreads) lds.X[w] = w < L ? pck[(size_t)i * L + w] : 0u;
+  for (int w = threadIdx.x; w < S; w += kThreads) {
+    lds.X[w] = w < L ? pck[(size_t)i * L + w] : 0u;
+    lds.Mw[w] = M[w];
+  }
   for (int w = threadIdx.x; w < D::RB / 4; w += kThreads) {
     reinterpret_cast<uint32_t*>(lds.yr)[w] = 0u;
     reinterpret_cast<uint32_t*>(lds.nr)[w] = 0u;
@@ -299,18 +290,42 @@ __global__ __launch_bounds__(kThreads) void unpack_chain_kernel(const uint8_t* _
   load_reversed<S>(cdig + 2 * D::DP, lds.rr);
   if (threadIdx.x == 0) lds.one[D::PY + D::DP - 1] = 1;
   __syncthreads();
-  mont_mul_wg<S, kModeU>(lds, lds.rr);  // Montgomery form: pck R mod M (below 2M)
+  mont_mul_wg<S, kModeU>(lds, lds.rr);  // Montgomery form: pck R mod M (magnitude below M)
   for (int j = t - 1; j >= 0; --j) {
     const int k = i * t + j;
     if (k < n) {
-      // key k = X R^-1 mod M (below M) via a product with 1, its digits in xb, then as words
+      // key k: X R^-1 (magnitude below 0.51 M) via a product with 1, its balanced digits in xb;
+      // as words: partial sums per word (digits starting in it, 64-bit, in the coefficient
+      // buffer, free until the next product), then one thread propagates the carries over
+      // S + 2 two's-complement words and adds M when the value is negative
       mont_mul_wg<S, kModeOut>(lds, lds.one);
-      for (int w = threadIdx.x; w < L; w += kThreads) {
-        const int kb = (32 * w) / 7, ke = min((32 * w + 31) / 7, D::DP - 1);
-        unsigned long long acc = 0;
-        for (int kk = ke; kk >= kb; --kk) acc = (acc << 7) | lds.xb[D::PX + kk];
-        ck[(size_t)k * L + w] = (uint32_t)(acc >> (32 * w - 7 * kb));
+      long long* pw = reinterpret_cast<long long*>(&lds.cf[0][0]);
+      for (int w = threadIdx.x; w < S + 2; w += kThreads) {
+        const int kb = (32 * w + 6) / 7, ke = min((32 * w + 31) / 7, D::DP - 1);
+        long long acc = 0;
+        for (int kk = kb; kk <= ke; ++kk)
+          acc += (long long)(int8_t)lds.xb[D::PX + kk] * (1LL << (7 * kk - 32 * w));
+        pw[w] = acc;
       }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        long long c = 0;
+        for (int w = 0; w < S + 2; ++w) {
+          const long long v = pw[w] + c;
+          lds.ow[w] = (uint32_t)v;
+          c = v >> 32;
+        }
+        if ((int32_t)lds.ow[S + 1] < 0) {
+          unsigned long long cy = 0;
+          for (int w = 0; w < S; ++w) {
+            const unsigned long long v = (unsigned long long)lds.ow[w] + lds.Mw[w] + cy;
+            lds.ow[w] = (uint32_t)v;
+            cy = v >> 32;
+          }
+        }
+      }
+      __syncthreads();
+      for (int w = threadIdx.x; w < L; w += kThreads) ck[(size_t)k * L + w] = lds.ow[w];
       __syncthreads();
     }
     if (j > 0)
@@ -325,10 +340,10 @@ void launch_unpack_chains(const ClientDev& cd, const uint8_t* cdig, const uint32
   if (n <= 0) return;
   const int groups = (n + t - 1) / t;
   switch (cd.P) {
-    case 1: unpack_chain_kernel<64><<<groups, kThreads, 0, s>>>(cdig, pck, n, t, dbits, cd.L, ck); break;
-    case 2: unpack_chain_kernel<128><<<groups, kThreads, 0, s>>>(cdig, pck, n, t, dbits, cd.L, ck); break;
-    case 3: unpack_chain_kernel<192><<<groups, kThreads, 0, s>>>(cdig, pck, n, t, dbits, cd.L, ck); break;
-    case 4: unpack_chain_kernel<256><<<groups, kThreads, 0, s>>>(cdig, pck, n, t, dbits, cd.L, ck); break;
+    case 1: unpack_chain_kernel<64><<<groups, kThreads, 0, s>>>(cd.N2, cdig, pck, n, t, dbits, cd.L, ck); break;
+    case 2: unpack_chain_kernel<128><<<groups, kThreads, 0, s>>>(cd.N2, cdig, pck, n, t, dbits, cd.L, ck); break;
+    case 3: unpack_chain_kernel<192><<<groups, kThreads, 0, s>>>(cd.N2, cdig, pck, n, t, dbits, cd.L, ck); break;
+    case 4: unpack_chain_kernel<256><<<groups, kThreads, 0, s>>>(cd.N2, cdig, pck, n, t, dbits, cd.L, ck); break;
   }
 }
 
