@@ -172,9 +172,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(rows of D, H and K shard across GPUs with only a query broadcast and a result gather, "
-              "but that path is not built).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs on "
+              "one GPU (rows of D, H and K would shard across GPUs with only a query broadcast and a "
+              "result gather, a path that does not exist here).", file=sys.stderr)
         return 2
 
     import torch
