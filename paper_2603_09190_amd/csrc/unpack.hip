@@ -20,10 +20,9 @@
 //     v_mfma_i32_16x16x64_i8 covers 16 coefficient rows r, 16 blocks u and four w's along K: its
 //     A operand (lane: row r, one w) is 16 consecutive bytes of y's digits stored in reverse,
 //     read at a byte offset and aligned with v_alignbyte; its B operand (lane: column u, one w)
-//     is one aligned 16-digit block of x.  The K steps are split evenly among the four
-//     wavefronts, each runs every column tile in its K steps (pairs with zero operands read zero
-//     padding, which costs less than branching around them), so a wavefront reads each A operand
-//     once for all column tiles, and each writes its partial coefficients to LDS;
+//     is one aligned 16-digit block of x.  Each of the eight wavefronts computes whole column
+//     tiles over all K steps (pairs with zero operands read zero padding, which costs less than
+//     branching around them) and writes its coefficients to LDS;
 //   - coefficients (magnitude below 2^25) become balanced digits locally: each digit depends on
 //     the coefficients at most five places below it, so each thread turns its own run of
 //     digits around with no exchange (see normalize).
@@ -35,7 +34,8 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
 
 template <int S>
 struct Dig {
@@ -60,7 +60,7 @@ enum NormMode { kModeT, kModeM, kModeU, kModeOut };
 template <int S>
 struct UnpackLds {
   using D = Dig<S>;
-  int cf[4][D::CF];                    // digit coefficients of a product, one partial per wavefront
+  int cf[D::CF];                       // digit coefficients of a product
   alignas(16) uint8_t xa[D::XB];       // digits of the chain value (B operand of a b), from PX
   alignas(16) uint8_t xb[D::XB];       // digits of T mod R, then of m (B operands), from PX
   alignas(16) uint8_t td[2 * D::DP];   // digits of T = a b
@@ -75,59 +75,63 @@ struct UnpackLds {
 };
 
 // Digit coefficients of x y for the 16-digit blocks u < ulim (NTL = ceil(ulim / 16) column
-// tiles): x's digits in xd (blocks), y's reversed in yr.  The K steps (ks = 0 .. (min(NB, ulim -
-// 1)) / 4) are split evenly among the wavefronts, and a wavefront runs every column tile in
-// each of its K steps: one A operand serves all the tiles of a K step, consecutive products go
-// to different accumulators, and there is no branch.  Pairs whose operands are zero read the
-// zero padding (and, for the low product, the extra terms only reach blocks u >= ulim).
-// Wavefront w writes its partial coefficients (zero past the NTL tiles) to cf[w].  Every
-// thread; no barrier inside.
+// tiles): x's digits in xd (blocks), y's reversed in yr.  Wavefront w takes column tiles
+// w kT .. w kT + kT - 1 (kT = 1 up to 6144-bit moduli, 2 at 8192; wavefronts past the last
+// tile idle, tiles in [NTL, NT) get zeros) over all K steps ks = 0 .. (min(NB, ulim - 1)) / 4,
+// so every coefficient is computed whole by one wavefront and written once.  The next K step's
+// operand reads are in flight during each step's products, and pairs whose operands are zero
+// read the zero padding (for the low product, the extra terms only reach blocks u >= ulim).
+// Every thread; no barrier inside.
 template <int S, int NTL>
-__device__ void mfma_product(const uint8_t* xd, const uint8_t* yr, int ulim, int (*cf)[Dig<S>::CF]) {
+__device__ void mfma_product(const uint8_t* xd, const uint8_t* yr, int ulim, int* cf) {
   using D = Dig<S>;
+  constexpr int kT = (D::NT + kWaves - 1) / kWaves;  // column tiles per wavefront
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int kn = (min(D::NB, ulim - 1) >> 2) + 1;
-  const int ka = kn * wave / 4, kb = kn * (wave + 1) / 4;
+  const int nt0 = wave * kT;
   // Lane (g, c) in K step ks: A = y_(16w + c - s), s = 0..15, w = 4 ks + g, i.e. the reversed
   // bytes from PY + DP - 1 - 16 w - c on; B = x's block v = 16 nt + c - w.  Both move down by
   // 64 bytes per K step; the A window's misalignment (o & 3) is the lane's for every step.
   const int oA = D::PY + D::DP - 1 - 16 * g - c;
   const int aA = oA & ~3, sh = oA & 3;
-  const uint8_t* pb = xd + D::PX + 16 * (c - g);
-  v4i acc[NTL];
+  const uint8_t* pb = xd + D::PX + 16 * (c - g) + 256 * nt0;
+  v4i acc[kT];
 #pragma unroll
-  for (int nt = 0; nt < NTL; ++nt) acc[nt] = v4i{0, 0, 0, 0};
-  // operands of K step ks: the five words under the A window, and the NTL B blocks
-  auto load = [&](int ks, uint32_t (&y)[5], v4i (&bf)[NTL]) {
-    const uint32_t* pa = reinterpret_cast<const uint32_t*>(yr + aA - 64 * ks);
+  for (int j = 0; j < kT; ++j) acc[j] = v4i{0, 0, 0, 0};
+  if (nt0 < NTL) {
+    auto load = [&](int ks, uint32_t (&y)[5], v4i (&bf)[kT]) {
+      const uint32_t* pa = reinterpret_cast<const uint32_t*>(yr + aA - 64 * ks);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) y[i] = pa[i];
+      for (int i = 0; i < 5; ++i) y[i] = pa[i];
 #pragma unroll
-    for (int nt = 0; nt < NTL; ++nt) bf[nt] = *reinterpret_cast<const v4i*>(pb + 256 * nt - 64 * ks);
-  };
-  // the next K step's reads are in flight during this one's products
-  uint32_t y[5], yn[5];
-  v4i bf[NTL], bn[NTL];
-  if (ka < kb) load(ka, y, bf);
-  for (int ks = ka; ks < kb; ++ks) {
-    if (ks + 1 < kb) load(ks + 1, yn, bn);
-    const v4i af = v4i{(int)__builtin_amdgcn_alignbyte(y[1], y[0], sh), (int)__builtin_amdgcn_alignbyte(y[2], y[1], sh),
-                       (int)__builtin_amdgcn_alignbyte(y[3], y[2], sh), (int)__builtin_amdgcn_alignbyte(y[4], y[3], sh)};
+      for (int j = 0; j < kT; ++j)
+        if (nt0 + j < NTL) bf[j] = *reinterpret_cast<const v4i*>(pb + 256 * j - 64 * ks);
+    };
+    uint32_t y[5], yn[5];
+    v4i bf[kT], bn[kT];
+    load(0, y, bf);
+    for (int ks = 0; ks < kn; ++ks) {
+      if (ks + 1 < kn) load(ks + 1, yn, bn);
+      const v4i af = v4i{(int)__builtin_amdgcn_alignbyte(y[1], y[0], sh), (int)__builtin_amdgcn_alignbyte(y[2], y[1], sh),
+                         (int)__builtin_amdgcn_alignbyte(y[3], y[2], sh), (int)__builtin_amdgcn_alignbyte(y[4], y[3], sh)};
 #pragma unroll
-    for (int nt = 0; nt < NTL; ++nt) acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[nt], acc[nt], 0, 0, 0);
+      for (int j = 0; j < kT; ++j)
+        if (nt0 + j < NTL) acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[j], acc[j], 0, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) y[i] = yn[i];
+      for (int i = 0; i < 5; ++i) y[i] = yn[i];
 #pragma unroll
-    for (int nt = 0; nt < NTL; ++nt) bf[nt] = bn[nt];
+      for (int j = 0; j < kT; ++j) bf[j] = bn[j];
+    }
   }
-  // acc[nt][e]: coefficient row 4 g + e of block 16 nt + c
-  int* dst = cf[wave] + 16 * c + 4 * g;
+  // acc[j][e]: coefficient row 4 g + e of block 16 (nt0 + j) + c (zero past the NTL tiles)
+  int* dst = cf + 16 * c + 4 * g;
 #pragma unroll
-  for (int nt = 0; nt < D::NT; ++nt) *reinterpret_cast<v4i*>(dst + 256 * nt) = nt < NTL ? acc[nt < NTL ? nt : 0] : v4i{0, 0, 0, 0};
+  for (int j = 0; j < kT; ++j)
+    if (nt0 + j < D::NT) *reinterpret_cast<v4i*>(dst + 256 * (nt0 + j)) = acc[j];
 }
 
-// Balanced digits of sum_k c_k 128^k (c_k the sum of the four partials in L.cf, plus the digits
+// Balanced digits of sum_k c_k 128^k (c_k in L.cf, plus the digits
 // td for kModeU and kModeOut) for k < K (K = DP for kModeM, else 2 DP; what lies above is
 // dropped), written where MODE says:
 //   kModeT: T's digits to td, and T mod R's to xb;   kModeM: m's digits to xb;
@@ -152,9 +156,7 @@ __device__ void normalize(UnpackLds<S>& L) {
   for (int i = 0; i < RUN + 8; i += 4) {
     const int k = k0 - 8 + i;
     v4i v = v4i{0, 0, 0, 0};
-    if (k >= 0)
-      v = *reinterpret_cast<const v4i*>(&L.cf[0][k]) + *reinterpret_cast<const v4i*>(&L.cf[1][k]) +
-          *reinterpret_cast<const v4i*>(&L.cf[2][k]) + *reinterpret_cast<const v4i*>(&L.cf[3][k]);
+    if (k >= 0) v = *reinterpret_cast<const v4i*>(&L.cf[k]);
 #pragma unroll
     for (int j = 0; j < 4; ++j) cv[i + j] = v[j];
   }
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(kThreads) void unpack_chain_kernel(const uint32_t* 
       // buffer, free until the next product), then one thread propagates the carries over
       // S + 2 two's-complement words and adds M when the value is negative
       mont_mul_wg<S, kModeOut>(lds, lds.one);
-      long long* pw = reinterpret_cast<long long*>(&lds.cf[0][0]);
+      long long* pw = reinterpret_cast<long long*>(lds.cf);
       for (int w = threadIdx.x; w < S + 2; w += kThreads) {
         const int kb = (32 * w + 6) / 7, ke = min((32 * w + 31) / 7, D::DP - 1);
         long long acc = 0;
