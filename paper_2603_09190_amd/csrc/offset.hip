@@ -409,49 +409,70 @@ void launch_scale_offsets(const ClientDev& cd, const uint32_t* cko, int n, uint3
     scale_offsets_kernel<2><<<blocks, 256, 0, s>>>(cd, cko, n, out);
 }
 
-// t_j from W[j][0 .. 4h+3): one wavefront per row, numbers of S = 64 P limbs (S >= h + 2
-// holds the sum), modulus N zero-padded to S limbs.
-template <int P>
-__global__ __launch_bounds__(256) void offset_reduce_kernel(ClientDev cd, const uint32_t* __restrict__ W,
-                                                            long long ldw,
-                                                            const uint32_t* __restrict__ b, int rows,
-                                                            uint32_t* __restrict__ T) {
-  const int j = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (j >= rows) return;
-  const uint32_t* w = W + (size_t)j * ldw;
-  const int npos = 4 * cd.h + 3;
-  WNum<P> v, m;
+// t_j from W[j][0 .. 4h+3), four rows per wavefront (one per 16-lane row): numbers of 16 Q
+// limbs, Q = 4 PN + 1, so that 16 Q >= h + 2 limbs hold the sum; modulus N zero above its h
+// limbs.  Lane l of a row folds the byte positions of its limbs [Q l, Q l + Q): limb i takes
+// W[4i .. 4i + 3], shifted by 8 bits per position, as one 16-byte load (W's rows and the
+// clients' column ranges of 4h + 4 entries are 16-byte aligned; entry 4h + 3, which the
+// contraction leaves unwritten, is dropped), and the lane keeps the carry out of its chunk
+// pending until the end, as the Montgomery steps expect.  The result goes out through the
+// wavefront's own LDS slice, so that each lane stores four consecutive limbs of a row at once.
+template <int Q>
+__global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, const uint32_t* __restrict__ W,
+                                                                 long long ldw, const uint32_t* __restrict__ b,
+                                                                 int rows, uint32_t* __restrict__ T) {
+  __shared__ uint32_t out[4][4][16 * Q];  // [wavefront][row][limb]
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int widx = blockIdx.x * (blockDim.x >> 6) + wv;
+  if (4 * widx >= rows) return;
+  const int mine = 4 * widx + row_index();
+  const int j = min(rows - 1, mine);  // rows past the end repeat the last one and store nothing
+  const u32x4* w = reinterpret_cast<const u32x4*>(W + (size_t)j * ldw);
+  RNum<Q> v, m;
   uint64_t carry = 0;
 #pragma unroll
-  for (int jj = 0; jj < P; ++jj) {
-    const int limb = P * lane_id() + jj;
+  for (int jj = 0; jj < Q; ++jj) {
+    const int limb = Q * row_lane() + jj;
     uint64_t x = carry;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int pos = 4 * limb + u;
-      if (pos < npos) x += (uint64_t)w[pos] << (8 * u);
+    if (limb <= cd.h) {
+      const u32x4 e = w[limb];
+      x += (uint64_t)e[0] + ((uint64_t)e[1] << 8) + ((uint64_t)e[2] << 16) +
+           (limb < cd.h ? (uint64_t)e[3] << 24 : 0u);
     }
     if (limb == 3) x += b[j];  // b_j 2^96
     v.v[jj] = (uint32_t)x;
     carry = x >> 32;
   }
-  wn_load(m, cd.NP);
+  rn_load_n(m, cd.NP, cd.h);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) redc_step(v, carry, m, cd.nprime);
-  const uint64_t ovf = wn_resolve(v, carry);
-  wn_cond_sub(v, ovf, m);
-  wn_store_n(T + (size_t)j * cd.h, v, cd.h);
+  for (int i = 0; i < 3; ++i) rn_redc_step(v, carry, m, cd.nprime);
+  const uint64_t ovf = rn_resolve(v, carry);
+  rn_cond_sub(v, ovf, m);
+  uint32_t* o = out[wv][row_index()];
+#pragma unroll
+  for (int jj = 0; jj < Q; ++jj) o[Q * row_lane() + jj] = v.v[jj];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+  if (mine < rows) {
+    uint32_t* t = T + (size_t)j * cd.h;
+    for (int c = 4 * row_lane(); c < cd.h; c += 64) {
+      if (c + 4 <= cd.h && (reinterpret_cast<uintptr_t>(t + c) & 15) == 0) {
+        *reinterpret_cast<u32x4*>(t + c) = u32x4{o[c], o[c + 1], o[c + 2], o[c + 3]};
+      } else {
+        for (int i = c; i < min(c + 4, cd.h); ++i) t[i] = o[i];
+      }
+    }
+  }
 }
 
 void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,
                           int rows, uint32_t* T, hipStream_t s) {
   if (rows <= 0) return;
-  const int blocks = (rows + 3) / 4;
-  switch (cd.P) {
-    case 1: offset_reduce_kernel<1><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
-    case 2: offset_reduce_kernel<2><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
-    case 3: offset_reduce_kernel<3><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
-    case 4: offset_reduce_kernel<4><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
+  const int blocks = (rows + 15) / 16;
+  switch (cd.PN) {
+    case 1: offset_reduce_quad_kernel<5><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
+    case 2: offset_reduce_quad_kernel<9><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
   }
 }
 

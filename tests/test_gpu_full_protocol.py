@@ -338,3 +338,45 @@ def test_answer_offset_one_call(native, nclients, n_bits, on_device):
                 assert np.array_equal(B[i], b), f"answer of client {i}, round {rnd}"
                 assert limbs_rows_to_ints(T[i]) == protocol.offset_answer(b, E, offs[i][0], cl.N), \
                     f"offset answer of client {i}, round {rnd}"
+
+
+@pytest.mark.parametrize("n_bits", [1024, 1100, 2048, 4096])
+def test_answer_offset_carry_and_wrap(native, n_bits):
+    """Offsets solved so that, before b is added, row j0's offset term is 2^96 - 1 (b's addition
+    carries out of the low three limbs, across the lanes that hold them) and row j1's is N - 1
+    (adding b wraps past N). Both call forms must still equal the oracle on every row. At 1100
+    bits a row is 35 limbs, so rows start off 16-byte boundaries."""
+    rows, cols, n = 40, 64, 10
+    log(f"answer_offset carry and wrap: N {n_bits}")
+    inst = make_instance(cfg=1990 + n_bits, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False)
+    cl = inst.clients[0]
+    N = cl.N
+    h = (n_bits + 31) // 32
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    b = server.answer(inst.D, cl.qu)
+    j0, j1 = [int(j) for j in np.nonzero(b)[0][:2]]
+    rng = np.random.default_rng(1991)
+    cko = [int(x) % N for x in rng.integers(0, 1 << 62, size=n)]
+    # solve E[j, 0] x0 + E[j, 1] x1 = target_j - sum_{k >= 2} E[j, k] cko_k (mod N) for j0, j1
+    rest = [sum(int(E[j, k]) * cko[k] for k in range(2, n)) for j in (j0, j1)]
+    r = [((1 << 96) - 1 - rest[0]) % N, (N - 1 - rest[1]) % N]
+    a, bb, c, d = int(E[j0, 0]), int(E[j0, 1]), int(E[j1, 0]), int(E[j1, 1])
+    inv = pow((a * d - bb * c) % N, -1, N)
+    cko[0] = (d * r[0] - bb * r[1]) * inv % N
+    cko[1] = (a * r[1] - c * r[0]) * inv % N
+    assert sum(int(E[j0, k]) * cko[k] for k in range(n)) % N == (1 << 96) - 1
+    assert sum(int(E[j1, k]) * cko[k] for k in range(n)) % N == N - 1
+    CKO = wl.ints_to_limbs(cko, h)
+    want = protocol.offset_answer(b, E, cko, N)
+    assert want[j1] == int(b[j1]) - 1 and want[j0] == (1 << 96) - 1 + int(b[j0])
+    with native.Server(inst.D, inst.A) as srv:
+        N_limbs, ckr, _ = client_arrays(cl, n_bits)
+        cid = srv.add_client(N_limbs, n_bits, ckr)
+        B = np.zeros((1, rows), np.uint32)
+        T = np.zeros((1, rows, h), np.uint32)
+        srv.answer_offset([cid], cl.qu[None], CKO[None], B, T)
+        assert np.array_equal(B[0], b)
+        assert limbs_rows_to_ints(T[0]) == want, "one call"
+        T2 = np.zeros((1, rows, h), np.uint32)
+        srv.offset_answer([cid], CKO[None], B, T2)
+        assert limbs_rows_to_ints(T2[0]) == want, "two calls"
