@@ -58,9 +58,9 @@ STEP_TRAFFIC = {"84ad8428d96d552e": 1076585960}
 #     SQ_INSTS_VALU_INT64 and SQ_INSTS_VALU_INT32 in SQ_INSTS_VALU.
 COUNTERS = {
     "gemm_i8.hip": {"629d2dbca623b53d": {"kernel": "gemm_planes_kernel<8, 2, 2, 256, 4, false, true>",
-                                         "mfma_busy_frac": 0.300}},
-    "hgemm.hip": {"dbb3df29fd3d6f3c": {"kernel": "hgemm_w8_kernel<4, true, true>", "mfma_busy_frac": 0.681}},
-    "offset.hip": {"7010379a06e6184e": {"kernel": "offset_gemm_kernel<5, 4, 3>", "mfma_busy_frac": 0.291}},
+                                         "mfma_busy_frac": 0.295}},
+    "hgemm.hip": {"264366dae458c891": {"kernel": "hgemm_w8_kernel<4, true, true>", "mfma_busy_frac": 0.676}},
+    "offset.hip": {"3ba996d72d9036c7": {"kernel": "offset_gemm_kernel<5, 4, 3>", "mfma_busy_frac": 0.292}},
     "hint.hip": {"228424c8ab17600b": {"kernel": "hint_rows_quad_kernel<2>", "valu_insts_per_simd_cycle": 0.323,
                                       "int64_share_of_valu": 0.267, "int32_share_of_valu": 0.407}},
     "lwec.hip": {"48d5a64197984e83": {"kernel": "compress_lwe_quad_kernel<3>", "valu_insts_per_simd_cycle": 0.294,
@@ -69,7 +69,8 @@ COUNTERS = {
 
 
 # Headers whose code the counted kernels of a source compile in: their text joins the key.
-COUNTER_DEPS = {"hint.hip": ("rownum.h", "wavenum.h"), "lwec.hip": ("rownum.h", "wavenum.h")}
+COUNTER_DEPS = {"hgemm.hip": ("stage.h",), "offset.hip": ("stage.h", "rownum.h", "wavenum.h"),
+                "hint.hip": ("rownum.h", "wavenum.h"), "lwec.hip": ("rownum.h", "wavenum.h")}
 
 
 def counters(name: str):
