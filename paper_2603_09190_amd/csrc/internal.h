@@ -213,9 +213,11 @@ void launch_offset_gemm(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int
                         const uint8_t* Yf, const int32_t* colsum, int batch, int h, uint32_t* W,
                         long long ldw, int cpc, int variant, hipStream_t s);
 // T[j] (h limbs) = (b[j] 2^96 + sum_pos W[j*ldw + pos] 2^(8 pos)) 2^-96 mod N, pos < 4h + 3,
-// where W was computed from offsets scaled by 2^96 (launch_scale_offsets).
+// where W was computed from offsets scaled by 2^96 (launch_scale_offsets).  With part non-null
+// (b unused), b[j] = sum_s part[j*nseg + s] mod 2^32 from launch_matvec_part, written to bout.
 void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,
-                          int rows, uint32_t* T, hipStream_t s);
+                          int rows, uint32_t* T, hipStream_t s, const uint32_t* part = nullptr, int nseg = 0,
+                          uint32_t* bout = nullptr);
 
 // C[j] = K_j (1 + T[j] N) mod N^2 for rows [0, rows): T is rows x h (any value below 2^(32h)),
 // K_j from the stored K', Y[j] = (K_j mod N) R_N mod N (h limbs); C is rows x L.

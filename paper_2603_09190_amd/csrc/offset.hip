@@ -417,10 +417,14 @@ void launch_scale_offsets(const ClientDev& cd, const uint32_t* cko, int n, uint3
 // contraction leaves unwritten, is dropped), and the lane keeps the carry out of its chunk
 // pending until the end, as the Montgomery steps expect.  The result goes out through the
 // wavefront's own LDS slice, so that each lane stores four consecutive limbs of a row at once.
+// With part non-null, b_j is not read from b but summed from the one-query matvec's nseg
+// per-segment partials part[j nseg + s] (mod 2^32), and written to bout[j].
 template <int Q>
 __global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, const uint32_t* __restrict__ W,
                                                                  long long ldw, const uint32_t* __restrict__ b,
-                                                                 int rows, uint32_t* __restrict__ T) {
+                                                                 const uint32_t* __restrict__ part, int nseg,
+                                                                 uint32_t* __restrict__ bout, int rows,
+                                                                 uint32_t* __restrict__ T) {
   __shared__ uint32_t out[4][4][16 * Q];  // [wavefront][row][limb]
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int widx = blockIdx.x * (blockDim.x >> 6) + wv;
@@ -428,6 +432,19 @@ __global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, c
   const int mine = 4 * widx + row_index();
   const int j = min(rows - 1, mine);  // rows past the end repeat the last one and store nothing
   const u32x4* w = reinterpret_cast<const u32x4*>(W + (size_t)j * ldw);
+  uint32_t bj;
+  if (part) {
+    uint32_t sum = 0;
+    for (int q = row_lane(); q < nseg; q += 16) sum += part[(size_t)j * nseg + q];
+    sum += __shfl_xor(sum, 8, 16);
+    sum += __shfl_xor(sum, 4, 16);
+    sum += __shfl_xor(sum, 2, 16);
+    sum += __shfl_xor(sum, 1, 16);
+    bj = sum;
+    if (row_lane() == 0 && mine < rows) bout[j] = bj;
+  } else {
+    bj = b[j];
+  }
   RNum<Q> v, m;
   uint64_t carry = 0;
 #pragma unroll
@@ -439,7 +456,7 @@ __global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, c
       x += (uint64_t)e[0] + ((uint64_t)e[1] << 8) + ((uint64_t)e[2] << 16) +
            (limb < cd.h ? (uint64_t)e[3] << 24 : 0u);
     }
-    if (limb == 3) x += b[j];  // b_j 2^96
+    if (limb == 3) x += bj;  // b_j 2^96
     v.v[jj] = (uint32_t)x;
     carry = x >> 32;
   }
@@ -467,12 +484,12 @@ __global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, c
 }
 
 void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,
-                          int rows, uint32_t* T, hipStream_t s) {
+                          int rows, uint32_t* T, hipStream_t s, const uint32_t* part, int nseg, uint32_t* bout) {
   if (rows <= 0) return;
   const int blocks = (rows + 15) / 16;
   switch (cd.PN) {
-    case 1: offset_reduce_quad_kernel<5><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
-    case 2: offset_reduce_quad_kernel<9><<<blocks, 256, 0, s>>>(cd, W, ldw, b, rows, T); break;
+    case 1: offset_reduce_quad_kernel<5><<<blocks, 256, 0, s>>>(cd, W, ldw, b, part, nseg, bout, rows, T); break;
+    case 2: offset_reduce_quad_kernel<9><<<blocks, 256, 0, s>>>(cd, W, ldw, b, part, nseg, bout, rows, T); break;
   }
 }
 

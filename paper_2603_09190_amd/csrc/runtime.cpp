@@ -1676,13 +1676,40 @@ pir_status pir_answer_offset(pir_server* s, const uint32_t* ids, uint32_t batch,
     dB = (uint32_t*)s->s_ab.p;
     dT = (uint32_t*)s->s_t.p;
   }
+  // One query with at most 64 column segments: the matvec writes per-segment partial sums (no
+  // packing of the query), and the reduction sums them into B as it folds W.
+  const int nseg = zp::answer_segments((int)s->pitch);
+  const bool parts = batch == 1 && nseg <= 64;
+  if (parts) {
+    if (reinterpret_cast<uintptr_t>(dQ) % 16 != 0) {  // the matvec reads the query 16 bytes at a time
+      ZP_TRY(s->scratch(s->s_q, qbytes));
+      ZP_HIP(hipMemcpyAsync(s->s_q.p, dQ, qbytes, hipMemcpyDeviceToDevice, st));
+      dQ = (const uint32_t*)s->s_q.p;
+    }
+    ZP_TRY(s->scratch(s->s_part, (size_t)nseg * s->rows * sizeof(uint32_t)));
+  }
   // the offset contraction (independent of B) on the second stream, the answer meanwhile on the
   // server's stream; the reduction needs both
   ZP_TRY(offset_contract(s, cs, dK, s->side));
   ZP_HIP(hipEventRecord(s->ev_join, s->side));
-  ZP_TRY(answer_impl(s, dQ, batch, dB, PIR_PTR_DEVICE, PIR_PATH_AUTO));
-  ZP_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
-  ZP_TRY(offset_reduce_all(s, cs, dB, dT));
+  if (parts) {
+    auto* part = (uint32_t*)s->s_part.p;
+    {
+      ProfScope ps(s, PIR_KERNEL_STEP_MATVEC);
+      zp::launch_matvec_part(s->D, (int)s->rows, (int)s->pitch, dQ, (int)s->cols, part, st);
+    }
+    ZP_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+    {
+      ProfScope ps(s, PIR_KERNEL_OFFSET);
+      zp::launch_offset_reduce(cs[0]->dev(), (const uint32_t*)s->s_w.p, 4 * h + 4, nullptr, (int)s->rows, dT, st,
+                               part, nseg, dB);
+    }
+    ZP_HIP(hipGetLastError());
+  } else {
+    ZP_TRY(answer_impl(s, dQ, batch, dB, PIR_PTR_DEVICE, PIR_PATH_AUTO));
+    ZP_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+    ZP_TRY(offset_reduce_all(s, cs, dB, dT));
+  }
   if (ptr_flags == PIR_PTR_HOST) {
     ZP_HIP(hipMemcpyAsync(B, dB, bbytes, hipMemcpyDeviceToHost, st));
     ZP_HIP(hipMemcpyAsync(T, dT, tbytes, hipMemcpyDeviceToHost, st));

@@ -293,11 +293,13 @@ def test_packed_offset_answer_many_rows(native):
     assert limbs_rows_to_ints(Tg[0]) == protocol.offset_answer_packed(t_or, ell, gamma, cl.N)
 
 
-@pytest.mark.parametrize("nclients,n_bits,on_device", [(1, 2048, False), (3, 1024, True), (2, 256, False)])
+@pytest.mark.parametrize("nclients,n_bits,on_device", [(1, 2048, False), (1, 1024, True), (3, 1024, True),
+                                                     (2, 256, False)])
 def test_answer_offset_one_call(native, nclients, n_bits, on_device):
     """pir_answer_offset: the answer and the offset answer in one call, the contraction on the
     server's second stream beside the answer; B and T equal the oracle on every row (and a row
-    update between calls is seen by both)."""
+    update between calls is seen by both). One client takes the one-query form (the matvec's
+    per-segment partials summed in the reduction), several the batched answer."""
     rows, cols, n = 150, 300, 12
     log(f"answer_offset: {nclients} clients, N {n_bits}, device {on_device}")
     inst = make_instance(cfg=990 + nclients, rows=rows, cols=cols, n=n, n_bits=n_bits, nclients=nclients,
@@ -380,3 +382,25 @@ def test_answer_offset_carry_and_wrap(native, n_bits):
         T2 = np.zeros((1, rows, h), np.uint32)
         srv.offset_answer([cid], CKO[None], B, T2)
         assert limbs_rows_to_ints(T2[0]) == want, "two calls"
+
+
+def test_answer_offset_one_query_many_segments(native):
+    """The one-query form of pir_answer_offset on a database of 70000 columns: 18 column
+    segments of partial sums, more than one per lane of a row in the reduction that adds them
+    into b. B and T equal the oracle on every row."""
+    rows, cols, n, n_bits = 40, 70000, 6, 1024
+    log(f"answer_offset one query, {cols} columns")
+    inst = make_instance(cfg=2990, rows=rows, cols=cols, n=n, n_bits=n_bits, encrypt_secret=False, zero_row=5)
+    cl = inst.clients[0]
+    h = (n_bits + 31) // 32
+    cko, CKO = _offsets(cl)
+    E = server.exponents(server.global_hint(inst.D, inst.A))
+    b = server.answer(inst.D, cl.qu)
+    with native.Server(inst.D, inst.A) as srv:
+        N_limbs, ckr, _ = client_arrays(cl, n_bits)
+        cid = srv.add_client(N_limbs, n_bits, ckr)
+        B = np.zeros((1, rows), np.uint32)
+        T = np.zeros((1, rows, h), np.uint32)
+        srv.answer_offset([cid], cl.qu[None], CKO[None], B, T)
+    assert np.array_equal(B[0], b)
+    assert limbs_rows_to_ints(T[0]) == protocol.offset_answer(b, E, cko, cl.N)
