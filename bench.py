@@ -386,7 +386,7 @@ def main() -> int:
     fpp_ms = timed_ms(fpp_step, args.steps)
     srv.set_packing(cid, 1)
     off_ops = 2.0 * rows * 4 * n * (4 * h + 3)
-    off_bytes = rows * 4 * n + rows * (4 * h + 3) * 4   # E's four byte planes in, W out
+    off_bytes = rows * 4 * n + rows * (h + 1) * 8   # E's four byte planes in, the folded limbs out
     full = {"ms_per_step": round(fp_ms, 4), "db_gbs": round(db_bytes / (fp_ms * 1e-3) / 1e9, 3),
             "one_call_ms_per_step": round(fp1_ms, 4),
             "one_call_db_gbs": round(db_bytes / (fp1_ms * 1e-3) / 1e9, 3),
@@ -394,7 +394,7 @@ def main() -> int:
             "offset_gemm_kernel_avg_us": round(og_avg * 1e3, 2),
             "offset_gemm_int8_tops": round(off_ops / (og_avg * 1e-3) / 1e12, 1),
             "offset_gemm_frac_of_peak": round(off_ops / (og_avg * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
-            # E's planes are read once and W written once: the HBM-side position of the contraction
+            # E's planes are read once and the folded limbs written once: the HBM-side position
             "offset_gemm_hbm_gbs": round(off_bytes / (og_avg * 1e-3) / 1e9, 1),
             "offset_gemm_hbm_frac": round(off_bytes / (og_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "offset_gemm_counters": counters("offset.hip"),

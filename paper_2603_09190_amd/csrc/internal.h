@@ -205,17 +205,18 @@ void launch_scale_offsets(const ClientDev& cd, const uint32_t* cko, int n, uint3
 long long offset_y_bytes(int n, int h);
 void launch_pack_y(const uint32_t* ys, int batch, int n, int h, uint8_t* Yf, int32_t* colsum,
                    hipStream_t s);
-// W[j ldw + i cpc + pos] = sum_k sum_a (byte a of E_jk) (byte pos - a of ys[i][k]) for j < rows,
-// pos < 4h + 3 and every client i < batch (exact: below 4 n 255^2 < 2^32).
+// With W_pos = sum_k sum_a (byte a of E_jk) (byte pos - a of ys[i][k]) for pos < 4h + 3 (exact:
+// below 4 n 255^2 < 2^32; zero beyond): X[j ldw + i cpc + l] = sum_{u<4} W_(4l+u) 2^(8u) for
+// l <= h, every row j < rows and client i < batch (cpc >= h + 1 words per client).
 // `variant` < offset_gemm_variants(h) picks the launch shape (identical bits for every one).
 int offset_gemm_variants(int h);
 void launch_offset_gemm(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
-                        const uint8_t* Yf, const int32_t* colsum, int batch, int h, uint32_t* W,
+                        const uint8_t* Yf, const int32_t* colsum, int batch, int h, uint64_t* X,
                         long long ldw, int cpc, int variant, hipStream_t s);
-// T[j] (h limbs) = (b[j] 2^96 + sum_pos W[j*ldw + pos] 2^(8 pos)) 2^-96 mod N, pos < 4h + 3,
-// where W was computed from offsets scaled by 2^96 (launch_scale_offsets).  With part non-null
-// (b unused), b[j] = sum_s part[j*nseg + s] mod 2^32 from launch_matvec_part, written to bout.
-void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,
+// T[j] (h limbs) = (b[j] 2^96 + sum_l X[j*ldw + l] 2^(32 l)) 2^-96 mod N, l <= h, where X was
+// computed from offsets scaled by 2^96 (launch_scale_offsets).  With part non-null (b unused),
+// b[j] = sum_s part[j*nseg + s] mod 2^32 from launch_matvec_part, written to bout.
+void launch_offset_reduce(const ClientDev& cd, const uint64_t* X, long long ldw, const uint32_t* b,
                           int rows, uint32_t* T, hipStream_t s, const uint32_t* part = nullptr, int nseg = 0,
                           uint32_t* bout = nullptr);
 

@@ -192,6 +192,15 @@ void launch_pack_y(const uint32_t* ys, int batch, int n, int h, uint8_t* Yc, int
 
 long long offset_y_bytes(int n, int h) { return (long long)offset_slices(n) * (offset_tiles(h) + 1) * 1024; }
 
+// A 64-bit value from another lane of the quad (DPP quad_perm C: kDppQuadXor1 takes lane i ^ 1,
+// kDppQuadXor2 lane i ^ 2).
+template <int C>
+__device__ __forceinline__ uint64_t quad_from(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, C, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), C, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // ---- the contraction
 //
 // A workgroup of 2 WC wavefronts takes 128 rows (eight 16-row tiles), one column group of
@@ -204,10 +213,13 @@ long long offset_y_bytes(int n, int h) { return (long long)offset_slices(n) * (o
 // need (one contiguous run); wavefront w issues the pieces w, w + 2 WC, ...  One barrier per
 // slice; the four planes then run back to back on the staged slice (4 x 4 x CWV MFMAs per
 // wavefront), plane a reading its B fragments a columns to the left.
-// Then each accumulator becomes a W entry, straight to memory:
+// Then each accumulator becomes a W entry:
 //   W = acc + 128 sum_{a in A(pos)} (colsum[pos - a] + Ers_a[j]) + 16384 n |A(pos)|,
 //   A(pos) = {a < 4 : 0 <= pos - a < 4h}
-// (exact modulo 2^32, and the true value is below 4 n 255^2 < 2^32 for n <= 16384).
+// (exact modulo 2^32, and the true value is below 4 n 255^2 < 2^32 for n <= 16384), and the
+// four positions of a 32-bit limb, which sit in four neighbouring lanes, are folded into one
+// 64-bit word X_l = sum_u W[4l + u] 2^(8u) (below 2^57) by two DPP exchanges within the quad:
+// the output holds limbs 0 .. h of each row (cpc words per client), half the bytes of W.
 // The grid is XCD-aware: workgroup L runs on XCD L mod 8, and each XCD takes the (client, column
 // group) items of its row blocks (x, x + 8, ...) one after the other, so a block's E stream comes
 // from HBM once and from that XCD's L2 for the other items.
@@ -215,7 +227,7 @@ template <int CWV, int WC, int NS>
 __global__ __launch_bounds__(128 * WC) __attribute__((amdgpu_waves_per_eu(WC / 2, WC / 2)))
 void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restrict__ Ers, int rows_pad, int rows,
                         int n, int S, const uint8_t* __restrict__ Yc, const int32_t* __restrict__ colsum,
-                        int batch, int nrb, int ncg, int NTq, int h, uint32_t* __restrict__ W, long long ldw,
+                        int batch, int nrb, int ncg, int NTq, int h, uint64_t* __restrict__ W, long long ldw,
                         int cpc) {
   constexpr int RW = 4, BR = 8, CW = CWV, BC = WC * CWV, NW = 2 * WC;
   constexpr int EA = 4 * BR;      // E pieces per stage: piece a BR + i is plane a of row tile i
@@ -330,16 +342,20 @@ void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restric
 #pragma unroll
     for (int t = 0; t < CW; ++t) {
       const int pos = (t0 + wc * CW + t) * 16 + r;
-      if (pos >= npos) continue;
+      const int limb = pos >> 2;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = rowbase + e;
-        if (row >= rows) continue;
         uint32_t v = (uint32_t)acc[i][t][e] + cterm[t];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
           if (amask[t] & (1u << a)) v += R[e][a];
-        W[(size_t)row * ldw + (size_t)ci * cpc + pos] = v;
+        if (pos >= npos) v = 0u;
+        // every lane takes part in the exchanges; only the quad's first lane stores
+        uint64_t x = (uint64_t)v << (8 * (r & 3));
+        x += quad_from<kDppQuadXor1>(x);
+        x += quad_from<kDppQuadXor2>(x);
+        if ((r & 3) == 0 && row < rows && limb <= h) W[(size_t)row * ldw + (size_t)ci * cpc + limb] = x;
       }
     }
   }
@@ -347,7 +363,7 @@ void offset_gemm_kernel(const uint8_t* __restrict__ Ep, const int32_t* __restric
 
 template <int CWV, int WC, int NS>
 static void launch_offset_gemm_t(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
-                                 const uint8_t* Yc, const int32_t* colsum, int batch, int h, uint32_t* W,
+                                 const uint8_t* Yc, const int32_t* colsum, int batch, int h, uint64_t* W,
                                  long long ldw, int cpc, hipStream_t s) {
   const int S = offset_slices(n), NTq = offset_tiles(h);
   const int ncg = NTq / (WC * CWV);
@@ -365,7 +381,7 @@ static bool offset_four_stages(int bc) { return 4 * (32 + bc + 1) * 1024 <= 1638
 int offset_gemm_variants(int h) { return offset_four_stages(offset_group(h)) ? 4 : 2; }
 
 void launch_offset_gemm(const uint8_t* Ep, const int32_t* Ers, int rows_pad, int rows, int n,
-                        const uint8_t* Yc, const int32_t* colsum, int batch, int h, uint32_t* W,
+                        const uint8_t* Yc, const int32_t* colsum, int batch, int h, uint64_t* W,
                         long long ldw, int cpc, int variant, hipStream_t s) {
   const int BC = offset_group(h);
   const int v = (variant >= 0 && variant < offset_gemm_variants(h)) ? variant : 0;
@@ -409,18 +425,16 @@ void launch_scale_offsets(const ClientDev& cd, const uint32_t* cko, int n, uint3
     scale_offsets_kernel<2><<<blocks, 256, 0, s>>>(cd, cko, n, out);
 }
 
-// t_j from W[j][0 .. 4h+3), four rows per wavefront (one per 16-lane row): numbers of 16 Q
-// limbs, Q = 4 PN + 1, so that 16 Q >= h + 2 limbs hold the sum; modulus N zero above its h
-// limbs.  Lane l of a row folds the byte positions of its limbs [Q l, Q l + Q): limb i takes
-// W[4i .. 4i + 3], shifted by 8 bits per position, as one 16-byte load (W's rows and the
-// clients' column ranges of 4h + 4 entries are 16-byte aligned; entry 4h + 3, which the
-// contraction leaves unwritten, is dropped), and the lane keeps the carry out of its chunk
-// pending until the end, as the Montgomery steps expect.  The result goes out through the
+// t_j from the folded limbs X[j][0 .. h] (X_l = sum_u W[4l + u] 2^(8u), below 2^57), four rows
+// per wavefront (one per 16-lane row): numbers of 16 Q limbs, Q = 4 PN + 1, so that
+// 16 Q >= h + 2 limbs hold the sum; modulus N zero above its h limbs.  Lane l of a row adds the
+// words of its limbs [Q l, Q l + Q) with carries along its chunk and keeps the carry out of the
+// chunk pending until the end, as the Montgomery steps expect.  The result goes out through the
 // wavefront's own LDS slice, so that each lane stores four consecutive limbs of a row at once.
 // With part non-null, b_j is not read from b but summed from the one-query matvec's nseg
 // per-segment partials part[j nseg + s] (mod 2^32), and written to bout[j].
 template <int Q>
-__global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, const uint32_t* __restrict__ W,
+__global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, const uint64_t* __restrict__ W,
                                                                  long long ldw, const uint32_t* __restrict__ b,
                                                                  const uint32_t* __restrict__ part, int nseg,
                                                                  uint32_t* __restrict__ bout, int rows,
@@ -431,16 +445,12 @@ __global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, c
   if (4 * widx >= rows) return;
   const int mine = 4 * widx + row_index();
   const int j = min(rows - 1, mine);  // rows past the end repeat the last one and store nothing
-  const u32x4* w = reinterpret_cast<const u32x4*>(W + (size_t)j * ldw);
+  const uint64_t* w = W + (size_t)j * ldw;
   uint32_t bj;
   if (part) {
     uint32_t sum = 0;
     for (int q = row_lane(); q < nseg; q += 16) sum += part[(size_t)j * nseg + q];
-    sum += __shfl_xor(sum, 8, 16);
-    sum += __shfl_xor(sum, 4, 16);
-    sum += __shfl_xor(sum, 2, 16);
-    sum += __shfl_xor(sum, 1, 16);
-    bj = sum;
+    bj = row_sum16(sum);
     if (row_lane() == 0 && mine < rows) bout[j] = bj;
   } else {
     bj = b[j];
@@ -451,11 +461,7 @@ __global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, c
   for (int jj = 0; jj < Q; ++jj) {
     const int limb = Q * row_lane() + jj;
     uint64_t x = carry;
-    if (limb <= cd.h) {
-      const u32x4 e = w[limb];
-      x += (uint64_t)e[0] + ((uint64_t)e[1] << 8) + ((uint64_t)e[2] << 16) +
-           (limb < cd.h ? (uint64_t)e[3] << 24 : 0u);
-    }
+    if (limb <= cd.h) x += w[limb];
     if (limb == 3) x += bj;  // b_j 2^96
     v.v[jj] = (uint32_t)x;
     carry = x >> 32;
@@ -483,7 +489,7 @@ __global__ __launch_bounds__(256) void offset_reduce_quad_kernel(ClientDev cd, c
   }
 }
 
-void launch_offset_reduce(const ClientDev& cd, const uint32_t* W, long long ldw, const uint32_t* b,
+void launch_offset_reduce(const ClientDev& cd, const uint64_t* W, long long ldw, const uint32_t* b,
                           int rows, uint32_t* T, hipStream_t s, const uint32_t* part, int nseg, uint32_t* bout) {
   if (rows <= 0) return;
   const int blocks = (rows + 15) / 16;

@@ -1500,26 +1500,26 @@ static pir_status offset_clients(pir_server* s, const uint32_t* ids, uint32_t ba
   return PIR_OK;
 }
 
-// The offset contraction of the full protocol's online step: W (rows x batch (4h + 4) words in
-// s_w) from the clients' offsets dK, launched on stream cst (the launch shape is tuned on the
-// server's stream first, on the first call of a shape).
+// The offset contraction of the full protocol's online step: the folded limbs X (rows x batch
+// (h + 1) 64-bit words in s_w) from the clients' offsets dK, launched on stream cst (the launch
+// shape is tuned on the server's stream first, on the first call of a shape).
 static pir_status offset_contract(pir_server* s, const std::vector<ClientState*>& cs, const uint32_t* dK,
                                   hipStream_t cst) {
   const uint32_t batch = (uint32_t)cs.size();
   ZP_TRY(refresh_all_stale_H(s));
   ZP_TRY(ensure_E(s));
   const uint32_t h = cs[0]->h;
-  const int cpc = (int)(4 * h + 4);
+  const int cpc = (int)(h + 1);
   const long long ncol = (long long)batch * cpc;
   const size_t kbytes = (size_t)batch * s->n * h * sizeof(uint32_t);
   const int NT = zp::offset_tiles((int)h);
   ZP_TRY(s->scratch(s->s_x, (size_t)batch * zp::offset_y_bytes((int)s->n, (int)h)));
   ZP_TRY(s->scratch(s->s_xcs, (size_t)batch * 16 * NT * sizeof(int32_t)));
-  ZP_TRY(s->scratch(s->s_w, (size_t)s->rows * ncol * sizeof(uint32_t)));
+  ZP_TRY(s->scratch(s->s_w, (size_t)s->rows * ncol * sizeof(uint64_t)));
   ZP_TRY(s->scratch(s->s_ys, kbytes));
   auto* X = (uint8_t*)s->s_x.p;
   auto* xcs = (int32_t*)s->s_xcs.p;
-  auto* W = (uint32_t*)s->s_w.p;
+  auto* W = (uint64_t*)s->s_w.p;
   auto* ys = (uint32_t*)s->s_ys.p;
   auto prepare = [&](hipStream_t on) {
     ProfScope ps(s, PIR_KERNEL_OFFSET, (int)batch, on);
@@ -1542,8 +1542,10 @@ static pir_status offset_contract(pir_server* s, const std::vector<ClientState*>
   }
   if (need_tune) {
     prepare(s->stream);
-    ZP_TRY(tune_variants(s, "offset", zp::offset_gemm_variants((int)h), [&](int v) { launch(v, s->stream); }, W,
-                         (int)s->rows, (int)ncol, true, ncol, &variant));
+    // the snapshot compares the 64-bit words as pairs of 32-bit ones
+    ZP_TRY(tune_variants(s, "offset", zp::offset_gemm_variants((int)h), [&](int v) { launch(v, s->stream); },
+                         reinterpret_cast<const uint32_t*>(W), (int)s->rows, (int)(2 * ncol), true, 2 * ncol,
+                         &variant));
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_otune[key] = variant;
   }
@@ -1560,14 +1562,14 @@ static pir_status offset_contract(pir_server* s, const std::vector<ClientState*>
   return PIR_OK;
 }
 
-// T[i] = (B[i] + W_i folded into limbs) mod N_i for the contraction in s_w, on the server's stream.
+// T[i] = (B[i] + X_i) mod N_i for the contraction's folded limbs in s_w, on the server's stream.
 static pir_status offset_reduce_all(pir_server* s, const std::vector<ClientState*>& cs, const uint32_t* dB,
                                     uint32_t* dT) {
   const uint32_t batch = (uint32_t)cs.size();
   const uint32_t h = cs[0]->h;
-  const int cpc = (int)(4 * h + 4);
+  const int cpc = (int)(h + 1);
   const long long ncol = (long long)batch * cpc;
-  const auto* W = (const uint32_t*)s->s_w.p;
+  const auto* W = (const uint64_t*)s->s_w.p;
   {
     ProfScope ps(s, PIR_KERNEL_OFFSET, (int)batch);
     for (uint32_t i = 0; i < batch; ++i)
@@ -1701,7 +1703,7 @@ pir_status pir_answer_offset(pir_server* s, const uint32_t* ids, uint32_t batch,
     ZP_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
     {
       ProfScope ps(s, PIR_KERNEL_OFFSET);
-      zp::launch_offset_reduce(cs[0]->dev(), (const uint32_t*)s->s_w.p, 4 * h + 4, nullptr, (int)s->rows, dT, st,
+      zp::launch_offset_reduce(cs[0]->dev(), (const uint64_t*)s->s_w.p, h + 1, nullptr, (int)s->rows, dT, st,
                                part, nseg, dB);
     }
     ZP_HIP(hipGetLastError());
