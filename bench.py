@@ -60,7 +60,7 @@ COUNTERS = {
     "gemm_i8.hip": {"629d2dbca623b53d": {"kernel": "gemm_planes_kernel<8, 2, 2, 256, 4, false, true>",
                                          "mfma_busy_frac": 0.295}},
     "hgemm.hip": {"264366dae458c891": {"kernel": "hgemm_w8_kernel<4, true, true>", "mfma_busy_frac": 0.676}},
-    "offset.hip": {"3ba996d72d9036c7": {"kernel": "offset_gemm_kernel<5, 4, 3>", "mfma_busy_frac": 0.292}},
+    "offset.hip": {"1e0f7e3a01b5cd70": {"kernel": "offset_gemm_kernel<5, 4, 3>", "mfma_busy_frac": 0.286}},
     "hint.hip": {"228424c8ab17600b": {"kernel": "hint_rows_quad_kernel<2>", "valu_insts_per_simd_cycle": 0.323,
                                       "int64_share_of_valu": 0.267, "int32_share_of_valu": 0.407}},
     "lwec.hip": {"48d5a64197984e83": {"kernel": "compress_lwe_quad_kernel<3>", "valu_insts_per_simd_cycle": 0.294,
